@@ -1,0 +1,196 @@
+"""Plain FP64 CPU oracle for the Kohn-Sham hot path (arXiv:2106.03872).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and
+the CPU-baseline leg of the benchmark may import this module; the product
+path never does.  It shares no code with the HIP library: its only inputs are
+arrays (potential, projector tables, coefficients) drawn by the seeded
+generator.
+
+Every step follows the paper's definitions directly, without blocking, fusion
+or reordering:
+
+* Orbitals live in Fourier space as plane-wave coefficients on the full FFT
+  box (the plane-wave basis of Section "DFT and TDDFT implementation"), with
+  ``psi(r) = Omega^{-1/2} sum_G chi(G) c_G exp(+i G.r)`` so that
+  ``int |psi|^2 = sum |c|^2``.
+* The Hamiltonian (Eq. hamiltonian, static potential) is applied in operator
+  form (Section "Implementation of the KS Hamiltonian"): kinetic energy
+  ``|G|^2/2`` diagonal in Fourier space, the local potential multiplicative in
+  real space, the Kleinman-Bylander non-local part (Eq. vnl) as sphere
+  projections in real space, with two Fourier transforms in between.  The
+  operator is restricted to the plane-wave sphere ``chi = [|G|^2/2 < E_cut]``:
+  ``H = chi (K + F^-1 (V + V_nl) F) chi``.
+* Time propagation: one step of the 4th-order truncated Taylor series of
+  ``exp(-i H dt)`` (Section "Real-time propagation"), written as explicit
+  powers ``sum_k (-i dt)^k / k! H^k c``.
+* Density: ``n(r) = sum_k f_k |psi_k(r)|^2`` (Eq. density with occupations).
+* Band energy ``sum_k f_k <psi_k|H|psi_k>`` and orbital norms.
+* Orthonormalisation by Cholesky of the overlap (the orthogonalisation step of
+  Section "Ground-state solution").
+
+Numerics: numpy FP64 / complex128; FFTs by ``scipy.fft`` (a library routine
+standing in for the DFT sums) using all host cores.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import scipy.fft
+import scipy.linalg
+
+WORKERS = os.cpu_count() or 1
+
+
+class Grid:
+    """FFT box, reciprocal vectors and the plane-wave sphere (row O1).
+
+    Box index ``j_a`` holds the integer frequency ``m_a = j_a`` for
+    ``j_a < ceil(n_a/2)`` and ``j_a - n_a`` otherwise; ``G_a = 2 pi m_a / L_a``;
+    ``K = |G|^2 / 2`` (kinetic term, diagonal in Fourier space);
+    ``chi = K < E_cut`` (strict), or the whole box when ``E_cut <= 0``.
+    """
+
+    def __init__(self, n, L, ecut):
+        self.n = tuple(int(x) for x in n)
+        self.L = tuple(float(x) for x in L)
+        self.ecut = float(ecut)
+        self.N = int(np.prod(self.n))
+        self.omega = float(np.prod(self.L))
+        self.dV = self.omega / self.N
+        self.m = []
+        self.G = []
+        for a in range(3):
+            na = self.n[a]
+            j = np.arange(na)
+            ma = np.where(j < (na + 1) // 2, j, j - na)
+            self.m.append(ma)
+            self.G.append(2.0 * np.pi * ma / self.L[a])
+        g0, g1, g2 = self.G
+        self.K = 0.5 * (g0[:, None, None] ** 2 + g1[None, :, None] ** 2 + g2[None, None, :] ** 2)
+        if self.ecut > 0:
+            self.chi = self.K < self.ecut
+        else:
+            self.chi = np.ones(self.n, dtype=bool)
+        self.npw = int(self.chi.sum())
+
+
+class Hamiltonian:
+    """Static Kohn-Sham Hamiltonian: grid, local potential, KB projectors.
+
+    ``atoms`` is a list of ``(idx, beta)`` pairs: flat C-order grid indices of
+    the sphere points of atom I and the projector values ``beta[j, p]`` there;
+    ``d[I, p]`` are the KB coefficients (Eq. vnl).
+    """
+
+    def __init__(self, grid, vloc, atoms=(), d=None):
+        self.grid = grid
+        self.vloc = np.asarray(vloc, dtype=np.float64).reshape(grid.n)
+        self.atoms = [(np.asarray(i, np.int64), np.asarray(b, np.float64)) for i, b in atoms]
+        self.d = np.zeros((0, 0)) if d is None else np.asarray(d, np.float64)
+
+
+def synthesize(grid, c):
+    """Row O2: real-space orbitals ``Omega^{-1/2} sum_G chi c_G e^{+iG.r}``.
+
+    ``c`` has shape ``[..., n0, n1, n2]``; coefficients outside the sphere are
+    ignored.
+    """
+    u = scipy.fft.ifftn(np.where(grid.chi, c, 0.0), axes=(-3, -2, -1), norm="forward",
+                        workers=WORKERS)
+    return u / math.sqrt(grid.omega)
+
+
+def analyze(grid, f):
+    """Row O6: ``Omega^{1/2} N^{-1} sum_r f(r) e^{-iG.r}`` on the full box."""
+    return scipy.fft.fftn(f, axes=(-3, -2, -1), norm="backward", workers=WORKERS) * (
+        math.sqrt(grid.omega) / grid.N)
+
+
+def projections(ham, psi_r):
+    """Row O4: ``P[I, p, k] = dV sum_{j in S_I} beta_Ip(r_j) psi_k(r_j)``.
+
+    The sphere integral of Eq. vnl becomes a grid sum with weight dV.
+    """
+    flat = psi_r.reshape(psi_r.shape[0], -1)
+    out = []
+    for idx, beta in ham.atoms:
+        out.append(ham.grid.dV * (beta.T @ flat[:, idx].T))   # [nproj, norb]
+    return out
+
+
+def nonlocal_field(ham, P, norb):
+    """Row O5: ``sum_I sum_p beta_Ip(r) d_Ip P[I, p, k]`` (overlapping spheres add)."""
+    out = np.zeros((norb, ham.grid.N), np.complex128)
+    for I, (idx, beta) in enumerate(ham.atoms):
+        contrib = beta @ (ham.d[I][:, None] * P[I])           # [npts, norb]
+        np.add.at(out, (slice(None), idx), contrib.T)
+    return out.reshape((norb,) + ham.grid.n)
+
+
+def ham_apply(ham, c):
+    """Rows O2-O7: ``H c = chi (K c + analyze(V psi + v_nl psi))``."""
+    c = np.asarray(c, np.complex128)
+    single = c.ndim == 3
+    if single:
+        c = c[None]
+    g = ham.grid
+    psi_r = synthesize(g, c)
+    phi = ham.vloc[None] * psi_r
+    if ham.atoms:
+        phi = phi + nonlocal_field(ham, projections(ham, psi_r), c.shape[0])
+    hc = np.where(g.chi, g.K * c + analyze(g, phi), 0.0)
+    return hc[0] if single else hc
+
+
+def taylor4_coefficients(dt):
+    """``(-i dt)^k / k!`` for k = 0..4 (truncated Taylor series of exp(-i H dt))."""
+    return [(-1j * dt) ** k / math.factorial(k) for k in range(5)]
+
+
+def taylor4_step(ham, c, dt, nsteps=1):
+    """Row O8: ``nsteps`` applications of ``sum_{k=0}^{4} (-i dt)^k/k! H^k``."""
+    a = taylor4_coefficients(dt)
+    acc = np.where(ham.grid.chi, np.asarray(c, np.complex128), 0.0)
+    for _ in range(nsteps):
+        w = acc
+        new = acc.copy()
+        for k in range(1, 5):
+            w = ham_apply(ham, w)
+            new = new + a[k] * w
+        acc = new
+    return acc
+
+
+def density(ham, c, occ):
+    """Row O9: ``n(r) = sum_k f_k |psi_k(r)|^2`` (Eq. density with occupations)."""
+    psi_r = synthesize(ham.grid, np.asarray(c, np.complex128))
+    return np.einsum("k,kxyz->xyz", np.asarray(occ, np.float64), np.abs(psi_r) ** 2)
+
+
+def norms(ham, c):
+    """Row O10: ``||c_k||^2`` over the plane-wave sphere."""
+    cc = np.where(ham.grid.chi, c, 0.0)
+    return np.sum(np.abs(cc) ** 2, axis=(-3, -2, -1))
+
+
+def band_energy(ham, c, occ):
+    """Row O10: ``E = sum_k f_k Re <c_k|H c_k>`` (band energy of a static potential)."""
+    c = np.where(ham.grid.chi, np.asarray(c, np.complex128), 0.0)
+    hc = ham_apply(ham, c)
+    e = np.sum(np.conj(c) * hc, axis=(-3, -2, -1))
+    return float(np.sum(np.asarray(occ) * e.real)), e
+
+
+def orthonormalize(ham, c):
+    """Row O11: ``S = C^H C`` over the sphere, ``S = L L^H``, ``C <- C L^{-H}``.
+
+    ``c`` is ``[norb, n0, n1, n2]``; the result is zero outside the sphere.
+    """
+    g = ham.grid
+    C = np.where(g.chi, np.asarray(c, np.complex128), 0.0).reshape(c.shape[0], -1).T  # [N, norb]
+    S = C.conj().T @ C
+    Lc = np.linalg.cholesky(S)
+    Cn = scipy.linalg.solve_triangular(Lc.conj(), C.T, lower=True)   # conj(L)^-1 C^T = (C L^-H)^T
+    return Cn.reshape(c.shape)

@@ -1,0 +1,389 @@
+"""Pins for the FP64 oracle: each check compares the oracle with something other
+than itself -- brute-force sums, closed forms, exact rational arithmetic,
+textbook library routines or invariants fixed by the mathematics.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import ks_oracle as ko
+from paper_2106_03872_amd import synth
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _folded(n):
+    # integer frequency of box index j (written independently of the oracle)
+    return np.array([j if 2 * j < n else j - n for j in range(n)])
+
+
+def _phase_mats(n, L):
+    """E_a[j, m] = exp(i G_m r_j), built from physical G and r."""
+    mats = []
+    for a in range(3):
+        r = np.arange(n[a]) * L[a] / n[a]
+        G = 2 * np.pi * _folded(n[a]) / L[a]
+        mats.append(np.exp(1j * np.outer(r, G)))
+    return mats
+
+
+def _dense_fourier(n, L):
+    """U[r, G] = exp(i G.r) / sqrt(N) over the flattened box."""
+    E0, E1, E2 = _phase_mats(n, L)
+    U = np.einsum("ad,be,cf->abcdef", E0, E1, E2).reshape(np.prod(n), np.prod(n))
+    return U / math.sqrt(np.prod(n))
+
+
+# ---------------------------------------------------------------- FFT (O2/O6)
+
+@pytest.mark.parametrize("n", [(4, 5, 6), (8, 9, 10), (12, 15, 4), (5, 5, 5)])
+@pytest.mark.parametrize("ecut", [0.0, 6.0])
+def test_synthesis_analysis_bruteforce(n, ecut):
+    rng = _rng(1)
+    L = tuple(rng.uniform(3.0, 6.0, 3))
+    g = ko.Grid(n, L, ecut)
+    c = _rand_c(rng, (2,) + n)
+    E0, E1, E2 = _phase_mats(n, L)
+    chi = np.array([[[0.5 * ((2 * np.pi * a / L[0]) ** 2 + (2 * np.pi * b / L[1]) ** 2
+                             + (2 * np.pi * cc / L[2]) ** 2) < ecut if ecut > 0 else True
+                      for cc in _folded(n[2])] for b in _folded(n[1])] for a in _folded(n[0])])
+    omega = np.prod(L)
+    bf = np.einsum("ad,be,cf,kdef->kabc", E0, E1, E2, np.where(chi, c, 0)) / math.sqrt(omega)
+    np.testing.assert_allclose(ko.synthesize(g, c), bf, rtol=0, atol=1e-12 * np.abs(bf).max())
+    f = _rand_c(rng, (2,) + n)
+    bfa = np.einsum("ad,be,cf,kabc->kdef", E0.conj(), E1.conj(), E2.conj(), f) * (
+        math.sqrt(omega) / np.prod(n))
+    np.testing.assert_allclose(ko.analyze(g, f), bfa, rtol=0, atol=1e-12 * np.abs(bfa).max())
+    assert g.npw == int(chi.sum())
+
+
+def test_parseval_roundtrip_delta():
+    rng = _rng(2)
+    g = ko.Grid((16, 12, 10), (7.0, 6.0, 5.0), 8.0)
+    c = _rand_c(rng, (3,) + g.n)
+    psi = ko.synthesize(g, c)
+    lhs = g.dV * np.sum(np.abs(psi) ** 2, axis=(1, 2, 3))
+    rhs = np.sum(np.abs(np.where(g.chi, c, 0)) ** 2, axis=(1, 2, 3))
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-13)
+    back = ko.analyze(g, psi)
+    np.testing.assert_allclose(back, np.where(g.chi, c, 0), atol=1e-13 * np.abs(c).max())
+    e0 = np.zeros(g.n, complex)
+    e0[0, 0, 0] = 1.0
+    np.testing.assert_allclose(ko.synthesize(g, e0), np.full(g.n, 1 / math.sqrt(g.omega)), rtol=1e-14)
+
+
+# --------------------------------------------------------- kinetic + mask (O1, O7)
+
+def test_plane_waves_are_eigenstates():
+    n, L = (12, 10, 8), (6.0, 5.0, 4.0)
+    g = ko.Grid(n, L, 9.0)
+    ham = ko.Hamiltonian(g, np.zeros(n))
+    inside = np.argwhere(g.chi)
+    outside = np.argwhere(~g.chi)
+    assert len(inside) > 50 and len(outside) > 50
+    rng = _rng(3)
+    for (a, b, c) in inside[rng.choice(len(inside), 25, replace=False)]:
+        e = np.zeros(n, complex)
+        e[a, b, c] = 1.0
+        m = (_folded(n[0])[a], _folded(n[1])[b], _folded(n[2])[c])
+        lam = 0.5 * sum((2 * np.pi * m[i] / L[i]) ** 2 for i in range(3))
+        he = ko.ham_apply(ham, e)
+        np.testing.assert_allclose(he, lam * e, atol=1e-12 * max(lam, 1))
+    for (a, b, c) in outside[:10]:
+        e = np.zeros(n, complex)
+        e[a, b, c] = 1.0
+        assert np.abs(ko.ham_apply(ham, e)).max() < 1e-14
+
+
+def test_constant_potential_shift():
+    rng = _rng(4)
+    g = ko.Grid((10, 12, 9), (5.0, 6.0, 4.5), 7.0)
+    v0 = -1.37
+    ham0 = ko.Hamiltonian(g, np.zeros(g.n))
+    ham = ko.Hamiltonian(g, np.full(g.n, v0))
+    c = _rand_c(rng, (2,) + g.n)
+    np.testing.assert_allclose(ko.ham_apply(ham, c),
+                               ko.ham_apply(ham0, c) + v0 * np.where(g.chi, c, 0), atol=1e-12)
+
+
+@pytest.mark.parametrize("ecut", [0.0, 5.0])
+def test_cosine_potential_with_phase(ecut):
+    """V = 2A cos(K.r + phi)  =>  (V psi)_G = A e^{i phi} c_{G-K} + A e^{-i phi} c_{G+K}."""
+    n, L = (10, 12, 8), (5.0, 6.0, 4.0)
+    g = ko.Grid(n, L, ecut)
+    k = (1, 2, -1)
+    A, phi = 0.7, 0.9
+    X = [np.arange(n[a]) * L[a] / n[a] for a in range(3)]
+    kr = sum((2 * np.pi * k[a] / L[a]) * X[a].reshape([-1 if i == a else 1 for i in range(3)])
+             for a in range(3))
+    V = 2 * A * np.cos(kr + phi)
+    ham = ko.Hamiltonian(g, V)
+    c = np.where(g.chi, _rand_c(_rng(5), n), 0)
+    Kc = 0.5 * sum((2 * np.pi * _folded(n[a]) / L[a]).reshape([-1 if i == a else 1 for i in range(3)]) ** 2
+                   for a in range(3)) * c
+    up = np.roll(c, shift=k, axis=(0, 1, 2))                     # c_{G-K}
+    dn = np.roll(c, shift=tuple(-x for x in k), axis=(0, 1, 2))  # c_{G+K}
+    expect = np.where(g.chi, Kc + A * np.exp(1j * phi) * up + A * np.exp(-1j * phi) * dn, 0)
+    np.testing.assert_allclose(ko.ham_apply(ham, c), expect, atol=1e-12)
+
+
+# ------------------------------------------------------------ non-local (O4/O5)
+
+def test_nonlocal_rank_one_real_space():
+    """Single projector: <beta|v_nl|beta> = d (dV sum beta^2)^2."""
+    rng = _rng(6)
+    g = ko.Grid((8, 8, 8), (4.0, 4.0, 4.0), 0.0)
+    idx = np.sort(rng.choice(g.N, 40, replace=False))
+    beta = rng.standard_normal((40, 1))
+    d = np.array([[1.7]])
+    ham = ko.Hamiltonian(g, np.zeros(g.n), [(idx, beta)], d)
+    bfield = np.zeros((1, g.N))
+    bfield[0, idx] = beta[:, 0]
+    bfield = bfield.reshape((1,) + g.n).astype(complex)
+    P = ko.projections(ham, bfield)
+    s = g.dV * np.sum(beta ** 2)
+    np.testing.assert_allclose(P[0][0, 0], s, rtol=1e-14)
+    phi = ko.nonlocal_field(ham, P, 1)
+    np.testing.assert_allclose(g.dV * np.vdot(bfield, phi), d[0, 0] * s * s, rtol=1e-13)
+
+
+def test_nonlocal_fourier_rank_one_and_psd():
+    """Sphere-projected v_nl in G space equals chi conj(b) d (b . c), with
+    b(G) = Omega^{-1/2} dV sum_j beta(r_j) e^{iG.r_j} computed by explicit phases."""
+    rng = _rng(7)
+    n, L = (8, 9, 10), (4.0, 4.5, 5.0)
+    g = ko.Grid(n, L, 12.0)
+    idx = np.sort(rng.choice(g.N, 60, replace=False))
+    beta = rng.standard_normal((60, 1))
+    dd = 0.8
+    ham = ko.Hamiltonian(g, np.zeros(n), [(idx, beta)], np.array([[dd]]))
+    j0, j1, j2 = np.unravel_index(idx, n)
+    r = np.stack([j0 * L[0] / n[0], j1 * L[1] / n[1], j2 * L[2] / n[2]], 1)
+    G = np.stack(np.meshgrid(*[2 * np.pi * _folded(n[a]) / L[a] for a in range(3)], indexing="ij"), -1)
+    b = np.einsum("j,xyzj->xyz", beta[:, 0], np.exp(1j * np.einsum("xyza,ja->xyzj", G, r)))
+    b *= g.dV / math.sqrt(g.omega)
+    for _ in range(3):
+        c = np.where(g.chi, _rand_c(rng, n), 0)
+        hc = ko.ham_apply(ham, c) - np.where(g.chi, g.K * c, 0)
+        expect = np.where(g.chi, np.conj(b) * dd * np.sum(b * c), 0)
+        np.testing.assert_allclose(hc, expect, atol=1e-12 * np.abs(expect).max())
+        assert np.vdot(c, hc).real >= -1e-12 and abs(np.vdot(c, hc).imag) < 1e-12
+
+
+def test_nonlocal_bruteforce_loops():
+    """Explicit loops over grid points and spheres, projectors evaluated from
+    their analytic form at minimum-image displacement (tiny grid)."""
+    spec = synth.Spec(name="bf", n=(7, 6, 8), L=(4.2, 3.6, 4.8), ecut=0.0, norb=2, natoms=2,
+                      seed=11)
+    sysm = synth.system(spec)
+    g = ko.Grid(spec.n, spec.L, 0.0)
+    atoms = [sysm.proj.atom(i) for i in range(spec.natoms)]
+    ham = ko.Hamiltonian(g, np.zeros(spec.n), atoms, sysm.proj.d)
+    psi = _rand_c(_rng(8), (2,) + spec.n)
+    P = ko.projections(ham, psi)
+    phi = ko.nonlocal_field(ham, P, 2)
+
+    def mi(x, L):
+        return (x + L / 2) % L - L / 2
+
+    pts = [(a, b, c) for a in range(spec.n[0]) for b in range(spec.n[1]) for c in range(spec.n[2])]
+    expect = np.zeros_like(psi)
+    for I, R in enumerate(sysm.pos):
+        vals = {}
+        for p in pts:
+            dvec = [mi(p[a] * spec.L[a] / spec.n[a] - R[a], spec.L[a]) for a in range(3)]
+            r2 = sum(x * x for x in dvec)
+            if r2 < synth.R_CUT ** 2:
+                gg = math.exp(-r2 / (2 * synth.SIGMA_BETA ** 2))
+                vals[p] = np.array([gg, dvec[0] * gg, dvec[1] * gg, dvec[2] * gg])
+        norm = np.sqrt(g.dV * sum(v * v for v in vals.values()))
+        for p in vals:
+            vals[p] = vals[p] / norm
+        for k in range(2):
+            proj = np.zeros(4, complex)
+            for p, bv in vals.items():
+                proj += g.dV * bv * psi[(k,) + p]
+            for p, bv in vals.items():
+                expect[(k,) + p] += np.sum(bv * sysm.proj.d[I] * proj)
+    np.testing.assert_allclose(phi, expect, atol=1e-12 * np.abs(expect).max())
+
+
+# ------------------------------------------------------------------- whole H
+
+def _tiny_system(n, L, ecut, seed, natoms=2, npts=12, nproj=3):
+    rng = _rng(seed)
+    g = ko.Grid(n, L, ecut)
+    V = rng.standard_normal(n)
+    atoms = []
+    for _ in range(natoms):
+        idx = np.sort(rng.choice(g.N, npts, replace=False))
+        atoms.append((idx, rng.standard_normal((npts, nproj))))
+    d = rng.uniform(0.5, 2.0, (natoms, nproj))
+    return g, ko.Hamiltonian(g, V, atoms, d)
+
+
+def _dense_H(g, ham):
+    U = _dense_fourier(g.n, g.L)
+    B = np.zeros((0, g.N))
+    D = []
+    for I, (idx, beta) in enumerate(ham.atoms):
+        Bi = np.zeros((beta.shape[1], g.N))
+        Bi[:, idx] = beta.T
+        B = np.vstack([B, Bi])
+        D.extend(ham.d[I])
+    M = np.diag(ham.vloc.ravel()) + g.dV * B.T @ np.diag(D) @ B
+    chi = g.chi.ravel().astype(float)
+    H = np.diag(g.K.ravel()) + U.conj().T @ M @ U
+    return chi[:, None] * H * chi[None, :]
+
+
+@pytest.mark.parametrize("n,ecut", [((4, 5, 6), 0.0), ((6, 5, 4), 9.0), ((5, 5, 5), 0.0)])
+def test_dense_hamiltonian(n, ecut):
+    g, ham = _tiny_system(n, (3.0, 3.5, 4.0), ecut, seed=9)
+    H = _dense_H(g, ham)
+    assert np.abs(H - H.conj().T).max() <= 1e-13 * np.abs(H).max()
+    rng = _rng(10)
+    c = _rand_c(rng, (3,) + n)
+    hc = ko.ham_apply(ham, c).reshape(3, -1)
+    cm = np.where(g.chi, c, 0).reshape(3, -1)
+    np.testing.assert_allclose(hc, cm @ H.T, atol=1e-12 * np.abs(H).max())
+    # Hermiticity through the oracle itself: <phi|H psi> = <H phi|psi>
+    a, b = c[0], c[1]
+    lhs = np.vdot(np.where(g.chi, a, 0), ko.ham_apply(ham, b))
+    rhs = np.vdot(ko.ham_apply(ham, a), np.where(g.chi, b, 0))
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+    ev = np.linalg.eigvals(H)
+    assert np.abs(ev.imag).max() < 1e-10 * np.abs(ev).max()
+
+
+# ----------------------------------------------------------------- Taylor-4 (O8)
+
+def _t4(z):
+    return sum(z ** k / math.factorial(k) for k in range(5))
+
+
+def test_taylor4_free_electrons_closed_form():
+    g = ko.Grid((10, 8, 12), (5.0, 4.0, 6.0), 6.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    c = _rand_c(_rng(11), (2,) + g.n)
+    dt, ns = 0.07, 3
+    out = ko.taylor4_step(ham, c, dt, ns)
+    expect = np.where(g.chi, _t4(-1j * g.K * dt) ** ns * c, 0)
+    np.testing.assert_allclose(out, expect, atol=1e-13 * np.abs(c).max())
+
+
+def test_taylor4_dense_eigen_closed_form_and_energy():
+    g, ham = _tiny_system((4, 5, 6), (3.0, 3.5, 4.0), 9.0, seed=12)
+    H = _dense_H(g, ham)
+    lam, Q = np.linalg.eigh(H)
+    c = np.where(g.chi, _rand_c(_rng(13), (2,) + g.n), 0)
+    dt, ns = 0.02, 4
+    out = ko.taylor4_step(ham, c, dt, ns).reshape(2, -1)
+    a = c.reshape(2, -1) @ Q.conj()                                # Q^H c per orbital
+    expect = (a * _t4(-1j * lam * dt) ** ns) @ Q.T
+    np.testing.assert_allclose(out, expect, atol=1e-12 * np.abs(c).max())
+    # norm:  sum |a|^2 (1 - t^6/72 + t^8/576)^n
+    th = lam * dt
+    amp = (1 - th ** 6 / 72 + th ** 8 / 576) ** ns
+    np.testing.assert_allclose(np.sum(np.abs(out) ** 2, 1), np.sum(np.abs(a) ** 2 * amp, 1), rtol=1e-12)
+    # band energy after n steps: sum_j |a_j|^2 lam_j |T4_j|^{2n}
+    occ = np.array([2.0, 1.0])
+    E, e = ko.band_energy(ham, out.reshape((2,) + g.n), occ)
+    Ee = np.sum(occ[:, None] * np.abs(a) ** 2 * lam[None] * amp[None])
+    assert abs(E - Ee) < 1e-11 * abs(Ee)
+    assert np.abs(e.imag).max() < 1e-11 * np.abs(e.real).max()
+
+
+def test_taylor4_amplification_exact_rational():
+    """|T4(-i th)|^2 = 1 - th^6/72 + th^8/576, checked with exact fractions and
+    against the oracle on a single plane wave."""
+    for th in [Fraction(1, 3), Fraction(1, 2), Fraction(1), Fraction(3, 2), Fraction(2)]:
+        re = 1 - th ** 2 / 2 + th ** 4 / 24
+        im = -(th - th ** 3 / 6)
+        assert re * re + im * im == 1 - th ** 6 / 72 + th ** 8 / 576
+    g = ko.Grid((8, 8, 8), (5.0, 5.0, 5.0), 0.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    e = np.zeros(g.n, complex)
+    e[1, 2, 0] = 1.0
+    lam = g.K[1, 2, 0]
+    for th in [0.5, 1.0, 2.0, 2.5]:
+        out = ko.taylor4_step(ham, e, th / lam, 1)
+        assert abs(np.sum(np.abs(out) ** 2) - (1 - th ** 6 / 72 + th ** 8 / 576)) < 1e-13
+
+
+def test_taylor4_fourth_order_convergence():
+    g, ham = _tiny_system((4, 4, 5), (3.0, 3.0, 3.5), 0.0, seed=14)
+    H = _dense_H(g, ham)
+    c = np.where(g.chi, _rand_c(_rng(15), g.n), 0)
+    errs = []
+    for dt in [0.04, 0.02, 0.01]:
+        ex = scipy.linalg.expm(-1j * H * dt) @ c.ravel()
+        errs.append(np.linalg.norm(ko.taylor4_step(ham, c, dt, 1).ravel() - ex))
+    # local error O(dt^5): halving dt divides the error by ~32
+    assert errs[0] / errs[1] > 25 and errs[1] / errs[2] > 25
+
+
+# --------------------------------------------------------------- density (O9)
+
+def test_density_invariants():
+    rng = _rng(16)
+    g = ko.Grid((12, 10, 9), (6.0, 5.0, 4.5), 7.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    c = _rand_c(rng, (4,) + g.n)
+    occ = np.array([2.0, 2.0, 1.0, 0.5])
+    n = ko.density(ham, c, occ)
+    assert n.min() >= 0
+    np.testing.assert_allclose(g.dV * n.sum(), np.sum(occ * ko.norms(ham, c)), rtol=1e-13)
+    perm = [2, 0, 3, 1]
+    np.testing.assert_allclose(ko.density(ham, c[perm], occ[perm]), n, rtol=1e-13)
+    # unitary mixing of the two equally occupied orbitals
+    th = 0.61
+    Um = np.array([[np.cos(th), 1j * np.sin(th)], [1j * np.sin(th), np.cos(th)]])
+    cm = c.copy()
+    cm[:2] = np.einsum("ij,jxyz->ixyz", Um, c[:2])
+    np.testing.assert_allclose(ko.density(ham, cm, occ), n, rtol=1e-12, atol=1e-14 * n.max())
+    # single plane wave: uniform f/Omega
+    e = np.zeros((1,) + g.n, complex)
+    e[0, 2, 1, 0] = 1.0
+    np.testing.assert_allclose(ko.density(ham, e, [2.0]), np.full(g.n, 2.0 / g.omega), rtol=1e-13)
+
+
+# ------------------------------------------------------- orthonormalisation (O11)
+
+def test_orthonormalize_matches_qr():
+    rng = _rng(17)
+    g = ko.Grid((10, 9, 8), (5.0, 4.5, 4.0), 8.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    c = _rand_c(rng, (6,) + g.n)
+    out = ko.orthonormalize(ham, c)
+    M = out.reshape(6, -1)
+    np.testing.assert_allclose(M.conj() @ M.T, np.eye(6), atol=1e-13)
+    assert np.abs(out[:, ~g.chi]).max() == 0
+    A = np.where(g.chi, c, 0).reshape(6, -1).T
+    Q, R = np.linalg.qr(A)
+    Q = Q * (np.sign(np.diag(R).real))[None, :]
+    np.testing.assert_allclose(M.T, Q, atol=1e-12)
+
+
+# --------------------------------------------------------------- generator
+
+def test_generator_deterministic_and_normalised():
+    spec = synth.CONFIGS["t24"]
+    a, b = synth.system(spec), synth.system(spec)
+    assert np.array_equal(a.vloc, b.vloc) and np.array_equal(a.proj.idx, b.proj.idx)
+    assert np.array_equal(synth.orbitals_box(spec), synth.orbitals_box(spec))
+    dV = np.prod(spec.L) / spec.npoints
+    for i in range(spec.natoms):
+        idx, beta = a.proj.atom(i)
+        np.testing.assert_allclose(dV * np.sum(beta ** 2, 0), 1.0, rtol=1e-13)
+        assert np.all(np.diff(idx) > 0)
+    assert a.vloc.min() < -1.5 and a.vloc.max() < 0
