@@ -1,0 +1,164 @@
+/*
+ * ks.h -- C ABI of libks: the data-parallel hot path of plane-wave real-time
+ * TDDFT (Andrade et al., arXiv:2106.03872) on one AMD Instinct MI355X.
+ *
+ * Physics (atomic units throughout, as in the statement of the Hamiltonian,
+ * Eq. hamiltonian):
+ *   H = -1/2 nabla^2 + V_loc(r) + sum_I sum_p |beta_Ip> d_Ip <beta_Ip|
+ * with a static multiplicative local potential (Section "Pseudopotentials":
+ * local pseudopotential, Hartree and XC combine into one field) and
+ * Kleinman-Bylander projectors localised in spheres (Eq. vnl).  H acts on the
+ * plane-wave sphere chi(G) = [|G|^2/2 < E_cut] (H = chi H chi), kinetic term
+ * in Fourier space, potential terms in real space, two FFTs per application
+ * (Section "Implementation of the KS Hamiltonian").
+ *
+ * Conventions shared by every call:
+ *  - Grid n = (n0, n1, n2), orthorhombic cell L = (L0, L1, L2) bohr, N = n0 n1 n2,
+ *    Omega = L0 L1 L2, dV = Omega / N.  n1 must equal n2; every n_a must be one
+ *    of 8 12 16 20 24 32 40 48 60 64 72 80 96 120 128.
+ *  - Orbitals are plane-wave coefficients on the full FFT box, complex128
+ *    interleaved (re, im), array [norb][n0][n1][n2] in C order (n2 fastest).
+ *    Box index j_a holds m_a = j_a for j_a < ceil(n_a/2), else j_a - n_a;
+ *    G_a = 2 pi m_a / L_a.  psi(r) = Omega^{-1/2} sum_G chi c_G exp(+i G.r),
+ *    so int |psi|^2 = sum |c|^2.  Inputs outside chi are ignored; outputs are
+ *    zero there.
+ *  - Real-space fields (V_loc, density) are float64 [n0][n1][n2] with
+ *    r_j = (j0 L0/n0, j1 L1/n1, j2 L2/n2).
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the system copies what it keeps.
+ *  - stream is a hipStream_t (NULL = default stream).  Calls taking a stream
+ *    are asynchronous with respect to the host and ordered on that stream.
+ *    One ks_system must not be used from two threads or two streams at once
+ *    (it owns one workspace); distinct systems are independent.
+ *  - Errors: every call returns a ks_status and never aborts; ks_last_error()
+ *    gives the message of the last failure on that system.
+ */
+#ifndef KS_H
+#define KS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KS_OK = 0,
+  KS_EINVAL = 1,        /* bad argument: null pointer, size, aliasing, cutoff */
+  KS_ENOMEM = 2,        /* device allocation failed */
+  KS_EDEVICE = 3,       /* a HIP runtime error; see ks_last_error */
+  KS_EUNSUPPORTED = 4   /* grid size or sphere without a kernel */
+} ks_status;
+
+typedef enum {
+  KS_FP64 = 0,          /* all arithmetic in float64 / complex128 */
+  KS_MIXED = 1          /* reserved: FP32 transforms, FP64 accumulators */
+} ks_precision;
+
+typedef struct ks_system ks_system;
+
+/*
+ * Create a system for grid n[3] (host), cell L[3] (host, bohr) and cutoff
+ * ecut (Ha; ecut <= 0 means the whole FFT box, no sphere).  Builds the
+ * plane-wave sphere tables (kinetic energies |G|^2/2 and the mask, from the
+ * plane-wave basis of Section "DFT and TDDFT implementation") and allocates
+ * the workspace, sized so that no later call allocates device memory (except
+ * the first ks_orthonormalize).  max_norb bounds norb in every later call.
+ * Errors: KS_EINVAL (null, n < 1, L <= 0, max_norb < 1, n1 != n2, sphere
+ * reaching the Nyquist plane), KS_EUNSUPPORTED (size without a kernel, sphere
+ * too large for LDS), KS_ENOMEM.  On error *out is NULL.
+ */
+ks_status ks_system_create(const int n[3], const double L[3], double ecut, int precision,
+                           int max_norb, ks_system** out);
+
+/* Free the system and its device memory after synchronising the device. */
+void ks_system_destroy(ks_system* sys);
+
+/* Message of the last failing call on sys (or of the last failing create
+ * when sys is NULL).  Valid until the next call on sys. */
+const char* ks_last_error(const ks_system* sys);
+
+/*
+ * Set the local potential V_loc(r) (Eq. hamiltonian: ionic local part plus
+ * any Hartree/XC/perturbation terms, combined as one multiplicative field).
+ * v: device float64 [n0][n1][n2], copied on `stream`.  Default: V = 0.
+ */
+ks_status ks_system_set_vloc(ks_system* sys, const double* v, void* stream);
+
+/*
+ * Set the Kleinman-Bylander non-local term of Eq. vnl:
+ *   v_nl psi(r) = sum_I sum_p beta_Ip(r) d_Ip dV sum_{j in S_I} beta_Ip(r_j) psi(r_j).
+ * natoms >= 0, nproj >= 1 projectors per atom.  All arrays are host memory:
+ *   npts [natoms]            number of grid points of sphere S_I
+ *   idx  [sum npts]          flat C-order grid indices of the points of S_I,
+ *                            atoms concatenated (duplicates count twice)
+ *   beta [sum npts][nproj]   projector values at those points (row-major)
+ *   d    [natoms][nproj]     KB coefficients
+ * The library copies and regroups them; it synchronises `stream` (pass the
+ * stream later calls use).  natoms = 0 removes the non-local term.
+ * Errors: KS_EINVAL on null arrays or an index outside [0, N).
+ */
+ks_status ks_system_set_projectors(ks_system* sys, int natoms, int nproj, const int* npts,
+                                   const int* idx, const double* beta, const double* d, void* stream);
+
+/*
+ * hpsi = H psi for norb orbitals (Section "Implementation of the KS
+ * Hamiltonian").  psi, hpsi: device complex128 [norb][n0][n1][n2]; they must
+ * not overlap.  Errors: KS_EINVAL (null, norb < 0 or > max_norb, psi == hpsi).
+ */
+ks_status ks_ham_apply(ks_system* sys, int norb, const void* psi, void* hpsi, void* stream);
+
+/*
+ * nsteps steps of the 4th-order truncated Taylor propagator (Section
+ * "Real-time propagation"):
+ *   psi <- sum_{k=0}^{4} (-i dt)^k / k!  H^k psi
+ * applied in place to psi (device complex128 [norb][n0][n1][n2]).
+ * rho: NULL, or device float64 [nsteps][n0][n1][n2] receiving the density
+ * sum_i occ_i |psi_i(r)|^2 (Eq. density) after each step; occ: device
+ * float64 [norb], required when rho is given.
+ * Errors: KS_EINVAL (null psi, norb out of range, nsteps < 0, rho without occ).
+ */
+ks_status ks_propagate_step(ks_system* sys, int norb, void* psi, double dt, int nsteps,
+                            const double* occ, double* rho, void* stream);
+
+/*
+ * rho(r) = sum_i occ_i |psi_i(r)|^2 (Eq. density with occupations).
+ * psi: device complex128 [norb][n0][n1][n2]; occ: device float64 [norb];
+ * rho: device float64 [n0][n1][n2] (overwritten).  Summation order over
+ * orbitals is fixed, so the result is deterministic.
+ */
+ks_status ks_density(ks_system* sys, int norb, const void* psi, const double* occ, double* rho,
+                     void* stream);
+
+/*
+ * Orbital norms and band energy (energy expression of Section "DFT and TDDFT
+ * implementation" reduced to sum_k f_k <psi_k|H|psi_k> for a static potential):
+ *   norms[i] = sum_G |c_iG|^2 over the sphere           (device float64 [norb])
+ *   energy[0] = sum_i occ_i Re <c_i|H c_i>               (device float64 [1])
+ * Either output may be NULL; occ (device [norb]) is required for energy.
+ */
+ks_status ks_reduce(ks_system* sys, int norb, const void* psi, const double* occ, double* norms,
+                    double* energy, void* stream);
+
+/*
+ * Orthonormalise the orbitals in place (orthogonalisation step of Section
+ * "Ground-state solution"): S = C^H C over the sphere, S = L L^H (Cholesky,
+ * positive diagonal), C <- C L^{-H}.  psi: device complex128
+ * [norb][n0][n1][n2].  KS_EINVAL if S is not positive definite.  The first
+ * call allocates a workspace for max_norb orbitals.
+ */
+ks_status ks_orthonormalize(ks_system* sys, int norb, void* psi, void* stream);
+
+/* Number of plane waves in the sphere (packed coefficients per orbital). */
+int ks_system_npw(const ks_system* sys);
+
+/* Orbitals processed per pass (chunk size of the internal pipeline). */
+int ks_system_chunk(const ks_system* sys);
+
+/* Set the chunk size (1 <= chunk <= max_norb); reallocates the workspace, so
+ * call it at set-up time only.  KS_EINVAL when out of range. */
+ks_status ks_system_set_chunk(ks_system* sys, int chunk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

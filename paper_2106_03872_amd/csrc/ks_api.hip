@@ -1,0 +1,533 @@
+// Host runtime of libks: system set-up (plane-wave sphere tables, twiddles,
+// projector runs), workspace ownership and the C ABI entry points declared in
+// include/ks.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ks_internal.h"
+
+using namespace ks;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+ks_status fail(ks_system* s, ks_status st, const std::string& msg) {
+  if (s) s->err = msg; else g_create_err = msg;
+  return st;
+}
+
+#define KS_HIP(s, call)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail((s), e_ == hipErrorOutOfMemory ? KS_ENOMEM : KS_EDEVICE,                     \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
+
+ks_status dalloc(ks_system* s, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(s, KS_ENOMEM, "hipMalloc(" + std::to_string(bytes) + " B): " + hipGetErrorString(e));
+  }
+  return KS_OK;
+}
+
+void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+template <typename T> ks_status upload(ks_system* s, T** dst, const std::vector<T>& v) {
+  dfree(reinterpret_cast<void*&>(*dst));
+  ks_status st = dalloc(s, reinterpret_cast<void**>(dst), v.size() * sizeof(T));
+  if (st != KS_OK) return st;
+  if (!v.empty()) KS_HIP(s, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return KS_OK;
+}
+
+ks_status launch_ok(ks_system* s, bool ok, const char* what) {
+  if (!ok) return fail(s, KS_EUNSUPPORTED, std::string("no kernel for this size: ") + what);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(s, KS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return KS_OK;
+}
+
+// exp(-2 pi i j / n), computed in long double and rounded
+std::vector<double2> twiddles(int n) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<double2> t(n);
+  for (int j = 0; j < n; ++j) {
+    const long double a = 2.0L * pi * (long double)j / (long double)n;
+    t[j] = double2{(double)cosl(a), (double)(-sinl(a))};
+  }
+  return t;
+}
+
+// |G|^2/2 for integer frequencies (same operation order as the definition
+// K = ((g0^2 + g1^2) + g2^2) / 2 with g_a = (2 pi m_a) / L_a)
+double kin(const double L[3], int m0, int m1, int m2) {
+  const double g0 = 2.0 * M_PI * m0 / L[0];
+  const double g1 = 2.0 * M_PI * m1 / L[1];
+  const double g2 = 2.0 * M_PI * m2 / L[2];
+  return 0.5 * (g0 * g0 + g1 * g1 + g2 * g2);
+}
+
+void free_workspace(ks_system* s) {
+  for (auto& p : s->pk) dfree(p);
+  dfree(s->T);
+  dfree(s->U);
+  dfree(s->partial);
+  dfree(reinterpret_cast<void*&>(s->DP));
+  s->partial_cap = s->dp_cap = 0;
+}
+
+ks_status alloc_proj_workspace(ks_system* s) {
+  dfree(s->partial);
+  dfree(reinterpret_cast<void*&>(s->DP));
+  const size_t pbytes = (size_t)s->cb * std::max(1, s->nchords) * std::max(1, s->nproj) * sizeof(double2);
+  const size_t dbytes = (size_t)s->cb * std::max(1, s->natoms) * std::max(1, s->nproj) * sizeof(double2);
+  ks_status st = dalloc(s, &s->partial, pbytes);
+  if (st != KS_OK) return st;
+  st = dalloc(s, reinterpret_cast<void**>(&s->DP), dbytes);
+  if (st != KS_OK) return st;
+  s->partial_cap = pbytes;
+  s->dp_cap = dbytes;
+  return KS_OK;
+}
+
+ks_status alloc_workspace(ks_system* s) {
+  free_workspace(s);
+  const size_t pk = (size_t)s->cb * s->npw_stride * sizeof(double2);
+  for (auto& p : s->pk) {
+    ks_status st = dalloc(s, &p, pk);
+    if (st != KS_OK) return st;
+  }
+  const size_t tb = (size_t)s->cb * s->nplanes * s->npl * sizeof(double2);
+  ks_status st = dalloc(s, &s->T, tb);
+  if (st != KS_OK) return st;
+  st = dalloc(s, &s->U, tb);
+  if (st != KS_OK) return st;
+  return alloc_proj_workspace(s);
+}
+
+int default_chunk(const ks_system* s) {
+  const double per = (double)s->nplanes * s->npl * sizeof(double2);
+  int cb = (int)std::max(1.0, std::floor(96.0 * 1024 * 1024 / per));
+  return std::max(1, std::min(cb, s->max_norb));
+}
+
+ks_status check_common(ks_system* s, int norb) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (norb < 0 || norb > s->max_norb)
+    return fail(s, KS_EINVAL, "norb " + std::to_string(norb) + " outside [0, " + std::to_string(s->max_norb) + "]");
+  return KS_OK;
+}
+
+// H applied to nb packed orbitals win; result per mode (see plane_fwd_kernel)
+ks_status hpsi_packed(ks_system* s, int nb, const void* win, void* wout, void* acc, HMode mode, Taylor tay,
+                      hipStream_t st) {
+  ks_status r = launch_ok(s, launch_plane_inv(s, nb, win, s->T, st), "plane_inv");
+  if (r != KS_OK) return r;
+  if (s->natoms > 0) {
+    r = launch_ok(s, launch_xproj(s, nb, s->T, s->partial, st), "xproj");
+    if (r != KS_OK) return r;
+    r = launch_ok(s, launch_proj_reduce(s, nb, s->partial, s->DP, st), "proj_reduce");
+    if (r != KS_OK) return r;
+  }
+  r = launch_ok(s, launch_xapply(s, nb, s->T, s->DP, s->U, st), "xapply");
+  if (r != KS_OK) return r;
+  return launch_ok(s, launch_plane_fwd(s, nb, s->U, win, wout, acc, mode, tay, st), "plane_fwd");
+}
+
+ks_status density_packed(ks_system* s, int nb, const void* pk, const double* occ, double* rho, int accumulate,
+                         hipStream_t st) {
+  ks_status r = launch_ok(s, launch_plane_inv(s, nb, pk, s->T, st), "plane_inv");
+  if (r != KS_OK) return r;
+  return launch_ok(s, launch_xdens(s, nb, s->T, occ, rho, accumulate, st), "xdens");
+}
+
+}  // namespace
+
+extern "C" {
+
+ks_status ks_system_create(const int n[3], const double L[3], double ecut, int precision, int max_norb,
+                           ks_system** out) {
+  if (!out) return fail(nullptr, KS_EINVAL, "out is null");
+  *out = nullptr;
+  if (!n || !L) return fail(nullptr, KS_EINVAL, "n or L is null");
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return fail(nullptr, KS_EINVAL, "grid size must be positive");
+    if (!(L[a] > 0.0) || !std::isfinite(L[a])) return fail(nullptr, KS_EINVAL, "cell lengths must be positive");
+    if (!supported_size(n[a]))
+      return fail(nullptr, KS_EUNSUPPORTED, "grid size " + std::to_string(n[a]) + " has no FFT kernel");
+  }
+  if (n[1] != n[2]) return fail(nullptr, KS_EINVAL, "n1 must equal n2");
+  if (max_norb < 1) return fail(nullptr, KS_EINVAL, "max_norb must be >= 1");
+  if (precision != KS_FP64) return fail(nullptr, KS_EUNSUPPORTED, "only KS_FP64 is available");
+  if (!std::isfinite(ecut)) return fail(nullptr, KS_EINVAL, "ecut must be finite");
+
+  ks_system* s = new ks_system();
+  for (int a = 0; a < 3; ++a) {
+    s->n[a] = n[a];
+    s->L[a] = L[a];
+  }
+  s->ecut = ecut;
+  s->prec = precision;
+  s->max_norb = max_norb;
+  s->N = (long long)n[0] * n[1] * n[2];
+  s->npl = n[1] * n[2];
+  s->omega = L[0] * L[1] * L[2];
+  s->dV = s->omega / (double)s->N;
+
+  // plane-wave sphere in packed order
+  std::vector<int> plane_col0, plane_m1lo, col_off, col_m2lo;
+  int prev_m0 = 0;
+  bool any_plane = false;
+  int npw = 0;
+  auto mlo = [&](int a) { return -(n[a] / 2); };
+  auto mhi = [&](int a) { return (n[a] - 1) / 2; };
+  for (int m0 = mlo(0); m0 <= mhi(0); ++m0) {
+    int first_col = 0, prev_m1 = 0, ncol = 0;
+    bool have_col = false;
+    std::vector<int> coff, cm2;
+    for (int m1 = mlo(1); m1 <= mhi(1); ++m1) {
+      int lo = 1 << 30, hi = -(1 << 30), cnt = 0;
+      for (int m2 = mlo(2); m2 <= mhi(2); ++m2) {
+        if (ecut <= 0.0 || kin(L, m0, m1, m2) < ecut) {
+          lo = std::min(lo, m2);
+          hi = std::max(hi, m2);
+          ++cnt;
+        }
+      }
+      if (cnt == 0) continue;
+      if (cnt != hi - lo + 1) {
+        delete s;
+        return fail(nullptr, KS_EUNSUPPORTED, "sphere column is not contiguous");
+      }
+      if (have_col && m1 != prev_m1 + 1) {
+        delete s;
+        return fail(nullptr, KS_EUNSUPPORTED, "sphere plane is not contiguous");
+      }
+      if (!have_col) first_col = m1;
+      have_col = true;
+      prev_m1 = m1;
+      coff.push_back(npw);
+      cm2.push_back(lo);
+      npw += cnt;
+      ++ncol;
+    }
+    if (ncol == 0) continue;
+    if (any_plane && m0 != prev_m0 + 1) {
+      delete s;
+      return fail(nullptr, KS_EUNSUPPORTED, "sphere planes are not contiguous");
+    }
+    if (!any_plane) s->m0lo = m0;
+    any_plane = true;
+    prev_m0 = m0;
+    plane_col0.push_back((int)col_off.size());
+    plane_m1lo.push_back(first_col);
+    col_off.insert(col_off.end(), coff.begin(), coff.end());
+    col_m2lo.insert(col_m2lo.end(), cm2.begin(), cm2.end());
+    s->ncol_max = std::max(s->ncol_max, ncol);
+  }
+  if (!any_plane) {
+    delete s;
+    return fail(nullptr, KS_EINVAL, "the plane-wave sphere is empty");
+  }
+  s->nplanes = (int)plane_col0.size();
+  s->ncols = (int)col_off.size();
+  plane_col0.push_back(s->ncols);
+  col_off.push_back(npw);
+  s->npw = npw;
+  s->npw_stride = (npw + 63) / 64 * 64;
+  s->xnb = x_tile_nb(n[0]);
+  s->ntiles = (s->npl + s->xnb - 1) / s->xnb;
+
+  if (plane_lds_bytes(s) > 160 * 1024) {
+    delete s;
+    return fail(nullptr, KS_EUNSUPPORTED, "plane-wave sphere too large for the plane pass LDS budget");
+  }
+
+  ks_status st;
+  if ((st = upload(s, &s->d_plane_col0, plane_col0)) != KS_OK ||
+      (st = upload(s, &s->d_plane_m1lo, plane_m1lo)) != KS_OK ||
+      (st = upload(s, &s->d_col_off, col_off)) != KS_OK || (st = upload(s, &s->d_col_m2lo, col_m2lo)) != KS_OK ||
+      (st = upload(s, &s->d_tw0, twiddles(n[0]))) != KS_OK || (st = upload(s, &s->d_tw1, twiddles(n[1]))) != KS_OK) {
+    g_create_err = s->err;
+    ks_system_destroy(s);
+    return st;
+  }
+  if ((st = dalloc(s, reinterpret_cast<void**>(&s->d_v), s->N * sizeof(double))) != KS_OK ||
+      (st = dalloc(s, reinterpret_cast<void**>(&s->red), 2 * (size_t)max_norb * sizeof(double))) != KS_OK) {
+    g_create_err = s->err;
+    ks_system_destroy(s);
+    return st;
+  }
+  if (hipMemset(s->d_v, 0, s->N * sizeof(double)) != hipSuccess) {
+    g_create_err = "hipMemset failed";
+    ks_system_destroy(s);
+    return KS_EDEVICE;
+  }
+  std::vector<int> zero_tiles(s->ntiles + 1, 0), zero_pen(s->npl + 1, 0), zero1(1, 0);
+  if ((st = upload(s, &s->d_tile_off, zero_tiles)) != KS_OK || (st = upload(s, &s->d_pen_off, zero_pen)) != KS_OK ||
+      (st = upload(s, &s->d_atom_off, zero1)) != KS_OK) {
+    g_create_err = s->err;
+    ks_system_destroy(s);
+    return st;
+  }
+  s->cb = default_chunk(s);
+  if ((st = alloc_workspace(s)) != KS_OK) {
+    g_create_err = s->err;
+    ks_system_destroy(s);
+    return st;
+  }
+  *out = s;
+  return KS_OK;
+}
+
+void ks_system_destroy(ks_system* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_workspace(s);
+  void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
+                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_ch_pencil, s->d_ch_atom, s->d_ch_r0, s->d_ch_len,
+                  s->d_ch_boff, s->d_tile_off, s->d_pen_off, s->d_atom_off, s->d_atom_list, s->d_beta,
+                  s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info};
+  for (void* p : ptrs) dfree(p);
+  delete s;
+}
+
+const char* ks_last_error(const ks_system* s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+int ks_system_npw(const ks_system* s) { return s ? s->npw : 0; }
+int ks_system_chunk(const ks_system* s) { return s ? s->cb : 0; }
+
+ks_status ks_system_set_chunk(ks_system* s, int chunk) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (chunk < 1 || chunk > s->max_norb) return fail(s, KS_EINVAL, "chunk outside [1, max_norb]");
+  KS_HIP(s, hipDeviceSynchronize());
+  s->cb = chunk;
+  return alloc_workspace(s);
+}
+
+ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (!v) return fail(s, KS_EINVAL, "v is null");
+  KS_HIP(s, hipMemcpyAsync(s->d_v, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  s->have_v = true;
+  return KS_OK;
+}
+
+ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
+                                   const double* beta, const double* d, void* stream) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (natoms < 0) return fail(s, KS_EINVAL, "natoms < 0");
+  if (natoms > 0 && (nproj < 1 || !npts || !d)) return fail(s, KS_EINVAL, "nproj < 1 or null npts/d");
+  KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
+  long long total = 0;
+  for (int I = 0; I < natoms; ++I) {
+    if (npts[I] < 0) return fail(s, KS_EINVAL, "negative npts");
+    total += npts[I];
+  }
+  if (total > 0 && (!idx || !beta)) return fail(s, KS_EINVAL, "idx or beta is null");
+  if (total > (1LL << 31) - 1) return fail(s, KS_EINVAL, "too many projector points");
+  struct Pt { int p, atom, j0, row; };
+  std::vector<Pt> pts;
+  pts.reserve(total);
+  long long off = 0;
+  for (int I = 0; I < natoms; ++I) {
+    for (int j = 0; j < npts[I]; ++j, ++off) {
+      const long long f = idx[off];
+      if (f < 0 || f >= s->N) return fail(s, KS_EINVAL, "projector index outside the grid");
+      pts.push_back(Pt{(int)(f % s->npl), I, (int)(f / s->npl), (int)off});
+    }
+  }
+  std::stable_sort(pts.begin(), pts.end(), [](const Pt& a, const Pt& b) {
+    if (a.p != b.p) return a.p < b.p;
+    if (a.atom != b.atom) return a.atom < b.atom;
+    return a.j0 < b.j0;
+  });
+  const int np = std::max(1, nproj);
+  std::vector<int> ch_pencil, ch_atom, ch_r0, ch_len, ch_boff;
+  std::vector<double> bch((size_t)total * np);
+  for (size_t k = 0; k < pts.size(); ++k) {
+    const Pt& q = pts[k];
+    const bool extend = k > 0 && q.p == pts[k - 1].p && q.atom == pts[k - 1].atom && q.j0 == pts[k - 1].j0 + 1;
+    if (extend) {
+      ch_len.back() += 1;
+    } else {
+      ch_pencil.push_back(q.p);
+      ch_atom.push_back(q.atom);
+      ch_r0.push_back(q.j0);
+      ch_len.push_back(1);
+      ch_boff.push_back((int)k);
+    }
+    for (int c = 0; c < np; ++c) bch[k * np + c] = beta[(size_t)q.row * np + c];
+  }
+  const int nch = (int)ch_pencil.size();
+  std::vector<int> tile_off(s->ntiles + 1), pen_off(s->npl + 1), atom_off(natoms + 1, 0), atom_list(nch);
+  {
+    int c = 0;
+    for (int t = 0; t <= s->ntiles; ++t) {
+      while (c < nch && ch_pencil[c] < t * s->xnb) ++c;
+      tile_off[t] = c;
+    }
+    tile_off[s->ntiles] = nch;
+    c = 0;
+    for (int p = 0; p <= s->npl; ++p) {
+      while (c < nch && ch_pencil[c] < p) ++c;
+      pen_off[p] = c;
+    }
+    for (int k = 0; k < nch; ++k) atom_off[ch_atom[k] + 1]++;
+    for (int I = 0; I < natoms; ++I) atom_off[I + 1] += atom_off[I];
+    std::vector<int> fill(atom_off.begin(), atom_off.end() - 1);
+    for (int k = 0; k < nch; ++k) atom_list[fill[ch_atom[k]]++] = k;
+  }
+  std::vector<double> kb((size_t)natoms * np);
+  for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
+  ks_status st;
+  if ((st = upload(s, &s->d_ch_pencil, ch_pencil)) != KS_OK || (st = upload(s, &s->d_ch_atom, ch_atom)) != KS_OK ||
+      (st = upload(s, &s->d_ch_r0, ch_r0)) != KS_OK || (st = upload(s, &s->d_ch_len, ch_len)) != KS_OK ||
+      (st = upload(s, &s->d_ch_boff, ch_boff)) != KS_OK || (st = upload(s, &s->d_beta, bch)) != KS_OK ||
+      (st = upload(s, &s->d_tile_off, tile_off)) != KS_OK || (st = upload(s, &s->d_pen_off, pen_off)) != KS_OK ||
+      (st = upload(s, &s->d_atom_off, atom_off)) != KS_OK || (st = upload(s, &s->d_atom_list, atom_list)) != KS_OK ||
+      (st = upload(s, &s->d_kb, kb)) != KS_OK)
+    return st;
+  s->natoms = (natoms > 0 && nch > 0) ? natoms : 0;
+  s->nproj = np;
+  s->nchords = nch;
+  s->npoints = (int)total;
+  return alloc_proj_workspace(s);
+}
+
+ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void* stream) {
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  if (norb == 0) return KS_OK;
+  if (!psi || !hpsi) return fail(s, KS_EINVAL, "psi or hpsi is null");
+  const size_t bytes = (size_t)norb * s->N * sizeof(double2);
+  const char* a = (const char*)psi;
+  const char* b = (const char*)hpsi;
+  if (a < b + bytes && b < a + bytes) return fail(s, KS_EINVAL, "psi and hpsi overlap");
+  hipStream_t st = (hipStream_t)stream;
+  Taylor none{{0.0, 0.0}, 0};
+  for (int o0 = 0; o0 < norb; o0 += s->cb) {
+    const int nb = std::min(s->cb, norb - o0);
+    const double2* in = (const double2*)psi + (size_t)o0 * s->N;
+    double2* out = (double2*)hpsi + (size_t)o0 * s->N;
+    if ((r = launch_ok(s, launch_pack(s, nb, in, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if ((r = hpsi_packed(s, nb, s->pk[0], s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
+    if ((r = launch_ok(s, launch_unpack(s, nb, s->pk[1], out, s->N, st), "unpack")) != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
+ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int nsteps, const double* occ,
+                            double* rho, void* stream) {
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  if (nsteps < 0) return fail(s, KS_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(s, KS_EINVAL, "dt must be finite");
+  if (norb == 0 || nsteps == 0) return KS_OK;
+  if (!psi) return fail(s, KS_EINVAL, "psi is null");
+  if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
+  hipStream_t st = (hipStream_t)stream;
+  // (-i dt)^k / k!
+  double2 coef[5];
+  {
+    double re = 1.0, im = 0.0;
+    coef[0] = double2{1.0, 0.0};
+    for (int k = 1; k <= 4; ++k) {
+      const double nr = im * dt, ni = -re * dt;  // multiply by -i dt
+      re = nr / k;
+      im = ni / k;
+      coef[k] = double2{re, im};
+    }
+  }
+  for (int o0 = 0; o0 < norb; o0 += s->cb) {
+    const int nb = std::min(s->cb, norb - o0);
+    double2* box = (double2*)psi + (size_t)o0 * s->N;
+    if ((r = launch_ok(s, launch_pack(s, nb, box, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    for (int step = 0; step < nsteps; ++step) {
+      // w1 = H psi -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored; acc (pk0) += a_k w_k
+      void* src[4] = {s->pk[0], s->pk[1], s->pk[2], s->pk[1]};
+      void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
+      for (int k = 1; k <= 4; ++k) {
+        Taylor tay{coef[k], k < 4 ? 1 : 0};
+        if ((r = hpsi_packed(s, nb, src[k - 1], dst[k - 1], s->pk[0], H_TAYLOR, tay, st)) != KS_OK) return r;
+      }
+      if (rho) {
+        if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho + (size_t)step * s->N, o0 > 0, st)) != KS_OK)
+          return r;
+      }
+    }
+    if ((r = launch_ok(s, launch_unpack(s, nb, s->pk[0], box, s->N, st), "unpack")) != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
+ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ, double* rho, void* stream) {
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  if (!rho) return fail(s, KS_EINVAL, "rho is null");
+  hipStream_t st = (hipStream_t)stream;
+  if (norb == 0) {
+    KS_HIP(s, hipMemsetAsync(rho, 0, s->N * sizeof(double), st));
+    return KS_OK;
+  }
+  if (!psi || !occ) return fail(s, KS_EINVAL, "psi or occ is null");
+  for (int o0 = 0; o0 < norb; o0 += s->cb) {
+    const int nb = std::min(s->cb, norb - o0);
+    const double2* box = (const double2*)psi + (size_t)o0 * s->N;
+    if ((r = launch_ok(s, launch_pack(s, nb, box, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho, o0 > 0, st)) != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
+ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, double* norms, double* energy,
+                    void* stream) {
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  if (energy && !occ) return fail(s, KS_EINVAL, "energy requires occ");
+  hipStream_t st = (hipStream_t)stream;
+  if (norb == 0) {
+    if (energy) KS_HIP(s, hipMemsetAsync(energy, 0, sizeof(double), st));
+    return KS_OK;
+  }
+  if (!psi) return fail(s, KS_EINVAL, "psi is null");
+  Taylor none{{0.0, 0.0}, 0};
+  for (int o0 = 0; o0 < norb; o0 += s->cb) {
+    const int nb = std::min(s->cb, norb - o0);
+    const double2* box = (const double2*)psi + (size_t)o0 * s->N;
+    if ((r = launch_ok(s, launch_pack(s, nb, box, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if (energy && (r = hpsi_packed(s, nb, s->pk[0], s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
+    if ((r = launch_ok(s, launch_dots(s, nb, s->pk[0], energy ? s->pk[1] : nullptr, s->red + 2 * (size_t)o0, st),
+                       "dots")) != KS_OK)
+      return r;
+  }
+  if (norms)
+    KS_HIP(s, hipMemcpy2DAsync(norms, sizeof(double), s->red, 2 * sizeof(double), sizeof(double), norb,
+                               hipMemcpyDeviceToDevice, st));
+  if (energy) return launch_ok(s, launch_energy_sum(norb, occ, s->red, energy, st), "energy_sum");
+  return KS_OK;
+}
+
+ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  (void)psi;
+  (void)stream;
+  return fail(s, KS_EUNSUPPORTED, "orthonormalisation is not built yet");
+}
+
+}  // extern "C"

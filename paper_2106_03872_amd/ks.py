@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libks (include/ks.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Device buffers are torch tensors on the current HIP device; the
+current torch stream is passed to every call.  Importing this module loads
+``libks.so`` and raises when it is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libks.so")
+HEADER = os.path.join(HERE, "..", "include", "ks.h")
+
+KS_OK, KS_EINVAL, KS_ENOMEM, KS_EDEVICE, KS_EUNSUPPORTED = range(5)
+KS_FP64, KS_MIXED = 0, 1
+_STATUS = {1: "KS_EINVAL", 2: "KS_ENOMEM", 3: "KS_EDEVICE", 4: "KS_EUNSUPPORTED"}
+
+
+class KSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    # torch ships its own HIP runtime (same SONAME as /opt/rocm's).  Loading
+    # torch first makes libks bind to that one copy; the other order would put
+    # two HIP runtimes in the process.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2106_03872_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "ks_system_create": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, ctypes.POINTER(P)]),
+        "ks_system_destroy": (None, [P]),
+        "ks_last_error": (ctypes.c_char_p, [P]),
+        "ks_system_set_vloc": (I, [P, P, P]),
+        "ks_system_set_projectors": (I, [P, I, I, P, P, P, P, P]),
+        "ks_ham_apply": (I, [P, I, P, P, P]),
+        "ks_propagate_step": (I, [P, I, P, D, I, P, P, P]),
+        "ks_density": (I, [P, I, P, P, P, P]),
+        "ks_reduce": (I, [P, I, P, P, P, P, P]),
+        "ks_orthonormalize": (I, [P, I, P, P]),
+        "ks_system_npw": (I, [P]),
+        "ks_system_chunk": (I, [P]),
+        "ks_system_set_chunk": (I, [P, I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def header_symbols():
+    """Entry points declared in include/ks.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ks_status|void|const char\*|int)\s+(ks_\w+)\s*\(", txt, re.M)))
+
+
+def library():
+    return _lib
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class System:
+    """One Kohn-Sham system (grid, cell, cutoff, potential, projectors)."""
+
+    def __init__(self, n, L, ecut, max_norb, precision=KS_FP64):
+        self.n = tuple(int(x) for x in n)
+        self.L = tuple(float(x) for x in L)
+        self.ecut = float(ecut)
+        self.max_norb = int(max_norb)
+        self.N = int(np.prod(self.n))
+        h = ctypes.c_void_p()
+        st = _lib.ks_system_create((ctypes.c_int * 3)(*self.n), (ctypes.c_double * 3)(*self.L),
+                                   self.ecut, int(precision), self.max_norb, ctypes.byref(h))
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_last_error(None).decode())
+        self._h = h
+
+    def _check(self, st):
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ks_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def npw(self):
+        return _lib.ks_system_npw(self._h)
+
+    @property
+    def chunk(self):
+        return _lib.ks_system_chunk(self._h)
+
+    def set_chunk(self, c):
+        self._check(_lib.ks_system_set_chunk(self._h, int(c)))
+
+    def box_shape(self, norb):
+        return (int(norb),) + self.n
+
+    # ---------------------------------------------------------------- set-up
+    def set_vloc(self, v):
+        import torch
+        self._check(_lib.ks_system_set_vloc(self._h, _ptr(v, torch.float64, self.n, "v"), _stream()))
+
+    def set_projectors(self, npts, idx, beta, d):
+        npts = np.ascontiguousarray(npts, np.int32)
+        idx = np.ascontiguousarray(idx, np.int32)
+        beta = np.ascontiguousarray(beta, np.float64)
+        d = np.ascontiguousarray(d, np.float64)
+        natoms = len(npts)
+        nproj = d.shape[1] if d.ndim == 2 and natoms else (beta.shape[1] if beta.ndim == 2 else 1)
+        if natoms and (beta.shape[0] != idx.shape[0] or int(npts.sum()) != idx.shape[0]):
+            raise ValueError("npts, idx and beta disagree")
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+        self._check(_lib.ks_system_set_projectors(self._h, natoms, int(nproj), ptr(npts), ptr(idx),
+                                                  ptr(beta), ptr(d), _stream()))
+        self._keep = (npts, idx, beta, d)
+
+    # ------------------------------------------------------------- hot path
+    def ham_apply(self, psi, hpsi=None):
+        import torch
+        norb = psi.shape[0]
+        if hpsi is None:
+            hpsi = torch.empty_like(psi)
+        self._check(_lib.ks_ham_apply(self._h, norb, _ptr(psi, torch.complex128, self.box_shape(norb), "psi"),
+                                      _ptr(hpsi, torch.complex128, self.box_shape(norb), "hpsi"), _stream()))
+        return hpsi
+
+    def propagate_step(self, psi, dt, nsteps=1, occ=None, rho=None):
+        import torch
+        norb = psi.shape[0]
+        self._check(_lib.ks_propagate_step(
+            self._h, norb, _ptr(psi, torch.complex128, self.box_shape(norb), "psi"), float(dt), int(nsteps),
+            _ptr(occ, torch.float64, (norb,), "occ"),
+            _ptr(rho, torch.float64, (int(nsteps),) + self.n, "rho"), _stream()))
+        return psi
+
+    def density(self, psi, occ, rho=None):
+        import torch
+        norb = psi.shape[0]
+        if rho is None:
+            rho = torch.empty(self.n, dtype=torch.float64, device=psi.device)
+        self._check(_lib.ks_density(self._h, norb, _ptr(psi, torch.complex128, self.box_shape(norb), "psi"),
+                                    _ptr(occ, torch.float64, (norb,), "occ"),
+                                    _ptr(rho, torch.float64, self.n, "rho"), _stream()))
+        return rho
+
+    def reduce(self, psi, occ=None, want_energy=True):
+        import torch
+        norb = psi.shape[0]
+        norms = torch.empty(norb, dtype=torch.float64, device=psi.device)
+        energy = torch.empty(1, dtype=torch.float64, device=psi.device) if want_energy else None
+        self._check(_lib.ks_reduce(self._h, norb, _ptr(psi, torch.complex128, self.box_shape(norb), "psi"),
+                                   _ptr(occ, torch.float64, (norb,), "occ"), _ptr(norms, torch.float64),
+                                   _ptr(energy, torch.float64), _stream()))
+        return norms, energy
+
+    def orthonormalize(self, psi):
+        import torch
+        norb = psi.shape[0]
+        self._check(_lib.ks_orthonormalize(self._h, norb, _ptr(psi, torch.complex128, self.box_shape(norb), "psi"),
+                                           _stream()))
+        return psi
+
+
+# module-level entry points with the names of the C ABI
+def ham_apply(system, psi, hpsi=None):
+    return system.ham_apply(psi, hpsi)
+
+
+def propagate_step(system, psi, dt, nsteps=1, occ=None, rho=None):
+    return system.propagate_step(psi, dt, nsteps, occ, rho)
+
+
+def density(system, psi, occ, rho=None):
+    return system.density(psi, occ, rho)
+
+
+def reduce(system, psi, occ=None):
+    return system.reduce(psi, occ)
+
+
+def orthonormalize(system, psi):
+    return system.orthonormalize(psi)
+
+
+def system_from_synth(sysm, max_norb=None, ecut=None):
+    """Create a System from a synth.System (potential + projectors uploaded)."""
+    import torch
+    spec = sysm.spec
+    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb)
+    s.set_vloc(torch.from_numpy(sysm.vloc).to("cuda"))
+    p = sysm.proj
+    s.set_projectors(p.npts, p.idx, p.beta, p.d)
+    return s
