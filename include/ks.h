@@ -158,6 +158,45 @@ int ks_system_chunk(const ks_system* sys);
  * call it at set-up time only.  KS_EINVAL when out of range. */
 ks_status ks_system_set_chunk(ks_system* sys, int chunk);
 
+/* ------------------------------------------------------------------------
+ * Introspection and kernel timing (instrumentation; not on the hot path).
+ */
+typedef struct {
+  int npw;          /* plane waves in the sphere (packed coefficients per orbital) */
+  int nplanes;      /* m0 planes touched by the sphere */
+  int ncols;        /* (m0, m1) columns touched by the sphere */
+  int chunk;        /* orbitals per internal pass */
+  int natoms;       /* atoms with at least one projector point */
+  int nproj;        /* projectors per atom */
+  int nchords;      /* runs of consecutive x-points of the projector spheres */
+  int npoints;      /* projector points (sum of npts) */
+  int x_tile;       /* x-pencils per block in the x-pencil passes */
+  int precision;    /* ks_precision */
+} ks_info;
+
+/* Fill *info for sys.  KS_EINVAL on null arguments. */
+ks_status ks_system_info(const ks_system* sys, ks_info* info);
+
+/* Kernel classes reported by ks_kernel_time. */
+typedef enum {
+  KS_K_PACK = 0, KS_K_UNPACK, KS_K_PLANE_INV, KS_K_XPROJ, KS_K_PROJ_REDUCE, KS_K_XAPPLY,
+  KS_K_PLANE_FWD, KS_K_XDENS, KS_K_DOTS, KS_K_COUNT
+} ks_kernel_id;
+
+/*
+ * enable != 0: record a HIP event pair around every kernel launch of sys on
+ * the stream it is launched on, and reset the accumulated times; enable == 0:
+ * stop recording.  Costs two event records per launch while on.
+ */
+ks_status ks_set_kernel_timing(ks_system* sys, int enable);
+
+/*
+ * Accumulated device time (ms) and launch count of one kernel class since
+ * timing was enabled.  Synchronises the recorded events.  Either output may
+ * be NULL.  KS_EINVAL for an unknown id.
+ */
+ks_status ks_kernel_time(ks_system* sys, int kernel_id, double* total_ms, long long* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,7 +40,16 @@ import numpy as np
 import scipy.fft
 import scipy.linalg
 
-WORKERS = os.cpu_count() or 1
+def _host_threads():
+    # the host share this process may use: OMP_NUM_THREADS when set, else the
+    # CPUs it is pinned to
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0)) or 1
+
+
+WORKERS = _host_threads()
 
 
 class Grid:

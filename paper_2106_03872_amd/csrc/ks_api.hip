@@ -61,6 +61,44 @@ ks_status launch_ok(ks_system* s, bool ok, const char* what) {
   return KS_OK;
 }
 
+// ---------------------------------------------------------------- timing
+constexpr int EV_PAIRS = 16384;
+
+void timing_flush(ks_system* s) {
+  for (int i = 0; i < s->ev_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(s->ev[2 * i + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]) == hipSuccess) {
+      s->kt_ms[s->ev_kid[i]] += ms;
+      s->kt_n[s->ev_kid[i]] += 1;
+    }
+  }
+  s->ev_used = 0;
+}
+
+void timing_free(ks_system* s) {
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  s->ev.clear();
+  s->ev_kid.clear();
+  s->ev_used = 0;
+  s->timing = false;
+}
+
+// Launch one kernel (f returns false when the size has no kernel); with
+// timing on, bracket it by an event pair on its stream.
+template <typename F> ks_status kcall(ks_system* s, int kid, hipStream_t st, const char* what, F&& f) {
+  int slot = -1;
+  if (s->timing) {
+    if (s->ev_used == EV_PAIRS) timing_flush(s);
+    slot = s->ev_used++;
+    s->ev_kid[slot] = kid;
+    (void)hipEventRecord(s->ev[2 * slot], st);
+  }
+  const bool ok = f();
+  if (slot >= 0) (void)hipEventRecord(s->ev[2 * slot + 1], st);
+  return launch_ok(s, ok, what);
+}
+
 // exp(-2 pi i j / n), computed in long double and rounded
 std::vector<double2> twiddles(int n) {
   const long double pi = 3.141592653589793238462643383279502884L;
@@ -135,24 +173,24 @@ ks_status check_common(ks_system* s, int norb) {
 // H applied to nb packed orbitals win; result per mode (see plane_fwd_kernel)
 ks_status hpsi_packed(ks_system* s, int nb, const void* win, void* wout, void* acc, HMode mode, Taylor tay,
                       hipStream_t st) {
-  ks_status r = launch_ok(s, launch_plane_inv(s, nb, win, s->T, st), "plane_inv");
+  ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, win, s->T, st); });
   if (r != KS_OK) return r;
   if (s->natoms > 0) {
-    r = launch_ok(s, launch_xproj(s, nb, s->T, s->partial, st), "xproj");
+    r = kcall(s, KS_K_XPROJ, st, "xproj", [&] { return launch_xproj(s, nb, s->T, s->partial, st); });
     if (r != KS_OK) return r;
-    r = launch_ok(s, launch_proj_reduce(s, nb, s->partial, s->DP, st), "proj_reduce");
+    r = kcall(s, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] { return launch_proj_reduce(s, nb, s->partial, s->DP, st); });
     if (r != KS_OK) return r;
   }
-  r = launch_ok(s, launch_xapply(s, nb, s->T, s->DP, s->U, st), "xapply");
+  r = kcall(s, KS_K_XAPPLY, st, "xapply", [&] { return launch_xapply(s, nb, s->T, s->DP, s->U, st); });
   if (r != KS_OK) return r;
-  return launch_ok(s, launch_plane_fwd(s, nb, s->U, win, wout, acc, mode, tay, st), "plane_fwd");
+  return kcall(s, KS_K_PLANE_FWD, st, "plane_fwd", [&] { return launch_plane_fwd(s, nb, s->U, win, wout, acc, mode, tay, st); });
 }
 
 ks_status density_packed(ks_system* s, int nb, const void* pk, const double* occ, double* rho, int accumulate,
                          hipStream_t st) {
-  ks_status r = launch_ok(s, launch_plane_inv(s, nb, pk, s->T, st), "plane_inv");
+  ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, pk, s->T, st); });
   if (r != KS_OK) return r;
-  return launch_ok(s, launch_xdens(s, nb, s->T, occ, rho, accumulate, st), "xdens");
+  return kcall(s, KS_K_XDENS, st, "xdens", [&] { return launch_xdens(s, nb, s->T, occ, rho, accumulate, st); });
 }
 
 }  // namespace
@@ -297,6 +335,7 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
 void ks_system_destroy(ks_system* s) {
   if (!s) return;
   (void)hipDeviceSynchronize();
+  timing_free(s);
   free_workspace(s);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
                   s->d_tw0f, s->d_tw1f, s->d_v, s->d_ch_pencil, s->d_ch_atom, s->d_ch_r0, s->d_ch_len,
@@ -424,9 +463,9 @@ ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void
     const int nb = std::min(s->cb, norb - o0);
     const double2* in = (const double2*)psi + (size_t)o0 * s->N;
     double2* out = (double2*)hpsi + (size_t)o0 * s->N;
-    if ((r = launch_ok(s, launch_pack(s, nb, in, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, in, s->N, s->pk[0], st); })) != KS_OK) return r;
     if ((r = hpsi_packed(s, nb, s->pk[0], s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
-    if ((r = launch_ok(s, launch_unpack(s, nb, s->pk[1], out, s->N, st), "unpack")) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[1], out, s->N, st); })) != KS_OK) return r;
   }
   return KS_OK;
 }
@@ -456,7 +495,7 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
   for (int o0 = 0; o0 < norb; o0 += s->cb) {
     const int nb = std::min(s->cb, norb - o0);
     double2* box = (double2*)psi + (size_t)o0 * s->N;
-    if ((r = launch_ok(s, launch_pack(s, nb, box, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
     for (int step = 0; step < nsteps; ++step) {
       // w1 = H psi -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored; acc (pk0) += a_k w_k
       void* src[4] = {s->pk[0], s->pk[1], s->pk[2], s->pk[1]};
@@ -470,7 +509,7 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
           return r;
       }
     }
-    if ((r = launch_ok(s, launch_unpack(s, nb, s->pk[0], box, s->N, st), "unpack")) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[0], box, s->N, st); })) != KS_OK) return r;
   }
   return KS_OK;
 }
@@ -488,7 +527,7 @@ ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ,
   for (int o0 = 0; o0 < norb; o0 += s->cb) {
     const int nb = std::min(s->cb, norb - o0);
     const double2* box = (const double2*)psi + (size_t)o0 * s->N;
-    if ((r = launch_ok(s, launch_pack(s, nb, box, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
     if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho, o0 > 0, st)) != KS_OK) return r;
   }
   return KS_OK;
@@ -509,16 +548,17 @@ ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, 
   for (int o0 = 0; o0 < norb; o0 += s->cb) {
     const int nb = std::min(s->cb, norb - o0);
     const double2* box = (const double2*)psi + (size_t)o0 * s->N;
-    if ((r = launch_ok(s, launch_pack(s, nb, box, s->N, s->pk[0], st), "pack")) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
     if (energy && (r = hpsi_packed(s, nb, s->pk[0], s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
-    if ((r = launch_ok(s, launch_dots(s, nb, s->pk[0], energy ? s->pk[1] : nullptr, s->red + 2 * (size_t)o0, st),
-                       "dots")) != KS_OK)
+    const void* hp = energy ? s->pk[1] : nullptr;
+    double* red = s->red + 2 * (size_t)o0;
+    if ((r = kcall(s, KS_K_DOTS, st, "dots", [&] { return launch_dots(s, nb, s->pk[0], hp, red, st); })) != KS_OK)
       return r;
   }
   if (norms)
     KS_HIP(s, hipMemcpy2DAsync(norms, sizeof(double), s->red, 2 * sizeof(double), sizeof(double), norb,
                                hipMemcpyDeviceToDevice, st));
-  if (energy) return launch_ok(s, launch_energy_sum(norb, occ, s->red, energy, st), "energy_sum");
+  if (energy) return kcall(s, KS_K_DOTS, st, "energy_sum", [&] { return launch_energy_sum(norb, occ, s->red, energy, st); });
   return KS_OK;
 }
 
@@ -528,6 +568,52 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   (void)psi;
   (void)stream;
   return fail(s, KS_EUNSUPPORTED, "orthonormalisation is not built yet");
+}
+
+ks_status ks_system_info(const ks_system* s, ks_info* info) {
+  if (!s || !info) return KS_EINVAL;
+  info->npw = s->npw;
+  info->nplanes = s->nplanes;
+  info->ncols = s->ncols;
+  info->chunk = s->cb;
+  info->natoms = s->natoms;
+  info->nproj = s->nproj;
+  info->nchords = s->nchords;
+  info->npoints = s->npoints;
+  info->x_tile = s->xnb;
+  info->precision = s->prec;
+  return KS_OK;
+}
+
+ks_status ks_set_kernel_timing(ks_system* s, int enable) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  timing_free(s);
+  for (int k = 0; k < 16; ++k) {
+    s->kt_ms[k] = 0.0;
+    s->kt_n[k] = 0;
+  }
+  if (!enable) return KS_OK;
+  s->ev.resize(2 * EV_PAIRS);
+  s->ev_kid.assign(EV_PAIRS, 0);
+  for (auto& e : s->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      timing_free(s);
+      return fail(s, KS_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(r));
+    }
+  }
+  s->timing = true;
+  return KS_OK;
+}
+
+ks_status ks_kernel_time(ks_system* s, int kernel_id, double* total_ms, long long* launches) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (kernel_id < 0 || kernel_id >= KS_K_COUNT) return fail(s, KS_EINVAL, "unknown kernel id");
+  timing_flush(s);
+  if (total_ms) *total_ms = s->kt_ms[kernel_id];
+  if (launches) *launches = s->kt_n[kernel_id];
+  return KS_OK;
 }
 
 }  // extern "C"

@@ -97,8 +97,15 @@ struct ks_system {
   int* ortho_info = nullptr;
   int ortho_cap = 0;
 
+  // kernel timing (ks_set_kernel_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;       // pairs
+  std::vector<int> ev_kid;          // kernel class of each pair
+  int ev_used = 0;
+  double kt_ms[16] = {0};
+  long long kt_n[16] = {0};
+
   std::string err;
-  std::vector<void*> owned;
 };
 
 namespace ks {

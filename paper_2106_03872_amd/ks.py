@@ -19,6 +19,15 @@ HEADER = os.path.join(HERE, "..", "include", "ks.h")
 
 KS_OK, KS_EINVAL, KS_ENOMEM, KS_EDEVICE, KS_EUNSUPPORTED = range(5)
 KS_FP64, KS_MIXED = 0, 1
+KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dots"]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nchords",
+                                            "npoints", "x_tile", "precision")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 _STATUS = {1: "KS_EINVAL", 2: "KS_ENOMEM", 3: "KS_EDEVICE", 4: "KS_EUNSUPPORTED"}
 
 
@@ -51,6 +60,9 @@ def _load():
         "ks_system_npw": (I, [P]),
         "ks_system_chunk": (I, [P]),
         "ks_system_set_chunk": (I, [P, I]),
+        "ks_system_info": (I, [P, P]),
+        "ks_set_kernel_timing": (I, [P, I]),
+        "ks_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -133,6 +145,23 @@ class System:
 
     def set_chunk(self, c):
         self._check(_lib.ks_system_set_chunk(self._h, int(c)))
+
+    def info(self):
+        inf = Info()
+        self._check(_lib.ks_system_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def set_kernel_timing(self, enable=True):
+        self._check(_lib.ks_set_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self):
+        """{kernel name: (total ms, launches)} since timing was enabled."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms, n = ctypes.c_double(), ctypes.c_longlong()
+            self._check(_lib.ks_kernel_time(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def box_shape(self, norb):
         return (int(norb),) + self.n
