@@ -44,8 +44,8 @@ def alg_bytes(info, spec, kernel, S=16):
     npl = spec.n[1] * spec.n[2]
     box_planes = info["nplanes"] * npl * S
     npw = info["npw"] * S
-    beta = info["npoints"] * info["nproj"] * 8 + info["nchords"] * 5 * 4
-    parts = info["nchords"] * info["nproj"] * S
+    beta = info["npoints"] * info["nproj"] * 8 + info["nruns"] * 3 * 4
+    parts = info["nslots"] * info["nproj"] * S
     if kernel == "plane_inv":
         return npw + box_planes, 0
     if kernel == "xproj":
@@ -67,7 +67,7 @@ def alg_bytes(info, spec, kernel, S=16):
     return 0, 0
 
 
-def cpu_baseline(spec, sysm, norb_sample=32):
+def cpu_baseline(spec, sysm, norb_sample=128):
     """The FP64 oracle, unchanged, on a bounded sample of the workload:
     norb_sample orbitals through one Taylor-4 step and the density."""
     from oracle import ks_oracle as ko

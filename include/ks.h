@@ -168,7 +168,8 @@ typedef struct {
   int chunk;        /* orbitals per internal pass */
   int natoms;       /* atoms with at least one projector point */
   int nproj;        /* projectors per atom */
-  int nchords;      /* runs of consecutive x-points of the projector spheres */
+  int nruns;        /* runs of consecutive x-points of the projector spheres */
+  int nslots;       /* (x-tile, atom) pairs touched by the projector spheres */
   int npoints;      /* projector points (sum of npts) */
   int x_tile;       /* x-pencils per block in the x-pencil passes */
   int precision;    /* ks_precision */

@@ -149,13 +149,50 @@ template <int SIGN, typename T> struct dft<8, SIGN, T> {
   }
 };
 
+// Prime-factor (Good-Thomas) codelets for N = N1 N2 with gcd(N1, N2) = 1:
+// input n = (N2 n1 + N1 n2) mod N, output k = (A k1 + B k2) mod N with
+// A = N2 (N2^-1 mod N1), B = N1 (N1^-1 mod N2); no twiddle factors.
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+template <int N1, int N2, int SIGN, typename T> struct dft_pfa {
+  static constexpr int N = N1 * N2;
+  static constexpr int A = N2 * inv_mod(N2 % N1, N1);
+  static constexpr int B = N1 * inv_mod(N1 % N2, N2);
+  __device__ __forceinline__ static void run(T* v) {
+    T a[N1][N2];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1)
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) a[n1][n2] = v[(N2 * n1 + N1 * n2) % N];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) dft<N2, SIGN, T>::run(a[n1]);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      T c[N1];
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) c[n1] = a[n1][k2];
+      dft<N1, SIGN, T>::run(c);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) v[(A * k1 + B * k2) % N] = c[k1];
+    }
+  }
+};
+
+template <int SIGN, typename T> struct dft<10, SIGN, T> : dft_pfa<2, 5, SIGN, T> {};
+template <int SIGN, typename T> struct dft<12, SIGN, T> : dft_pfa<3, 4, SIGN, T> {};
+template <int SIGN, typename T> struct dft<15, SIGN, T> : dft_pfa<3, 5, SIGN, T> {};
+
 // ------------------------------------------------------------- radix plans
 
 template <int... Rs> struct radix_list {};
 
-template <int N> struct plan;   // factorisation used for length N
+template <int N> struct plan;   // factorisation used for length N (first radix first)
 template <> struct plan<8> { using list = radix_list<8>; };
-template <> struct plan<12> { using list = radix_list<4, 3>; };
+template <> struct plan<12> { using list = radix_list<12>; };
 template <> struct plan<16> { using list = radix_list<4, 4>; };
 template <> struct plan<20> { using list = radix_list<4, 5>; };
 template <> struct plan<24> { using list = radix_list<4, 6>; };
@@ -164,19 +201,36 @@ template <> struct plan<32> { using list = radix_list<4, 8>; };
 template <> struct plan<36> { using list = radix_list<6, 6>; };
 template <> struct plan<40> { using list = radix_list<8, 5>; };
 template <> struct plan<48> { using list = radix_list<8, 6>; };
-template <> struct plan<60> { using list = radix_list<4, 3, 5>; };
+template <> struct plan<60> { using list = radix_list<12, 5>; };
 template <> struct plan<64> { using list = radix_list<8, 8>; };
-template <> struct plan<72> { using list = radix_list<8, 3, 3>; };
-template <> struct plan<80> { using list = radix_list<4, 4, 5>; };
-template <> struct plan<96> { using list = radix_list<6, 4, 4>; };
-template <> struct plan<100> { using list = radix_list<4, 5, 5>; };
-template <> struct plan<120> { using list = radix_list<8, 5, 3>; };
+template <> struct plan<72> { using list = radix_list<12, 6>; };
+template <> struct plan<80> { using list = radix_list<8, 10>; };
+template <> struct plan<96> { using list = radix_list<12, 8>; };
+template <> struct plan<100> { using list = radix_list<10, 10>; };
+template <> struct plan<120> { using list = radix_list<12, 10>; };
 template <> struct plan<128> { using list = radix_list<8, 4, 4>; };
 
-// One Stockham stage over a batch of NB transforms laid out at
-// buf[t * ts + e] (element stride 1).  tw[j] = exp(-2 pi i j / N).
-template <int N, int R, int NS, int SIGN, int NB, int NT, typename T>
-__device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const T* tw) {
+// Where a stage reads from / writes to.  LDS stages work in place on the
+// batch buffer; the first stage may instead pull its inputs from a loader
+// functor and the last stage may push its outputs to a store functor.
+enum { SRC_LDS = 0, SRC_FN = 1 };
+enum { DST_LDS = 0, DST_FN = 1, DST_FN_LDS = 2 };   // DST_FN_LDS: the functor writes the batch buffer
+
+struct no_load {
+  template <typename T> __device__ T operator()(int, int) const { return T{}; }
+};
+struct no_store {
+  template <typename T> __device__ void operator()(int, int, T, int, int) const {}
+};
+
+// One Stockham stage over a batch of NB transforms laid out at buf[t*ts + e].
+// tw[j] = exp(-2 pi i j / N) (global or LDS).
+//   load(t, e)             -> element e of transform t        (SRC_FN)
+//   store(t, e, v, it, q)  <- output element e of transform t (DST_FN*); it and q
+//                             index the caller's per-thread register arrays
+template <int N, int R, int NS, int SIGN, int NB, int NT, int SRC, int DST, typename T, class Load, class Store>
+__device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const T* __restrict__ tw, Load& load,
+                                               Store& store) {
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
   constexpr int ITEMS = (TOT + NT - 1) / NT;
@@ -188,17 +242,20 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
     const int t = i % NB, b = i / NB;
     if ((TOT % NT == 0 || i < TOT) && t < ntrans) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[it][q] = buf[t * ts + b + q * NBF];
+      for (int q = 0; q < R; ++q) {
+        if constexpr (SRC == SRC_FN) v[it][q] = load(t, b + q * NBF);
+        else v[it][q] = buf[t * ts + b + q * NBF];
+      }
     }
   }
-  __syncthreads();
+  if constexpr (SRC == SRC_LDS && DST != DST_FN) __syncthreads();
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const int i = tid + it * NT;
     const int t = i % NB, b = i / NB;
     if ((TOT % NT == 0 || i < TOT) && t < ntrans) {
       const int k = b % NS;
-      if (NS > 1) {
+      if constexpr (NS > 1) {
 #pragma unroll
         for (int q = 1; q < R; ++q) {
           const T w = tw[q * k * (N / (NS * R))];
@@ -208,29 +265,87 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
       dft<R, SIGN, T>::run(v[it]);
       const int o = (b / NS) * NS * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[t * ts + o + q * NS] = v[it][q];
+      for (int q = 0; q < R; ++q) {
+        if constexpr (DST == DST_LDS) buf[t * ts + o + q * NS] = v[it][q];
+        else store(t, o + q * NS, v[it][q], it, q);
+      }
     }
   }
-  __syncthreads();
+  if constexpr (DST != DST_FN) __syncthreads();
 }
 
-template <int N, int NS, int SIGN, int NB, int NT, typename T, int R, int... Rest>
-__device__ __forceinline__ void stockham_run(T* buf, int ts, int ntrans, const T* tw) {
-  stockham_stage<N, R, NS, SIGN, NB, NT, T>(buf, ts, ntrans, tw);
-  if constexpr (sizeof...(Rest) > 0) stockham_run<N, NS * R, SIGN, NB, NT, T, Rest...>(buf, ts, ntrans, tw);
+template <int N, int NS, int SIGN, int NB, int NT, int SRC, int DST, typename T, class Load, class Store, int R,
+          int... Rest>
+__device__ __forceinline__ void stockham_run(T* buf, int ts, int ntrans, const T* tw, Load& load, Store& store) {
+  constexpr bool last = sizeof...(Rest) == 0;
+  stockham_stage<N, R, NS, SIGN, NB, NT, SRC, (last ? DST : DST_LDS), T>(buf, ts, ntrans, tw, load, store);
+  if constexpr (!last)
+    stockham_run<N, NS * R, SIGN, NB, NT, SRC_LDS, DST, T, Load, Store, Rest...>(buf, ts, ntrans, tw, load, store);
 }
 
-template <int N, int SIGN, int NB, int NT, typename T, int... Rs>
-__device__ __forceinline__ void fft_batch_impl(radix_list<Rs...>, T* buf, int ts, int ntrans, const T* tw) {
-  stockham_run<N, 1, SIGN, NB, NT, T, Rs...>(buf, ts, ntrans, tw);
+template <int N, int SIGN, int NB, int NT, int SRC, int DST, typename T, class Load, class Store, int... Rs>
+__device__ __forceinline__ void fft_io_impl(radix_list<Rs...>, T* buf, int ts, int ntrans, const T* tw, Load& load,
+                                            Store& store) {
+  stockham_run<N, 1, SIGN, NB, NT, SRC, DST, T, Load, Store, Rs...>(buf, ts, ntrans, tw, load, store);
 }
 
-// In-place DFT  x_k <- sum_j x_j exp(SIGN 2 pi i j k / N)  of transforms
-// t < ntrans (t < NB) stored at buf[t * ts + 0 .. N-1].  Block-collective.
+// DFT  x_k = sum_j x_j exp(SIGN 2 pi i j k / N)  of transforms t < ntrans
+// (t < NB) of a batch, block-collective.  buf[t*ts + 0..N-1] is the exchange
+// buffer; inputs come from buf (SRC_LDS) or load (SRC_FN), outputs go to buf
+// (DST_LDS) or store (DST_FN, DST_FN_LDS).  The caller must synchronise the
+// block before a SRC_FN call whose first stage overwrites buf, and after a
+// DST_FN call before buf is overwritten.
+template <int N, int SIGN, int NB, int NT, int SRC, int DST, typename T, class Load, class Store>
+__device__ __forceinline__ void fft_io(T* buf, int ts, int ntrans, const T* tw, Load&& load, Store&& store) {
+  fft_io_impl<N, SIGN, NB, NT, SRC, DST, T>(typename plan<N>::list{}, buf, ts, ntrans, tw, load, store);
+}
+
+// In-place DFT of transforms in buf (natural order in and out).
 template <int N, int SIGN, int NB, int NT, typename T>
 __device__ __forceinline__ void fft_batch(T* buf, int ts, int ntrans, const T* tw) {
-  fft_batch_impl<N, SIGN, NB, NT, T>(typename plan<N>::list{}, buf, ts, ntrans, tw);
+  fft_io<N, SIGN, NB, NT, SRC_LDS, DST_LDS, T>(buf, ts, ntrans, tw, no_load{}, no_store{});
 }
+
+// Output positions of the last stage: f(it, q, t, e) for every (item, q) the
+// calling thread will produce (used to prefetch per-element data).
+template <int N, int NB, int NT, int R, int NS, class F>
+__device__ __forceinline__ void last_stage_positions_impl(int ntrans, F& f) {
+  constexpr int NBF = N / R;
+  constexpr int TOT = NB * NBF;
+  constexpr int ITEMS = (TOT + NT - 1) / NT;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const int i = tid + it * NT;
+    const int t = i % NB, b = i / NB;
+    if ((TOT % NT == 0 || i < TOT) && t < ntrans) {
+      const int o = (b / NS) * NS * R + b % NS;
+#pragma unroll
+      for (int q = 0; q < R; ++q) f(it, q, t, o + q * NS);
+    }
+  }
+}
+
+template <int N, int NB, int NT, int NSacc, int R, int... Rest, class F>
+__device__ __forceinline__ void last_positions_run(radix_list<R, Rest...>, int ntrans, F& f) {
+  if constexpr (sizeof...(Rest) == 0) last_stage_positions_impl<N, NB, NT, R, NSacc>(ntrans, f);
+  else last_positions_run<N, NB, NT, NSacc * R>(radix_list<Rest...>{}, ntrans, f);
+}
+
+template <int N, int NB, int NT, class F>
+__device__ __forceinline__ void last_stage_positions(int ntrans, F&& f) {
+  last_positions_run<N, NB, NT, 1>(typename plan<N>::list{}, ntrans, f);
+}
+
+// number of (item, q) slots per thread in the last stage
+template <int N, int NB, int NT, typename L> struct last_stage_shape;
+template <int N, int NB, int NT, int R> struct last_stage_shape<N, NB, NT, radix_list<R>> {
+  static constexpr int radix = R;
+  static constexpr int items = (NB * (N / R) + NT - 1) / NT;
+};
+template <int N, int NB, int NT, int R, int R2, int... Rest>
+struct last_stage_shape<N, NB, NT, radix_list<R, R2, Rest...>> : last_stage_shape<N, NB, NT, radix_list<R2, Rest...>> {};
+template <int N, int NB, int NT> using last_shape = last_stage_shape<N, NB, NT, typename plan<N>::list>;
 
 __device__ __forceinline__ int fold(int j, int n) { return 2 * j < n ? j : j - n; }
 __device__ __forceinline__ int wrap(int m, int n) { return m < 0 ? m + n : m; }

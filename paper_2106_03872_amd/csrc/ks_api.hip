@@ -131,7 +131,7 @@ void free_workspace(ks_system* s) {
 ks_status alloc_proj_workspace(ks_system* s) {
   dfree(s->partial);
   dfree(reinterpret_cast<void*&>(s->DP));
-  const size_t pbytes = (size_t)s->cb * std::max(1, s->nchords) * std::max(1, s->nproj) * sizeof(double2);
+  const size_t pbytes = (size_t)s->cb * std::max(1, s->nslots) * std::max(1, s->nproj) * sizeof(double2);
   const size_t dbytes = (size_t)s->cb * std::max(1, s->natoms) * std::max(1, s->nproj) * sizeof(double2);
   ks_status st = dalloc(s, &s->partial, pbytes);
   if (st != KS_OK) return st;
@@ -315,9 +315,9 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
     ks_system_destroy(s);
     return KS_EDEVICE;
   }
-  std::vector<int> zero_tiles(s->ntiles + 1, 0), zero_pen(s->npl + 1, 0), zero1(1, 0);
-  if ((st = upload(s, &s->d_tile_off, zero_tiles)) != KS_OK || (st = upload(s, &s->d_pen_off, zero_pen)) != KS_OK ||
-      (st = upload(s, &s->d_atom_off, zero1)) != KS_OK) {
+  std::vector<int> zero_tiles(s->ntiles + 1, 0), zero1(1, 0);
+  if ((st = upload(s, &s->d_slot_off, zero_tiles)) != KS_OK ||
+      (st = upload(s, &s->d_up_off, zero_tiles)) != KS_OK || (st = upload(s, &s->d_atom_slot_off, zero1)) != KS_OK) {
     g_create_err = s->err;
     ks_system_destroy(s);
     return st;
@@ -338,8 +338,9 @@ void ks_system_destroy(ks_system* s) {
   timing_free(s);
   free_workspace(s);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
-                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_ch_pencil, s->d_ch_atom, s->d_ch_r0, s->d_ch_len,
-                  s->d_ch_boff, s->d_tile_off, s->d_pen_off, s->d_atom_off, s->d_atom_list, s->d_beta,
+                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
+                  s->d_atom_slot_off, s->d_atom_slots,
+                  s->d_up_off, s->d_up_lds, s->d_up_ent, s->d_ent_slot, s->d_ent_brow, s->d_beta,
                   s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info};
   for (void* p : ptrs) dfree(p);
   delete s;
@@ -371,6 +372,8 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (natoms < 0) return fail(s, KS_EINVAL, "natoms < 0");
   if (natoms > 0 && (nproj < 1 || !npts || !d)) return fail(s, KS_EINVAL, "nproj < 1 or null npts/d");
+  if (nproj > KB_MAX_NPROJ)
+    return fail(s, KS_EUNSUPPORTED, "more than " + std::to_string(KB_MAX_NPROJ) + " projectors per atom");
   KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
   long long total = 0;
   for (int I = 0; I < natoms; ++I) {
@@ -378,8 +381,10 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
     total += npts[I];
   }
   if (total > 0 && (!idx || !beta)) return fail(s, KS_EINVAL, "idx or beta is null");
-  if (total > (1LL << 31) - 1) return fail(s, KS_EINVAL, "too many projector points");
-  struct Pt { int p, atom, j0, row; };
+  if (total > (1LL << 30)) return fail(s, KS_EINVAL, "too many projector points");
+  const int np = std::max(1, nproj);
+  const int NB = s->xnb, W = s->n[0] + 1;
+  struct Pt { int tile, p, atom, j0, row; };
   std::vector<Pt> pts;
   pts.reserve(total);
   long long off = 0;
@@ -387,64 +392,106 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
     for (int j = 0; j < npts[I]; ++j, ++off) {
       const long long f = idx[off];
       if (f < 0 || f >= s->N) return fail(s, KS_EINVAL, "projector index outside the grid");
-      pts.push_back(Pt{(int)(f % s->npl), I, (int)(f / s->npl), (int)off});
+      const int p = (int)(f % s->npl);
+      pts.push_back(Pt{p / NB, p, I, (int)(f / s->npl), (int)off});
     }
   }
+  // projection side: order (tile, atom, pencil, j0); runs of consecutive j0
   std::stable_sort(pts.begin(), pts.end(), [](const Pt& a, const Pt& b) {
-    if (a.p != b.p) return a.p < b.p;
+    if (a.tile != b.tile) return a.tile < b.tile;
     if (a.atom != b.atom) return a.atom < b.atom;
+    if (a.p != b.p) return a.p < b.p;
     return a.j0 < b.j0;
   });
-  const int np = std::max(1, nproj);
-  std::vector<int> ch_pencil, ch_atom, ch_r0, ch_len, ch_boff;
-  std::vector<double> bch((size_t)total * np);
+  const int nt = s->ntiles;
+  std::vector<double> brows((size_t)total * np);
+  std::vector<int> pt_lds(total);
+  std::vector<int> slot_off(nt + 1, 0), slot_atom, slot_pt;
+  int nruns = 0;
   for (size_t k = 0; k < pts.size(); ++k) {
     const Pt& q = pts[k];
-    const bool extend = k > 0 && q.p == pts[k - 1].p && q.atom == pts[k - 1].atom && q.j0 == pts[k - 1].j0 + 1;
-    if (extend) {
-      ch_len.back() += 1;
-    } else {
-      ch_pencil.push_back(q.p);
-      ch_atom.push_back(q.atom);
-      ch_r0.push_back(q.j0);
-      ch_len.push_back(1);
-      ch_boff.push_back((int)k);
+    const bool new_slot = k == 0 || q.tile != pts[k - 1].tile || q.atom != pts[k - 1].atom;
+    const bool extend = !new_slot && q.p == pts[k - 1].p && q.j0 == pts[k - 1].j0 + 1;
+    if (new_slot) {
+      slot_atom.push_back(q.atom);
+      slot_pt.push_back((int)k);
+      slot_off[q.tile + 1]++;
     }
-    for (int c = 0; c < np; ++c) bch[k * np + c] = beta[(size_t)q.row * np + c];
+    if (!extend) ++nruns;
+    pt_lds[k] = (q.p - q.tile * NB) * W + q.j0;
+    for (int c = 0; c < np; ++c) brows[k * np + c] = beta[(size_t)q.row * np + c];
   }
-  const int nch = (int)ch_pencil.size();
-  std::vector<int> tile_off(s->ntiles + 1), pen_off(s->npl + 1), atom_off(natoms + 1, 0), atom_list(nch);
+  const int nslots = (int)slot_atom.size();
+  slot_pt.push_back((int)total);
+  for (int t = 0; t < nt; ++t) {
+    slot_off[t + 1] += slot_off[t];
+    if ((slot_off[t + 1] - slot_off[t]) * np > KB_TILE_DP)
+      return fail(s, KS_EUNSUPPORTED, "too many atoms touch one x-tile (" +
+                                          std::to_string(slot_off[t + 1] - slot_off[t]) + " x " +
+                                          std::to_string(np) + " projectors > " + std::to_string(KB_TILE_DP) + ")");
+  }
+  std::vector<int> atom_slot_off(natoms + 1, 0), atom_slots(nslots);
+  for (int k = 0; k < nslots; ++k) atom_slot_off[slot_atom[k] + 1]++;
+  for (int I = 0; I < natoms; ++I) atom_slot_off[I + 1] += atom_slot_off[I];
   {
-    int c = 0;
-    for (int t = 0; t <= s->ntiles; ++t) {
-      while (c < nch && ch_pencil[c] < t * s->xnb) ++c;
-      tile_off[t] = c;
-    }
-    tile_off[s->ntiles] = nch;
-    c = 0;
-    for (int p = 0; p <= s->npl; ++p) {
-      while (c < nch && ch_pencil[c] < p) ++c;
-      pen_off[p] = c;
-    }
-    for (int k = 0; k < nch; ++k) atom_off[ch_atom[k] + 1]++;
-    for (int I = 0; I < natoms; ++I) atom_off[I + 1] += atom_off[I];
-    std::vector<int> fill(atom_off.begin(), atom_off.end() - 1);
-    for (int k = 0; k < nch; ++k) atom_list[fill[ch_atom[k]]++] = k;
+    std::vector<int> fill(atom_slot_off.begin(), atom_slot_off.end() - 1);
+    for (int k = 0; k < nslots; ++k) atom_slots[fill[slot_atom[k]]++] = k;
   }
+  // scatter side: order (tile, pencil, j0, atom); one entry per (point, atom)
+  std::vector<int> slot_of;   // per pts (projection order): tile-local slot index
+  slot_of.resize(pts.size());
+  {
+    int t_prev = -1, local = -1;
+    for (size_t k = 0; k < pts.size(); ++k) {
+      const bool new_slot = k == 0 || pts[k].tile != pts[k - 1].tile || pts[k].atom != pts[k - 1].atom;
+      if (pts[k].tile != t_prev) { local = -1; t_prev = pts[k].tile; }
+      if (new_slot) ++local;
+      slot_of[k] = local;
+    }
+  }
+  std::vector<int> order(pts.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const Pt& x = pts[a];
+    const Pt& y = pts[b];
+    if (x.tile != y.tile) return x.tile < y.tile;
+    if (x.p != y.p) return x.p < y.p;
+    if (x.j0 != y.j0) return x.j0 < y.j0;
+    return x.atom < y.atom;
+  });
+  std::vector<int> up_off(nt + 1, 0), up_lds, up_ent, ent_slot, ent_brow;
+  for (size_t i = 0; i < order.size(); ++i) {
+    const Pt& q = pts[order[i]];
+    const bool new_pt = i == 0 || q.tile != pts[order[i - 1]].tile || q.p != pts[order[i - 1]].p ||
+                        q.j0 != pts[order[i - 1]].j0;
+    if (new_pt) {
+      up_lds.push_back((q.p - q.tile * NB) * W + q.j0);
+      up_ent.push_back((int)ent_slot.size());
+      up_off[q.tile + 1]++;
+    }
+    ent_slot.push_back(slot_of[order[i]]);
+    ent_brow.push_back(order[i]);
+  }
+  up_ent.push_back((int)ent_slot.size());
+  for (int t = 0; t < nt; ++t) up_off[t + 1] += up_off[t];
   std::vector<double> kb((size_t)natoms * np);
   for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
   ks_status st;
-  if ((st = upload(s, &s->d_ch_pencil, ch_pencil)) != KS_OK || (st = upload(s, &s->d_ch_atom, ch_atom)) != KS_OK ||
-      (st = upload(s, &s->d_ch_r0, ch_r0)) != KS_OK || (st = upload(s, &s->d_ch_len, ch_len)) != KS_OK ||
-      (st = upload(s, &s->d_ch_boff, ch_boff)) != KS_OK || (st = upload(s, &s->d_beta, bch)) != KS_OK ||
-      (st = upload(s, &s->d_tile_off, tile_off)) != KS_OK || (st = upload(s, &s->d_pen_off, pen_off)) != KS_OK ||
-      (st = upload(s, &s->d_atom_off, atom_off)) != KS_OK || (st = upload(s, &s->d_atom_list, atom_list)) != KS_OK ||
-      (st = upload(s, &s->d_kb, kb)) != KS_OK)
+  if ((st = upload(s, &s->d_pt_lds, pt_lds)) != KS_OK ||
+      (st = upload(s, &s->d_slot_off, slot_off)) != KS_OK || (st = upload(s, &s->d_slot_atom, slot_atom)) != KS_OK ||
+      (st = upload(s, &s->d_slot_pt, slot_pt)) != KS_OK ||
+      (st = upload(s, &s->d_atom_slot_off, atom_slot_off)) != KS_OK ||
+      (st = upload(s, &s->d_atom_slots, atom_slots)) != KS_OK || (st = upload(s, &s->d_up_off, up_off)) != KS_OK ||
+      (st = upload(s, &s->d_up_lds, up_lds)) != KS_OK || (st = upload(s, &s->d_up_ent, up_ent)) != KS_OK ||
+      (st = upload(s, &s->d_ent_slot, ent_slot)) != KS_OK || (st = upload(s, &s->d_ent_brow, ent_brow)) != KS_OK ||
+      (st = upload(s, &s->d_beta, brows)) != KS_OK || (st = upload(s, &s->d_kb, kb)) != KS_OK)
     return st;
-  s->natoms = (natoms > 0 && nch > 0) ? natoms : 0;
+  s->natoms = (natoms > 0 && total > 0) ? natoms : 0;
   s->nproj = np;
-  s->nchords = nch;
+  s->nslots = nslots;
+  s->nruns = nruns;
   s->npoints = (int)total;
+  s->nuniq = (int)up_lds.size();
   return alloc_proj_workspace(s);
 }
 
@@ -578,7 +625,8 @@ ks_status ks_system_info(const ks_system* s, ks_info* info) {
   info->chunk = s->cb;
   info->natoms = s->natoms;
   info->nproj = s->nproj;
-  info->nchords = s->nchords;
+  info->nruns = s->nruns;
+  info->nslots = s->nslots;
   info->npoints = s->npoints;
   info->x_tile = s->xnb;
   info->precision = s->prec;

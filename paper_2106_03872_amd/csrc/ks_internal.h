@@ -21,22 +21,32 @@ struct SphereTab {
   int n0, n1, n2;
 };
 
-// Kleinman-Bylander projector points regrouped into runs ("chords") of
-// consecutive j0 along x-pencils (fixed j1, j2).
-struct ChordTab {
-  const int* ch_pencil;    // [nchords] pencil index j1*n2+j2
-  const int* ch_atom;      // [nchords]
-  const int* ch_r0;        // [nchords] first j0 of the run
-  const int* ch_len;       // [nchords]
-  const int* ch_boff;      // [nchords] first row of the run in beta
-  const double* beta;      // [npoints][nproj] reordered projector values
-  const int* tile_off;     // [ntiles+1] chord range of each x-tile
-  const int* pen_off;      // [npencils+1] chord range of each pencil
-  const int* atom_off;     // [natoms+1]
-  const int* atom_list;    // chords of each atom, ascending
-  const double* d;         // [natoms][nproj]
-  int nchords, natoms, nproj;
+// Kleinman-Bylander projector tables, grouped per x-tile (NB consecutive
+// x-pencils p = j1*n2 + j2).  Positions are LDS offsets w*(n0+1) + j0 in the
+// tile's pencil buffer (w = p - tile*NB).
+//  - slot:  one (tile, atom) pair; the points of a slot are contiguous rows
+//           of beta, ordered (tile, atom, pencil, j0)
+//  - unique point: one grid point of the tile touched by any sphere, with its
+//           list of (slot, beta row) entries ordered by atom (scatter side)
+struct ProjTab {
+  const int* pt_lds;         // [npoints] LDS offset of each beta row's point
+  const int* slot_off;       // [ntiles+1] slot range of each tile
+  const int* slot_atom;      // [nslots]
+  const int* slot_pt;        // [nslots+1] beta-row range of each slot
+  const int* atom_slot_off;  // [natoms+1]
+  const int* atom_slots;     // slots of each atom, ascending
+  const int* up_off;         // [ntiles+1]
+  const int* up_lds;         // [nunique]
+  const int* up_ent;         // [nunique+1]
+  const int* ent_slot;       // [nentries] slot index local to the tile
+  const int* ent_brow;       // [nentries]
+  const double* beta;        // [npoints][nproj]
+  const double* d;           // [natoms][nproj]
+  int natoms, nproj, nslots;
 };
+
+constexpr int KB_MAX_NPROJ = 8;        // projectors per atom
+constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-tile
 
 enum HMode { H_OUT = 0, H_TAYLOR = 1 };
 
@@ -73,11 +83,11 @@ struct ks_system {
   bool have_v = false;
 
   // projectors
-  int natoms = 0, nproj = 0, nchords = 0, npoints = 0;
+  int natoms = 0, nproj = 0, nslots = 0, nruns = 0, npoints = 0, nuniq = 0;
   int xnb = 32, ntiles = 0;
-  int *d_ch_pencil = nullptr, *d_ch_atom = nullptr, *d_ch_r0 = nullptr, *d_ch_len = nullptr,
-      *d_ch_boff = nullptr, *d_tile_off = nullptr, *d_pen_off = nullptr, *d_atom_off = nullptr,
-      *d_atom_list = nullptr;
+  int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
+      *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_lds = nullptr,
+      *d_up_ent = nullptr, *d_ent_slot = nullptr, *d_ent_brow = nullptr;
   double *d_beta = nullptr, *d_kb = nullptr;
 
   // workspace (one chunk of cb orbitals)
@@ -85,7 +95,7 @@ struct ks_system {
   void* pk[3] = {nullptr, nullptr, nullptr};  // packed chunk buffers
   void* T = nullptr;                          // [cb][nplanes][n1*n2]
   void* U = nullptr;
-  void* partial = nullptr;                    // [cb][nchords][nproj]
+  void* partial = nullptr;                    // [cb][nslots][nproj]
   double2* DP = nullptr;                      // [cb][natoms][nproj]
   double* red = nullptr;                      // [2*max_norb]
   size_t partial_cap = 0, dp_cap = 0;

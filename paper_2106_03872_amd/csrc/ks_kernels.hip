@@ -36,7 +36,7 @@ bool supported_size(int n) {
 // pencils per x-tile
 int x_tile_nb(int n0) { return n0 <= 32 ? 64 : 32; }
 template <int N> struct xnb { static constexpr int value = N <= 32 ? 64 : 32; };
-constexpr int PNB = 32;  // transforms per batch in the plane passes
+constexpr int NTP = 384; // threads per plane-pass block
 
 template <typename T> __device__ __forceinline__ T czero() { return T{0, 0}; }
 
@@ -105,60 +105,18 @@ __global__ __launch_bounds__(NT) void unpack_kernel(const T* __restrict__ pk, in
 }
 
 // ----------------------------------------------------------- plane synthesis
-// Block (plane pi, orbital o).  LDS: twiddles [N] | Z [ncol][N+1] | Y [PNB][N+1].
+// Block (plane pi, orbital o).  LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1].
+// z-synthesis of each disk column straight from the packed coefficients into
+// Z; y-synthesis of YB r2-columns at a time straight from Z into T.
+
+template <int N> struct pnb { static constexpr int value = N <= 64 ? 64 : (N <= 96 ? 48 : (N <= 120 ? 24 : 16)); };
 
 template <int N, typename R>
-__global__ __launch_bounds__(NT) void plane_inv_kernel(const cplx<R>* __restrict__ pk, int pk_stride,
-                                                       cplx<R>* __restrict__ Tout, SphereTab tab,
-                                                       const cplx<R>* __restrict__ twN, int ncol_max) {
+__global__ __launch_bounds__(NTP) void plane_inv_kernel(const cplx<R>* __restrict__ pk, int pk_stride,
+                                                        cplx<R>* __restrict__ Tout, SphereTab tab,
+                                                        const cplx<R>* __restrict__ twN, int ncol_max) {
   using C = cplx<R>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* tw = reinterpret_cast<C*>(smem_raw);
-  C* Z = tw + N;
-  C* Y = Z + ncol_max * (N + 1);
-  const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
-  const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
-  const int m1lo = tab.plane_m1lo[pi];
-  for (int i = tid; i < N; i += NT) tw[i] = twN[i];
-  const C* in = pk + (long long)o * pk_stride;
-  for (int i = tid; i < nc * N; i += NT) {
-    const int c = i / N, j2 = i - c * N;
-    const int off = tab.col_off[c0 + c], len = tab.col_off[c0 + c + 1] - off;
-    const int t = fold(j2, N) - tab.col_m2lo[c0 + c];
-    Z[c * (N + 1) + j2] = (t >= 0 && t < len) ? in[off + t] : czero<C>();
-  }
-  __syncthreads();
-  for (int cb = 0; cb < nc; cb += PNB) fft_batch<N, +1, PNB, NT>(Z + cb * (N + 1), N + 1, nc - cb, tw);
-  C* out = Tout + ((long long)o * tab.nplanes + pi) * N * N;
-  for (int w0 = 0; w0 < N; w0 += PNB) {
-    for (int i = tid; i < PNB * N; i += NT) {
-      const int w = i % PNB, j1 = i / PNB;
-      const int c = fold(j1, N) - m1lo;
-      Y[w * (N + 1) + j1] = (c >= 0 && c < nc && w0 + w < N) ? Z[c * (N + 1) + w0 + w] : czero<C>();
-    }
-    __syncthreads();
-    fft_batch<N, +1, PNB, NT>(Y, N + 1, N - w0, tw);
-    for (int i = tid; i < PNB * N; i += NT) {
-      const int w = i % PNB, r1 = i / PNB;
-      if (w0 + w < N) out[r1 * N + w0 + w] = Y[w * (N + 1) + r1];
-    }
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------------ plane analysis
-// Block (plane pi, orbital o): y-analysis of U's plane, keep the disk columns,
-// z-analysis of each column, keep its m2 run, then the kinetic term and the
-// output mode.
-
-template <int N, typename R>
-__global__ __launch_bounds__(NT) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin,
-                                                       const cplx<R>* win,
-                                                       cplx<R>* __restrict__ wout, double2* acc,
-                                                       int pk_stride, int acc_stride, SphereTab tab,
-                                                       const cplx<R>* __restrict__ twN, int ncol_max, int mode,
-                                                       Taylor tay, double g0, double g1, double g2) {
-  using C = cplx<R>;
+  constexpr int YB = pnb<N>::value;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* tw = reinterpret_cast<C*>(smem_raw);
   C* Z = tw + N;
@@ -168,155 +126,221 @@ __global__ __launch_bounds__(NT) void plane_fwd_kernel(const cplx<R>* __restrict
   const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
   const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
   const int m1lo = tab.plane_m1lo[pi];
-  for (int i = tid; i < N; i += NT) tw[i] = twN[i];
-  for (int i = tid; i <= nc; i += NT) s_off[i] = tab.col_off[c0 + i];
-  for (int i = tid; i < nc; i += NT) s_m2lo[i] = tab.col_m2lo[c0 + i];
-  const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
-  for (int w0 = 0; w0 < N; w0 += PNB) {
-    for (int i = tid; i < PNB * N; i += NT) {
-      const int w = i % PNB, r1 = i / PNB;
-      Y[w * (N + 1) + r1] = (w0 + w < N) ? u[r1 * N + w0 + w] : czero<C>();
-    }
-    __syncthreads();
-    fft_batch<N, -1, PNB, NT>(Y, N + 1, N - w0, tw);
-    for (int i = tid; i < PNB * nc; i += NT) {
-      const int w = i % PNB, c = i / PNB;
-      if (w0 + w < N) Z[c * (N + 1) + w0 + w] = Y[w * (N + 1) + wrap(m1lo + c, N)];
-    }
+  for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
+  for (int i = tid; i <= nc; i += NTP) s_off[i] = tab.col_off[c0 + i];
+  for (int i = tid; i < nc; i += NTP) s_m2lo[i] = tab.col_m2lo[c0 + i];
+  __syncthreads();
+  const C* in = pk + (long long)o * pk_stride;
+  for (int cb = 0; cb < nc; cb += YB) {
+    fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
+        Z + cb * (N + 1), N + 1, nc - cb, tw,
+        [&](int t, int e) -> C {
+          const int c = cb + t;
+          const int idx = fold(e, N) - s_m2lo[c];
+          return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? in[s_off[c] + idx] : czero<C>();
+        },
+        no_store{});
+  }
+  C* out = Tout + ((long long)o * tab.nplanes + pi) * N * N;
+  for (int w0 = 0; w0 < N; w0 += YB) {
+    fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(
+        Y, N + 1, N - w0, tw,
+        [&](int t, int e) -> C {
+          const int c = fold(e, N) - m1lo;
+          return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
+        },
+        [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; });
     __syncthreads();
   }
-  for (int cb = 0; cb < nc; cb += PNB) fft_batch<N, -1, PNB, NT>(Z + cb * (N + 1), N + 1, nc - cb, tw);
-  // epilogue over the packed elements of this plane
-  const int m0 = tab.m0lo + pi;
-  const double k0 = g0 * m0;
+}
+
+// ------------------------------------------------------------ plane analysis
+// Block (plane pi, orbital o): y-analysis of YB r2-columns of U at a time,
+// keeping the disk columns in Z; z-analysis of each column with the kinetic
+// term and the output mode applied to the outputs inside the sphere.
+
+template <int N, typename R>
+__global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, const cplx<R>* win,
+                                                        cplx<R>* __restrict__ wout, double2* acc, int pk_stride,
+                                                        int acc_stride, SphereTab tab,
+                                                        const cplx<R>* __restrict__ twN, int ncol_max, int mode,
+                                                        Taylor tay, double g0, double g1, double g2) {
+  using C = cplx<R>;
+  constexpr int YB = pnb<N>::value;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  C* Z = tw + N;
+  C* Y = Z + ncol_max * (N + 1);
+  __shared__ int s_off[130];
+  __shared__ int s_m2lo[129];
+  const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
+  const int m1lo = tab.plane_m1lo[pi];
+  for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
+  for (int i = tid; i <= nc; i += NTP) s_off[i] = tab.col_off[c0 + i];
+  for (int i = tid; i < nc; i += NTP) s_m2lo[i] = tab.col_m2lo[c0 + i];
+  __syncthreads();
+  const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
+  for (int w0 = 0; w0 < N; w0 += YB) {
+    fft_io<N, -1, YB, NTP, SRC_FN, DST_FN, C>(
+        Y, N + 1, N - w0, tw, [&](int t, int e) -> C { return u[e * N + w0 + t]; },
+        [&](int t, int e, C v, int, int) {
+          const int c = fold(e, N) - m1lo;
+          if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
+        });
+    __syncthreads();
+  }
+  const double k0 = g0 * (tab.m0lo + pi);
   const long long ob = (long long)o * pk_stride;
-  for (int e = s_off[0] + tid; e < s_off[nc]; e += NT) {
-    const int c = find_col(s_off, nc, e);
-    const int m1 = m1lo + c, m2 = s_m2lo[c] + (e - s_off[c]);
-    const double k1 = g1 * m1, k2 = g2 * m2;
-    const double K = 0.5 * (k0 * k0 + k1 * k1 + k2 * k2);
-    const C ph = Z[c * (N + 1) + wrap(m2, N)];
-    const C w = win[ob + e];
-    const double2 hw{K * double(w.x) + double(ph.x), K * double(w.y) + double(ph.y)};
-    if (mode == H_OUT) {
-      wout[ob + e] = to_c<C>(hw);
-    } else {
-      if (tay.write_w) wout[ob + e] = to_c<C>(hw);
-      double2* a = acc + (long long)o * acc_stride + e;
-      double2 av = *a;
-      av.x += tay.coef.x * hw.x - tay.coef.y * hw.y;
-      av.y += tay.coef.x * hw.y + tay.coef.y * hw.x;
-      *a = av;
-    }
+  double2* accp = acc ? acc + (long long)o * acc_stride : nullptr;
+  for (int cb = 0; cb < nc; cb += YB) {
+    fft_io<N, -1, YB, NTP, SRC_LDS, DST_FN, C>(
+        Z + cb * (N + 1), N + 1, nc - cb, tw, no_load{}, [&](int t, int e, C ph, int, int) {
+          const int c = cb + t;
+          const int m2 = fold(e, N);
+          const int idx = m2 - s_m2lo[c];
+          if (idx < 0 || idx >= s_off[c + 1] - s_off[c]) return;
+          const int ep = s_off[c] + idx;
+          const double k1 = g1 * (m1lo + c), k2 = g2 * m2;
+          const double K = 0.5 * (k0 * k0 + k1 * k1 + k2 * k2);
+          const C w = win[ob + ep];
+          const double2 hw{K * double(w.x) + double(ph.x), K * double(w.y) + double(ph.y)};
+          if (mode == H_OUT) {
+            wout[ob + ep] = to_c<C>(hw);
+          } else {
+            if (tay.write_w) wout[ob + ep] = to_c<C>(hw);
+            double2 av = accp[ep];
+            av.x += tay.coef.x * hw.x - tay.coef.y * hw.y;
+            av.y += tay.coef.x * hw.y + tay.coef.y * hw.x;
+            accp[ep] = av;
+          }
+        });
   }
 }
 
 // -------------------------------------------------------------- x-pencil passes
-// Block (tile of NB consecutive pencils p = j1*n2 + j2, orbital o).
-// LDS: twiddles [N0] | X [NB][N0+1], X[w][j0].
+// Block (tile of NB consecutive pencils p = j1*n2 + j2, orbital o).  The
+// x-synthesis reads T (planes m0 of each pencil) straight into its first
+// stage; LDS X[w][j0] holds one exchange buffer of the tile.
 
 template <int N0, int NB, typename C>
-__device__ __forceinline__ void x_load(C* X, const C* __restrict__ Tin, long long plane_stride, int nplanes,
-                                       int m0lo, int p0, int npencils) {
-  const int tid = threadIdx.x;
-  for (int i = tid; i < nplanes * NB; i += NT) {
-    const int w = i % NB, pi = i / NB;
-    const int p = p0 + w;
-    X[w * (N0 + 1) + wrap(m0lo + pi, N0)] = (p < npencils) ? Tin[pi * plane_stride + p] : czero<C>();
+struct TLoader {
+  const C* Tin;
+  int npl, nplanes, m0lo, p0;
+  __device__ C operator()(int t, int e) const {
+    const int pi = fold(e, N0) - m0lo;
+    const int p = p0 + t;
+    return (pi >= 0 && pi < nplanes && p < npl) ? Tin[(long long)pi * npl + p] : czero<C>();
   }
-  for (int i = tid; i < (N0 - nplanes) * NB; i += NT) {
-    const int w = i % NB, jj = i / NB;
-    int j0 = m0lo + nplanes + jj;
-    j0 = ((j0 % N0) + N0) % N0;
-    X[w * (N0 + 1) + j0] = czero<C>();
-  }
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
 }
 
 template <int N0, typename R>
 __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ partial,
-                                                   SphereTab tab, ChordTab ct, const cplx<R>* __restrict__ tw0,
+                                                   SphereTab tab, ProjTab pt, const cplx<R>* __restrict__ tw0,
                                                    double scale) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
-  __shared__ C tw[N0];
   __shared__ C X[NB * (N0 + 1)];
   const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
   const int npl = tab.n1 * tab.n2;
-  const int p0 = tile * NB;
-  const int chA = ct.tile_off[tile], chB = ct.tile_off[tile + 1];
-  if (chA == chB) return;  // no sphere point in this tile (uniform per block)
-  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
-  x_load<N0, NB>(X, Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0, npl);
-  __syncthreads();
-  fft_batch<N0, +1, NB, NT>(X, N0 + 1, NB, tw);
-  const int np = ct.nproj;
-  for (int i = tid; i < (chB - chA) * np; i += NT) {
-    const int ch = chA + i / np, q = i % np;
-    const int w = ct.ch_pencil[ch] - p0, r0 = ct.ch_r0[ch], len = ct.ch_len[ch], bo = ct.ch_boff[ch];
-    double sx = 0.0, sy = 0.0;
-    for (int l = 0; l < len; ++l) {
-      const double b = ct.beta[(long long)(bo + l) * np + q];
-      const C x = X[w * (N0 + 1) + r0 + l];
-      sx += b * double(x.x);
-      sy += b * double(x.y);
+  const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
+  if (ns == 0) return;  // no sphere point in this tile (uniform per block)
+  const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, tile * NB};
+  fft_io<N0, +1, NB, NT, SRC_FN, DST_LDS, C>(X, N0 + 1, NB, tw0, ld, no_store{});
+  const int np = pt.nproj;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int sl = wave; sl < ns; sl += NT / 64) {
+    const int k0 = pt.slot_pt[sA + sl], k1 = pt.slot_pt[sA + sl + 1];
+    double ax[KB_MAX_NPROJ], ay[KB_MAX_NPROJ];
+#pragma unroll
+    for (int q = 0; q < KB_MAX_NPROJ; ++q) ax[q] = ay[q] = 0.0;
+    for (int base = k0; base < k1; base += 64) {
+      const int k = base + lane;
+      C x = czero<C>();
+      if (k < k1) x = X[pt.pt_lds[k]];
+      const double* b = pt.beta + (long long)k * np;
+#pragma unroll
+      for (int q = 0; q < KB_MAX_NPROJ; ++q) {
+        if (q < np) {
+          const double bv = k < k1 ? b[q] : 0.0;
+          ax[q] += wave_sum(bv * double(x.x));
+          ay[q] += wave_sum(bv * double(x.y));
+        }
+      }
     }
-    partial[((long long)o * ct.nchords + ch) * np + q] = C{R(sx * scale), R(sy * scale)};
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < KB_MAX_NPROJ; ++q)
+        if (q < np) partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(ax[q] * scale), R(ay[q] * scale)};
+    }
   }
 }
 
 template <int N0, typename R>
 __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ Uout,
                                                     const double* __restrict__ V, const double2* __restrict__ DP,
-                                                    SphereTab tab, ChordTab ct, const cplx<R>* __restrict__ tw0,
+                                                    SphereTab tab, ProjTab pt, const cplx<R>* __restrict__ tw0,
                                                     double sc_in, double sc_out) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
-  __shared__ C tw[N0];
+  using LS = last_shape<N0, NB, NT>;
   __shared__ C X[NB * (N0 + 1)];
+  __shared__ double2 dps[KB_TILE_DP];
   const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
-  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
-  x_load<N0, NB>(X, Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0, npl);
-  __syncthreads();
-  fft_batch<N0, +1, NB, NT>(X, N0 + 1, NB, tw);
-  const int np = ct.nproj;
-  for (int i = tid; i < N0 * NB; i += NT) {
-    const int w = i % NB, r0 = i / NB;
-    const int p = p0 + w;
-    if (p >= npl) continue;
-    const C x = X[w * (N0 + 1) + r0];
-    const double v = V[(long long)r0 * npl + p] * sc_in;
-    double fx = v * double(x.x), fy = v * double(x.y);
-    if (ct.natoms > 0) {
-      const int cA = ct.pen_off[p], cB = ct.pen_off[p + 1];
-      for (int ch = cA; ch < cB; ++ch) {
-        const int t = r0 - ct.ch_r0[ch];
-        if (t < 0 || t >= ct.ch_len[ch]) continue;
-        const double* b = ct.beta + (long long)(ct.ch_boff[ch] + t) * np;
-        const double2* dp = DP + ((long long)o * ct.natoms + ct.ch_atom[ch]) * np;
+  // potential at the outputs of this thread's last synthesis stage (times Omega^-1/2)
+  double vr[LS::items][LS::radix];
+  last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+    vr[it][q] = (p0 + t < npl) ? V[(long long)e * npl + p0 + t] * sc_in : 0.0;
+  });
+  const int np = pt.nproj;
+  const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
+  for (int i = tid; i < ns * np; i += NT) {
+    const int sl = i / np, q = i - sl * np;
+    dps[i] = DP[((long long)o * pt.natoms + pt.slot_atom[sA + sl]) * np + q];
+  }
+  const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
+  // synthesis, then psi <- V psi as the outputs are written
+  fft_io<N0, +1, NB, NT, SRC_FN, DST_FN_LDS, C>(X, N0 + 1, NB, tw0, ld, [&](int t, int e, C v, int it, int q) {
+    X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
+  });
+  if (ns > 0) {
+    const int uA = pt.up_off[tile], uB = pt.up_off[tile + 1];
+    for (int u = uA + tid; u < uB; u += NT) {
+      double fx = 0.0, fy = 0.0;
+      for (int e = pt.up_ent[u]; e < pt.up_ent[u + 1]; ++e) {
+        const double* b = pt.beta + (long long)pt.ent_brow[e] * np;
+        const double2* dp = dps + pt.ent_slot[e] * np;
         for (int q = 0; q < np; ++q) {
           fx += b[q] * dp[q].x;
           fy += b[q] * dp[q].y;
         }
       }
+      C& x = X[pt.up_lds[u]];
+      x = C{R(double(x.x) + fx), R(double(x.y) + fy)};
     }
-    X[w * (N0 + 1) + r0] = C{R(fx), R(fy)};
+    __syncthreads();
   }
-  __syncthreads();
-  fft_batch<N0, -1, NB, NT>(X, N0 + 1, NB, tw);
   C* out = Uout + (long long)o * tab.nplanes * npl;
-  for (int i = tid; i < tab.nplanes * NB; i += NT) {
-    const int w = i % NB, pi = i / NB;
-    const int p = p0 + w;
-    if (p < npl) {
-      const C x = X[w * (N0 + 1) + wrap(tab.m0lo + pi, N0)];
-      out[(long long)pi * npl + p] = C{R(double(x.x) * sc_out), R(double(x.y) * sc_out)};
-    }
-  }
+  const int nplanes = tab.nplanes, m0lo = tab.m0lo;
+  fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw0, no_load{}, [&](int t, int e, C v, int, int) {
+    const int pi = fold(e, N0) - m0lo;
+    const int p = p0 + t;
+    if (pi >= 0 && pi < nplanes && p < npl)
+      out[(long long)pi * npl + p] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
+  });
 }
 
-// density: block = tile, loops over the nb orbitals of the chunk in order
+// density: block = tile, loops over the nb orbitals of the chunk in order;
+// |psi|^2 is accumulated straight from the last synthesis stage.
 template <int N0, typename R>
 __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    const double* __restrict__ occ, double* __restrict__ rho,
@@ -324,65 +348,62 @@ __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ T
                                                    double inv_omega) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
-  constexpr int IT = (N0 * NB + NT - 1) / NT;
-  __shared__ C tw[N0];
+  using LS = last_shape<N0, NB, NT>;
   __shared__ C X[NB * (N0 + 1)];
-  const int tile = blockIdx.x, tid = threadIdx.x;
+  const int tile = blockIdx.x;
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
-  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
-  double a[IT];
+  double a[LS::items][LS::radix];
 #pragma unroll
-  for (int k = 0; k < IT; ++k) a[k] = 0.0;
+  for (int it = 0; it < LS::items; ++it)
+#pragma unroll
+    for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
   for (int o = 0; o < nb; ++o) {
-    x_load<N0, NB>(X, Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0, npl);
-    __syncthreads();
-    fft_batch<N0, +1, NB, NT>(X, N0 + 1, NB, tw);
+    const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
     const double f = occ[o] * inv_omega;
-#pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int i = tid + k * NT;
-      if (i < N0 * NB) {
-        const int w = i % NB, r0 = i / NB;
-        const C x = X[w * (N0 + 1) + r0];
-        a[k] += f * (double(x.x) * double(x.x) + double(x.y) * double(x.y));
-      }
-    }
+    fft_io<N0, +1, NB, NT, SRC_FN, DST_FN, C>(X, N0 + 1, NB, tw0, ld, [&](int, int, C v, int it, int q) {
+      a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
+    });
     __syncthreads();
   }
-#pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int i = tid + k * NT;
-    if (i < N0 * NB) {
-      const int w = i % NB, r0 = i / NB;
-      const int p = p0 + w;
-      if (p < npl) {
-        double* r = rho + (long long)r0 * npl + p;
-        *r = accumulate ? *r + a[k] : a[k];
-      }
+  last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+    const int p = p0 + t;
+    if (p < npl) {
+      double* r = rho + (long long)e * npl + p;
+      *r = accumulate ? *r + a[it][q] : a[it][q];
     }
-  }
+  });
 }
 
-// KB projections: P_Ip = sum of the runs of atom I (ascending chord order),
-// DP = d_Ip P_Ip.  One thread per (orbital, atom, projector).
+// KB projections: P_Ip = sum over the (tile, atom) slots of atom I in
+// ascending order, DP = d_Ip P_Ip (Eq. vnl).  One wavefront per (atom, orbital):
+// lane = 8 * slot-lane + q; slot-lanes are combined in a fixed order.
 template <typename C>
-__global__ __launch_bounds__(NT) void proj_reduce_kernel(const C* __restrict__ partial, double2* __restrict__ DP,
-                                                         ChordTab ct, int nb) {
-  const long long i = (long long)blockIdx.x * NT + threadIdx.x;
-  const long long tot = (long long)nb * ct.natoms * ct.nproj;
-  if (i >= tot) return;
-  const int q = i % ct.nproj;
-  const int I = (i / ct.nproj) % ct.natoms;
-  const int o = i / ((long long)ct.nproj * ct.natoms);
+__global__ __launch_bounds__(64) void proj_reduce_kernel(const C* __restrict__ partial, double2* __restrict__ DP,
+                                                         ProjTab pt) {
+  __shared__ double2 red[64];
+  const int I = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
+  const int q = lane & 7, sl = lane >> 3;
+  const int np = pt.nproj;
   double sx = 0.0, sy = 0.0;
-  for (int k = ct.atom_off[I]; k < ct.atom_off[I + 1]; ++k) {
-    const C v = partial[((long long)o * ct.nchords + ct.atom_list[k]) * ct.nproj + q];
-    sx += double(v.x);
-    sy += double(v.y);
+  if (q < np) {
+    for (int k = pt.atom_slot_off[I] + sl; k < pt.atom_slot_off[I + 1]; k += 8) {
+      const C v = partial[((long long)o * pt.nslots + pt.atom_slots[k]) * np + q];
+      sx += double(v.x);
+      sy += double(v.y);
+    }
   }
-  const double dd = ct.d[I * ct.nproj + q];
-  DP[i] = double2{dd * sx, dd * sy};
+  red[lane] = double2{sx, sy};
+  __syncthreads();
+  if (lane < 8 && q < np) {
+    double tx = 0.0, ty = 0.0;
+    for (int j = 0; j < 8; ++j) {
+      tx += red[j * 8 + lane].x;
+      ty += red[j * 8 + lane].y;
+    }
+    const double dd = pt.d[I * np + q];
+    DP[((long long)o * pt.natoms + I) * np + q] = double2{dd * tx, dd * ty};
+  }
 }
 
 // per-orbital sums over the packed sphere: out[2o] = sum |a|^2, out[2o+1] = sum Re conj(a) b
@@ -443,28 +464,31 @@ static SphereTab sphere_tab(const ks_system* s) {
   return t;
 }
 
-static ChordTab chord_tab(const ks_system* s) {
-  ChordTab c;
-  c.ch_pencil = s->d_ch_pencil;
-  c.ch_atom = s->d_ch_atom;
-  c.ch_r0 = s->d_ch_r0;
-  c.ch_len = s->d_ch_len;
-  c.ch_boff = s->d_ch_boff;
+static ProjTab proj_tab(const ks_system* s) {
+  ProjTab c;
+  c.pt_lds = s->d_pt_lds;
+  c.slot_off = s->d_slot_off;
+  c.slot_atom = s->d_slot_atom;
+  c.slot_pt = s->d_slot_pt;
+  c.atom_slot_off = s->d_atom_slot_off;
+  c.atom_slots = s->d_atom_slots;
+  c.up_off = s->d_up_off;
+  c.up_lds = s->d_up_lds;
+  c.up_ent = s->d_up_ent;
+  c.ent_slot = s->d_ent_slot;
+  c.ent_brow = s->d_ent_brow;
   c.beta = s->d_beta;
-  c.tile_off = s->d_tile_off;
-  c.pen_off = s->d_pen_off;
-  c.atom_off = s->d_atom_off;
-  c.atom_list = s->d_atom_list;
   c.d = s->d_kb;
-  c.nchords = s->nchords;
   c.natoms = s->natoms;
   c.nproj = s->nproj;
+  c.nslots = s->nslots;
   return c;
 }
 
 size_t plane_lds_bytes(const ks_system* s) {
   const int N = s->n[1];
-  return sizeof(double2) * ((size_t)N + (size_t)s->ncol_max * (N + 1) + (size_t)PNB * (N + 1));
+  const int yb = N <= 64 ? 64 : (N <= 96 ? 48 : (N <= 120 ? 24 : 16));   // pnb<N>
+  return sizeof(double2) * ((size_t)N + (size_t)s->ncol_max * (N + 1) + (size_t)yb * (N + 1));
 }
 
 bool launch_pack(const ks_system* s, int nb, const double2* box, long long box_stride, void* pk, hipStream_t st) {
@@ -483,7 +507,7 @@ bool launch_unpack(const ks_system* s, int nb, const void* pk, double2* box, lon
 template <int N>
 static void plane_inv_n(const ks_system* s, int nb, const void* pk, void* T, hipStream_t st) {
   const size_t lds = plane_lds_bytes(s);
-  plane_inv_kernel<N, double><<<dim3(s->nplanes, nb), NT, lds, st>>>(
+  plane_inv_kernel<N, double><<<dim3(s->nplanes, nb), NTP, lds, st>>>(
       (const double2*)pk, s->npw_stride, (double2*)T, sphere_tab(s), s->d_tw1, s->ncol_max);
 }
 
@@ -502,7 +526,7 @@ static void plane_fwd_n(const ks_system* s, int nb, const void* U, const void* w
                         HMode mode, Taylor tay, hipStream_t st) {
   const size_t lds = plane_lds_bytes(s);
   const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
-  plane_fwd_kernel<N, double><<<dim3(s->nplanes, nb), NT, lds, st>>>(
+  plane_fwd_kernel<N, double><<<dim3(s->nplanes, nb), NTP, lds, st>>>(
       (const double2*)U, (const double2*)win, (double2*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
       sphere_tab(s), s->d_tw1, s->ncol_max, (int)mode, tay, g0, g1, g2);
 }
@@ -522,7 +546,7 @@ template <int N0>
 static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
   const double scale = s->dV / sqrt(s->omega);
   xproj_kernel<N0, double><<<dim3(s->ntiles, nb), NT, 0, st>>>((const double2*)T, (double2*)partial,
-                                                                sphere_tab(s), chord_tab(s), s->d_tw0, scale);
+                                                                sphere_tab(s), proj_tab(s), s->d_tw0, scale);
 }
 
 bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
@@ -536,10 +560,8 @@ bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipS
 }
 
 bool launch_proj_reduce(const ks_system* s, int nb, const void* partial, double2* DP, hipStream_t st) {
-  const long long tot = (long long)nb * s->natoms * s->nproj;
-  if (tot == 0) return true;
-  proj_reduce_kernel<double2><<<(unsigned)((tot + NT - 1) / NT), NT, 0, st>>>((const double2*)partial, DP,
-                                                                             chord_tab(s), nb);
+  if (s->natoms == 0 || nb == 0) return true;
+  proj_reduce_kernel<double2><<<dim3(s->natoms, nb), 64, 0, st>>>((const double2*)partial, DP, proj_tab(s));
   return true;
 }
 
@@ -548,7 +570,7 @@ static void xapply_n(const ks_system* s, int nb, const void* T, const double2* D
   const double sc_in = 1.0 / sqrt(s->omega);
   const double sc_out = sqrt(s->omega) / (double)s->N;
   xapply_kernel<N0, double><<<dim3(s->ntiles, nb), NT, 0, st>>>((const double2*)T, (double2*)U, s->d_v, DP,
-                                                                 sphere_tab(s), chord_tab(s), s->d_tw0, sc_in,
+                                                                 sphere_tab(s), proj_tab(s), s->d_tw0, sc_in,
                                                                  sc_out);
 }
 

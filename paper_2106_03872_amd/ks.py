@@ -23,8 +23,8 @@ KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "pla
 
 
 class Info(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nchords",
-                                            "npoints", "x_tile", "precision")]
+    _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nruns",
+                                            "nslots", "npoints", "x_tile", "precision")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
