@@ -159,6 +159,35 @@ int ks_system_chunk(const ks_system* sys);
 ks_status ks_system_set_chunk(ks_system* sys, int chunk);
 
 /* ------------------------------------------------------------------------
+ * Host-only planning calls (no device needed).  They expose the set-up
+ * tables so that their construction can be checked on any machine.
+ */
+
+/*
+ * The packed plane-wave sphere of grid n[3], cell L[3] and cutoff ecut (same
+ * rules as ks_system_create; ecut <= 0 = full box): *npw receives the number
+ * of plane waves; m_out (host int [npw][3], nullable) the integer frequencies
+ * (m0, m1, m2) in the library's packed order (planes m0 ascending, then m1,
+ * then a contiguous run of m2).  KS_EINVAL on bad arguments.
+ */
+ks_status ks_plan_sphere(const int n[3], const double L[3], double ecut, int* npw, int* m_out);
+
+/*
+ * The Kleinman-Bylander point tables that ks_system_set_projectors builds for
+ * grid n[3] (same arguments, host memory).  counts[4] receives (slots, unique
+ * points, entries, runs).  Optional outputs (host, nullable):
+ *   point_flat    [unique points]     flat grid index of each unique point
+ *   point_entries [unique points + 1] entry range of each unique point
+ *   entry_atom    [entries]           atom of each entry
+ *   entry_row     [entries]           input row (index into idx/beta) of each entry
+ * Call once with NULL outputs to size them.  Errors as for
+ * ks_system_set_projectors.
+ */
+ks_status ks_plan_projectors(const int n[3], int natoms, int nproj, const int* npts, const int* idx,
+                             const double* beta, int* counts, int* point_flat, int* point_entries,
+                             int* entry_atom, int* entry_row);
+
+/* ------------------------------------------------------------------------
  * Introspection and kernel timing (instrumentation; not on the hot path).
  */
 typedef struct {

@@ -119,6 +119,183 @@ double kin(const double L[3], int m0, int m1, int m2) {
   return 0.5 * (g0 * g0 + g1 * g1 + g2 * g2);
 }
 
+// Packed plane-wave sphere (row a0): planes m0, columns m1, runs of m2.
+struct SphereHost {
+  std::vector<int> plane_col0, plane_m1lo, col_off, col_m2lo;
+  int m0lo = 0, npw = 0, ncol_max = 0;
+};
+
+ks_status build_sphere(const int n[3], const double L[3], double ecut, SphereHost& h, std::string& err) {
+  int prev_m0 = 0;
+  bool any_plane = false;
+  auto mlo = [&](int a) { return -(n[a] / 2); };
+  auto mhi = [&](int a) { return (n[a] - 1) / 2; };
+  for (int m0 = mlo(0); m0 <= mhi(0); ++m0) {
+    int first_col = 0, prev_m1 = 0, ncol = 0;
+    bool have_col = false;
+    std::vector<int> coff, cm2;
+    for (int m1 = mlo(1); m1 <= mhi(1); ++m1) {
+      int lo = 1 << 30, hi = -(1 << 30), cnt = 0;
+      for (int m2 = mlo(2); m2 <= mhi(2); ++m2) {
+        if (ecut <= 0.0 || kin(L, m0, m1, m2) < ecut) {
+          lo = std::min(lo, m2);
+          hi = std::max(hi, m2);
+          ++cnt;
+        }
+      }
+      if (cnt == 0) continue;
+      if (cnt != hi - lo + 1) { err = "sphere column is not contiguous"; return KS_EUNSUPPORTED; }
+      if (have_col && m1 != prev_m1 + 1) { err = "sphere plane is not contiguous"; return KS_EUNSUPPORTED; }
+      if (!have_col) first_col = m1;
+      have_col = true;
+      prev_m1 = m1;
+      coff.push_back(h.npw);
+      cm2.push_back(lo);
+      h.npw += cnt;
+      ++ncol;
+    }
+    if (ncol == 0) continue;
+    if (any_plane && m0 != prev_m0 + 1) { err = "sphere planes are not contiguous"; return KS_EUNSUPPORTED; }
+    if (!any_plane) h.m0lo = m0;
+    any_plane = true;
+    prev_m0 = m0;
+    h.plane_col0.push_back((int)h.col_off.size());
+    h.plane_m1lo.push_back(first_col);
+    h.col_off.insert(h.col_off.end(), coff.begin(), coff.end());
+    h.col_m2lo.insert(h.col_m2lo.end(), cm2.begin(), cm2.end());
+    h.ncol_max = std::max(h.ncol_max, ncol);
+  }
+  if (!any_plane) { err = "the plane-wave sphere is empty"; return KS_EINVAL; }
+  h.plane_col0.push_back((int)h.col_off.size());
+  h.col_off.push_back(h.npw);
+  return KS_OK;
+}
+
+// Kleinman-Bylander tables per x-tile (row a0 for Eq. vnl): slots (tile,
+// atom) with their beta rows ordered (tile, atom, pencil, j0), and the unique
+// grid points of each tile with their (slot, beta row) entries ordered by
+// atom.  LDS positions are w*(n0+1) + j0 within the tile's pencil buffer.
+struct ProjHost {
+  int nproj = 1, npoints = 0, nruns = 0, ntiles = 0, xnb = 32;
+  std::vector<double> brows;
+  std::vector<int> brow_input;   // input row of each beta row
+  std::vector<int> pt_lds, slot_off, slot_atom, slot_pt, atom_slot_off, atom_slots;
+  std::vector<int> up_off, up_lds, up_ent, ent_slot, ent_brow;
+};
+
+ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* npts, const int* idx,
+                     const double* beta, ProjHost& h, std::string& err) {
+  if (natoms < 0) { err = "natoms < 0"; return KS_EINVAL; }
+  if (natoms > 0 && (nproj < 1 || !npts)) { err = "nproj < 1 or npts is null"; return KS_EINVAL; }
+  if (nproj > KB_MAX_NPROJ) {
+    err = "more than " + std::to_string(KB_MAX_NPROJ) + " projectors per atom";
+    return KS_EUNSUPPORTED;
+  }
+  const long long N = (long long)n[0] * n[1] * n[2];
+  const int npl = n[1] * n[2];
+  long long total = 0;
+  for (int I = 0; I < natoms; ++I) {
+    if (npts[I] < 0) { err = "negative npts"; return KS_EINVAL; }
+    total += npts[I];
+  }
+  if (total > 0 && (!idx || !beta)) { err = "idx or beta is null"; return KS_EINVAL; }
+  if (total > (1LL << 30)) { err = "too many projector points"; return KS_EINVAL; }
+  const int np = std::max(1, nproj);
+  const int NB = xnb, W = n[0] + 1;
+  const int nt = (npl + NB - 1) / NB;
+  h.nproj = np;
+  h.npoints = (int)total;
+  h.ntiles = nt;
+  h.xnb = xnb;
+  struct Pt { int tile, p, atom, j0, row; };
+  std::vector<Pt> pts;
+  pts.reserve(total);
+  long long off = 0;
+  for (int I = 0; I < natoms; ++I) {
+    for (int j = 0; j < npts[I]; ++j, ++off) {
+      const long long f = idx[off];
+      if (f < 0 || f >= N) { err = "projector index outside the grid"; return KS_EINVAL; }
+      const int p = (int)(f % npl);
+      pts.push_back(Pt{p / NB, p, I, (int)(f / npl), (int)off});
+    }
+  }
+  // projection side: order (tile, atom, pencil, j0)
+  std::stable_sort(pts.begin(), pts.end(), [](const Pt& a, const Pt& b) {
+    if (a.tile != b.tile) return a.tile < b.tile;
+    if (a.atom != b.atom) return a.atom < b.atom;
+    if (a.p != b.p) return a.p < b.p;
+    return a.j0 < b.j0;
+  });
+  h.brows.assign((size_t)total * np, 0.0);
+  h.brow_input.assign(total, 0);
+  h.pt_lds.assign(total, 0);
+  h.slot_off.assign(nt + 1, 0);
+  std::vector<int> slot_of(pts.size());   // tile-local slot index of each beta row
+  int local = -1;
+  for (size_t k = 0; k < pts.size(); ++k) {
+    const Pt& q = pts[k];
+    const bool new_slot = k == 0 || q.tile != pts[k - 1].tile || q.atom != pts[k - 1].atom;
+    const bool extend = !new_slot && q.p == pts[k - 1].p && q.j0 == pts[k - 1].j0 + 1;
+    if (k == 0 || q.tile != pts[k - 1].tile) local = -1;
+    if (new_slot) {
+      h.slot_atom.push_back(q.atom);
+      h.slot_pt.push_back((int)k);
+      h.slot_off[q.tile + 1]++;
+      ++local;
+    }
+    slot_of[k] = local;
+    if (!extend) ++h.nruns;
+    h.pt_lds[k] = (q.p - q.tile * NB) * W + q.j0;
+    h.brow_input[k] = q.row;
+    for (int c = 0; c < np; ++c) h.brows[k * np + c] = beta[(size_t)q.row * np + c];
+  }
+  const int nslots = (int)h.slot_atom.size();
+  h.slot_pt.push_back((int)total);
+  for (int t = 0; t < nt; ++t) {
+    h.slot_off[t + 1] += h.slot_off[t];
+    if ((h.slot_off[t + 1] - h.slot_off[t]) * np > KB_TILE_DP) {
+      err = "too many atoms touch one x-tile (" + std::to_string(h.slot_off[t + 1] - h.slot_off[t]) + " x " +
+            std::to_string(np) + " projectors > " + std::to_string(KB_TILE_DP) + ")";
+      return KS_EUNSUPPORTED;
+    }
+  }
+  h.atom_slot_off.assign(natoms + 1, 0);
+  h.atom_slots.assign(nslots, 0);
+  for (int k = 0; k < nslots; ++k) h.atom_slot_off[h.slot_atom[k] + 1]++;
+  for (int I = 0; I < natoms; ++I) h.atom_slot_off[I + 1] += h.atom_slot_off[I];
+  {
+    std::vector<int> fill(h.atom_slot_off.begin(), h.atom_slot_off.end() - 1);
+    for (int k = 0; k < nslots; ++k) h.atom_slots[fill[h.slot_atom[k]]++] = k;
+  }
+  // scatter side: order (tile, pencil, j0, atom); one entry per (point, atom)
+  std::vector<int> order(pts.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const Pt& x = pts[a];
+    const Pt& y = pts[b];
+    if (x.tile != y.tile) return x.tile < y.tile;
+    if (x.p != y.p) return x.p < y.p;
+    if (x.j0 != y.j0) return x.j0 < y.j0;
+    return x.atom < y.atom;
+  });
+  h.up_off.assign(nt + 1, 0);
+  for (size_t i = 0; i < order.size(); ++i) {
+    const Pt& q = pts[order[i]];
+    const bool new_pt = i == 0 || q.tile != pts[order[i - 1]].tile || q.p != pts[order[i - 1]].p ||
+                        q.j0 != pts[order[i - 1]].j0;
+    if (new_pt) {
+      h.up_lds.push_back((q.p - q.tile * NB) * W + q.j0);
+      h.up_ent.push_back((int)h.ent_slot.size());
+      h.up_off[q.tile + 1]++;
+    }
+    h.ent_slot.push_back(slot_of[order[i]]);
+    h.ent_brow.push_back(order[i]);
+  }
+  h.up_ent.push_back((int)h.ent_slot.size());
+  for (int t = 0; t < nt; ++t) h.up_off[t + 1] += h.up_off[t];
+  return KS_OK;
+}
+
 void free_workspace(ks_system* s) {
   for (auto& p : s->pk) dfree(p);
   dfree(s->T);
@@ -226,65 +403,24 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   s->omega = L[0] * L[1] * L[2];
   s->dV = s->omega / (double)s->N;
 
-  // plane-wave sphere in packed order
-  std::vector<int> plane_col0, plane_m1lo, col_off, col_m2lo;
-  int prev_m0 = 0;
-  bool any_plane = false;
-  int npw = 0;
-  auto mlo = [&](int a) { return -(n[a] / 2); };
-  auto mhi = [&](int a) { return (n[a] - 1) / 2; };
-  for (int m0 = mlo(0); m0 <= mhi(0); ++m0) {
-    int first_col = 0, prev_m1 = 0, ncol = 0;
-    bool have_col = false;
-    std::vector<int> coff, cm2;
-    for (int m1 = mlo(1); m1 <= mhi(1); ++m1) {
-      int lo = 1 << 30, hi = -(1 << 30), cnt = 0;
-      for (int m2 = mlo(2); m2 <= mhi(2); ++m2) {
-        if (ecut <= 0.0 || kin(L, m0, m1, m2) < ecut) {
-          lo = std::min(lo, m2);
-          hi = std::max(hi, m2);
-          ++cnt;
-        }
-      }
-      if (cnt == 0) continue;
-      if (cnt != hi - lo + 1) {
-        delete s;
-        return fail(nullptr, KS_EUNSUPPORTED, "sphere column is not contiguous");
-      }
-      if (have_col && m1 != prev_m1 + 1) {
-        delete s;
-        return fail(nullptr, KS_EUNSUPPORTED, "sphere plane is not contiguous");
-      }
-      if (!have_col) first_col = m1;
-      have_col = true;
-      prev_m1 = m1;
-      coff.push_back(npw);
-      cm2.push_back(lo);
-      npw += cnt;
-      ++ncol;
-    }
-    if (ncol == 0) continue;
-    if (any_plane && m0 != prev_m0 + 1) {
+  SphereHost sh;
+  {
+    std::string msg;
+    const ks_status r = build_sphere(n, L, ecut, sh, msg);
+    if (r != KS_OK) {
       delete s;
-      return fail(nullptr, KS_EUNSUPPORTED, "sphere planes are not contiguous");
+      return fail(nullptr, r, msg);
     }
-    if (!any_plane) s->m0lo = m0;
-    any_plane = true;
-    prev_m0 = m0;
-    plane_col0.push_back((int)col_off.size());
-    plane_m1lo.push_back(first_col);
-    col_off.insert(col_off.end(), coff.begin(), coff.end());
-    col_m2lo.insert(col_m2lo.end(), cm2.begin(), cm2.end());
-    s->ncol_max = std::max(s->ncol_max, ncol);
   }
-  if (!any_plane) {
-    delete s;
-    return fail(nullptr, KS_EINVAL, "the plane-wave sphere is empty");
-  }
-  s->nplanes = (int)plane_col0.size();
-  s->ncols = (int)col_off.size();
-  plane_col0.push_back(s->ncols);
-  col_off.push_back(npw);
+  std::vector<int>& plane_col0 = sh.plane_col0;
+  std::vector<int>& plane_m1lo = sh.plane_m1lo;
+  std::vector<int>& col_off = sh.col_off;
+  std::vector<int>& col_m2lo = sh.col_m2lo;
+  const int npw = sh.npw;
+  s->m0lo = sh.m0lo;
+  s->ncol_max = sh.ncol_max;
+  s->nplanes = (int)plane_m1lo.size();
+  s->ncols = (int)col_m2lo.size();
   s->npw = npw;
   s->npw_stride = (npw + 63) / 64 * 64;
   s->xnb = x_tile_nb(n[0]);
@@ -370,128 +506,33 @@ ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
 ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
                                    const double* beta, const double* d, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
-  if (natoms < 0) return fail(s, KS_EINVAL, "natoms < 0");
-  if (natoms > 0 && (nproj < 1 || !npts || !d)) return fail(s, KS_EINVAL, "nproj < 1 or null npts/d");
-  if (nproj > KB_MAX_NPROJ)
-    return fail(s, KS_EUNSUPPORTED, "more than " + std::to_string(KB_MAX_NPROJ) + " projectors per atom");
+  if (natoms > 0 && !d) return fail(s, KS_EINVAL, "d is null");
+  ProjHost ph;
+  {
+    std::string msg;
+    const ks_status r = build_proj(s->n, s->xnb, natoms, nproj, npts, idx, beta, ph, msg);
+    if (r != KS_OK) return fail(s, r, msg);
+  }
   KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
-  long long total = 0;
-  for (int I = 0; I < natoms; ++I) {
-    if (npts[I] < 0) return fail(s, KS_EINVAL, "negative npts");
-    total += npts[I];
-  }
-  if (total > 0 && (!idx || !beta)) return fail(s, KS_EINVAL, "idx or beta is null");
-  if (total > (1LL << 30)) return fail(s, KS_EINVAL, "too many projector points");
-  const int np = std::max(1, nproj);
-  const int NB = s->xnb, W = s->n[0] + 1;
-  struct Pt { int tile, p, atom, j0, row; };
-  std::vector<Pt> pts;
-  pts.reserve(total);
-  long long off = 0;
-  for (int I = 0; I < natoms; ++I) {
-    for (int j = 0; j < npts[I]; ++j, ++off) {
-      const long long f = idx[off];
-      if (f < 0 || f >= s->N) return fail(s, KS_EINVAL, "projector index outside the grid");
-      const int p = (int)(f % s->npl);
-      pts.push_back(Pt{p / NB, p, I, (int)(f / s->npl), (int)off});
-    }
-  }
-  // projection side: order (tile, atom, pencil, j0); runs of consecutive j0
-  std::stable_sort(pts.begin(), pts.end(), [](const Pt& a, const Pt& b) {
-    if (a.tile != b.tile) return a.tile < b.tile;
-    if (a.atom != b.atom) return a.atom < b.atom;
-    if (a.p != b.p) return a.p < b.p;
-    return a.j0 < b.j0;
-  });
-  const int nt = s->ntiles;
-  std::vector<double> brows((size_t)total * np);
-  std::vector<int> pt_lds(total);
-  std::vector<int> slot_off(nt + 1, 0), slot_atom, slot_pt;
-  int nruns = 0;
-  for (size_t k = 0; k < pts.size(); ++k) {
-    const Pt& q = pts[k];
-    const bool new_slot = k == 0 || q.tile != pts[k - 1].tile || q.atom != pts[k - 1].atom;
-    const bool extend = !new_slot && q.p == pts[k - 1].p && q.j0 == pts[k - 1].j0 + 1;
-    if (new_slot) {
-      slot_atom.push_back(q.atom);
-      slot_pt.push_back((int)k);
-      slot_off[q.tile + 1]++;
-    }
-    if (!extend) ++nruns;
-    pt_lds[k] = (q.p - q.tile * NB) * W + q.j0;
-    for (int c = 0; c < np; ++c) brows[k * np + c] = beta[(size_t)q.row * np + c];
-  }
-  const int nslots = (int)slot_atom.size();
-  slot_pt.push_back((int)total);
-  for (int t = 0; t < nt; ++t) {
-    slot_off[t + 1] += slot_off[t];
-    if ((slot_off[t + 1] - slot_off[t]) * np > KB_TILE_DP)
-      return fail(s, KS_EUNSUPPORTED, "too many atoms touch one x-tile (" +
-                                          std::to_string(slot_off[t + 1] - slot_off[t]) + " x " +
-                                          std::to_string(np) + " projectors > " + std::to_string(KB_TILE_DP) + ")");
-  }
-  std::vector<int> atom_slot_off(natoms + 1, 0), atom_slots(nslots);
-  for (int k = 0; k < nslots; ++k) atom_slot_off[slot_atom[k] + 1]++;
-  for (int I = 0; I < natoms; ++I) atom_slot_off[I + 1] += atom_slot_off[I];
-  {
-    std::vector<int> fill(atom_slot_off.begin(), atom_slot_off.end() - 1);
-    for (int k = 0; k < nslots; ++k) atom_slots[fill[slot_atom[k]]++] = k;
-  }
-  // scatter side: order (tile, pencil, j0, atom); one entry per (point, atom)
-  std::vector<int> slot_of;   // per pts (projection order): tile-local slot index
-  slot_of.resize(pts.size());
-  {
-    int t_prev = -1, local = -1;
-    for (size_t k = 0; k < pts.size(); ++k) {
-      const bool new_slot = k == 0 || pts[k].tile != pts[k - 1].tile || pts[k].atom != pts[k - 1].atom;
-      if (pts[k].tile != t_prev) { local = -1; t_prev = pts[k].tile; }
-      if (new_slot) ++local;
-      slot_of[k] = local;
-    }
-  }
-  std::vector<int> order(pts.size());
-  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const Pt& x = pts[a];
-    const Pt& y = pts[b];
-    if (x.tile != y.tile) return x.tile < y.tile;
-    if (x.p != y.p) return x.p < y.p;
-    if (x.j0 != y.j0) return x.j0 < y.j0;
-    return x.atom < y.atom;
-  });
-  std::vector<int> up_off(nt + 1, 0), up_lds, up_ent, ent_slot, ent_brow;
-  for (size_t i = 0; i < order.size(); ++i) {
-    const Pt& q = pts[order[i]];
-    const bool new_pt = i == 0 || q.tile != pts[order[i - 1]].tile || q.p != pts[order[i - 1]].p ||
-                        q.j0 != pts[order[i - 1]].j0;
-    if (new_pt) {
-      up_lds.push_back((q.p - q.tile * NB) * W + q.j0);
-      up_ent.push_back((int)ent_slot.size());
-      up_off[q.tile + 1]++;
-    }
-    ent_slot.push_back(slot_of[order[i]]);
-    ent_brow.push_back(order[i]);
-  }
-  up_ent.push_back((int)ent_slot.size());
-  for (int t = 0; t < nt; ++t) up_off[t + 1] += up_off[t];
+  const int np = ph.nproj;
   std::vector<double> kb((size_t)natoms * np);
   for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
   ks_status st;
-  if ((st = upload(s, &s->d_pt_lds, pt_lds)) != KS_OK ||
-      (st = upload(s, &s->d_slot_off, slot_off)) != KS_OK || (st = upload(s, &s->d_slot_atom, slot_atom)) != KS_OK ||
-      (st = upload(s, &s->d_slot_pt, slot_pt)) != KS_OK ||
-      (st = upload(s, &s->d_atom_slot_off, atom_slot_off)) != KS_OK ||
-      (st = upload(s, &s->d_atom_slots, atom_slots)) != KS_OK || (st = upload(s, &s->d_up_off, up_off)) != KS_OK ||
-      (st = upload(s, &s->d_up_lds, up_lds)) != KS_OK || (st = upload(s, &s->d_up_ent, up_ent)) != KS_OK ||
-      (st = upload(s, &s->d_ent_slot, ent_slot)) != KS_OK || (st = upload(s, &s->d_ent_brow, ent_brow)) != KS_OK ||
-      (st = upload(s, &s->d_beta, brows)) != KS_OK || (st = upload(s, &s->d_kb, kb)) != KS_OK)
+  if ((st = upload(s, &s->d_pt_lds, ph.pt_lds)) != KS_OK ||
+      (st = upload(s, &s->d_slot_off, ph.slot_off)) != KS_OK || (st = upload(s, &s->d_slot_atom, ph.slot_atom)) != KS_OK ||
+      (st = upload(s, &s->d_slot_pt, ph.slot_pt)) != KS_OK ||
+      (st = upload(s, &s->d_atom_slot_off, ph.atom_slot_off)) != KS_OK ||
+      (st = upload(s, &s->d_atom_slots, ph.atom_slots)) != KS_OK || (st = upload(s, &s->d_up_off, ph.up_off)) != KS_OK ||
+      (st = upload(s, &s->d_up_lds, ph.up_lds)) != KS_OK || (st = upload(s, &s->d_up_ent, ph.up_ent)) != KS_OK ||
+      (st = upload(s, &s->d_ent_slot, ph.ent_slot)) != KS_OK || (st = upload(s, &s->d_ent_brow, ph.ent_brow)) != KS_OK ||
+      (st = upload(s, &s->d_beta, ph.brows)) != KS_OK || (st = upload(s, &s->d_kb, kb)) != KS_OK)
     return st;
-  s->natoms = (natoms > 0 && total > 0) ? natoms : 0;
+  s->natoms = (natoms > 0 && ph.npoints > 0) ? natoms : 0;
   s->nproj = np;
-  s->nslots = nslots;
-  s->nruns = nruns;
-  s->npoints = (int)total;
-  s->nuniq = (int)up_lds.size();
+  s->nslots = (int)ph.slot_atom.size();
+  s->nruns = ph.nruns;
+  s->npoints = ph.npoints;
+  s->nuniq = (int)ph.up_lds.size();
   return alloc_proj_workspace(s);
 }
 
@@ -612,9 +653,95 @@ ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, 
 ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   ks_status r = check_common(s, norb);
   if (r != KS_OK) return r;
-  (void)psi;
-  (void)stream;
-  return fail(s, KS_EUNSUPPORTED, "orthonormalisation is not built yet");
+  if (norb == 0) return KS_OK;
+  if (!psi) return fail(s, KS_EINVAL, "psi is null");
+  hipStream_t st = (hipStream_t)stream;
+  if (!s->ortho_pk) {
+    const size_t n = (size_t)s->max_norb;
+    if ((r = dalloc(s, &s->ortho_pk, 2 * n * s->npw_stride * sizeof(double2))) != KS_OK ||
+        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_S), n * n * sizeof(double2))) != KS_OK ||
+        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_W), n * n * sizeof(double2))) != KS_OK ||
+        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK) {
+      dfree(s->ortho_pk);
+      return r;
+    }
+  }
+  double2* P = (double2*)s->ortho_pk;
+  double2* Y = P + (size_t)s->max_norb * s->npw_stride;
+  KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
+  double2* box = (double2*)psi;
+  if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, norb, box, s->N, P, st); })) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, st), "overlap")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_info, st), "cholesky")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_trtri(norb, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_apply_lower(norb, s->npw, s->ortho_W, P, s->npw_stride, Y, st), "apply")) != KS_OK)
+    return r;
+  int info = 0;
+  KS_HIP(s, hipMemcpyAsync(&info, s->ortho_info, sizeof(int), hipMemcpyDeviceToHost, st));
+  KS_HIP(s, hipStreamSynchronize(st));
+  if (info) return fail(s, KS_EINVAL, "overlap matrix is not positive definite (orbitals linearly dependent)");
+  return kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, norb, Y, box, s->N, st); });
+}
+
+ks_status ks_plan_sphere(const int n[3], const double L[3], double ecut, int* npw, int* m_out) {
+  if (!n || !L || !npw) return fail(nullptr, KS_EINVAL, "null argument");
+  for (int a = 0; a < 3; ++a)
+    if (n[a] < 1 || !(L[a] > 0.0)) return fail(nullptr, KS_EINVAL, "bad grid or cell");
+  SphereHost h;
+  std::string msg;
+  const ks_status r = build_sphere(n, L, ecut, h, msg);
+  if (r != KS_OK) return fail(nullptr, r, msg);
+  *npw = h.npw;
+  if (m_out) {
+    const int nplanes = (int)h.plane_m1lo.size();
+    for (int pi = 0; pi < nplanes; ++pi) {
+      for (int c = h.plane_col0[pi]; c < h.plane_col0[pi + 1]; ++c) {
+        const int m1 = h.plane_m1lo[pi] + (c - h.plane_col0[pi]);
+        for (int e = h.col_off[c]; e < h.col_off[c + 1]; ++e) {
+          m_out[3 * e] = h.m0lo + pi;
+          m_out[3 * e + 1] = m1;
+          m_out[3 * e + 2] = h.col_m2lo[c] + (e - h.col_off[c]);
+        }
+      }
+    }
+  }
+  return KS_OK;
+}
+
+ks_status ks_plan_projectors(const int n[3], int natoms, int nproj, const int* npts, const int* idx,
+                             const double* beta, int* counts, int* point_flat, int* point_entries,
+                             int* entry_atom, int* entry_row) {
+  if (!n || !counts) return fail(nullptr, KS_EINVAL, "null argument");
+  ProjHost h;
+  std::string msg;
+  const int xnb = x_tile_nb(n[0]);
+  const ks_status r = build_proj(n, xnb, natoms, nproj, npts, idx, beta, h, msg);
+  if (r != KS_OK) return fail(nullptr, r, msg);
+  const int nuniq = (int)h.up_lds.size(), nent = (int)h.ent_slot.size();
+  counts[0] = (int)h.slot_atom.size();
+  counts[1] = nuniq;
+  counts[2] = nent;
+  counts[3] = h.nruns;
+  const int W = n[0] + 1, npl = n[1] * n[2];
+  for (int t = 0; t < h.ntiles; ++t) {
+    for (int u = h.up_off[t]; u < h.up_off[t + 1]; ++u) {
+      if (point_flat) {
+        const int w = h.up_lds[u] / W, j0 = h.up_lds[u] % W;
+        point_flat[u] = j0 * npl + t * xnb + w;
+      }
+      if (point_entries) point_entries[u] = h.up_ent[u];
+      for (int e = h.up_ent[u]; e < h.up_ent[u + 1]; ++e) {
+        const int slot = h.slot_off[t] + h.ent_slot[e];
+        if (entry_atom) entry_atom[e] = h.slot_atom[slot];
+        if (entry_row) entry_row[e] = h.brow_input[h.ent_brow[e]];
+        // projection side consistency: the entry's beta row lies in its slot
+        if (h.ent_brow[e] < h.slot_pt[slot] || h.ent_brow[e] >= h.slot_pt[slot + 1])
+          return fail(nullptr, KS_EDEVICE, "inconsistent projector tables");
+      }
+    }
+  }
+  if (point_entries) point_entries[nuniq] = nent;
+  return KS_OK;
 }
 
 ks_status ks_system_info(const ks_system* s, ks_info* info) {

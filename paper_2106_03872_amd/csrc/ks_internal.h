@@ -136,6 +136,11 @@ bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, 
 bool launch_dots(const ks_system* s, int nb, const void* a, const void* b, double* out, hipStream_t st);
 bool launch_energy_sum(int norb, const double* occ, const double* red, double* energy, hipStream_t st);
 
+bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hipStream_t st);
+bool launch_cholesky(int n, double2* S, int* info, hipStream_t st);
+bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);
+bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st);
+
 bool supported_size(int n);
 int x_tile_nb(int n0);
 size_t plane_lds_bytes(const ks_system* s);

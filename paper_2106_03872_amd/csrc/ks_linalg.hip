@@ -1,0 +1,310 @@
+// Dense complex FP64 linear algebra for the orthonormalisation of the
+// orbitals (orthogonalisation step of Section "Ground-state solution"):
+//   S = C^H C  (overlap over the packed plane-wave sphere, MFMA FP64)
+//   S = L L^H  (blocked right-looking Cholesky)
+//   X = L^-1   (blocked triangular inverse)
+//   C <- conj(X) C  (rows = orbitals), i.e. Psi <- Psi L^-H  (MFMA FP64)
+// The matrices are small (n = orbitals <= a few thousand); the two GEMMs are
+// the only large contractions and run on the matrix cores.
+#include "ks_internal.h"
+
+namespace ks {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ MFMA GEMM
+// Cout[m][n] = sum_k op(A)[m][k] * B(k, n) for complex FP64, op = conj when
+// CONJ_A.  A is row-major [M][lda] (k contiguous).  B is either [N][ldb] with
+// k contiguous (B_KN = false: B(k, n) = Bm[n][k]) or [K][ldb] with n
+// contiguous (B_KN = true).  LOWER_A: A is lower triangular (k <= m), so
+// k-tiles above the diagonal are skipped.  LOWER_OUT: only tiles with
+// m-tile >= n-tile are produced.
+//
+// v_mfma_f64_16x16x4_f64 operand layout (64 lanes): A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <bool CONJ_A, bool B_KN, bool LOWER_A, bool LOWER_OUT>
+__global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, const double2* __restrict__ A, long long lda,
+                                                         const double2* __restrict__ Bm, long long ldb,
+                                                         double2* __restrict__ Cout, long long ldc) {
+  __shared__ double2 As[GBK][GBM + 1];
+  __shared__ double2 Bs[GBK][GBN + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  if (LOWER_OUT && n0 > m0) return;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  dvec4 re[2][2], im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
+  const int kend = LOWER_A ? min(K, m0 + GBM) : K;
+  const double sa = CONJ_A ? -1.0 : 1.0;
+  for (int k0 = 0; k0 < kend; k0 += GBK) {
+    // A tile: 64 rows x 16 k, k fastest across threads
+    for (int i = tid; i < GBM * GBK; i += 256) {
+      const int kk = i % GBK, mm = i / GBK;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < M && k < K) ? A[(long long)m * lda + k] : double2{0.0, 0.0};
+    }
+    if (B_KN) {
+      for (int i = tid; i < GBN * GBK; i += 256) {
+        const int nn = i % GBN, kk = i / GBN;
+        const int n = n0 + nn, k = k0 + kk;
+        Bs[kk][nn] = (n < N && k < K) ? Bm[(long long)k * ldb + n] : double2{0.0, 0.0};
+      }
+    } else {
+      for (int i = tid; i < GBN * GBK; i += 256) {
+        const int kk = i % GBK, nn = i / GBK;
+        const int n = n0 + nn, k = k0 + kk;
+        Bs[kk][nn] = (n < N && k < K) ? Bm[(long long)n * ldb + k] : double2{0.0, 0.0};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 4) {
+      const int kr = ks + (lane >> 4), c = lane & 15;
+      double2 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[kr][wm + t * 16 + c];
+        b[t] = Bs[kr][wn + t * 16 + c];
+      }
+#pragma unroll
+      for (int ta = 0; ta < 2; ++ta) {
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+          re[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, b[tb].x, re[ta][tb], 0, 0, 0);
+          re[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-sa * a[ta].y, b[tb].y, re[ta][tb], 0, 0, 0);
+          im[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, b[tb].y, im[ta][tb], 0, 0, 0);
+          im[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa * a[ta].y, b[tb].x, im[ta][tb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ta = 0; ta < 2; ++ta) {
+#pragma unroll
+    for (int tb = 0; tb < 2; ++tb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + ta * 16 + (lane >> 4) * 4 + r;
+        const int n = n0 + wn + tb * 16 + (lane & 15);
+        if (m < M && n < N) Cout[(long long)m * ldc + n] = double2{re[ta][tb][r], im[ta][tb][r]};
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ blocked Cholesky
+constexpr int CB = 32;
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ double2 zmulc(double2 a, double2 b) { return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
+
+// factor the diagonal block at k0 in place (lower), upper part zeroed
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int k0, int* info) {
+  __shared__ double2 a[CB][CB + 1];
+  const int tid = threadIdx.x;
+  const int nb = min(CB, n - k0);
+  for (int i = tid; i < CB * CB; i += 256) {
+    const int r = i / CB, c = i % CB;
+    a[r][c] = (r < nb && c < nb && c <= r) ? S[(long long)(k0 + r) * n + k0 + c] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      double d = a[j][j].x;
+      if (!(d > 0.0)) {
+        info[0] = 1;
+        d = 1.0;
+      }
+      a[j][j] = double2{sqrt(d), 0.0};
+    }
+    __syncthreads();
+    const double inv = 1.0 / a[j][j].x;
+    for (int i = j + 1 + tid; i < nb; i += 256) a[i][j] = double2{a[i][j].x * inv, a[i][j].y * inv};
+    __syncthreads();
+    for (int t = tid; t < CB * CB; t += 256) {
+      const int r = t / CB, c = t % CB;
+      if (c > j && r >= c && r < nb) {
+        const double2 u = zmulc(a[r][j], a[c][j]);
+        a[r][c] = double2{a[r][c].x - u.x, a[r][c].y - u.y};
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < nb * nb; i += 256) {
+    const int r = i / nb, c = i % nb;
+    S[(long long)(k0 + r) * n + k0 + c] = c <= r ? a[r][c] : double2{0.0, 0.0};
+  }
+}
+
+// rows below the diagonal block: L_rk = A_rk L_kk^-H (one thread per row,
+// rows staged in LDS and solved in place)
+__global__ __launch_bounds__(64) void trsm_panel_kernel(double2* S, int n, int k0) {
+  __shared__ double2 l[CB][CB + 1];
+  __shared__ double2 x[64][CB + 1];
+  const int nb = min(CB, n - k0);
+  const int tid = threadIdx.x;
+  const int rb = k0 + nb + blockIdx.x * 64;
+  for (int i = tid; i < CB * CB; i += 64) {
+    const int r = i / CB, c = i % CB;
+    l[r][c] = (r < nb && c < nb) ? S[(long long)(k0 + r) * n + k0 + c] : double2{0.0, 0.0};
+  }
+  for (int i = tid; i < 64 * CB; i += 64) {
+    const int r = i / CB, c = i % CB;
+    x[r][c] = (rb + r < n && c < nb) ? S[(long long)(rb + r) * n + k0 + c] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  if (rb + tid < n) {
+    for (int j = 0; j < nb; ++j) {
+      double2 v = x[tid][j];
+      for (int m = 0; m < j; ++m) {
+        const double2 u = zmulc(x[tid][m], l[j][m]);
+        v.x -= u.x;
+        v.y -= u.y;
+      }
+      const double inv = 1.0 / l[j][j].x;
+      x[tid][j] = double2{v.x * inv, v.y * inv};
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < 64 * CB; i += 64) {
+    const int r = i / CB, c = i % CB;
+    if (rb + r < n && c < nb) S[(long long)(rb + r) * n + k0 + c] = x[r][c];
+  }
+}
+
+// trailing update of the lower triangle: A_ij -= L_ik L_jk^H for tiles i >= j > k
+__global__ __launch_bounds__(256) void herk_update_kernel(double2* S, int n, int k0) {
+  __shared__ double2 li[CB][CB + 1], lj[CB][CB + 1];
+  const int nb = min(CB, n - k0);
+  const int r0 = k0 + nb + blockIdx.y * CB, c0 = k0 + nb + blockIdx.x * CB;
+  if (c0 > r0 || r0 >= n) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < CB * CB; i += 256) {
+    const int r = i / CB, c = i % CB;
+    li[r][c] = (r0 + r < n && c < nb) ? S[(long long)(r0 + r) * n + k0 + c] : double2{0.0, 0.0};
+    lj[r][c] = (c0 + r < n && c < nb) ? S[(long long)(c0 + r) * n + k0 + c] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+  for (int t = tid; t < CB * CB; t += 256) {
+    const int r = t / CB, c = t % CB;
+    const int gr = r0 + r, gc = c0 + c;
+    if (gr < n && gc < n && gc <= gr) {
+      double sx = 0.0, sy = 0.0;
+      for (int m = 0; m < nb; ++m) {
+        const double2 u = zmulc(li[r][m], lj[c][m]);
+        sx += u.x;
+        sy += u.y;
+      }
+      double2* p = S + (long long)gr * n + gc;
+      *p = double2{p->x - sx, p->y - sy};
+    }
+  }
+}
+
+// ------------------------------------------------------- blocked lower inverse
+// Block row I of X = L^-1 for all block columns J <= I (one block per J):
+//   X_II = L_II^-1,   X_IJ = -L_II^-1 sum_{K=J}^{I-1} L_IK X_KJ.
+// The right-hand side is accumulated from LDS tiles; then each of 32 threads
+// solves one column by forward substitution with L_II, in place.
+__global__ __launch_bounds__(256) void trtri_row_kernel(const double2* __restrict__ L, double2* __restrict__ X, int n,
+                                                        int I) {
+  __shared__ double2 lii[CB][CB + 1], lik[CB][CB + 1], xkj[CB][CB + 1], t[CB][CB + 1];
+  const int J = blockIdx.x, tid = threadIdx.x;
+  const int r0 = I * CB, c0 = J * CB;
+  const int nr = min(CB, n - r0), ncl = min(CB, n - c0);
+  for (int i = tid; i < CB * CB; i += 256) {
+    const int r = i / CB, c = i % CB;
+    lii[r][c] = (r < nr && c < nr) ? L[(long long)(r0 + r) * n + r0 + c] : double2{0.0, 0.0};
+    t[r][c] = double2{(J == I && r == c) ? 1.0 : 0.0, 0.0};
+  }
+  for (int K = J; K < I; ++K) {
+    const int k0 = K * CB;
+    __syncthreads();
+    for (int i = tid; i < CB * CB; i += 256) {
+      const int r = i / CB, c = i % CB;
+      lik[r][c] = (r < nr) ? L[(long long)(r0 + r) * n + k0 + c] : double2{0.0, 0.0};
+      xkj[r][c] = (c < ncl) ? X[(long long)(k0 + r) * n + c0 + c] : double2{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int i = tid; i < CB * CB; i += 256) {
+      const int r = i / CB, c = i % CB;
+      double sx = 0.0, sy = 0.0;
+      for (int m = 0; m < CB; ++m) {
+        const double2 u = zmul(lik[r][m], xkj[m][c]);
+        sx += u.x;
+        sy += u.y;
+      }
+      t[r][c] = double2{t[r][c].x - sx, t[r][c].y - sy};
+    }
+  }
+  __syncthreads();
+  if (tid < ncl) {
+    const int c = tid;
+    for (int r = 0; r < nr; ++r) {
+      double2 v = t[r][c];
+      for (int m = 0; m < r; ++m) {
+        const double2 u = zmul(lii[r][m], t[m][c]);
+        v.x -= u.x;
+        v.y -= u.y;
+      }
+      const double inv = 1.0 / lii[r][r].x;
+      t[r][c] = double2{v.x * inv, v.y * inv};
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < CB * CB; i += 256) {
+    const int r = i / CB, c = i % CB;
+    if (r < nr && c < ncl) X[(long long)(r0 + r) * n + c0 + c] = t[r][c];
+  }
+}
+
+__global__ void zero_upper_kernel(double2* X, int n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long long)n * n) return;
+  const int r = i / n, c = i % n;
+  if (c > r) X[i] = double2{0.0, 0.0};
+}
+
+// ------------------------------------------------------------------ launchers
+
+bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hipStream_t st) {
+  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
+  // S[i][j] = sum_e conj(P[i][e]) P[j][e]
+  zgemm_mfma_kernel<true, false, false, true><<<grid, 256, 0, st>>>(norb, norb, npw, P, ldp, P, ldp, S, norb);
+  return true;
+}
+
+bool launch_cholesky(int n, double2* S, int* info, hipStream_t st) {
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    potrf_diag_kernel<<<1, 256, 0, st>>>(S, n, k0, info);
+    const int rest = n - k0 - min(CB, n - k0);
+    if (rest > 0) {
+      trsm_panel_kernel<<<(rest + 63) / 64, 64, 0, st>>>(S, n, k0);
+      const int nt = (rest + CB - 1) / CB;
+      herk_update_kernel<<<dim3(nt, nt), 256, 0, st>>>(S, n, k0);
+    }
+  }
+  return true;
+}
+
+bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st) {
+  const int nbk = (n + CB - 1) / CB;
+  zero_upper_kernel<<<(unsigned)(((long long)n * n + 255) / 256), 256, 0, st>>>(X, n);
+  for (int I = 0; I < nbk; ++I) trtri_row_kernel<<<I + 1, 256, 0, st>>>(L, X, n, I);
+  return true;
+}
+
+bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st) {
+  dim3 grid((npw + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
+  // Y[i][e] = sum_{j <= i} conj(X[i][j]) P[j][e]
+  zgemm_mfma_kernel<true, true, true, false><<<grid, 256, 0, st>>>(norb, npw, norb, X, norb, P, ldp, Y, ldp);
+  return true;
+}
+
+}  // namespace ks

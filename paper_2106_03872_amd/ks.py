@@ -61,6 +61,8 @@ def _load():
         "ks_system_chunk": (I, [P]),
         "ks_system_set_chunk": (I, [P, I]),
         "ks_system_info": (I, [P, P]),
+        "ks_plan_sphere": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, ctypes.POINTER(I), P]),
+        "ks_plan_projectors": (I, [ctypes.POINTER(I), I, I, P, P, P, ctypes.POINTER(I), P, P, P, P]),
         "ks_set_kernel_timing": (I, [P, I]),
         "ks_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
     }
@@ -82,6 +84,49 @@ def header_symbols():
 
 def library():
     return _lib
+
+
+def plan_sphere(n, L, ecut):
+    """Integer frequencies (m0, m1, m2) of the packed plane-wave sphere, in the
+    library's packed order (host-only call)."""
+    nn = (ctypes.c_int * 3)(*[int(x) for x in n])
+    LL = (ctypes.c_double * 3)(*[float(x) for x in L])
+    npw = ctypes.c_int()
+    st = _lib.ks_plan_sphere(nn, LL, float(ecut), ctypes.byref(npw), None)
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_last_error(None).decode())
+    m = np.zeros((npw.value, 3), np.int32)
+    st = _lib.ks_plan_sphere(nn, LL, float(ecut), ctypes.byref(npw), m.ctypes.data_as(ctypes.c_void_p))
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_last_error(None).decode())
+    return m
+
+
+def plan_projectors(n, npts, idx, beta, nproj=None):
+    """Kleinman-Bylander point tables (host-only call): dict with counts and,
+    per unique grid point, its flat index and its (atom, input row) entries."""
+    npts = np.ascontiguousarray(npts, np.int32)
+    idx = np.ascontiguousarray(idx, np.int32)
+    beta = np.ascontiguousarray(beta, np.float64)
+    nproj = beta.shape[1] if nproj is None else nproj
+    nn = (ctypes.c_int * 3)(*[int(x) for x in n])
+    counts = (ctypes.c_int * 4)()
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+    args = (nn, len(npts), int(nproj), ptr(npts), ptr(idx), ptr(beta), counts)
+    st = _lib.ks_plan_projectors(*args, None, None, None, None)
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_last_error(None).decode())
+    nslots, nuniq, nent, nruns = list(counts)
+    flat = np.zeros(nuniq, np.int32)
+    pent = np.zeros(nuniq + 1, np.int32)
+    eatom = np.zeros(nent, np.int32)
+    erow = np.zeros(nent, np.int32)
+    st = _lib.ks_plan_projectors(*args, flat.ctypes.data_as(ctypes.c_void_p), pent.ctypes.data_as(ctypes.c_void_p),
+                                 eatom.ctypes.data_as(ctypes.c_void_p), erow.ctypes.data_as(ctypes.c_void_p))
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_last_error(None).decode())
+    return {"slots": nslots, "unique": nuniq, "entries": nent, "runs": nruns, "point_flat": flat,
+            "point_entries": pent, "entry_atom": eatom, "entry_row": erow}
 
 
 def _stream():

@@ -182,3 +182,40 @@ def test_full_size_cfg3_sampled(ks):
     assert rel_err(c[sample].cpu().numpy(), ref) < TOL
     rr = ko.density(ham, ref[1:2], [2.0])
     assert np.linalg.norm(rho[0].cpu().numpy() - rr) / np.linalg.norm(rr) < TOL
+
+
+# ------------------------------------------------------- orthonormalisation (a10)
+
+@pytest.mark.parametrize("name", ["t24", "t48", "cfg2_64"])
+def test_orthonormalize_parity(ks, name):
+    """Cholesky orthonormalisation vs the oracle.  The Cholesky factor is
+    unique (positive diagonal), so the result is compared element by element;
+    the tolerance scales with the conditioning of the overlap matrix
+    (first-order perturbation of a Cholesky factor is bounded by
+    cond(S) times the rounding of S)."""
+    spec, sysm = _case(name)
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    cn = c.cpu().numpy()
+    ref = ko.orthonormalize(ham, cn)
+    A = np.where(ham.grid.chi, cn, 0).reshape(spec.norb, -1)
+    sv = np.linalg.svd(A, compute_uv=False)
+    cond = (sv[0] / sv[-1]) ** 2
+    gs.orthonormalize(c)
+    got = c.cpu().numpy()
+    tol = max(1e-12, 1e-14 * cond * np.sqrt(spec.norb))
+    assert rel_err(got, ref) < tol, (rel_err(got, ref), cond)
+    M = got.reshape(spec.norb, -1)
+    assert np.abs(M.conj() @ M.T - np.eye(spec.norb)).max() < 1e-12
+    assert np.all(got[:, ~ham.grid.chi] == 0)
+
+
+def test_orthonormalize_rejects_dependent(ks):
+    spec, sysm = _case("t24")
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    c[3] = c[1]                                    # linearly dependent set
+    with pytest.raises(ks.KSError) as e:
+        gs.orthonormalize(c)
+    assert e.value.status == ks.KS_EINVAL

@@ -1,0 +1,82 @@
+"""Host-side set-up tables of the HIP library, checked on the CPU against the
+oracle and against their inputs (no GPU needed)."""
+import numpy as np
+import pytest
+
+from oracle import ks_oracle as ko
+from paper_2106_03872_amd import ks, synth
+
+
+@pytest.mark.parametrize("n,L,ecut", [
+    ((16, 16, 16), (10, 10, 10), 10.0), ((24, 24, 24), (10, 10, 10), 10.0),
+    ((32, 32, 32), (10.0, 11.0, 12.0), 10.0), ((60, 60, 60), (19.8,) * 3, 10.0),
+    ((96, 96, 96), (30,) * 3, 10.0), ((20, 16, 16), (7.0, 5.0, 6.0), 0.0),
+    ((12, 8, 8), (4.0, 3.0, 3.5), 3.0), ((8, 8, 8), (3.0, 3.0, 3.0), 100.0),
+])
+def test_sphere_matches_oracle_mask(n, L, ecut):
+    m = ks.plan_sphere(n, L, ecut)
+    g = ko.Grid(n, L, ecut)
+    assert len(m) == g.npw
+    got = {tuple(x) for x in m}
+    want = {(int(g.m[0][a]), int(g.m[1][b]), int(g.m[2][c])) for a, b, c in np.argwhere(g.chi)}
+    assert got == want
+    # packed order: m0 ascending, then m1, then contiguous runs of m2
+    key = m[:, 0].astype(np.int64) * 1_000_000 + m[:, 1] * 1000 + m[:, 2]
+    assert np.all(np.diff(key) > 0)
+    same_col = (np.diff(m[:, 0]) == 0) & (np.diff(m[:, 1]) == 0)
+    assert np.all(np.diff(m[:, 2])[same_col] == 1)
+
+
+def test_sphere_rejects_bad_arguments():
+    with pytest.raises(ks.KSError):
+        ks.plan_sphere((16, 16, 16), (10, 0, 10), 10.0)
+    # a tiny positive cutoff keeps only G = 0
+    assert ks.plan_sphere((16, 16, 16), (10, 10, 10), 1e-6).tolist() == [[0, 0, 0]]
+
+
+def _check_tables(n, npts, idx, beta):
+    t = ks.plan_projectors(n, npts, idx, beta)
+    atom_of_row = np.repeat(np.arange(len(npts)), npts)
+    pe = t["point_entries"]
+    assert pe[0] == 0 and pe[-1] == t["entries"] == len(idx)
+    assert len(np.unique(t["point_flat"])) == t["unique"]
+    got = []
+    for u in range(t["unique"]):
+        ats = t["entry_atom"][pe[u]:pe[u + 1]]
+        assert np.all(np.diff(ats) >= 0)           # entries of a point ordered by atom
+        for e in range(pe[u], pe[u + 1]):
+            got.append((int(t["point_flat"][u]), int(t["entry_atom"][e]), int(t["entry_row"][e])))
+    want = [(int(idx[r]), int(atom_of_row[r]), r) for r in range(len(idx))]
+    assert sorted(got) == sorted(want)
+    assert t["unique"] == len(np.unique(idx))
+    return t
+
+
+@pytest.mark.parametrize("name", ["cfg1_16", "t24", "t40", "t32x", "t60"])
+def test_projector_tables_cover_inputs(name):
+    spec = synth.CONFIGS[name]
+    p = synth.projectors(spec)
+    t = _check_tables(spec.n, p.npts, p.idx, p.beta)
+    assert t["slots"] >= spec.natoms
+
+
+def test_projector_tables_duplicates_and_overlaps():
+    rng = np.random.default_rng(3)
+    n = (24, 24, 24)
+    N = int(np.prod(n))
+    npts = np.array([50, 0, 80, 30], np.int32)
+    idx = np.concatenate([rng.integers(0, N, k) for k in npts]).astype(np.int32)
+    idx[10] = idx[11]                 # duplicate inside one atom
+    idx[60:70] = idx[0:10]            # atom 2 overlaps atom 0
+    beta = rng.standard_normal((len(idx), 4))
+    _check_tables(n, npts, idx, beta)
+
+
+def test_projector_tables_errors():
+    n = (16, 16, 16)
+    with pytest.raises(ks.KSError) as e:
+        ks.plan_projectors(n, [2], [0, 16 ** 3], np.zeros((2, 4)))
+    assert e.value.status == ks.KS_EINVAL
+    with pytest.raises(ks.KSError) as e:
+        ks.plan_projectors(n, [1], [0], np.zeros((1, 9)))
+    assert e.value.status == ks.KS_EUNSUPPORTED
