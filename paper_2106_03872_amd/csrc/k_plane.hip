@@ -1,0 +1,181 @@
+// Plane passes of the Kohn-Sham Hamiltonian (HIP, gfx950): per m0 plane of
+// the plane-wave sphere, z- and y-synthesis into T, and y- and z-analysis of
+// U with the kinetic term and the Taylor-4 epilogue (Section
+// "Implementation of the KS Hamiltonian"; Section "Real-time propagation").
+#include "ks_common.hpp"
+
+namespace ks {
+
+// ----------------------------------------------------------- plane synthesis
+// Block (plane pi, orbital o).  LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1].
+// z-synthesis of each disk column straight from the packed coefficients into
+// Z; y-synthesis of YB r2-columns at a time straight from Z into T.
+
+template <int N, typename R, typename TIN>
+__global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ pk, int pk_stride,
+                                                        cplx<R>* __restrict__ Tout, SphereTab tab,
+                                                        const cplx<R>* __restrict__ twN, int ncol_max) {
+  using C = cplx<R>;
+  constexpr int YB = pnb<N>::value;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  C* Z = tw + N;
+  C* Y = Z + ncol_max * (N + 1);
+  __shared__ int s_off[130];
+  __shared__ int s_m2lo[129];
+  const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
+  const int m1lo = tab.plane_m1lo[pi];
+  for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
+  for (int i = tid; i <= nc; i += NTP) s_off[i] = tab.col_off[c0 + i];
+  for (int i = tid; i < nc; i += NTP) s_m2lo[i] = tab.col_m2lo[c0 + i];
+  __syncthreads();
+  const TIN* in = pk + (long long)o * pk_stride;
+  for (int cb = 0; cb < nc; cb += YB) {
+    fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
+        Z + cb * (N + 1), N + 1, nc - cb, tw,
+        [&](int t, int e) -> C {
+          const int c = cb + t;
+          const int idx = fold(e, N) - s_m2lo[c];
+          return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? cvt<C>(in[s_off[c] + idx]) : czero<C>();
+        },
+        no_store{});
+  }
+  C* out = Tout + ((long long)o * tab.nplanes + pi) * N * N;
+  for (int w0 = 0; w0 < N; w0 += YB) {
+    fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(
+        Y, N + 1, N - w0, tw,
+        [&](int t, int e) -> C {
+          const int c = fold(e, N) - m1lo;
+          return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
+        },
+        [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; });
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ plane analysis
+// Block (plane pi, orbital o): y-analysis of YB r2-columns of U at a time,
+// keeping the disk columns in Z; z-analysis of each column with the kinetic
+// term and the output mode applied to the outputs inside the sphere.
+
+template <int N, typename R, typename TW>
+__global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, const TW* win,
+                                                        cplx<R>* __restrict__ wout, double2* acc, int pk_stride,
+                                                        int acc_stride, SphereTab tab,
+                                                        const cplx<R>* __restrict__ twN, int ncol_max, int mode,
+                                                        Taylor tay, double g0, double g1, double g2) {
+  using C = cplx<R>;
+  constexpr int YB = pnb<N>::value;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  C* Z = tw + N;
+  C* Y = Z + ncol_max * (N + 1);
+  __shared__ int s_off[130];
+  __shared__ int s_m2lo[129];
+  const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
+  const int m1lo = tab.plane_m1lo[pi];
+  for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
+  for (int i = tid; i <= nc; i += NTP) s_off[i] = tab.col_off[c0 + i];
+  for (int i = tid; i < nc; i += NTP) s_m2lo[i] = tab.col_m2lo[c0 + i];
+  __syncthreads();
+  const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
+  for (int w0 = 0; w0 < N; w0 += YB) {
+    fft_io<N, -1, YB, NTP, SRC_FN, DST_FN, C>(
+        Y, N + 1, N - w0, tw, [&](int t, int e) -> C { return u[e * N + w0 + t]; },
+        [&](int t, int e, C v, int, int) {
+          const int c = fold(e, N) - m1lo;
+          if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
+        });
+    __syncthreads();
+  }
+  const double k0 = g0 * (tab.m0lo + pi);
+  const long long ob = (long long)o * pk_stride;
+  double2* accp = acc ? acc + (long long)o * acc_stride : nullptr;
+  for (int cb = 0; cb < nc; cb += YB) {
+    fft_io<N, -1, YB, NTP, SRC_LDS, DST_FN, C>(
+        Z + cb * (N + 1), N + 1, nc - cb, tw, no_load{}, [&](int t, int e, C ph, int, int) {
+          const int c = cb + t;
+          const int m2 = fold(e, N);
+          const int idx = m2 - s_m2lo[c];
+          if (idx < 0 || idx >= s_off[c + 1] - s_off[c]) return;
+          const int ep = s_off[c] + idx;
+          const double k1 = g1 * (m1lo + c), k2 = g2 * m2;
+          const double K = 0.5 * (k0 * k0 + k1 * k1 + k2 * k2);
+          const TW w = win[ob + ep];
+          const double2 hw{K * double(w.x) + double(ph.x), K * double(w.y) + double(ph.y)};
+          if (mode == H_OUT) {
+            wout[ob + ep] = to_c<C>(hw);
+          } else {
+            if (tay.write_w) wout[ob + ep] = to_c<C>(hw);
+            double2 av = accp[ep];
+            av.x += tay.coef.x * hw.x - tay.coef.y * hw.y;
+            av.y += tay.coef.x * hw.y + tay.coef.y * hw.x;
+            accp[ep] = av;
+          }
+        });
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+size_t plane_lds_bytes(const ks_system* s) {
+  const int N = s->n[1];
+  const int yb = N <= 64 ? 64 : (N <= 96 ? 48 : (N <= 120 ? 24 : 16));   // pnb<N>
+  const size_t es = s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2);
+  return es * ((size_t)N + (size_t)s->ncol_max * (N + 1) + (size_t)yb * (N + 1));
+}
+
+template <int N, typename R, typename TIN>
+static void plane_inv_t(const ks_system* s, int nb, const void* pk, void* T, const void* tw, hipStream_t st) {
+  plane_inv_kernel<N, R, TIN><<<dim3(s->nplanes, nb), NTP, plane_lds_bytes(s), st>>>(
+      (const TIN*)pk, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max);
+}
+
+template <int N>
+static void plane_inv_n(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, hipStream_t st) {
+  if (!mixed(s)) plane_inv_t<N, double, double2>(s, nb, pk, T, s->d_tw1, st);
+  else if (in_fp64) plane_inv_t<N, float, double2>(s, nb, pk, T, s->d_tw1f, st);
+  else plane_inv_t<N, float, float2>(s, nb, pk, T, s->d_tw1f, st);
+}
+
+bool launch_plane_inv(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, hipStream_t st) {
+  switch (s->n[1]) {
+#define KS_CASE(v) case v: plane_inv_n<v>(s, nb, pk, in_fp64, T, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+template <int N, typename R, typename TW>
+static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, HMode mode,
+                        Taylor tay, const void* tw, hipStream_t st) {
+  const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
+  plane_fwd_kernel<N, R, TW><<<dim3(s->nplanes, nb), NTP, plane_lds_bytes(s), st>>>(
+      (const cplx<R>*)U, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
+      sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
+}
+
+template <int N>
+static void plane_fwd_n(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
+                        void* acc, HMode mode, Taylor tay, hipStream_t st) {
+  if (!mixed(s)) plane_fwd_t<N, double, double2>(s, nb, U, win, wout, acc, mode, tay, s->d_tw1, st);
+  else if (win_fp64) plane_fwd_t<N, float, double2>(s, nb, U, win, wout, acc, mode, tay, s->d_tw1f, st);
+  else plane_fwd_t<N, float, float2>(s, nb, U, win, wout, acc, mode, tay, s->d_tw1f, st);
+}
+
+bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
+                      void* acc, HMode mode, Taylor tay, hipStream_t st) {
+  switch (s->n[1]) {
+#define KS_CASE(v) case v: plane_fwd_n<v>(s, nb, U, win, win_fp64, wout, acc, mode, tay, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+}  // namespace ks

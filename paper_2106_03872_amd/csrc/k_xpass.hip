@@ -1,0 +1,234 @@
+// x-pencil passes of the Kohn-Sham Hamiltonian (HIP, gfx950): x-synthesis
+// in LDS, Kleinman-Bylander projections (Eq. vnl), local potential and KB
+// scatter, x-analysis; the density sum (Eq. density).
+#include "ks_common.hpp"
+
+namespace ks {
+
+// -------------------------------------------------------------- x-pencil passes
+// Block (tile of NB consecutive pencils p = j1*n2 + j2, orbital o).  The
+// x-synthesis reads T (planes m0 of each pencil) straight into its first
+// stage; LDS X[w][j0] holds one exchange buffer of the tile.
+
+template <int N0, int NB, typename C>
+struct TLoader {
+  const C* Tin;
+  int npl, nplanes, m0lo, p0;
+  __device__ C operator()(int t, int e) const {
+    const int pi = fold(e, N0) - m0lo;
+    const int p = p0 + t;
+    return (pi >= 0 && pi < nplanes && p < npl) ? Tin[(long long)pi * npl + p] : czero<C>();
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+template <int N0, typename R>
+__global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ partial,
+                                                   SphereTab tab, ProjTab pt, const cplx<R>* __restrict__ tw0,
+                                                   double scale) {
+  using C = cplx<R>;
+  constexpr int NB = xnb<N0>::value;
+  __shared__ C X[NB * (N0 + 1)];
+  const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int npl = tab.n1 * tab.n2;
+  const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
+  if (ns == 0) return;  // no sphere point in this tile (uniform per block)
+  const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, tile * NB};
+  fft_io<N0, +1, NB, NT, SRC_FN, DST_LDS, C>(X, N0 + 1, NB, tw0, ld, no_store{});
+  const int np = pt.nproj;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int sl = wave; sl < ns; sl += NT / 64) {
+    const int k0 = pt.slot_pt[sA + sl], k1 = pt.slot_pt[sA + sl + 1];
+    double ax[KB_MAX_NPROJ], ay[KB_MAX_NPROJ];
+#pragma unroll
+    for (int q = 0; q < KB_MAX_NPROJ; ++q) ax[q] = ay[q] = 0.0;
+    for (int base = k0; base < k1; base += 64) {
+      const int k = base + lane;
+      C x = czero<C>();
+      if (k < k1) x = X[pt.pt_lds[k]];
+      const double* b = pt.beta + (long long)k * np;
+#pragma unroll
+      for (int q = 0; q < KB_MAX_NPROJ; ++q) {
+        if (q < np) {
+          const double bv = k < k1 ? b[q] : 0.0;
+          ax[q] += wave_sum(bv * double(x.x));
+          ay[q] += wave_sum(bv * double(x.y));
+        }
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < KB_MAX_NPROJ; ++q)
+        if (q < np) partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(ax[q] * scale), R(ay[q] * scale)};
+    }
+  }
+}
+
+template <int N0, typename R>
+__global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ Uout,
+                                                    const double* __restrict__ V, const double2* __restrict__ DP,
+                                                    SphereTab tab, ProjTab pt, const cplx<R>* __restrict__ tw0,
+                                                    double sc_in, double sc_out) {
+  using C = cplx<R>;
+  constexpr int NB = xnb<N0>::value;
+  using LS = last_shape<N0, NB, NT>;
+  __shared__ C X[NB * (N0 + 1)];
+  __shared__ double2 dps[KB_TILE_DP];
+  const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int npl = tab.n1 * tab.n2;
+  const int p0 = tile * NB;
+  // potential at the outputs of this thread's last synthesis stage (times Omega^-1/2)
+  double vr[LS::items][LS::radix];
+  last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+    vr[it][q] = (p0 + t < npl) ? V[(long long)e * npl + p0 + t] * sc_in : 0.0;
+  });
+  const int np = pt.nproj;
+  const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
+  for (int i = tid; i < ns * np; i += NT) {
+    const int sl = i / np, q = i - sl * np;
+    dps[i] = DP[((long long)o * pt.natoms + pt.slot_atom[sA + sl]) * np + q];
+  }
+  const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
+  // synthesis, then psi <- V psi as the outputs are written
+  fft_io<N0, +1, NB, NT, SRC_FN, DST_FN_LDS, C>(X, N0 + 1, NB, tw0, ld, [&](int t, int e, C v, int it, int q) {
+    X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
+  });
+  if (ns > 0) {
+    const int uA = pt.up_off[tile], uB = pt.up_off[tile + 1];
+    for (int u = uA + tid; u < uB; u += NT) {
+      double fx = 0.0, fy = 0.0;
+      for (int e = pt.up_ent[u]; e < pt.up_ent[u + 1]; ++e) {
+        const double* b = pt.beta + (long long)pt.ent_brow[e] * np;
+        const double2* dp = dps + pt.ent_slot[e] * np;
+        for (int q = 0; q < np; ++q) {
+          fx += b[q] * dp[q].x;
+          fy += b[q] * dp[q].y;
+        }
+      }
+      C& x = X[pt.up_lds[u]];
+      x = C{R(double(x.x) + fx), R(double(x.y) + fy)};
+    }
+    __syncthreads();
+  }
+  C* out = Uout + (long long)o * tab.nplanes * npl;
+  const int nplanes = tab.nplanes, m0lo = tab.m0lo;
+  fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw0, no_load{}, [&](int t, int e, C v, int, int) {
+    const int pi = fold(e, N0) - m0lo;
+    const int p = p0 + t;
+    if (pi >= 0 && pi < nplanes && p < npl)
+      out[(long long)pi * npl + p] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
+  });
+}
+
+// density: block = tile, loops over the nb orbitals of the chunk in order;
+// |psi|^2 is accumulated straight from the last synthesis stage.
+template <int N0, typename R>
+__global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ Tin, int nb,
+                                                   const double* __restrict__ occ, double* __restrict__ rho,
+                                                   int accumulate, SphereTab tab, const cplx<R>* __restrict__ tw0,
+                                                   double inv_omega) {
+  using C = cplx<R>;
+  constexpr int NB = xnb<N0>::value;
+  using LS = last_shape<N0, NB, NT>;
+  __shared__ C X[NB * (N0 + 1)];
+  const int tile = blockIdx.x;
+  const int npl = tab.n1 * tab.n2;
+  const int p0 = tile * NB;
+  double a[LS::items][LS::radix];
+#pragma unroll
+  for (int it = 0; it < LS::items; ++it)
+#pragma unroll
+    for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
+  for (int o = 0; o < nb; ++o) {
+    const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
+    const double f = occ[o] * inv_omega;
+    fft_io<N0, +1, NB, NT, SRC_FN, DST_FN, C>(X, N0 + 1, NB, tw0, ld, [&](int, int, C v, int it, int q) {
+      a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
+    });
+    __syncthreads();
+  }
+  last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+    const int p = p0 + t;
+    if (p < npl) {
+      double* r = rho + (long long)e * npl + p;
+      *r = accumulate ? *r + a[it][q] : a[it][q];
+    }
+  });
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int N0>
+static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
+  const double scale = s->dV / sqrt(s->omega);
+  if (!mixed(s))
+    xproj_kernel<N0, double><<<dim3(s->ntiles, nb), NT, 0, st>>>((const double2*)T, (double2*)partial,
+                                                                  sphere_tab(s), proj_tab(s), s->d_tw0, scale);
+  else
+    xproj_kernel<N0, float><<<dim3(s->ntiles, nb), NT, 0, st>>>((const float2*)T, (float2*)partial, sphere_tab(s),
+                                                                 proj_tab(s), s->d_tw0f, scale);
+}
+
+bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
+  switch (s->n[0]) {
+#define KS_CASE(v) case v: xproj_n<v>(s, nb, T, partial, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+template <int N0>
+static void xapply_n(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
+  const double sc_in = 1.0 / sqrt(s->omega);
+  const double sc_out = sqrt(s->omega) / (double)s->N;
+  if (!mixed(s))
+    xapply_kernel<N0, double><<<dim3(s->ntiles, nb), NT, 0, st>>>((const double2*)T, (double2*)U, s->d_v, DP,
+                                                                   sphere_tab(s), proj_tab(s), s->d_tw0, sc_in,
+                                                                   sc_out);
+  else
+    xapply_kernel<N0, float><<<dim3(s->ntiles, nb), NT, 0, st>>>((const float2*)T, (float2*)U, s->d_v, DP,
+                                                                  sphere_tab(s), proj_tab(s), s->d_tw0f, sc_in,
+                                                                  sc_out);
+}
+
+bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
+  switch (s->n[0]) {
+#define KS_CASE(v) case v: xapply_n<v>(s, nb, T, DP, U, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+template <int N0>
+static void xdens_n(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
+                    hipStream_t st) {
+  if (!mixed(s))
+    xdens_kernel<N0, double><<<dim3(s->ntiles), NT, 0, st>>>((const double2*)T, nb, occ, rho, accumulate,
+                                                              sphere_tab(s), s->d_tw0, 1.0 / s->omega);
+  else
+    xdens_kernel<N0, float><<<dim3(s->ntiles), NT, 0, st>>>((const float2*)T, nb, occ, rho, accumulate,
+                                                             sphere_tab(s), s->d_tw0f, 1.0 / s->omega);
+}
+
+bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
+                  hipStream_t st) {
+  switch (s->n[0]) {
+#define KS_CASE(v) case v: xdens_n<v>(s, nb, T, occ, rho, accumulate, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+}  // namespace ks

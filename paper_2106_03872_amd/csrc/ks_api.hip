@@ -110,6 +110,16 @@ std::vector<double2> twiddles(int n) {
   return t;
 }
 
+std::vector<float2> twiddles_f(int n) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<float2> t(n);
+  for (int j = 0; j < n; ++j) {
+    const long double a = 2.0L * pi * (long double)j / (long double)n;
+    t[j] = float2{(float)cosl(a), (float)(-sinl(a))};
+  }
+  return t;
+}
+
 // |G|^2/2 for integer frequencies (same operation order as the definition
 // K = ((g0^2 + g1^2) + g2^2) / 2 with g_a = (2 pi m_a) / L_a)
 double kin(const double L[3], int m0, int m1, int m2) {
@@ -321,12 +331,13 @@ ks_status alloc_proj_workspace(ks_system* s) {
 
 ks_status alloc_workspace(ks_system* s) {
   free_workspace(s);
-  const size_t pk = (size_t)s->cb * s->npw_stride * sizeof(double2);
-  for (auto& p : s->pk) {
-    ks_status st = dalloc(s, &p, pk);
+  const size_t es = s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2);   // working precision
+  for (int i = 0; i < 3; ++i) {
+    // pk[0] holds the FP64 orbital state / Taylor accumulator
+    ks_status st = dalloc(s, &s->pk[i], (size_t)s->cb * s->npw_stride * (i == 0 ? sizeof(double2) : es));
     if (st != KS_OK) return st;
   }
-  const size_t tb = (size_t)s->cb * s->nplanes * s->npl * sizeof(double2);
+  const size_t tb = (size_t)s->cb * s->nplanes * s->npl * es;
   ks_status st = dalloc(s, &s->T, tb);
   if (st != KS_OK) return st;
   st = dalloc(s, &s->U, tb);
@@ -335,7 +346,7 @@ ks_status alloc_workspace(ks_system* s) {
 }
 
 int default_chunk(const ks_system* s) {
-  const double per = (double)s->nplanes * s->npl * sizeof(double2);
+  const double per = (double)s->nplanes * s->npl * (s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2));
   int cb = (int)std::max(1.0, std::floor(96.0 * 1024 * 1024 / per));
   return std::max(1, std::min(cb, s->max_norb));
 }
@@ -348,9 +359,10 @@ ks_status check_common(ks_system* s, int norb) {
 }
 
 // H applied to nb packed orbitals win; result per mode (see plane_fwd_kernel)
-ks_status hpsi_packed(ks_system* s, int nb, const void* win, void* wout, void* acc, HMode mode, Taylor tay,
+// win_fp64: the input is the FP64 orbital state (else the working precision)
+ks_status hpsi_packed(ks_system* s, int nb, const void* win, bool win_fp64, void* wout, void* acc, HMode mode, Taylor tay,
                       hipStream_t st) {
-  ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, win, s->T, st); });
+  ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, win, win_fp64, s->T, st); });
   if (r != KS_OK) return r;
   if (s->natoms > 0) {
     r = kcall(s, KS_K_XPROJ, st, "xproj", [&] { return launch_xproj(s, nb, s->T, s->partial, st); });
@@ -360,12 +372,12 @@ ks_status hpsi_packed(ks_system* s, int nb, const void* win, void* wout, void* a
   }
   r = kcall(s, KS_K_XAPPLY, st, "xapply", [&] { return launch_xapply(s, nb, s->T, s->DP, s->U, st); });
   if (r != KS_OK) return r;
-  return kcall(s, KS_K_PLANE_FWD, st, "plane_fwd", [&] { return launch_plane_fwd(s, nb, s->U, win, wout, acc, mode, tay, st); });
+  return kcall(s, KS_K_PLANE_FWD, st, "plane_fwd", [&] { return launch_plane_fwd(s, nb, s->U, win, win_fp64, wout, acc, mode, tay, st); });
 }
 
 ks_status density_packed(ks_system* s, int nb, const void* pk, const double* occ, double* rho, int accumulate,
                          hipStream_t st) {
-  ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, pk, s->T, st); });
+  ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, pk, true, s->T, st); });
   if (r != KS_OK) return r;
   return kcall(s, KS_K_XDENS, st, "xdens", [&] { return launch_xdens(s, nb, s->T, occ, rho, accumulate, st); });
 }
@@ -387,7 +399,7 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   }
   if (n[1] != n[2]) return fail(nullptr, KS_EINVAL, "n1 must equal n2");
   if (max_norb < 1) return fail(nullptr, KS_EINVAL, "max_norb must be >= 1");
-  if (precision != KS_FP64) return fail(nullptr, KS_EUNSUPPORTED, "only KS_FP64 is available");
+  if (precision != KS_FP64 && precision != KS_MIXED) return fail(nullptr, KS_EUNSUPPORTED, "unknown precision");
   if (!std::isfinite(ecut)) return fail(nullptr, KS_EINVAL, "ecut must be finite");
 
   ks_system* s = new ks_system();
@@ -435,7 +447,8 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   if ((st = upload(s, &s->d_plane_col0, plane_col0)) != KS_OK ||
       (st = upload(s, &s->d_plane_m1lo, plane_m1lo)) != KS_OK ||
       (st = upload(s, &s->d_col_off, col_off)) != KS_OK || (st = upload(s, &s->d_col_m2lo, col_m2lo)) != KS_OK ||
-      (st = upload(s, &s->d_tw0, twiddles(n[0]))) != KS_OK || (st = upload(s, &s->d_tw1, twiddles(n[1]))) != KS_OK) {
+      (st = upload(s, &s->d_tw0, twiddles(n[0]))) != KS_OK || (st = upload(s, &s->d_tw1, twiddles(n[1]))) != KS_OK ||
+      (st = upload(s, &s->d_tw0f, twiddles_f(n[0]))) != KS_OK || (st = upload(s, &s->d_tw1f, twiddles_f(n[1]))) != KS_OK) {
     g_create_err = s->err;
     ks_system_destroy(s);
     return st;
@@ -552,8 +565,9 @@ ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void
     const double2* in = (const double2*)psi + (size_t)o0 * s->N;
     double2* out = (double2*)hpsi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, in, s->N, s->pk[0], st); })) != KS_OK) return r;
-    if ((r = hpsi_packed(s, nb, s->pk[0], s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
-    if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[1], out, s->N, st); })) != KS_OK) return r;
+    if ((r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
+    const bool fp64 = s->prec == KS_FP64;
+    if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[1], fp64, out, s->N, st); })) != KS_OK) return r;
   }
   return KS_OK;
 }
@@ -590,14 +604,15 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
       void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
       for (int k = 1; k <= 4; ++k) {
         Taylor tay{coef[k], k < 4 ? 1 : 0};
-        if ((r = hpsi_packed(s, nb, src[k - 1], dst[k - 1], s->pk[0], H_TAYLOR, tay, st)) != KS_OK) return r;
+        const bool in64 = k == 1 || s->prec == KS_FP64;
+        if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], s->pk[0], H_TAYLOR, tay, st)) != KS_OK) return r;
       }
       if (rho) {
         if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho + (size_t)step * s->N, o0 > 0, st)) != KS_OK)
           return r;
       }
     }
-    if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[0], box, s->N, st); })) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[0], true, box, s->N, st); })) != KS_OK) return r;
   }
   return KS_OK;
 }
@@ -637,7 +652,7 @@ ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, 
     const int nb = std::min(s->cb, norb - o0);
     const double2* box = (const double2*)psi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
-    if (energy && (r = hpsi_packed(s, nb, s->pk[0], s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
+    if (energy && (r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
     const void* hp = energy ? s->pk[1] : nullptr;
     double* red = s->red + 2 * (size_t)o0;
     if ((r = kcall(s, KS_K_DOTS, st, "dots", [&] { return launch_dots(s, nb, s->pk[0], hp, red, st); })) != KS_OK)
@@ -680,7 +695,7 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   KS_HIP(s, hipMemcpyAsync(&info, s->ortho_info, sizeof(int), hipMemcpyDeviceToHost, st));
   KS_HIP(s, hipStreamSynchronize(st));
   if (info) return fail(s, KS_EINVAL, "overlap matrix is not positive definite (orbitals linearly dependent)");
-  return kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, norb, Y, box, s->N, st); });
+  return kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, norb, Y, true, box, s->N, st); });
 }
 
 ks_status ks_plan_sphere(const int n[3], const double L[3], double ecut, int* npw, int* m_out) {

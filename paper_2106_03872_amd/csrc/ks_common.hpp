@@ -1,0 +1,79 @@
+// Device helpers and launch constants shared by the kernel translation units.
+#pragma once
+#include "fft_device.hpp"
+#include "ks_internal.h"
+
+namespace ks {
+
+constexpr int NT = 256;   // threads per x-pencil block
+
+#define KS_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128)
+
+// pencils per x-tile (host side: x_tile_nb)
+template <int N> struct xnb { static constexpr int value = N <= 32 ? 64 : 32; };
+constexpr int NTP = 384; // threads per plane-pass block
+
+template <typename T> __device__ __forceinline__ T czero() { return T{0, 0}; }
+
+template <typename T> __device__ __forceinline__ T to_c(double2 a) {
+  return T{static_cast<decltype(T{}.x)>(a.x), static_cast<decltype(T{}.x)>(a.y)};
+}
+template <typename T> __device__ __forceinline__ double2 to_d(T a) { return double2{double(a.x), double(a.y)}; }
+template <typename C, typename T> __device__ __forceinline__ C cvt(T a) {
+  using E = decltype(C{}.x);
+  return C{E(a.x), E(a.y)};
+}
+
+// largest c in [0, nc) with off[c] <= e (off ascending)
+__device__ __forceinline__ int find_col(const int* off, int nc, int e) {
+  int lo = 0, hi = nc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+
+template <int N> struct pnb { static constexpr int value = N <= 64 ? 64 : (N <= 96 ? 48 : (N <= 120 ? 24 : 16)); };
+
+inline SphereTab sphere_tab(const ks_system* s) {
+
+  SphereTab t;
+  t.plane_col0 = s->d_plane_col0;
+  t.plane_m1lo = s->d_plane_m1lo;
+  t.col_off = s->d_col_off;
+  t.col_m2lo = s->d_col_m2lo;
+  t.nplanes = s->nplanes;
+  t.m0lo = s->m0lo;
+  t.n0 = s->n[0];
+  t.n1 = s->n[1];
+  t.n2 = s->n[2];
+  return t;
+}
+
+inline ProjTab proj_tab(const ks_system* s) {
+  ProjTab c;
+  c.pt_lds = s->d_pt_lds;
+  c.slot_off = s->d_slot_off;
+  c.slot_atom = s->d_slot_atom;
+  c.slot_pt = s->d_slot_pt;
+  c.atom_slot_off = s->d_atom_slot_off;
+  c.atom_slots = s->d_atom_slots;
+  c.up_off = s->d_up_off;
+  c.up_lds = s->d_up_lds;
+  c.up_ent = s->d_up_ent;
+  c.ent_slot = s->d_ent_slot;
+  c.ent_brow = s->d_ent_brow;
+  c.beta = s->d_beta;
+  c.d = s->d_kb;
+  c.natoms = s->natoms;
+  c.nproj = s->nproj;
+  c.nslots = s->nslots;
+  return c;
+}
+
+
+inline bool mixed(const ks_system* s) { return s->prec == KS_MIXED; }
+
+}  // namespace ks

@@ -123,19 +123,18 @@ namespace ks {
 // launchers (ks_kernels.hip); return false when the size has no kernel
 bool launch_pack(const ks_system* s, int nb, const double2* box, long long box_stride, void* pk,
                  hipStream_t st);
-bool launch_unpack(const ks_system* s, int nb, const void* pk, double2* box, long long box_stride,
+bool launch_unpack(const ks_system* s, int nb, const void* pk, bool pk_fp64, double2* box, long long box_stride,
                    hipStream_t st);
-bool launch_plane_inv(const ks_system* s, int nb, const void* pk, void* T, hipStream_t st);
+bool launch_plane_inv(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, hipStream_t st);
 bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st);
 bool launch_proj_reduce(const ks_system* s, int nb, const void* partial, double2* DP, hipStream_t st);
 bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st);
-bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc,
-                      HMode mode, Taylor tay, hipStream_t st);
+bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
+                      void* acc, HMode mode, Taylor tay, hipStream_t st);
 bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
                   hipStream_t st);
 bool launch_dots(const ks_system* s, int nb, const void* a, const void* b, double* out, hipStream_t st);
 bool launch_energy_sum(int norb, const double* occ, const double* red, double* energy, hipStream_t st);
-
 bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hipStream_t st);
 bool launch_cholesky(int n, double2* S, int* info, hipStream_t st);
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);

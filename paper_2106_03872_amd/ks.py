@@ -298,11 +298,11 @@ def orthonormalize(system, psi):
     return system.orthonormalize(psi)
 
 
-def system_from_synth(sysm, max_norb=None, ecut=None):
+def system_from_synth(sysm, max_norb=None, ecut=None, precision=KS_FP64):
     """Create a System from a synth.System (potential + projectors uploaded)."""
     import torch
     spec = sysm.spec
-    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb)
+    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb, precision)
     s.set_vloc(torch.from_numpy(sysm.vloc).to("cuda"))
     p = sysm.proj
     s.set_projectors(p.npts, p.idx, p.beta, p.d)
