@@ -85,6 +85,91 @@ def cpu_baseline(spec, sysm, norb_sample=128):
                       f"{spec.n[0]}^3 grid, {spec.natoms} atoms; {dt:.1f} s"}
 
 
+def setup_workload(spec, precision, chunk=0):
+    """System + orthonormalised resident orbitals of one workload."""
+    import torch
+
+    from paper_2106_03872_amd import ks, synth
+    sysm = synth.system(spec)
+    dev = torch.device("cuda:0")
+    gs = ks.system_from_synth(sysm, precision=precision)
+    if chunk:
+        gs.set_chunk(chunk)
+    sel, vals = synth.orbital_values(spec)
+    c = torch.zeros((spec.norb, spec.npoints), dtype=torch.complex128, device=dev)
+    c[:, torch.from_numpy(sel).to(dev)] = torch.from_numpy(vals).to(dev)
+    c = c.reshape((spec.norb,) + tuple(spec.n))
+    del vals
+    gs.orthonormalize(c)                 # Cholesky of the overlap (set-up)
+    state = ks.State(gs, spec.norb)
+    state.upload(c)
+    del c
+    torch.cuda.synchronize()
+    return sysm, gs, state
+
+
+def run_steps(spec, gs, state, steps, warmup, timing=True):
+    """Warm up, then time `steps` steps (Taylor-4 + density + norms)."""
+    import torch
+    occ = torch.full((spec.norb,), float(spec.occ), dtype=torch.float64, device="cuda")
+    rho = torch.empty((1,) + tuple(spec.n), dtype=torch.float64, device="cuda")
+    norms0, e0 = state.reduce(occ)
+    for _ in range(warmup):
+        state.propagate(spec.dt, 1, occ, rho)
+        state.reduce(None, want_energy=False)
+    torch.cuda.synchronize()
+    if timing:
+        gs.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        state.propagate(spec.dt, 1, occ, rho)
+        state.reduce(None, want_energy=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = gs.kernel_times() if timing else {}
+    if timing:
+        gs.set_kernel_timing(False)
+    norms1, e1 = state.reduce(occ)
+    nel = float(occ.sum().item())
+    phys = {"norm_drift_max": float(torch.max(torch.abs(norms1 / norms0 - 1.0)).item()),
+            "band_energy_per_electron_start": e0.item() / nel, "band_energy_per_electron_end": e1.item() / nel,
+            "steps_total": warmup + steps}
+    return (t1 - t0) * 1e3 / steps, kt, phys, rho
+
+
+def kernel_table(info, spec, ktimes, steps, ms_step):
+    orbitals = {"plane_inv": 5 * spec.norb, "xproj": 4 * spec.norb, "proj_reduce": 4 * spec.norb,
+                "xapply": 4 * spec.norb, "plane_fwd": 4 * spec.norb, "xdens": spec.norb, "pack": 0,
+                "unpack": 0, "dots": spec.norb}
+    es = 16 if info["precision"] == 0 else 8
+    kernels = {}
+    for name, (ms, n) in ktimes.items():
+        if n == 0:
+            continue
+        po, pl = alg_bytes(info, spec, name, S=es)
+        byt = po * orbitals[name] * steps + pl * n
+        kernels[name] = {"ms_total": round(ms, 3), "launches": n, "avg_us": round(1e3 * ms / n, 2),
+                         "share": round(ms / (ms_step * steps), 4), "alg_GBs": round(byt / (ms * 1e-3) / 1e9, 1)}
+    return kernels
+
+
+def run_serving(nreq, nsteps, budget_gb, log):
+    from paper_2106_03872_amd import serve, synth
+    trace = synth.serving_trace(nreq, 200.0, 2000)
+    reqs = [serve.Request(rid=i, arrival=t, spec=sp, nsteps=nsteps) for i, (t, sp) in enumerate(trace)]
+    be = serve.HipBackend()
+    log(f"[bench] serving: preparing {nreq} requests")
+    be.prepare(reqs)
+    srv = serve.Server(be, int(budget_gb * 2 ** 30))
+    done = srv.run(reqs)
+    rep = serve.Server.report(done, srv.elapsed, serve.hpsi_per_step)
+    rep.update({"hbm_budget_GiB": budget_gb, "max_resident_GiB": round(srv.max_used / 2 ** 30, 2),
+                "precision": "mixed", "steps_per_request": nsteps, "arrivals": "Poisson, mean 200/s",
+                "drift_max": max(float(abs(r.result["norms"] - 1.0).max()) for r in done)})
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +178,11 @@ def main():
     ap.add_argument("--workload", default="cfg3_96")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-steps", type=int, default=50)
+    ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -106,81 +196,52 @@ def main():
 
     from paper_2106_03872_amd import ks, synth
     spec = synth.CONFIGS[args.workload]
+    torch.cuda.set_device(0)
     log(f"[bench] workload {spec.name}: n={spec.n} L={spec.L} norb={spec.norb} natoms={spec.natoms}")
-    sysm = synth.system(spec)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    gs = ks.system_from_synth(sysm)
-    if args.chunk:
-        gs.set_chunk(args.chunk)
+    sysm, gs, state = setup_workload(spec, ks.KS_FP64, args.chunk)
     info = gs.info()
-    sel, vals = synth.orbital_values(spec)
-    c = torch.zeros((spec.norb, spec.npoints), dtype=torch.complex128, device=dev)
-    c[:, torch.from_numpy(sel).to(dev)] = torch.from_numpy(vals).to(dev)
-    c = c.reshape((spec.norb,) + tuple(spec.n))
-    del vals
-    occ = torch.full((spec.norb,), float(spec.occ), dtype=torch.float64, device=dev)
-    rho = torch.empty((1,) + tuple(spec.n), dtype=torch.float64, device=dev)
-    try:
-        gs.orthonormalize(c)
-        ortho = True
-    except ks.KSError:
-        norms0, _ = gs.reduce(c, None, want_energy=False)
-        c /= torch.sqrt(norms0).reshape(-1, 1, 1, 1)
-        ortho = False
-    norms_start, e_start = gs.reduce(c, occ)
-    torch.cuda.synchronize()
-    log(f"[bench] set-up done (orthonormalised: {ortho}), chunk {info['chunk']}, npw {info['npw']}")
-
-    for _ in range(args.warmup):
-        gs.propagate_step(c, spec.dt, 1, occ, rho)
-        gs.reduce(c, None, want_energy=False)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} steps done")
-
-    gs.set_kernel_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        gs.propagate_step(c, spec.dt, 1, occ, rho)
-        norms, _ = gs.reduce(c, None, want_energy=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ktimes = gs.kernel_times()
-    gs.set_kernel_timing(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    log(f"[bench] FP64 set-up done, chunk {info['chunk']}, npw {info['npw']}")
+    ms_step, ktimes, phys, rho64 = run_steps(spec, gs, state, args.steps, args.warmup)
     hpsi_per_step = 4 * spec.norb
     value = hpsi_per_step / (ms_step * 1e-3)
-    log(f"[bench] {args.steps} steps: {ms_step:.2f} ms/step, {value:.1f} orbital.Hpsi/s")
-
-    norms_end, e_end = gs.reduce(c, occ)
-    drift = float(torch.max(torch.abs(norms_end / norms_start - 1.0)).item())
-    nel = float(occ.sum().item())
-
-    # per-kernel achieved bandwidth from the event times
-    nsteps_total = args.steps
-    orbitals = {"plane_inv": 5 * spec.norb, "xproj": 4 * spec.norb, "proj_reduce": 4 * spec.norb,
-                "xapply": 4 * spec.norb, "plane_fwd": 4 * spec.norb, "xdens": spec.norb, "pack": 2 * spec.norb,
-                "unpack": spec.norb, "dots": spec.norb}
-    kernels = {}
-    for name, (ms, n) in ktimes.items():
-        if n == 0:
-            continue
-        po, pl = alg_bytes(info, spec, name)
-        byt = po * orbitals[name] * nsteps_total + pl * n
-        kernels[name] = {"ms_total": round(ms, 3), "launches": n, "avg_us": round(1e3 * ms / n, 2),
-                         "share": round(ms / (ms_step * args.steps), 4),
-                         "alg_GBs": round(byt / (ms * 1e-3) / 1e9, 1)}
+    log(f"[bench] FP64 {args.steps} steps: {ms_step:.2f} ms/step, {value:.1f} orbital.Hpsi/s")
+    kernels = kernel_table(info, spec, ktimes, args.steps, ms_step)
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dk = kernels[dom]
+    po, pl = alg_bytes(info, spec, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dk["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_us": dk["avg_us"],
-            "alg_bytes_per_orbital": alg_bytes(info, spec, dom)[0],
-            "alg_bytes_per_launch_shared": alg_bytes(info, spec, dom)[1]}
+            "frac": round(dk["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_us": dk["avg_us"],
+            "alg_bytes_per_orbital": po, "alg_bytes_per_launch_shared": pl}
+    psi64 = state.download()
+    state.close()
+    gs.close()
+
+    mixed = None
+    if not args.no_mixed:
+        _, gm, sm = setup_workload(spec, ks.KS_MIXED, 0)
+        ms_m, kt_m, phys_m, _ = run_steps(spec, gm, sm, args.steps, args.warmup)
+        psim = sm.download()
+        # compare after the same number of steps from the same orthonormalised start
+        d = (psim - psi64).reshape(spec.norb, -1).norm(dim=1) / psi64.reshape(spec.norb, -1).norm(dim=1)
+        mixed = {"value": round(hpsi_per_step / (ms_m * 1e-3), 1), "ms_per_step": round(ms_m, 3),
+                 "speedup_vs_fp64": round(ms_step / ms_m, 3), "orbital_rel_err_vs_fp64_max": float(d.max().item()),
+                 "band_energy_per_electron_diff_vs_fp64":
+                     abs(phys_m["band_energy_per_electron_end"] - phys["band_energy_per_electron_end"]),
+                 "kernels": kernel_table(gm.info(), spec, kt_m, args.steps, ms_m), "chunk": gm.info()["chunk"]}
+        log(f"[bench] mixed: {ms_m:.2f} ms/step ({mixed['speedup_vs_fp64']}x), err vs FP64 {mixed['orbital_rel_err_vs_fp64_max']:.2e}")
+        sm.close()
+        gm.close()
+        del psim
+    del psi64
+
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log)
+        log(f"[bench] serving: p50 {serving['step_latency_ms_p50']:.2f} ms, p99 {serving['step_latency_ms_p99']:.2f} ms, "
+            f"{serving['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s over {serving['makespan_s']:.1f} s")
 
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         a.fill_(1.0)
         b = torch.empty_like(a)
         for _ in range(3):
@@ -208,14 +269,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded Gaussian potential, KB projectors and orbitals; no pseudopotential files)",
         "config": {"workload": f"{spec.name}: {spec.n[0]}x{spec.n[1]}x{spec.n[2]} grid, L={spec.L[0]} bohr, "
-                               f"{spec.norb} orbitals (f={spec.occ}), {spec.natoms} atoms x 4 KB projectors, "
-                               f"E_cut={spec.ecut} Ha, Taylor-4 dt={spec.dt} + density + norms per step",
+                               f"{spec.norb} orthonormalised orbitals (f={spec.occ}), {spec.natoms} atoms x 4 KB "
+                               f"projectors, E_cut={spec.ecut} Ha; step = Taylor-4 (dt={spec.dt}) + density + norms "
+                               f"on HBM-resident orbitals",
                    "global_batch": spec.norb, "grid": list(spec.n), "npw": info["npw"],
                    "chunk": info["chunk"], "hpsi_per_step": hpsi_per_step, "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": kernels,
-        "physics": {"norm_drift_max": drift, "band_energy_per_electron_start": e_start.item() / nel,
-                    "band_energy_per_electron_end": e_end.item() / nel, "steps_total": args.warmup + args.steps},
+        "physics": phys,
+        "mixed": mixed,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -51,7 +51,8 @@ typedef enum {
 
 typedef enum {
   KS_FP64 = 0,          /* all arithmetic in float64 / complex128 */
-  KS_MIXED = 1          /* reserved: FP32 transforms, FP64 accumulators */
+  KS_MIXED = 1          /* FP32 (complex64) transforms and pointwise work; orbital
+                           state, Taylor sum, density, norms, energy in FP64 */
 } ks_precision;
 
 typedef struct ks_system ks_system;
@@ -147,6 +148,43 @@ ks_status ks_reduce(ks_system* sys, int norb, const void* psi, const double* occ
  * call allocates a workspace for max_norb orbitals.
  */
 ks_status ks_orthonormalize(ks_system* sys, int norb, void* psi, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Resident orbitals.  A ks_state holds norb orbitals of one system on the
+ * device in the library's packed FP64 sphere layout, so that repeated steps
+ * need no box conversion.  It belongs to its system (same stream rules) and
+ * must be destroyed before the system.
+ */
+typedef struct ks_state ks_state;
+
+/* Allocate the state (device memory for norb packed orbitals). */
+ks_status ks_state_create(ks_system* sys, int norb, ks_state** out);
+/* Free the state (synchronises the device). */
+void ks_state_destroy(ks_state* state);
+/* psi (device complex128 box [norb][n0][n1][n2]) -> state; outside chi ignored. */
+ks_status ks_state_upload(ks_state* state, const void* psi, void* stream);
+/* state -> psi (device complex128 box; zero outside chi). */
+ks_status ks_state_download(ks_state* state, void* psi, void* stream);
+/* As ks_propagate_step, on the resident orbitals. */
+ks_status ks_state_propagate(ks_state* state, double dt, int nsteps, const double* occ, double* rho, void* stream);
+/* As ks_reduce, on the resident orbitals. */
+ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, double* energy, void* stream);
+/*
+ * Capture one propagation step (ks_state_propagate with nsteps = 1 and the
+ * given dt, occ, rho) into a HIP graph owned by the state; stream must not be
+ * the default stream and kernel timing must be off.  Replaces an earlier
+ * capture.  ks_state_replay launches the captured step on any stream.
+ */
+ks_status ks_state_capture(ks_state* state, double dt, const double* occ, double* rho, void* stream);
+ks_status ks_state_replay(ks_state* state, void* stream);
+
+/*
+ * Device bytes a system of this shape plus a resident state of norb orbitals
+ * will hold (host-only estimate for admission control; npoints = projector
+ * points, chunk = 0 for the default chunk).
+ */
+ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int precision, int norb, int npoints,
+                            int nproj, int chunk, unsigned long long* bytes);
 
 /* Number of plane waves in the sphere (packed coefficients per orbital). */
 int ks_system_npw(const ks_system* sys);

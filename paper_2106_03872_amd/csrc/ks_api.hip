@@ -382,6 +382,40 @@ ks_status density_packed(ks_system* s, int nb, const void* pk, const double* occ
   return kcall(s, KS_K_XDENS, st, "xdens", [&] { return launch_xdens(s, nb, s->T, occ, rho, accumulate, st); });
 }
 
+// (-i dt)^k / k!, k = 0..4 (truncated Taylor series of exp(-i H dt))
+void taylor_coefficients(double dt, double2 coef[5]) {
+  double re = 1.0, im = 0.0;
+  coef[0] = double2{1.0, 0.0};
+  for (int k = 1; k <= 4; ++k) {
+    const double nr = im * dt, ni = -re * dt;  // multiply by -i dt
+    re = nr / k;
+    im = ni / k;
+    coef[k] = double2{re, im};
+  }
+}
+
+// nsteps Taylor-4 steps on nb packed FP64 orbitals `state` (stride npw_stride),
+// in place; with rho, the density after step s is written (accumulate = 0) or
+// added (accumulate = 1) to rho + s*N.
+ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nsteps, const double* occ, double* rho,
+                        int accumulate, hipStream_t st) {
+  double2 coef[5];
+  taylor_coefficients(dt, coef);
+  ks_status r;
+  for (int step = 0; step < nsteps; ++step) {
+    // w1 = H psi -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored; state += a_k w_k
+    void* src[4] = {state, s->pk[1], s->pk[2], s->pk[1]};
+    void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
+    for (int k = 1; k <= 4; ++k) {
+      Taylor tay{coef[k], k < 4 ? 1 : 0};
+      const bool in64 = k == 1 || s->prec == KS_FP64;
+      if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], state, H_TAYLOR, tay, st)) != KS_OK) return r;
+    }
+    if (rho && (r = density_packed(s, nb, state, occ, rho + (size_t)step * s->N, accumulate, st)) != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -582,36 +616,12 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
   hipStream_t st = (hipStream_t)stream;
-  // (-i dt)^k / k!
-  double2 coef[5];
-  {
-    double re = 1.0, im = 0.0;
-    coef[0] = double2{1.0, 0.0};
-    for (int k = 1; k <= 4; ++k) {
-      const double nr = im * dt, ni = -re * dt;  // multiply by -i dt
-      re = nr / k;
-      im = ni / k;
-      coef[k] = double2{re, im};
-    }
-  }
   for (int o0 = 0; o0 < norb; o0 += s->cb) {
     const int nb = std::min(s->cb, norb - o0);
     double2* box = (double2*)psi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
-    for (int step = 0; step < nsteps; ++step) {
-      // w1 = H psi -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored; acc (pk0) += a_k w_k
-      void* src[4] = {s->pk[0], s->pk[1], s->pk[2], s->pk[1]};
-      void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
-      for (int k = 1; k <= 4; ++k) {
-        Taylor tay{coef[k], k < 4 ? 1 : 0};
-        const bool in64 = k == 1 || s->prec == KS_FP64;
-        if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], s->pk[0], H_TAYLOR, tay, st)) != KS_OK) return r;
-      }
-      if (rho) {
-        if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho + (size_t)step * s->N, o0 > 0, st)) != KS_OK)
-          return r;
-      }
-    }
+    if ((r = taylor_packed(s, nb, (double2*)s->pk[0], dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, st)) != KS_OK)
+      return r;
     if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[0], true, box, s->N, st); })) != KS_OK) return r;
   }
   return KS_OK;
@@ -756,6 +766,158 @@ ks_status ks_plan_projectors(const int n[3], int natoms, int nproj, const int* n
     }
   }
   if (point_entries) point_entries[nuniq] = nent;
+  return KS_OK;
+}
+
+// ------------------------------------------------------------ resident state
+
+ks_status ks_state_create(ks_system* s, int norb, ks_state** out) {
+  if (!out) return fail(s, KS_EINVAL, "out is null");
+  *out = nullptr;
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  if (norb < 1) return fail(s, KS_EINVAL, "norb must be >= 1");
+  ks_state* t = new ks_state();
+  t->sys = s;
+  t->norb = norb;
+  if ((r = dalloc(s, reinterpret_cast<void**>(&t->data), (size_t)norb * s->npw_stride * sizeof(double2))) != KS_OK) {
+    delete t;
+    return r;
+  }
+  *out = t;
+  return KS_OK;
+}
+
+static void state_drop_graph(ks_state* t) {
+  if (t->exec) (void)hipGraphExecDestroy(t->exec);
+  if (t->graph) (void)hipGraphDestroy(t->graph);
+  t->exec = nullptr;
+  t->graph = nullptr;
+}
+
+void ks_state_destroy(ks_state* t) {
+  if (!t) return;
+  (void)hipDeviceSynchronize();
+  state_drop_graph(t);
+  void* p = t->data;
+  dfree(p);
+  delete t;
+}
+
+ks_status ks_state_upload(ks_state* t, const void* psi, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (!psi) return fail(s, KS_EINVAL, "psi is null");
+  hipStream_t st = (hipStream_t)stream;
+  const double2* box = (const double2*)psi;
+  return kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, t->norb, box, s->N, t->data, st); });
+}
+
+ks_status ks_state_download(ks_state* t, void* psi, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (!psi) return fail(s, KS_EINVAL, "psi is null");
+  hipStream_t st = (hipStream_t)stream;
+  double2* box = (double2*)psi;
+  return kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, t->norb, t->data, true, box, s->N, st); });
+}
+
+ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* occ, double* rho, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (nsteps < 0) return fail(s, KS_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(s, KS_EINVAL, "dt must be finite");
+  if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
+  hipStream_t st = (hipStream_t)stream;
+  ks_status r;
+  for (int o0 = 0; o0 < t->norb; o0 += s->cb) {
+    const int nb = std::min(s->cb, t->norb - o0);
+    double2* slice = t->data + (size_t)o0 * s->npw_stride;
+    if ((r = taylor_packed(s, nb, slice, dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, st)) != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
+ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double* energy, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (energy && !occ) return fail(s, KS_EINVAL, "energy requires occ");
+  hipStream_t st = (hipStream_t)stream;
+  Taylor none{{0.0, 0.0}, 0};
+  ks_status r;
+  for (int o0 = 0; o0 < t->norb; o0 += s->cb) {
+    const int nb = std::min(s->cb, t->norb - o0);
+    const double2* slice = t->data + (size_t)o0 * s->npw_stride;
+    if (energy && (r = hpsi_packed(s, nb, slice, true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
+    const void* hp = energy ? s->pk[1] : nullptr;
+    double* red = s->red + 2 * (size_t)o0;
+    if ((r = kcall(s, KS_K_DOTS, st, "dots", [&] { return launch_dots(s, nb, slice, hp, red, st); })) != KS_OK)
+      return r;
+  }
+  if (norms)
+    KS_HIP(s, hipMemcpy2DAsync(norms, sizeof(double), s->red, 2 * sizeof(double), sizeof(double), t->norb,
+                               hipMemcpyDeviceToDevice, st));
+  if (energy)
+    return kcall(s, KS_K_DOTS, st, "energy_sum", [&] { return launch_energy_sum(t->norb, occ, s->red, energy, st); });
+  return KS_OK;
+}
+
+ks_status ks_state_capture(ks_state* t, double dt, const double* occ, double* rho, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (!stream) return fail(s, KS_EINVAL, "capture needs a non-default stream");
+  if (s->timing) return fail(s, KS_EINVAL, "kernel timing must be off while capturing");
+  if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
+  hipStream_t st = (hipStream_t)stream;
+  state_drop_graph(t);
+  KS_HIP(s, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  const ks_status r = ks_state_propagate(t, dt, 1, occ, rho, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (r != KS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return fail(s, KS_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  t->graph = g;
+  const hipError_t e2 = hipGraphInstantiate(&t->exec, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    state_drop_graph(t);
+    return fail(s, KS_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  }
+  return KS_OK;
+}
+
+ks_status ks_state_replay(ks_state* t, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (!t->exec) return fail(s, KS_EINVAL, "no captured step");
+  KS_HIP(s, hipGraphLaunch(t->exec, (hipStream_t)stream));
+  return KS_OK;
+}
+
+ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int precision, int norb, int npoints,
+                            int nproj, int chunk, unsigned long long* bytes) {
+  if (!n || !L || !bytes || norb < 1 || npoints < 0) return fail(nullptr, KS_EINVAL, "bad argument");
+  SphereHost h;
+  std::string msg;
+  const ks_status r = build_sphere(n, L, ecut, h, msg);
+  if (r != KS_OK) return fail(nullptr, r, msg);
+  const double es = precision == KS_FP64 ? 16.0 : 8.0;
+  const double npl = (double)n[1] * n[2], N = (double)n[0] * npl;
+  const double nplanes = (double)h.plane_m1lo.size();
+  const double stride = (double)((h.npw + 63) / 64 * 64);
+  int cb = chunk;
+  if (cb <= 0) cb = std::max(1, std::min(norb, (int)std::floor(96.0 * 1024 * 1024 / (nplanes * npl * es))));
+  const double np = std::max(1, nproj);
+  double b = 0.0;
+  b += (double)cb * stride * (16.0 + 2.0 * es);         // packed chunk buffers
+  b += 2.0 * cb * nplanes * npl * es;                   // plane intermediates
+  b += N * 8.0 + 2.0 * norb * 8.0;                      // potential, reductions
+  b += npoints * (np * 8.0 + 4 * 4.0) + 64.0 * 1024;    // KB tables
+  b += (double)cb * npoints * np * 16.0 / 8.0;          // projection partials (upper bound)
+  b += (double)norb * stride * 16.0;                    // resident state
+  *bytes = (unsigned long long)b;
   return KS_OK;
 }
 

@@ -118,6 +118,15 @@ struct ks_system {
   std::string err;
 };
 
+// Orbitals kept resident on the device in the packed FP64 layout.
+struct ks_state {
+  ks_system* sys = nullptr;
+  int norb = 0;
+  double2* data = nullptr;     // [norb][npw_stride]
+  hipGraph_t graph = nullptr;  // one captured propagation step
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace ks {
 
 // launchers (ks_kernels.hip); return false when the size has no kernel

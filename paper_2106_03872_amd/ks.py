@@ -61,6 +61,16 @@ def _load():
         "ks_system_chunk": (I, [P]),
         "ks_system_set_chunk": (I, [P, I]),
         "ks_system_info": (I, [P, P]),
+        "ks_state_create": (I, [P, I, ctypes.POINTER(P)]),
+        "ks_state_destroy": (None, [P]),
+        "ks_state_upload": (I, [P, P, P]),
+        "ks_state_download": (I, [P, P, P]),
+        "ks_state_propagate": (I, [P, D, I, P, P, P]),
+        "ks_state_reduce": (I, [P, P, P, P, P]),
+        "ks_state_capture": (I, [P, D, P, P, P]),
+        "ks_state_replay": (I, [P, P]),
+        "ks_plan_footprint": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, I, I, I,
+                                  ctypes.POINTER(ctypes.c_ulonglong)]),
         "ks_plan_sphere": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, ctypes.POINTER(I), P]),
         "ks_plan_projectors": (I, [ctypes.POINTER(I), I, I, P, P, P, ctypes.POINTER(I), P, P, P, P]),
         "ks_set_kernel_timing": (I, [P, I]),
@@ -275,6 +285,80 @@ class System:
         self._check(_lib.ks_orthonormalize(self._h, norb, _ptr(psi, torch.complex128, self.box_shape(norb), "psi"),
                                            _stream()))
         return psi
+
+
+class State:
+    """Orbitals of one system resident on the device (packed FP64 layout)."""
+
+    def __init__(self, system, norb):
+        self.system = system
+        self.norb = int(norb)
+        h = ctypes.c_void_p()
+        system._check(_lib.ks_state_create(system._h, self.norb, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ks_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _st(self, stream):
+        return ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+
+    def upload(self, psi, stream=None):
+        import torch
+        self.system._check(_lib.ks_state_upload(
+            self._h, _ptr(psi, torch.complex128, self.system.box_shape(self.norb), "psi"), self._st(stream)))
+
+    def download(self, psi=None, stream=None):
+        import torch
+        if psi is None:
+            psi = torch.empty(self.system.box_shape(self.norb), dtype=torch.complex128, device="cuda")
+        self.system._check(_lib.ks_state_download(
+            self._h, _ptr(psi, torch.complex128, self.system.box_shape(self.norb), "psi"), self._st(stream)))
+        return psi
+
+    def propagate(self, dt, nsteps=1, occ=None, rho=None, stream=None):
+        import torch
+        self.system._check(_lib.ks_state_propagate(
+            self._h, float(dt), int(nsteps), _ptr(occ, torch.float64, (self.norb,), "occ"),
+            _ptr(rho, torch.float64, None, "rho"), self._st(stream)))
+
+    def reduce(self, occ=None, want_energy=True, stream=None):
+        import torch
+        norms = torch.empty(self.norb, dtype=torch.float64, device="cuda")
+        energy = torch.empty(1, dtype=torch.float64, device="cuda") if want_energy else None
+        self.system._check(_lib.ks_state_reduce(self._h, _ptr(occ, torch.float64, (self.norb,), "occ"),
+                                                _ptr(norms, torch.float64), _ptr(energy, torch.float64),
+                                                self._st(stream)))
+        return norms, energy
+
+    def capture(self, dt, occ=None, rho=None, stream=None):
+        import torch
+        if stream is None:
+            raise ValueError("capture needs an explicit non-default stream")
+        self.system._check(_lib.ks_state_capture(self._h, float(dt), _ptr(occ, torch.float64, (self.norb,), "occ"),
+                                                 _ptr(rho, torch.float64, None, "rho"), self._st(stream)))
+
+    def replay(self, stream=None):
+        self.system._check(_lib.ks_state_replay(self._h, self._st(stream)))
+
+
+def plan_footprint(n, L, ecut, norb, npoints, nproj=4, precision=KS_FP64, chunk=0):
+    """Device bytes of a system plus a resident state (host-only estimate)."""
+    out = ctypes.c_ulonglong()
+    st = _lib.ks_plan_footprint((ctypes.c_int * 3)(*[int(x) for x in n]), (ctypes.c_double * 3)(*[float(x) for x in L]),
+                                float(ecut), int(precision), int(norb), int(npoints), int(nproj), int(chunk),
+                                ctypes.byref(out))
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_last_error(None).decode())
+    return int(out.value)
 
 
 # module-level entry points with the names of the C ABI
