@@ -144,8 +144,10 @@ ks_status ks_reduce(ks_system* sys, int norb, const void* psi, const double* occ
  * Orthonormalise the orbitals in place (orthogonalisation step of Section
  * "Ground-state solution"): S = C^H C over the sphere, S = L L^H (Cholesky,
  * positive diagonal), C <- C L^{-H}.  psi: device complex128
- * [norb][n0][n1][n2].  KS_EINVAL if S is not positive definite.  The first
- * call allocates a workspace for max_norb orbitals.
+ * [norb][n0][n1][n2].  KS_EINVAL when a Cholesky pivot drops to 1e-12 of its
+ * diagonal entry of S (numerically linearly dependent orbitals).  The first
+ * call allocates a workspace for max_norb orbitals; the call synchronises
+ * `stream` to read the pivot check.
  */
 ks_status ks_orthonormalize(ks_system* sys, int norb, void* psi, void* stream);
 

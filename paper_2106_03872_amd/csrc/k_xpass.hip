@@ -41,32 +41,52 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   if (ns == 0) return;  // no sphere point in this tile (uniform per block)
   const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, tile * NB};
   fft_io<N0, +1, NB, NT, SRC_FN, DST_LDS, C>(X, N0 + 1, NB, tw0, ld, no_store{});
+  // Projections: items (segment, slot, projector); each sums beta * psi over
+  // its segment of the slot's points, then the segments of every (slot,
+  // projector) are added in order.  The partial sums are staged in X once all
+  // reads of psi are done.
   const int np = pt.nproj;
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int sl = wave; sl < ns; sl += NT / 64) {
-    const int k0 = pt.slot_pt[sA + sl], k1 = pt.slot_pt[sA + sl + 1];
-    double ax[KB_MAX_NPROJ], ay[KB_MAX_NPROJ];
+  const int pairs = ns * np;
+  int nseg = NT / pairs;
+  nseg = nseg < 1 ? 1 : (nseg > 16 ? 16 : nseg);
+  const int items = pairs * nseg;
+  // items <= max(NT, pairs) and pairs <= KB_TILE_DP, so PJ items per thread suffice
+  constexpr int PJ = ((NT > KB_TILE_DP ? NT : KB_TILE_DP) + NT - 1) / NT;
+  double sx[PJ], sy[PJ];
 #pragma unroll
-    for (int q = 0; q < KB_MAX_NPROJ; ++q) ax[q] = ay[q] = 0.0;
-    for (int base = k0; base < k1; base += 64) {
-      const int k = base + lane;
-      C x = czero<C>();
-      if (k < k1) x = X[pt.pt_lds[k]];
-      const double* b = pt.beta + (long long)k * np;
-#pragma unroll
-      for (int q = 0; q < KB_MAX_NPROJ; ++q) {
-        if (q < np) {
-          const double bv = k < k1 ? b[q] : 0.0;
-          ax[q] += wave_sum(bv * double(x.x));
-          ay[q] += wave_sum(bv * double(x.y));
-        }
+  for (int j = 0; j < PJ; ++j) {
+    sx[j] = sy[j] = 0.0;
+    const int i = tid + j * NT;
+    if (i < items) {
+      const int pr = i % pairs, seg = i / pairs;
+      const int sl = pr / np, q = pr - sl * np;
+      const int k0 = pt.slot_pt[sA + sl], len = pt.slot_pt[sA + sl + 1] - k0;
+      const int a = k0 + (len * seg) / nseg, b = k0 + (len * (seg + 1)) / nseg;
+      for (int k = a; k < b; ++k) {
+        const double bv = pt.beta[(long long)k * np + q];
+        const C x = X[pt.pt_lds[k]];
+        sx[j] += bv * double(x.x);
+        sy[j] += bv * double(x.y);
       }
     }
-    if (lane == 0) {
+  }
+  __syncthreads();
+  double2* red = reinterpret_cast<double2*>(X);   // holds >= 256 double2 for every supported N0, R
 #pragma unroll
-      for (int q = 0; q < KB_MAX_NPROJ; ++q)
-        if (q < np) partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(ax[q] * scale), R(ay[q] * scale)};
+  for (int j = 0; j < PJ; ++j) {
+    const int i = tid + j * NT;
+    if (i < items) red[i] = double2{sx[j], sy[j]};
+  }
+  __syncthreads();
+  for (int pr = tid; pr < pairs; pr += NT) {
+    double tx = 0.0, ty = 0.0;
+    for (int seg = 0; seg < nseg; ++seg) {
+      const double2 v = red[seg * pairs + pr];
+      tx += v.x;
+      ty += v.y;
     }
+    const int sl = pr / np, q = pr - sl * np;
+    partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(tx * scale), R(ty * scale)};
   }
 }
 
@@ -94,24 +114,34 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     const int sl = i / np, q = i - sl * np;
     dps[i] = DP[((long long)o * pt.natoms + pt.slot_atom[sA + sl]) * np + q];
   }
+  // first unique point of this thread (fetched before the transform)
+  const int uA = pt.up_off[tile], uB = pt.up_off[tile + 1];
+  int u_pos = -1, u_e0 = 0, u_e1 = 0;
+  if (uA + tid < uB) {
+    u_pos = pt.up_lds[uA + tid];
+    u_e0 = pt.up_ent[uA + tid];
+    u_e1 = pt.up_ent[uA + tid + 1];
+  }
   const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
   // synthesis, then psi <- V psi as the outputs are written
   fft_io<N0, +1, NB, NT, SRC_FN, DST_FN_LDS, C>(X, N0 + 1, NB, tw0, ld, [&](int t, int e, C v, int it, int q) {
     X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
   });
   if (ns > 0) {
-    const int uA = pt.up_off[tile], uB = pt.up_off[tile + 1];
     for (int u = uA + tid; u < uB; u += NT) {
+      const int pos = (u == uA + tid) ? u_pos : pt.up_lds[u];
+      const int e0 = (u == uA + tid) ? u_e0 : pt.up_ent[u];
+      const int e1 = (u == uA + tid) ? u_e1 : pt.up_ent[u + 1];
       double fx = 0.0, fy = 0.0;
-      for (int e = pt.up_ent[u]; e < pt.up_ent[u + 1]; ++e) {
-        const double* b = pt.beta + (long long)pt.ent_brow[e] * np;
+      for (int e = e0; e < e1; ++e) {
+        const double* b = pt.beta_ent + (long long)e * np;
         const double2* dp = dps + pt.ent_slot[e] * np;
         for (int q = 0; q < np; ++q) {
           fx += b[q] * dp[q].x;
           fy += b[q] * dp[q].y;
         }
       }
-      C& x = X[pt.up_lds[u]];
+      C& x = X[pos];
       x = C{R(double(x.x) + fx), R(double(x.y) + fy)};
     }
     __syncthreads();

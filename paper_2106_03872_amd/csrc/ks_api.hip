@@ -347,7 +347,7 @@ ks_status alloc_workspace(ks_system* s) {
 
 int default_chunk(const ks_system* s) {
   const double per = (double)s->nplanes * s->npl * (s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2));
-  int cb = (int)std::max(1.0, std::floor(96.0 * 1024 * 1024 / per));
+  int cb = (int)std::max(1.0, std::floor(1024.0 * 1024 * 1024 / per));
   return std::max(1, std::min(cb, s->max_norb));
 }
 
@@ -523,8 +523,8 @@ void ks_system_destroy(ks_system* s) {
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
                   s->d_tw0f, s->d_tw1f, s->d_v, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
-                  s->d_up_off, s->d_up_lds, s->d_up_ent, s->d_ent_slot, s->d_ent_brow, s->d_beta,
-                  s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info};
+                  s->d_up_off, s->d_up_lds, s->d_up_ent, s->d_ent_slot, s->d_ent_brow, s->d_beta, s->d_beta_ent,
+                  s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
   for (void* p : ptrs) dfree(p);
   delete s;
 }
@@ -564,6 +564,9 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
   const int np = ph.nproj;
   std::vector<double> kb((size_t)natoms * np);
   for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
+  std::vector<double> bent(ph.ent_brow.size() * np);
+  for (size_t e = 0; e < ph.ent_brow.size(); ++e)
+    for (int c = 0; c < np; ++c) bent[e * np + c] = ph.brows[(size_t)ph.ent_brow[e] * np + c];
   ks_status st;
   if ((st = upload(s, &s->d_pt_lds, ph.pt_lds)) != KS_OK ||
       (st = upload(s, &s->d_slot_off, ph.slot_off)) != KS_OK || (st = upload(s, &s->d_slot_atom, ph.slot_atom)) != KS_OK ||
@@ -572,7 +575,8 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
       (st = upload(s, &s->d_atom_slots, ph.atom_slots)) != KS_OK || (st = upload(s, &s->d_up_off, ph.up_off)) != KS_OK ||
       (st = upload(s, &s->d_up_lds, ph.up_lds)) != KS_OK || (st = upload(s, &s->d_up_ent, ph.up_ent)) != KS_OK ||
       (st = upload(s, &s->d_ent_slot, ph.ent_slot)) != KS_OK || (st = upload(s, &s->d_ent_brow, ph.ent_brow)) != KS_OK ||
-      (st = upload(s, &s->d_beta, ph.brows)) != KS_OK || (st = upload(s, &s->d_kb, kb)) != KS_OK)
+      (st = upload(s, &s->d_beta, ph.brows)) != KS_OK || (st = upload(s, &s->d_beta_ent, bent)) != KS_OK ||
+      (st = upload(s, &s->d_kb, kb)) != KS_OK)
     return st;
   s->natoms = (natoms > 0 && ph.npoints > 0) ? natoms : 0;
   s->nproj = np;
@@ -686,7 +690,8 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
     if ((r = dalloc(s, &s->ortho_pk, 2 * n * s->npw_stride * sizeof(double2))) != KS_OK ||
         (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_S), n * n * sizeof(double2))) != KS_OK ||
         (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_W), n * n * sizeof(double2))) != KS_OK ||
-        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK) {
+        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK ||
+        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_diag), n * sizeof(double))) != KS_OK) {
       dfree(s->ortho_pk);
       return r;
     }
@@ -697,7 +702,7 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   double2* box = (double2*)psi;
   if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, norb, box, s->N, P, st); })) != KS_OK) return r;
   if ((r = launch_ok(s, launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, st), "overlap")) != KS_OK) return r;
-  if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_info, st), "cholesky")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(norb, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_apply_lower(norb, s->npw, s->ortho_W, P, s->npw_stride, Y, st), "apply")) != KS_OK)
     return r;
@@ -845,8 +850,10 @@ ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double*
   hipStream_t st = (hipStream_t)stream;
   Taylor none{{0.0, 0.0}, 0};
   ks_status r;
-  for (int o0 = 0; o0 < t->norb; o0 += s->cb) {
-    const int nb = std::min(s->cb, t->norb - o0);
+  // norms only: one launch over every resident orbital
+  const int step = energy ? s->cb : t->norb;
+  for (int o0 = 0; o0 < t->norb; o0 += step) {
+    const int nb = std::min(step, t->norb - o0);
     const double2* slice = t->data + (size_t)o0 * s->npw_stride;
     if (energy && (r = hpsi_packed(s, nb, slice, true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
     const void* hp = energy ? s->pk[1] : nullptr;
@@ -908,7 +915,7 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
   const double nplanes = (double)h.plane_m1lo.size();
   const double stride = (double)((h.npw + 63) / 64 * 64);
   int cb = chunk;
-  if (cb <= 0) cb = std::max(1, std::min(norb, (int)std::floor(96.0 * 1024 * 1024 / (nplanes * npl * es))));
+  if (cb <= 0) cb = std::max(1, std::min(norb, (int)std::floor(1024.0 * 1024 * 1024 / (nplanes * npl * es))));
   const double np = std::max(1, nproj);
   double b = 0.0;
   b += (double)cb * stride * (16.0 + 2.0 * es);         // packed chunk buffers

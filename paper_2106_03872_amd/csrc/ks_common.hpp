@@ -66,6 +66,7 @@ inline ProjTab proj_tab(const ks_system* s) {
   c.ent_slot = s->d_ent_slot;
   c.ent_brow = s->d_ent_brow;
   c.beta = s->d_beta;
+  c.beta_ent = s->d_beta_ent;
   c.d = s->d_kb;
   c.natoms = s->natoms;
   c.nproj = s->nproj;

@@ -40,7 +40,8 @@ struct ProjTab {
   const int* up_ent;         // [nunique+1]
   const int* ent_slot;       // [nentries] slot index local to the tile
   const int* ent_brow;       // [nentries]
-  const double* beta;        // [npoints][nproj]
+  const double* beta;        // [npoints][nproj], rows in slot order
+  const double* beta_ent;    // [nentries][nproj], rows in entry order
   const double* d;           // [natoms][nproj]
   int natoms, nproj, nslots;
 };
@@ -88,7 +89,7 @@ struct ks_system {
   int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
       *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_lds = nullptr,
       *d_up_ent = nullptr, *d_ent_slot = nullptr, *d_ent_brow = nullptr;
-  double *d_beta = nullptr, *d_kb = nullptr;
+  double *d_beta = nullptr, *d_beta_ent = nullptr, *d_kb = nullptr;
 
   // workspace (one chunk of cb orbitals)
   int cb = 1;
@@ -105,6 +106,7 @@ struct ks_system {
   double2* ortho_S = nullptr;
   double2* ortho_W = nullptr;
   int* ortho_info = nullptr;
+  double* ortho_diag = nullptr;
   int ortho_cap = 0;
 
   // kernel timing (ks_set_kernel_timing)
@@ -145,7 +147,7 @@ bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, 
 bool launch_dots(const ks_system* s, int nb, const void* a, const void* b, double* out, hipStream_t st);
 bool launch_energy_sum(int norb, const double* occ, const double* red, double* energy, hipStream_t st);
 bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hipStream_t st);
-bool launch_cholesky(int n, double2* S, int* info, hipStream_t st);
+bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st);
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st);
 

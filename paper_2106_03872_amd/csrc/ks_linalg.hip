@@ -20,8 +20,9 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 // k-tiles above the diagonal are skipped.  LOWER_OUT: only tiles with
 // m-tile >= n-tile are produced.
 //
-// v_mfma_f64_16x16x4_f64 operand layout (64 lanes): A[i][k] in lane i + 16k,
-// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i / 4), element i % 4.
+// v_mfma_f64_16x16x4_f64 operand layout on gfx950 (64 lanes, measured):
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
+// j + 16 (i mod 4), element i div 4 of the 4-double accumulator.
 constexpr int GBM = 64, GBN = 64, GBK = 16;
 
 template <bool CONJ_A, bool B_KN, bool LOWER_A, bool LOWER_OUT>
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, co
     for (int tb = 0; tb < 2; ++tb) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + ta * 16 + (lane >> 4) * 4 + r;
+        const int m = m0 + wm + ta * 16 + 4 * r + (lane >> 4);
         const int n = n0 + wn + tb * 16 + (lane & 15);
         if (m < M && n < N) Cout[(long long)m * ldc + n] = double2{re[ta][tb][r], im[ta][tb][r]};
       }
@@ -104,8 +105,11 @@ constexpr int CB = 32;
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ double2 zmulc(double2 a, double2 b) { return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
 
-// factor the diagonal block at k0 in place (lower), upper part zeroed
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int k0, int* info) {
+// factor the diagonal block at k0 in place (lower), upper part zeroed; a
+// pivot at or below 1e-12 of the original diagonal entry sets *info (the
+// orbitals are numerically linearly dependent)
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int k0, const double* __restrict__ diag0,
+                                                         int* info) {
   __shared__ double2 a[CB][CB + 1];
   const int tid = threadIdx.x;
   const int nb = min(CB, n - k0);
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int 
   for (int j = 0; j < nb; ++j) {
     if (tid == 0) {
       double d = a[j][j].x;
-      if (!(d > 0.0)) {
+      if (!(d > 1e-12 * diag0[k0 + j])) {
         info[0] = 1;
         d = 1.0;
       }
@@ -280,9 +284,15 @@ bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hi
   return true;
 }
 
-bool launch_cholesky(int n, double2* S, int* info, hipStream_t st) {
+__global__ void save_diag_kernel(const double2* __restrict__ S, int n, double* __restrict__ d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = S[(long long)i * n + i].x;
+}
+
+bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st) {
+  save_diag_kernel<<<(n + 255) / 256, 256, 0, st>>>(S, n, diag0);
   for (int k0 = 0; k0 < n; k0 += CB) {
-    potrf_diag_kernel<<<1, 256, 0, st>>>(S, n, k0, info);
+    potrf_diag_kernel<<<1, 256, 0, st>>>(S, n, k0, diag0, info);
     const int rest = n - k0 - min(CB, n - k0);
     if (rest > 0) {
       trsm_panel_kernel<<<(rest + 63) / 64, 64, 0, st>>>(S, n, k0);
