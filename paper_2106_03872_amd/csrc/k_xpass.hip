@@ -12,12 +12,14 @@ namespace ks {
 
 template <int N0, int NB, typename C>
 struct TLoader {
-  const C* Tin;
-  int npl, nplanes, m0lo, p0;
+  const C* base;   // T of this orbital at the tile's first pencil
+  int npl, nplanes, m0lo, tvalid;
+  __device__ TLoader(const C* Tin, int o, int npl_, int nplanes_, int m0lo_, int p0)
+      : base(Tin + ((long long)o * nplanes_ * npl_ + p0)), npl(npl_), nplanes(nplanes_), m0lo(m0lo_),
+        tvalid(npl_ - p0) {}
   __device__ C operator()(int t, int e) const {
     const int pi = fold(e, N0) - m0lo;
-    const int p = p0 + t;
-    return (pi >= 0 && pi < nplanes && p < npl) ? Tin[(long long)pi * npl + p] : czero<C>();
+    return (pi >= 0 && pi < nplanes && t < tvalid) ? base[pi * npl + t] : czero<C>();
   }
 };
 
@@ -35,12 +37,14 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
   __shared__ C X[NB * (N0 + 1)];
+  __shared__ C tw[N0];
   const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
   const int npl = tab.n1 * tab.n2;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
   if (ns == 0) return;  // no sphere point in this tile (uniform per block)
-  const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, tile * NB};
-  fft_io<N0, +1, NB, NT, SRC_FN, DST_LDS, C>(X, N0 + 1, NB, tw0, ld, no_store{});
+  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
+  const TLoader<N0, NB, C> ld(Tin, o, npl, tab.nplanes, tab.m0lo, tile * NB);
+  fft_io<N0, +1, NB, NT, SRC_FN, DST_LDS, C>(X, N0 + 1, NB, tw, ld, no_store{});
   // Projections: items (segment, slot, projector); each sums beta * psi over
   // its segment of the slot's points, then the segments of every (slot,
   // projector) are added in order.  The partial sums are staged in X once all
@@ -100,13 +104,16 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   using LS = last_shape<N0, NB, NT>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ double2 dps[KB_TILE_DP];
+  __shared__ C tw[N0];
   const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
   // potential at the outputs of this thread's last synthesis stage (times Omega^-1/2)
   double vr[LS::items][LS::radix];
+  const double* vbase = V + p0;
   last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
-    vr[it][q] = (p0 + t < npl) ? V[(long long)e * npl + p0 + t] * sc_in : 0.0;
+    vr[it][q] = (p0 + t < npl) ? vbase[e * npl + t] * sc_in : 0.0;
   });
   const int np = pt.nproj;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
@@ -122,9 +129,9 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     u_e0 = pt.up_ent[uA + tid];
     u_e1 = pt.up_ent[uA + tid + 1];
   }
-  const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
+  const TLoader<N0, NB, C> ld(Tin, o, npl, tab.nplanes, tab.m0lo, p0);
   // synthesis, then psi <- V psi as the outputs are written
-  fft_io<N0, +1, NB, NT, SRC_FN, DST_FN_LDS, C>(X, N0 + 1, NB, tw0, ld, [&](int t, int e, C v, int it, int q) {
+  fft_io<N0, +1, NB, NT, SRC_FN, DST_FN_LDS, C>(X, N0 + 1, NB, tw, ld, [&](int t, int e, C v, int it, int q) {
     X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
   });
   if (ns > 0) {
@@ -148,48 +155,60 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   }
   C* out = Uout + (long long)o * tab.nplanes * npl;
   const int nplanes = tab.nplanes, m0lo = tab.m0lo;
-  fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw0, no_load{}, [&](int t, int e, C v, int, int) {
+  C* obase = out + p0;
+  const int tvalid = npl - p0;
+  fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, [&](int t, int e, C v, int, int) {
     const int pi = fold(e, N0) - m0lo;
-    const int p = p0 + t;
-    if (pi >= 0 && pi < nplanes && p < npl)
-      out[(long long)pi * npl + p] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
+    if (pi >= 0 && pi < nplanes && t < tvalid) obase[pi * npl + t] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
   });
 }
 
-// density: block = tile, loops over the nb orbitals of the chunk in order;
-// |psi|^2 is accumulated straight from the last synthesis stage.
+// density: block (tile, group of DENS_GROUP orbitals); |psi|^2 is accumulated
+// straight from the last synthesis stage over the group's orbitals in order
+// and written to the group's partial density; dens_sum adds the groups in
+// order.
 template <int N0, typename R>
 __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ Tin, int nb,
-                                                   const double* __restrict__ occ, double* __restrict__ rho,
-                                                   int accumulate, SphereTab tab, const cplx<R>* __restrict__ tw0,
+                                                   const double* __restrict__ occ, double* __restrict__ part,
+                                                   SphereTab tab, const cplx<R>* __restrict__ tw0,
                                                    double inv_omega) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
   using LS = last_shape<N0, NB, NT>;
   __shared__ C X[NB * (N0 + 1)];
-  const int tile = blockIdx.x;
+  __shared__ C tw[N0];
+  const int tile = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
+  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
   double a[LS::items][LS::radix];
 #pragma unroll
   for (int it = 0; it < LS::items; ++it)
 #pragma unroll
     for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
-  for (int o = 0; o < nb; ++o) {
-    const TLoader<N0, NB, C> ld{Tin + (long long)o * tab.nplanes * npl, npl, tab.nplanes, tab.m0lo, p0};
+  const int oa = g * DENS_GROUP, ob = min(nb, oa + DENS_GROUP);
+  for (int o = oa; o < ob; ++o) {
+    const TLoader<N0, NB, C> ld(Tin, o, npl, tab.nplanes, tab.m0lo, p0);
     const double f = occ[o] * inv_omega;
-    fft_io<N0, +1, NB, NT, SRC_FN, DST_FN, C>(X, N0 + 1, NB, tw0, ld, [&](int, int, C v, int it, int q) {
+    fft_io<N0, +1, NB, NT, SRC_FN, DST_FN, C>(X, N0 + 1, NB, tw, ld, [&](int, int, C v, int it, int q) {
       a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
     });
     __syncthreads();
   }
+  double* pb = part + (long long)g * tab.n0 * npl + p0;
   last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
-    const int p = p0 + t;
-    if (p < npl) {
-      double* r = rho + (long long)e * npl + p;
-      *r = accumulate ? *r + a[it][q] : a[it][q];
-    }
+    if (p0 + t < npl) pb[e * npl + t] = a[it][q];
   });
+}
+
+// rho (+)= sum over groups g = 0..ng-1 of part[g] (in order)
+__global__ __launch_bounds__(NT) void dens_sum_kernel(const double* __restrict__ part, int ng, long long N,
+                                                      double* __restrict__ rho, int accumulate) {
+  const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+  if (i >= N) return;
+  double s = accumulate ? rho[i] : 0.0;
+  for (int g = 0; g < ng; ++g) s += part[g * N + i];
+  rho[i] = s;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -240,25 +259,28 @@ bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP,
 }
 
 template <int N0>
-static void xdens_n(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
-                    hipStream_t st) {
+static void xdens_n(const ks_system* s, int nb, const void* T, const double* occ, double* part, hipStream_t st) {
+  const int ng = (nb + DENS_GROUP - 1) / DENS_GROUP;
   if (!mixed(s))
-    xdens_kernel<N0, double><<<dim3(s->ntiles), NT, 0, st>>>((const double2*)T, nb, occ, rho, accumulate,
-                                                              sphere_tab(s), s->d_tw0, 1.0 / s->omega);
+    xdens_kernel<N0, double><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, occ, part, sphere_tab(s),
+                                                                  s->d_tw0, 1.0 / s->omega);
   else
-    xdens_kernel<N0, float><<<dim3(s->ntiles), NT, 0, st>>>((const float2*)T, nb, occ, rho, accumulate,
-                                                             sphere_tab(s), s->d_tw0f, 1.0 / s->omega);
+    xdens_kernel<N0, float><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, occ, part, sphere_tab(s),
+                                                                 s->d_tw0f, 1.0 / s->omega);
 }
 
 bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
                   hipStream_t st) {
   switch (s->n[0]) {
-#define KS_CASE(v) case v: xdens_n<v>(s, nb, T, occ, rho, accumulate, st); return true;
+#define KS_CASE(v) case v: xdens_n<v>(s, nb, T, occ, s->dens_part, st); break;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:
       return false;
   }
+  const int ng = (nb + DENS_GROUP - 1) / DENS_GROUP;
+  dens_sum_kernel<<<(unsigned)((s->N + NT - 1) / NT), NT, 0, st>>>(s->dens_part, ng, s->N, rho, accumulate);
+  return true;
 }
 
 }  // namespace ks

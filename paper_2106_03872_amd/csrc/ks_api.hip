@@ -312,6 +312,7 @@ void free_workspace(ks_system* s) {
   dfree(s->U);
   dfree(s->partial);
   dfree(reinterpret_cast<void*&>(s->DP));
+  dfree(reinterpret_cast<void*&>(s->dens_part));
   s->partial_cap = s->dp_cap = 0;
 }
 
@@ -335,6 +336,11 @@ ks_status alloc_workspace(ks_system* s) {
   for (int i = 0; i < 3; ++i) {
     // pk[0] holds the FP64 orbital state / Taylor accumulator
     ks_status st = dalloc(s, &s->pk[i], (size_t)s->cb * s->npw_stride * (i == 0 ? sizeof(double2) : es));
+    if (st != KS_OK) return st;
+  }
+  {
+    ks_status st = dalloc(s, reinterpret_cast<void**>(&s->dens_part),
+                          (size_t)((s->cb + 7) / 8) * s->N * sizeof(double));
     if (st != KS_OK) return st;
   }
   const size_t tb = (size_t)s->cb * s->nplanes * s->npl * es;
@@ -921,6 +927,7 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
   b += (double)cb * stride * (16.0 + 2.0 * es);         // packed chunk buffers
   b += 2.0 * cb * nplanes * npl * es;                   // plane intermediates
   b += N * 8.0 + 2.0 * norb * 8.0;                      // potential, reductions
+  b += (double)((cb + 7) / 8) * N * 8.0;                // partial densities
   b += npoints * (np * 8.0 + 4 * 4.0) + 64.0 * 1024;    // KB tables
   b += (double)cb * npoints * np * 16.0 / 8.0;          // projection partials (upper bound)
   b += (double)norb * stride * 16.0;                    // resident state

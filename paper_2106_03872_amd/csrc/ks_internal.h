@@ -99,6 +99,7 @@ struct ks_system {
   void* partial = nullptr;                    // [cb][nslots][nproj]
   double2* DP = nullptr;                      // [cb][natoms][nproj]
   double* red = nullptr;                      // [2*max_norb]
+  double* dens_part = nullptr;                // [ceil(cb/8)][N] partial densities
   size_t partial_cap = 0, dp_cap = 0;
 
   // orthonormalisation workspace (allocated on first use)
