@@ -213,7 +213,7 @@ template <> struct plan<128> { using list = radix_list<8, 4, 4>; };
 // Where a stage reads from / writes to.  LDS stages work in place on the
 // batch buffer; the first stage may instead pull its inputs from a loader
 // functor and the last stage may push its outputs to a store functor.
-enum { SRC_LDS = 0, SRC_FN = 1 };
+enum { SRC_LDS = 0, SRC_FN = 1, SRC_PRE = 2 };   // SRC_PRE: inputs already in a register array (fft_preload)
 enum { DST_LDS = 0, DST_FN = 1, DST_FN_LDS = 2 };   // DST_FN_LDS: the functor writes the batch buffer
 
 struct no_load {
@@ -244,11 +244,12 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         if constexpr (SRC == SRC_FN) v[it][q] = load(t, b + q * NBF);
+        else if constexpr (SRC == SRC_PRE) v[it][q] = load.v[it][q];
         else v[it][q] = buf[t * ts + b + q * NBF];
       }
     }
   }
-  if constexpr (SRC == SRC_LDS && DST != DST_FN) __syncthreads();
+  if constexpr (SRC == SRC_LDS && DST != DST_FN) __syncthreads();   // in place: all reads before writes
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const int i = tid + it * NT;
@@ -298,6 +299,35 @@ __device__ __forceinline__ void fft_io_impl(radix_list<Rs...>, T* buf, int ts, i
 template <int N, int SIGN, int NB, int NT, int SRC, int DST, typename T, class Load, class Store>
 __device__ __forceinline__ void fft_io(T* buf, int ts, int ntrans, const T* tw, Load&& load, Store&& store) {
   fft_io_impl<N, SIGN, NB, NT, SRC, DST, T>(typename plan<N>::list{}, buf, ts, ntrans, tw, load, store);
+}
+
+// First-stage inputs of one batch held in registers, so that the loads of the
+// next batch can be issued before the current one is transformed.
+template <int N, int NB, int NT, typename T, typename L> struct first_stage_regs;
+template <int N, int NB, int NT, typename T, int R, int... Rest>
+struct first_stage_regs<N, NB, NT, T, radix_list<R, Rest...>> {
+  static constexpr int radix = R;
+  static constexpr int NBF = N / R;
+  static constexpr int TOT = NB * NBF;
+  static constexpr int items = (TOT + NT - 1) / NT;
+  T v[items][R];
+};
+template <int N, int NB, int NT, typename T> using fft_regs = first_stage_regs<N, NB, NT, T, typename plan<N>::list>;
+
+// Load the first-stage inputs of transforms t < ntrans: load(t, e) as in fft_io.
+template <int N, int NB, int NT, typename T, class Load>
+__device__ __forceinline__ void fft_preload(fft_regs<N, NB, NT, T>& r, int ntrans, Load&& load) {
+  using FR = fft_regs<N, NB, NT, T>;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < FR::items; ++it) {
+    const int i = tid + it * NT;
+    const int t = i % NB, b = i / NB;
+    if ((FR::TOT % NT == 0 || i < FR::TOT) && t < ntrans) {
+#pragma unroll
+      for (int q = 0; q < FR::radix; ++q) r.v[it][q] = load(t, b + q * FR::NBF);
+    }
+  }
 }
 
 // In-place DFT of transforms in buf (natural order in and out).

@@ -187,10 +187,16 @@ __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ T
 #pragma unroll
     for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
   const int oa = g * DENS_GROUP, ob = min(nb, oa + DENS_GROUP);
+  // the next orbital's T is loaded while the current one is transformed
+  using FR = fft_regs<N0, NB, NT, C>;
+  FR pre, cur;
+  if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
-    const TLoader<N0, NB, C> ld(Tin, o, npl, tab.nplanes, tab.m0lo, p0);
+    cur = pre;
+    if (o + 1 < ob)
+      fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     const double f = occ[o] * inv_omega;
-    fft_io<N0, +1, NB, NT, SRC_FN, DST_FN, C>(X, N0 + 1, NB, tw, ld, [&](int, int, C v, int it, int q) {
+    fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN, C>(X, N0 + 1, NB, tw, cur, [&](int, int, C v, int it, int q) {
       a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
     });
     __syncthreads();

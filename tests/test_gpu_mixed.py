@@ -88,3 +88,18 @@ def test_mixed_energy_after_50_steps(ks):
     assert d_e < 1e-6
     assert abs(emx.item() - e64.item()) / nel < 1e-5
     assert rel_err(b.cpu().numpy(), a.cpu().numpy()) < 1e-5
+
+
+def test_mixed_propagation_vs_oracle(ks):
+    spec, sysm = _case("t24")
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
+    c = orbitals_device(spec)
+    c0 = c.cpu().numpy()
+    occ = torch.from_numpy(synth.occupations(spec)).cuda()
+    rho = torch.empty((spec.nsteps,) + spec.n, dtype=torch.float64, device="cuda")
+    gs.propagate_step(c, spec.dt, spec.nsteps, occ, rho)
+    ref = ko.taylor4_step(ham, c0, spec.dt, spec.nsteps)
+    assert rel_err(c.cpu().numpy(), ref) < TOL_H
+    rr = ko.density(ham, ref, synth.occupations(spec))
+    assert np.linalg.norm(rho[-1].cpu().numpy() - rr) / np.linalg.norm(rr) < TOL_H

@@ -219,3 +219,63 @@ def test_orthonormalize_rejects_dependent(ks):
     with pytest.raises(ks.KSError) as e:
         gs.orthonormalize(c)
     assert e.value.status == ks.KS_EINVAL
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_anisotropic_grid_and_ragged_tile(ks):
+    """n0 != n1 = n2 (different x-pencil length), non-cubic cell; 40*40 = 1600
+    pencils is not a multiple of the 32-pencil x-tile width... (50 tiles), and
+    the 60-point case in SMALL covers a ragged last tile."""
+    spec = synth.Spec(name="aniso", n=(24, 40, 40), L=(7.5, 12.5, 13.0), ecut=10.0, norb=5, natoms=3, seed=91)
+    print("[case] aniso", file=sys.stderr, flush=True)
+    sysm = synth.system(spec)
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    assert rel_err(gs.ham_apply(c).cpu().numpy(), ko.ham_apply(ham, c.cpu().numpy())) < TOL
+    occ = torch.full((spec.norb,), 1.5, dtype=torch.float64, device="cuda")
+    rho = gs.density(c, occ).cpu().numpy()
+    rr = ko.density(ham, c.cpu().numpy(), np.full(spec.norb, 1.5))
+    assert np.linalg.norm(rho - rr) / np.linalg.norm(rr) < TOL
+
+
+def test_duplicate_and_overlapping_projector_points(ks):
+    """Projector lists with a repeated point inside one atom and two atoms
+    sharing points: every entry counts (the sums of Eq. vnl run over list
+    entries)."""
+    spec = synth.CONFIGS["t24"]
+    print("[case] duplicates", file=sys.stderr, flush=True)
+    sysm = synth.system(spec)
+    rng = np.random.default_rng(12)
+    npts = sysm.proj.npts.copy()
+    idx = sysm.proj.idx.copy()
+    beta = sysm.proj.beta.copy()
+    idx[5] = idx[6]                                   # duplicate within atom 0
+    o1 = int(npts[0])
+    idx[o1:o1 + 20] = idx[0:20]                       # atom 1 shares 20 points with atom 0
+    beta[o1:o1 + 20] = rng.standard_normal((20, 4))
+    atoms = []
+    off = 0
+    for n_ in npts:
+        atoms.append((idx[off:off + n_], beta[off:off + n_]))
+        off += n_
+    g = ko.Grid(spec.n, spec.L, spec.ecut)
+    ham = ko.Hamiltonian(g, sysm.vloc, atoms, sysm.proj.d)
+    gs = ks.System(spec.n, spec.L, spec.ecut, spec.norb)
+    gs.set_vloc(torch.from_numpy(sysm.vloc).cuda())
+    gs.set_projectors(npts, idx, beta, sysm.proj.d)
+    c = orbitals_device(spec)
+    assert rel_err(gs.ham_apply(c).cpu().numpy(), ko.ham_apply(ham, c.cpu().numpy())) < TOL
+
+
+def test_single_orbital_and_max_chunk(ks):
+    spec, sysm = _case("t40")
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    gs.set_chunk(spec.norb)
+    one = c[2:3].contiguous()
+    assert rel_err(gs.ham_apply(one).cpu().numpy(), ko.ham_apply(ham, one.cpu().numpy())) < TOL
+    gs.set_chunk(1)
+    assert rel_err(gs.ham_apply(c).cpu().numpy(), ko.ham_apply(ham, c.cpu().numpy())) < TOL
