@@ -242,6 +242,8 @@ typedef struct {
   int npoints;      /* projector points (sum of npts) */
   int x_tile;       /* x-pencils per block in the x-pencil passes */
   int precision;    /* ks_precision */
+  int x_half;       /* 1 if every sphere plane has |m0| < n0/4: the x-synthesis loads and
+                       transforms only the nonzero half of its first-stage inputs */
 } ks_info;
 
 /* Fill *info for sys.  KS_EINVAL on null arguments. */

@@ -223,6 +223,18 @@ struct no_store {
   template <typename T> __device__ void operator()(int, int, T, int, int) const {}
 };
 
+// threadIdx.x behind an empty volatile asm: the per-thread index arithmetic of
+// each stage is then computed where it is used instead of being hoisted out
+// of a caller's loop and kept live across it (which costs more registers
+// than the few integer operations it saves).
+template <int NT>
+__device__ __forceinline__ int fresh_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  __builtin_assume(t >= 0 && t < NT);
+  return t;
+}
+
 // One Stockham stage over a batch of NB transforms laid out at buf[t*ts + e].
 // tw[j] = exp(-2 pi i j / N) (global or LDS).
 //   load(t, e)             -> element e of transform t        (SRC_FN)
@@ -234,7 +246,7 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
   constexpr int ITEMS = (TOT + NT - 1) / NT;
-  const int tid = threadIdx.x;
+  const int tid = fresh_tid<NT>();
   T v[ITEMS][R];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
@@ -244,7 +256,7 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         if constexpr (SRC == SRC_FN) v[it][q] = load(t, b + q * NBF);
-        else if constexpr (SRC == SRC_PRE) v[it][q] = load.v[it][q];
+        else if constexpr (SRC == SRC_PRE) v[it][q] = load.r.get(it, q);
         else v[it][q] = buf[t * ts + b + q * NBF];
       }
     }
@@ -272,6 +284,7 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
       }
     }
   }
+  if constexpr (SRC == SRC_PRE) load.refill();
   if constexpr (DST != DST_FN) __syncthreads();
 }
 
@@ -302,30 +315,53 @@ __device__ __forceinline__ void fft_io(T* buf, int ts, int ntrans, const T* tw, 
 }
 
 // First-stage inputs of one batch held in registers, so that the loads of the
-// next batch can be issued before the current one is transformed.
-template <int N, int NB, int NT, typename T, typename L> struct first_stage_regs;
-template <int N, int NB, int NT, typename T, int R, int... Rest>
-struct first_stage_regs<N, NB, NT, T, radix_list<R, Rest...>> {
+// next batch can be issued before the current one is transformed.  HALF: the
+// inputs are known to vanish outside the band e < N/4 or e >= 3N/4 (a sphere
+// of planes |m| < N/4); the first-stage element q of a butterfly reads
+// e = b + q*N/R, so only q < R/4 and q >= 3R/4 are held and loaded.
+template <int N, int NB, int NT, typename T, typename L, bool HALF> struct first_stage_regs;
+template <int N, int NB, int NT, typename T, int R, int... Rest, bool HALF>
+struct first_stage_regs<N, NB, NT, T, radix_list<R, Rest...>, HALF> {
+  static_assert(!HALF || R % 4 == 0, "band-limited input needs a first radix divisible by 4");
   static constexpr int radix = R;
   static constexpr int NBF = N / R;
   static constexpr int TOT = NB * NBF;
   static constexpr int items = (TOT + NT - 1) / NT;
-  T v[items][R];
+  static constexpr int nq = HALF ? R / 2 : R;
+  static constexpr bool held(int q) { return !HALF || q < R / 4 || q >= 3 * R / 4; }
+  static constexpr int slot(int q) { return (!HALF || q < R / 4) ? q : q - R / 2; }
+  T v[items][nq];
+  __device__ __forceinline__ T get(int it, int q) const { return held(q) ? v[it][slot(q)] : T{0, 0}; }
 };
-template <int N, int NB, int NT, typename T> using fft_regs = first_stage_regs<N, NB, NT, T, typename plan<N>::list>;
+template <int N, int NB, int NT, typename T, bool HALF = false>
+using fft_regs = first_stage_regs<N, NB, NT, T, typename plan<N>::list, HALF>;
+
+// SRC_PRE source: r holds the first-stage inputs; refill() is called once the
+// first stage has consumed them and written its outputs, so that the loads it
+// issues (typically the next batch into r) overlap the rest of the transform.
+template <class FR, class F>
+struct pre_src {
+  FR& r;
+  F refill;
+};
+template <class FR, class F>
+__device__ __forceinline__ pre_src<FR, F> preloaded(FR& r, F refill) {
+  return pre_src<FR, F>{r, refill};
+}
 
 // Load the first-stage inputs of transforms t < ntrans: load(t, e) as in fft_io.
-template <int N, int NB, int NT, typename T, class Load>
-__device__ __forceinline__ void fft_preload(fft_regs<N, NB, NT, T>& r, int ntrans, Load&& load) {
-  using FR = fft_regs<N, NB, NT, T>;
-  const int tid = threadIdx.x;
+template <int N, int NB, int NT, typename T, bool HALF, class Load>
+__device__ __forceinline__ void fft_preload(fft_regs<N, NB, NT, T, HALF>& r, int ntrans, Load&& load) {
+  using FR = fft_regs<N, NB, NT, T, HALF>;
+  const int tid = fresh_tid<NT>();
 #pragma unroll
   for (int it = 0; it < FR::items; ++it) {
     const int i = tid + it * NT;
     const int t = i % NB, b = i / NB;
     if ((FR::TOT % NT == 0 || i < FR::TOT) && t < ntrans) {
 #pragma unroll
-      for (int q = 0; q < FR::radix; ++q) r.v[it][q] = load(t, b + q * FR::NBF);
+      for (int q = 0; q < FR::radix; ++q)
+        if (FR::held(q)) r.v[it][FR::slot(q)] = load(t, b + q * FR::NBF);
     }
   }
 }
@@ -343,7 +379,7 @@ __device__ __forceinline__ void last_stage_positions_impl(int ntrans, F& f) {
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
   constexpr int ITEMS = (TOT + NT - 1) / NT;
-  const int tid = threadIdx.x;
+  const int tid = fresh_tid<NT>();
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const int i = tid + it * NT;

@@ -83,13 +83,14 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
   const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
   // the U columns of the next chunk are loaded while the current one is transformed
   using FR = fft_regs<N, YB, NTP, C>;
-  FR pre, cur;
+  FR pre;
   fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return u[e * N + t]; });
   for (int w0 = 0; w0 < N; w0 += YB) {
-    cur = pre;
     const int w1 = w0 + YB;
-    if (w1 < N) fft_preload<N, YB, NTP, C>(pre, N - w1, [&](int t, int e) -> C { return u[e * N + w1 + t]; });
-    fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, cur, [&](int t, int e, C v, int, int) {
+    auto next = [&] {
+      if (w1 < N) fft_preload<N, YB, NTP, C>(pre, N - w1, [&](int t, int e) -> C { return u[e * N + w1 + t]; });
+    };
+    fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, preloaded(pre, next), [&](int t, int e, C v, int, int) {
       const int c = fold(e, N) - m1lo;
       if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
     });

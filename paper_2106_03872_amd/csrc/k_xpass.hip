@@ -19,7 +19,7 @@ struct TLoader {
         tvalid(npl_ - p0) {}
   __device__ C operator()(int t, int e) const {
     const int pi = fold(e, N0) - m0lo;
-    return (pi >= 0 && pi < nplanes && t < tvalid) ? base[pi * npl + t] : czero<C>();
+    return (pi >= 0 && pi < nplanes && t < tvalid) ? base[(unsigned)(pi * npl + t)] : czero<C>();
   }
 };
 
@@ -30,21 +30,33 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-template <int N0, typename R>
-__global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ partial,
-                                                   SphereTab tab, ProjTab pt, const cplx<R>* __restrict__ tw0,
-                                                   double scale) {
+// Orbital groups: block (tile, y) handles the orbitals [y*nb/ng, (y+1)*nb/ng)
+// of its tile in order (ng = gridDim.y).  The next orbital's T is loaded into
+// registers while the current one is transformed, and the per-tile data
+// (twiddles, potential, KB tables) is fetched once per block.
+
+__device__ __forceinline__ void orbital_range(int nb, int& oa, int& ob) {
+  oa = (int)((long long)blockIdx.y * nb / gridDim.y);
+  ob = (int)((long long)(blockIdx.y + 1) * nb / gridDim.y);
+}
+
+template <int N0, typename R, bool HB>
+__global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, int nb,
+                                                   cplx<R>* __restrict__ partial, SphereTab tab, ProjTab pt,
+                                                   const cplx<R>* __restrict__ tw0, double scale) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
+  using FR = fft_regs<N0, NB, NT, C, HB>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ C tw[N0];
-  const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int tile = blockIdx.x, tid = threadIdx.x;
+  int oa, ob;
+  orbital_range(nb, oa, ob);
   const int npl = tab.n1 * tab.n2;
+  const int p0 = tile * NB;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
   if (ns == 0) return;  // no sphere point in this tile (uniform per block)
   for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
-  const TLoader<N0, NB, C> ld(Tin, o, npl, tab.nplanes, tab.m0lo, tile * NB);
-  fft_io<N0, +1, NB, NT, SRC_FN, DST_LDS, C>(X, N0 + 1, NB, tw, ld, no_store{});
   // Projections: items (segment, slot, projector); each sums beta * psi over
   // its segment of the slot's points, then the segments of every (slot,
   // projector) are added in order.  The partial sums are staged in X once all
@@ -56,56 +68,96 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   const int items = pairs * nseg;
   // items <= max(NT, pairs) and pairs <= KB_TILE_DP, so PJ items per thread suffice
   constexpr int PJ = ((NT > KB_TILE_DP ? NT : KB_TILE_DP) + NT - 1) / NT;
-  double sx[PJ], sy[PJ];
+  // The first KP points of every item (LDS position, beta) are the same for
+  // all orbitals of the block and stay in registers.
+  constexpr int KP = 8;
+  int ka[PJ], kb[PJ], kq[PJ];
+  int cpos[PJ][KP];
+  double cbeta[PJ][KP];
 #pragma unroll
   for (int j = 0; j < PJ; ++j) {
-    sx[j] = sy[j] = 0.0;
     const int i = tid + j * NT;
+    ka[j] = kb[j] = kq[j] = 0;
     if (i < items) {
       const int pr = i % pairs, seg = i / pairs;
-      const int sl = pr / np, q = pr - sl * np;
+      const int sl = pr / np;
+      kq[j] = pr - sl * np;
       const int k0 = pt.slot_pt[sA + sl], len = pt.slot_pt[sA + sl + 1] - k0;
-      const int a = k0 + (len * seg) / nseg, b = k0 + (len * (seg + 1)) / nseg;
-      for (int k = a; k < b; ++k) {
-        const double bv = pt.beta[(long long)k * np + q];
+      ka[j] = k0 + (len * seg) / nseg;
+      kb[j] = k0 + (len * (seg + 1)) / nseg;
+    }
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+      const int k = ka[j] + c;
+      const bool in = k < kb[j];
+      cpos[j][c] = in ? pt.pt_lds[k] : 0;
+      cbeta[j][c] = in ? pt.beta[(long long)k * np + kq[j]] : 0.0;
+    }
+  }
+  double2* red = reinterpret_cast<double2*>(X);   // holds >= 256 double2 for every supported N0, R
+  FR pre;
+  if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
+  for (int o = oa; o < ob; ++o) {
+    auto next = [&] {
+      if (o + 1 < ob)
+        fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+    };
+    fft_io<N0, +1, NB, NT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
+    double sx[PJ], sy[PJ];
+#pragma unroll
+    for (int j = 0; j < PJ; ++j) {
+      sx[j] = sy[j] = 0.0;
+#pragma unroll
+      for (int c = 0; c < KP; ++c) {
+        if (ka[j] + c < kb[j]) {
+          const C x = X[cpos[j][c]];
+          sx[j] += cbeta[j][c] * double(x.x);
+          sy[j] += cbeta[j][c] * double(x.y);
+        }
+      }
+      for (int k = ka[j] + KP; k < kb[j]; ++k) {
+        const double bv = pt.beta[(long long)k * np + kq[j]];
         const C x = X[pt.pt_lds[k]];
         sx[j] += bv * double(x.x);
         sy[j] += bv * double(x.y);
       }
     }
-  }
-  __syncthreads();
-  double2* red = reinterpret_cast<double2*>(X);   // holds >= 256 double2 for every supported N0, R
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < PJ; ++j) {
-    const int i = tid + j * NT;
-    if (i < items) red[i] = double2{sx[j], sy[j]};
-  }
-  __syncthreads();
-  for (int pr = tid; pr < pairs; pr += NT) {
-    double tx = 0.0, ty = 0.0;
-    for (int seg = 0; seg < nseg; ++seg) {
-      const double2 v = red[seg * pairs + pr];
-      tx += v.x;
-      ty += v.y;
+    for (int j = 0; j < PJ; ++j) {
+      const int i = tid + j * NT;
+      if (i < items) red[i] = double2{sx[j], sy[j]};
     }
-    const int sl = pr / np, q = pr - sl * np;
-    partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(tx * scale), R(ty * scale)};
+    __syncthreads();
+    for (int pr = tid; pr < pairs; pr += NT) {
+      double tx = 0.0, ty = 0.0;
+      for (int seg = 0; seg < nseg; ++seg) {
+        const double2 v = red[seg * pairs + pr];
+        tx += v.x;
+        ty += v.y;
+      }
+      const int sl = pr / np, q = pr - sl * np;
+      partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(tx * scale), R(ty * scale)};
+    }
+    __syncthreads();   // red (= X) is rewritten by the next orbital's first stage
   }
 }
 
-template <int N0, typename R>
-__global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ Uout,
-                                                    const double* __restrict__ V, const double2* __restrict__ DP,
-                                                    SphereTab tab, ProjTab pt, const cplx<R>* __restrict__ tw0,
-                                                    double sc_in, double sc_out) {
+template <int N0, typename R, bool HB>
+__global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, int nb,
+                                                    cplx<R>* __restrict__ Uout, const double* __restrict__ V,
+                                                    const double2* __restrict__ DP, SphereTab tab, ProjTab pt,
+                                                    const cplx<R>* __restrict__ tw0, double sc_in, double sc_out) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
   using LS = last_shape<N0, NB, NT>;
+  using FR = fft_regs<N0, NB, NT, C, HB>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ double2 dps[KB_TILE_DP];
   __shared__ C tw[N0];
-  const int tile = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int tile = blockIdx.x, tid = threadIdx.x;
+  int oa, ob;
+  orbital_range(nb, oa, ob);
   for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
@@ -115,13 +167,18 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
     vr[it][q] = (p0 + t < npl) ? vbase[e * npl + t] * sc_in : 0.0;
   });
+  // KB coefficients d*P of this tile's slots: thread tid < ns*np stages one
+  // (slot, projector) value per orbital.
   const int np = pt.nproj;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
-  for (int i = tid; i < ns * np; i += NT) {
-    const int sl = i / np, q = i - sl * np;
-    dps[i] = DP[((long long)o * pt.natoms + pt.slot_atom[sA + sl]) * np + q];
+  const int ndp = ns * np;   // <= KB_TILE_DP <= NT
+  const long long dp_stride = (long long)pt.natoms * np;
+  long long dp_off = 0;
+  if (tid < ndp) {
+    const int sl = tid / np, q = tid - sl * np;
+    dp_off = (long long)pt.slot_atom[sA + sl] * np + q;
   }
-  // first unique point of this thread (fetched before the transform)
+  // first unique point of this thread (fetched once per block)
   const int uA = pt.up_off[tile], uB = pt.up_off[tile + 1];
   int u_pos = -1, u_e0 = 0, u_e1 = 0;
   if (uA + tid < uB) {
@@ -129,45 +186,59 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     u_e0 = pt.up_ent[uA + tid];
     u_e1 = pt.up_ent[uA + tid + 1];
   }
-  const TLoader<N0, NB, C> ld(Tin, o, npl, tab.nplanes, tab.m0lo, p0);
-  // synthesis, then psi <- V psi as the outputs are written
-  fft_io<N0, +1, NB, NT, SRC_FN, DST_FN_LDS, C>(X, N0 + 1, NB, tw, ld, [&](int t, int e, C v, int it, int q) {
-    X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
-  });
-  if (ns > 0) {
-    for (int u = uA + tid; u < uB; u += NT) {
-      const int pos = (u == uA + tid) ? u_pos : pt.up_lds[u];
-      const int e0 = (u == uA + tid) ? u_e0 : pt.up_ent[u];
-      const int e1 = (u == uA + tid) ? u_e1 : pt.up_ent[u + 1];
-      double fx = 0.0, fy = 0.0;
-      for (int e = e0; e < e1; ++e) {
-        const double* b = pt.beta_ent + (long long)e * np;
-        const double2* dp = dps + pt.ent_slot[e] * np;
-        for (int q = 0; q < np; ++q) {
-          fx += b[q] * dp[q].x;
-          fy += b[q] * dp[q].y;
-        }
-      }
-      C& x = X[pos];
-      x = C{R(double(x.x) + fx), R(double(x.y) + fy)};
-    }
-    __syncthreads();
-  }
-  C* out = Uout + (long long)o * tab.nplanes * npl;
   const int nplanes = tab.nplanes, m0lo = tab.m0lo;
-  C* obase = out + p0;
   const int tvalid = npl - p0;
-  fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, [&](int t, int e, C v, int, int) {
-    const int pi = fold(e, N0) - m0lo;
-    if (pi >= 0 && pi < nplanes && t < tvalid) obase[pi * npl + t] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
-  });
+  FR pre;
+  if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, nplanes, m0lo, p0));
+  double2 dnext = {0.0, 0.0};
+  if (tid < ndp && oa < ob) dnext = DP[oa * dp_stride + dp_off];
+  for (int o = oa; o < ob; ++o) {
+    // this orbital's d*P (fetched one orbital ahead); the previous orbital's
+    // scatter has finished reading dps, and the stage barriers publish it
+    if (tid < ndp) dps[tid] = dnext;
+    auto next = [&] {
+      if (o + 1 < ob) {
+        fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, nplanes, m0lo, p0));
+        if (tid < ndp) dnext = DP[(o + 1) * dp_stride + dp_off];
+      }
+    };
+    // synthesis, then psi <- V psi as the outputs are written
+    fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int t, int e, C v, int it, int q) {
+      X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
+    });
+    if (ns > 0) {
+      for (int u = uA + tid; u < uB; u += NT) {
+        const int pos = (u == uA + tid) ? u_pos : pt.up_lds[u];
+        const int e0 = (u == uA + tid) ? u_e0 : pt.up_ent[u];
+        const int e1 = (u == uA + tid) ? u_e1 : pt.up_ent[u + 1];
+        double fx = 0.0, fy = 0.0;
+        for (int e = e0; e < e1; ++e) {
+          const double* b = pt.beta_ent + (long long)e * np;
+          const double2* dp = dps + pt.ent_slot[e] * np;
+          for (int q = 0; q < np; ++q) {
+            fx += b[q] * dp[q].x;
+            fy += b[q] * dp[q].y;
+          }
+        }
+        C& x = X[pos];
+        x = C{R(double(x.x) + fx), R(double(x.y) + fy)};
+      }
+      __syncthreads();
+    }
+    C* obase = Uout + (long long)o * nplanes * npl + p0;
+    fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, [&](int t, int e, C v, int, int) {
+      const int pi = fold(e, N0) - m0lo;
+      if (pi >= 0 && pi < nplanes && t < tvalid) obase[(unsigned)(pi * npl + t)] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
+    });
+    __syncthreads();   // X and dps are rewritten for the next orbital
+  }
 }
 
 // density: block (tile, group of DENS_GROUP orbitals); |psi|^2 is accumulated
 // straight from the last synthesis stage over the group's orbitals in order
 // and written to the group's partial density; dens_sum adds the groups in
 // order.
-template <int N0, typename R>
+template <int N0, typename R, bool HB>
 __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    const double* __restrict__ occ, double* __restrict__ part,
                                                    SphereTab tab, const cplx<R>* __restrict__ tw0,
@@ -187,16 +258,17 @@ __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ T
 #pragma unroll
     for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
   const int oa = g * DENS_GROUP, ob = min(nb, oa + DENS_GROUP);
-  // the next orbital's T is loaded while the current one is transformed
-  using FR = fft_regs<N0, NB, NT, C>;
-  FR pre, cur;
+  // the next orbital's T is loaded once the first stage has consumed the current one
+  using FR = fft_regs<N0, NB, NT, C, HB>;
+  FR pre;
   if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
-    cur = pre;
-    if (o + 1 < ob)
-      fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+    auto next = [&] {
+      if (o + 1 < ob)
+        fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+    };
     const double f = occ[o] * inv_omega;
-    fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN, C>(X, N0 + 1, NB, tw, cur, [&](int, int, C v, int it, int q) {
+    fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int, int, C v, int it, int q) {
       a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
     });
     __syncthreads();
@@ -219,20 +291,32 @@ __global__ __launch_bounds__(NT) void dens_sum_kernel(const double* __restrict__
 
 // ------------------------------------------------------------------ launchers
 
-template <int N0>
+// Orbital groups per x-pass launch: groups of at most X_GROUP orbitals (sizes
+// differing by at most one), fewer orbitals per group when the launch would
+// otherwise have too few blocks to fill the chip (about 12 per CU).
+static int x_groups(const ks_system* s, int nb) {
+  const long long blocks = (long long)s->ntiles * nb;
+  long long g = blocks / (256 * 12);
+  g = g < 1 ? 1 : (g > X_GROUP ? X_GROUP : g);
+  return (int)((nb + g - 1) / g);
+}
+
+template <int N0, bool HB>
 static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
   const double scale = s->dV / sqrt(s->omega);
+  const int ng = x_groups(s, nb);
   if (!mixed(s))
-    xproj_kernel<N0, double><<<dim3(s->ntiles, nb), NT, 0, st>>>((const double2*)T, (double2*)partial,
+    xproj_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, (double2*)partial,
                                                                   sphere_tab(s), proj_tab(s), s->d_tw0, scale);
   else
-    xproj_kernel<N0, float><<<dim3(s->ntiles, nb), NT, 0, st>>>((const float2*)T, (float2*)partial, sphere_tab(s),
-                                                                 proj_tab(s), s->d_tw0f, scale);
+    xproj_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, (float2*)partial,
+                                                                 sphere_tab(s), proj_tab(s), s->d_tw0f, scale);
 }
 
 bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
   switch (s->n[0]) {
-#define KS_CASE(v) case v: xproj_n<v>(s, nb, T, partial, st); return true;
+#define KS_CASE(v) \
+  case v: s->x_half ? xproj_n<v, true>(s, nb, T, partial, st) : xproj_n<v, false>(s, nb, T, partial, st); return true;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:
@@ -240,23 +324,25 @@ bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipS
   }
 }
 
-template <int N0>
+template <int N0, bool HB>
 static void xapply_n(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
   const double sc_in = 1.0 / sqrt(s->omega);
   const double sc_out = sqrt(s->omega) / (double)s->N;
+  const int ng = x_groups(s, nb);
   if (!mixed(s))
-    xapply_kernel<N0, double><<<dim3(s->ntiles, nb), NT, 0, st>>>((const double2*)T, (double2*)U, s->d_v, DP,
-                                                                   sphere_tab(s), proj_tab(s), s->d_tw0, sc_in,
+    xapply_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, (double2*)U, s->d_v,
+                                                                   DP, sphere_tab(s), proj_tab(s), s->d_tw0, sc_in,
                                                                    sc_out);
   else
-    xapply_kernel<N0, float><<<dim3(s->ntiles, nb), NT, 0, st>>>((const float2*)T, (float2*)U, s->d_v, DP,
-                                                                  sphere_tab(s), proj_tab(s), s->d_tw0f, sc_in,
+    xapply_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, (float2*)U, s->d_v,
+                                                                  DP, sphere_tab(s), proj_tab(s), s->d_tw0f, sc_in,
                                                                   sc_out);
 }
 
 bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
   switch (s->n[0]) {
-#define KS_CASE(v) case v: xapply_n<v>(s, nb, T, DP, U, st); return true;
+#define KS_CASE(v) \
+  case v: s->x_half ? xapply_n<v, true>(s, nb, T, DP, U, st) : xapply_n<v, false>(s, nb, T, DP, U, st); return true;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:
@@ -264,21 +350,22 @@ bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP,
   }
 }
 
-template <int N0>
+template <int N0, bool HB>
 static void xdens_n(const ks_system* s, int nb, const void* T, const double* occ, double* part, hipStream_t st) {
   const int ng = (nb + DENS_GROUP - 1) / DENS_GROUP;
   if (!mixed(s))
-    xdens_kernel<N0, double><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, occ, part, sphere_tab(s),
+    xdens_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, occ, part, sphere_tab(s),
                                                                   s->d_tw0, 1.0 / s->omega);
   else
-    xdens_kernel<N0, float><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, occ, part, sphere_tab(s),
+    xdens_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, occ, part, sphere_tab(s),
                                                                  s->d_tw0f, 1.0 / s->omega);
 }
 
 bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
                   hipStream_t st) {
   switch (s->n[0]) {
-#define KS_CASE(v) case v: xdens_n<v>(s, nb, T, occ, s->dens_part, st); break;
+#define KS_CASE(v) \
+  case v: s->x_half ? xdens_n<v, true>(s, nb, T, occ, s->dens_part, st) : xdens_n<v, false>(s, nb, T, occ, s->dens_part, st); break;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:

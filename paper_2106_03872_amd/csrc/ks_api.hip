@@ -477,6 +477,7 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   s->npw_stride = (npw + 63) / 64 * 64;
   s->xnb = x_tile_nb(n[0]);
   s->ntiles = (s->npl + s->xnb - 1) / s->xnb;
+  s->x_half = s->m0lo >= -(n[0] / 4) && s->m0lo + s->nplanes - 1 < n[0] / 4;
 
   if (plane_lds_bytes(s) > 160 * 1024) {
     delete s;
@@ -948,6 +949,7 @@ ks_status ks_system_info(const ks_system* s, ks_info* info) {
   info->npoints = s->npoints;
   info->x_tile = s->xnb;
   info->precision = s->prec;
+  info->x_half = s->x_half ? 1 : 0;
   return KS_OK;
 }
 

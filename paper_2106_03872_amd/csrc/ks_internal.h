@@ -86,6 +86,7 @@ struct ks_system {
   // projectors
   int natoms = 0, nproj = 0, nslots = 0, nruns = 0, npoints = 0, nuniq = 0;
   int xnb = 32, ntiles = 0;
+  bool x_half = false;   // every sphere plane has |m0| < n0/4 (band-limited x-synthesis input)
   int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
       *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_lds = nullptr,
       *d_up_ent = nullptr, *d_ent_slot = nullptr, *d_ent_brow = nullptr;

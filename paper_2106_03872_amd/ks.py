@@ -24,7 +24,7 @@ KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "pla
 
 class Info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nruns",
-                                            "nslots", "npoints", "x_tile", "precision")]
+                                            "nslots", "npoints", "x_tile", "precision", "x_half")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
