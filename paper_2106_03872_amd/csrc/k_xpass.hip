@@ -143,6 +143,85 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   }
 }
 
+// KB scatter (Eq. vnl): X[point] += sum over the point's entries (in atom
+// order) of beta_entry . dP[slot].
+template <typename C>
+__device__ __forceinline__ void kb_add(C* X, int key, double fx, double fy) {
+  C& x = X[key & ((1 << UP_POS_BITS) - 1)];
+  x = C{decltype(x.x)(double(x.x) + fx), decltype(x.x)(double(x.y) + fy)};
+}
+
+// extra entries of a point where spheres overlap (rare)
+__device__ __forceinline__ void kb_extra(const double2* dps, const ProjTab& pt, int np, int u, int key, double& fx,
+                                         double& fy) {
+  const int nx = key >> (UP_POS_BITS + UP_SLOT_BITS);
+  if (nx == 0) return;
+  const int x0 = pt.up_x[u];
+  for (int e = x0; e < x0 + nx; ++e) {
+    const double* b = pt.x_beta + (long long)e * np;
+    const double2* dp = dps + pt.x_slot[e] * np;
+    for (int q = 0; q < np; ++q) {
+      fx += b[q] * dp[q].x;
+      fy += b[q] * dp[q].y;
+    }
+  }
+}
+
+// NP projectors per atom fixed at compile time: two unique points per thread
+// and pass, u and u + NT, with the table loads of both issued before either
+// is used.
+template <int NP, typename C>
+__device__ __forceinline__ void kb_scatter_fixed(C* X, const double2* dps, const ProjTab& pt, int uA, int uB) {
+  const int tid = threadIdx.x;
+  for (int u = uA + tid; u < uB; u += 2 * NT) {
+    const int ub = u + NT;
+    const bool two = ub < uB;
+    const int ka = pt.up_key[u];
+    const int kb = two ? pt.up_key[ub] : 0;
+    double ba[NP], bb[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      ba[q] = pt.up_beta[(long long)u * NP + q];
+      bb[q] = two ? pt.up_beta[(long long)ub * NP + q] : 0.0;
+    }
+    const double2* da = dps + ((ka >> UP_POS_BITS) & UP_MAX_SLOT) * NP;
+    const double2* db = dps + ((kb >> UP_POS_BITS) & UP_MAX_SLOT) * NP;
+    double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const double2 pa = da[q], pb = db[q];
+      ax += ba[q] * pa.x;
+      ay += ba[q] * pa.y;
+      bx += bb[q] * pb.x;
+      by += bb[q] * pb.y;
+    }
+    kb_extra(dps, pt, NP, u, ka, ax, ay);
+    kb_add(X, ka, ax, ay);
+    if (two) {
+      kb_extra(dps, pt, NP, ub, kb, bx, by);
+      kb_add(X, kb, bx, by);
+    }
+  }
+}
+
+// any number of projectors per atom: one point at a time
+template <typename C>
+__device__ __forceinline__ void kb_scatter_any(C* X, const double2* dps, const ProjTab& pt, int uA, int uB) {
+  const int np = pt.nproj, tid = threadIdx.x;
+  for (int u = uA + tid; u < uB; u += NT) {
+    const int key = pt.up_key[u];
+    const double* b = pt.up_beta + (long long)u * np;
+    const double2* dp = dps + ((key >> UP_POS_BITS) & UP_MAX_SLOT) * np;
+    double fx = 0.0, fy = 0.0;
+    for (int q = 0; q < np; ++q) {
+      fx += b[q] * dp[q].x;
+      fy += b[q] * dp[q].y;
+    }
+    kb_extra(dps, pt, np, u, key, fx, fy);
+    kb_add(X, key, fx, fy);
+  }
+}
+
 template <int N0, typename R, bool HB>
 __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                     cplx<R>* __restrict__ Uout, const double* __restrict__ V,
@@ -178,14 +257,7 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     const int sl = tid / np, q = tid - sl * np;
     dp_off = (long long)pt.slot_atom[sA + sl] * np + q;
   }
-  // first unique point of this thread (fetched once per block)
   const int uA = pt.up_off[tile], uB = pt.up_off[tile + 1];
-  int u_pos = -1, u_e0 = 0, u_e1 = 0;
-  if (uA + tid < uB) {
-    u_pos = pt.up_lds[uA + tid];
-    u_e0 = pt.up_ent[uA + tid];
-    u_e1 = pt.up_ent[uA + tid + 1];
-  }
   const int nplanes = tab.nplanes, m0lo = tab.m0lo;
   const int tvalid = npl - p0;
   FR pre;
@@ -207,22 +279,8 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
       X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
     });
     if (ns > 0) {
-      for (int u = uA + tid; u < uB; u += NT) {
-        const int pos = (u == uA + tid) ? u_pos : pt.up_lds[u];
-        const int e0 = (u == uA + tid) ? u_e0 : pt.up_ent[u];
-        const int e1 = (u == uA + tid) ? u_e1 : pt.up_ent[u + 1];
-        double fx = 0.0, fy = 0.0;
-        for (int e = e0; e < e1; ++e) {
-          const double* b = pt.beta_ent + (long long)e * np;
-          const double2* dp = dps + pt.ent_slot[e] * np;
-          for (int q = 0; q < np; ++q) {
-            fx += b[q] * dp[q].x;
-            fy += b[q] * dp[q].y;
-          }
-        }
-        C& x = X[pos];
-        x = C{R(double(x.x) + fx), R(double(x.y) + fy)};
-      }
+      if (np == 4) kb_scatter_fixed<4>(X, dps, pt, uA, uB);
+      else kb_scatter_any(X, dps, pt, uA, uB);
       __syncthreads();
     }
     C* obase = Uout + (long long)o * nplanes * npl + p0;

@@ -530,7 +530,7 @@ void ks_system_destroy(ks_system* s) {
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
                   s->d_tw0f, s->d_tw1f, s->d_v, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
-                  s->d_up_off, s->d_up_lds, s->d_up_ent, s->d_ent_slot, s->d_ent_brow, s->d_beta, s->d_beta_ent,
+                  s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta,
                   s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
   for (void* p : ptrs) dfree(p);
   delete s;
@@ -571,18 +571,32 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
   const int np = ph.nproj;
   std::vector<double> kb((size_t)natoms * np);
   for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
-  std::vector<double> bent(ph.ent_brow.size() * np);
-  for (size_t e = 0; e < ph.ent_brow.size(); ++e)
-    for (int c = 0; c < np; ++c) bent[e * np + c] = ph.brows[(size_t)ph.ent_brow[e] * np + c];
+  // scatter tables: the primary entry of each unique point stored with it
+  const int nuniq = (int)ph.up_lds.size();
+  std::vector<int> up_key(nuniq), up_x(nuniq), x_slot;
+  std::vector<double> up_beta((size_t)nuniq * np), x_beta;
+  for (int u = 0; u < nuniq; ++u) {
+    const int e0 = ph.up_ent[u], e1 = ph.up_ent[u + 1];
+    const int nx = e1 - e0 - 1, slot = ph.ent_slot[e0];
+    if (ph.up_lds[u] >= (1 << UP_POS_BITS) || slot > UP_MAX_SLOT || nx > UP_MAX_EXTRA)
+      return fail(s, KS_EUNSUPPORTED, "projector sphere overlap or x-tile too large for the scatter tables");
+    up_key[u] = ph.up_lds[u] | slot << UP_POS_BITS | nx << (UP_POS_BITS + UP_SLOT_BITS);
+    up_x[u] = (int)x_slot.size();
+    for (int c = 0; c < np; ++c) up_beta[(size_t)u * np + c] = ph.brows[(size_t)ph.ent_brow[e0] * np + c];
+    for (int e = e0 + 1; e < e1; ++e) {
+      x_slot.push_back(ph.ent_slot[e]);
+      for (int c = 0; c < np; ++c) x_beta.push_back(ph.brows[(size_t)ph.ent_brow[e] * np + c]);
+    }
+  }
   ks_status st;
   if ((st = upload(s, &s->d_pt_lds, ph.pt_lds)) != KS_OK ||
       (st = upload(s, &s->d_slot_off, ph.slot_off)) != KS_OK || (st = upload(s, &s->d_slot_atom, ph.slot_atom)) != KS_OK ||
       (st = upload(s, &s->d_slot_pt, ph.slot_pt)) != KS_OK ||
       (st = upload(s, &s->d_atom_slot_off, ph.atom_slot_off)) != KS_OK ||
       (st = upload(s, &s->d_atom_slots, ph.atom_slots)) != KS_OK || (st = upload(s, &s->d_up_off, ph.up_off)) != KS_OK ||
-      (st = upload(s, &s->d_up_lds, ph.up_lds)) != KS_OK || (st = upload(s, &s->d_up_ent, ph.up_ent)) != KS_OK ||
-      (st = upload(s, &s->d_ent_slot, ph.ent_slot)) != KS_OK || (st = upload(s, &s->d_ent_brow, ph.ent_brow)) != KS_OK ||
-      (st = upload(s, &s->d_beta, ph.brows)) != KS_OK || (st = upload(s, &s->d_beta_ent, bent)) != KS_OK ||
+      (st = upload(s, &s->d_up_key, up_key)) != KS_OK || (st = upload(s, &s->d_up_x, up_x)) != KS_OK ||
+      (st = upload(s, &s->d_x_slot, x_slot)) != KS_OK || (st = upload(s, &s->d_beta, ph.brows)) != KS_OK ||
+      (st = upload(s, &s->d_up_beta, up_beta)) != KS_OK || (st = upload(s, &s->d_x_beta, x_beta)) != KS_OK ||
       (st = upload(s, &s->d_kb, kb)) != KS_OK)
     return st;
   s->natoms = (natoms > 0 && ph.npoints > 0) ? natoms : 0;

@@ -63,12 +63,12 @@ inline ProjTab proj_tab(const ks_system* s) {
   c.atom_slot_off = s->d_atom_slot_off;
   c.atom_slots = s->d_atom_slots;
   c.up_off = s->d_up_off;
-  c.up_lds = s->d_up_lds;
-  c.up_ent = s->d_up_ent;
-  c.ent_slot = s->d_ent_slot;
-  c.ent_brow = s->d_ent_brow;
+  c.up_key = s->d_up_key;
+  c.up_x = s->d_up_x;
+  c.up_beta = s->d_up_beta;
+  c.x_slot = s->d_x_slot;
+  c.x_beta = s->d_x_beta;
   c.beta = s->d_beta;
-  c.beta_ent = s->d_beta_ent;
   c.d = s->d_kb;
   c.natoms = s->natoms;
   c.nproj = s->nproj;

@@ -26,8 +26,10 @@ struct SphereTab {
 // tile's pencil buffer (w = p - tile*NB).
 //  - slot:  one (tile, atom) pair; the points of a slot are contiguous rows
 //           of beta, ordered (tile, atom, pencil, j0)
-//  - unique point: one grid point of the tile touched by any sphere, with its
-//           list of (slot, beta row) entries ordered by atom (scatter side)
+//  - unique point: one grid point of the tile touched by any sphere; its
+//           entries (slot, beta row), ordered by atom, are the primary entry
+//           (the first atom) stored with the point, and the extra entries of
+//           points where spheres overlap, stored apart (scatter side)
 struct ProjTab {
   const int* pt_lds;         // [npoints] LDS offset of each beta row's point
   const int* slot_off;       // [ntiles+1] slot range of each tile
@@ -35,16 +37,20 @@ struct ProjTab {
   const int* slot_pt;        // [nslots+1] beta-row range of each slot
   const int* atom_slot_off;  // [natoms+1]
   const int* atom_slots;     // slots of each atom, ascending
-  const int* up_off;         // [ntiles+1]
-  const int* up_lds;         // [nunique]
-  const int* up_ent;         // [nunique+1]
-  const int* ent_slot;       // [nentries] slot index local to the tile
-  const int* ent_brow;       // [nentries]
+  const int* up_off;         // [ntiles+1] unique-point range of each tile
+  const int* up_key;         // [nunique] LDS offset | primary slot << 16 | extra entries << 24
+  const int* up_x;           // [nunique] first extra entry of the point
+  const double* up_beta;     // [nunique][nproj] beta row of the primary entry
+  const int* x_slot;         // [nextra] tile-local slot of each extra entry
+  const double* x_beta;      // [nextra][nproj]
   const double* beta;        // [npoints][nproj], rows in slot order
-  const double* beta_ent;    // [nentries][nproj], rows in entry order
   const double* d;           // [natoms][nproj]
   int natoms, nproj, nslots;
 };
+
+// up_key fields
+constexpr int UP_POS_BITS = 16, UP_SLOT_BITS = 8;
+constexpr int UP_MAX_SLOT = (1 << UP_SLOT_BITS) - 1, UP_MAX_EXTRA = 127;
 
 constexpr int KB_MAX_NPROJ = 8;        // projectors per atom
 constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-tile
@@ -88,9 +94,9 @@ struct ks_system {
   int xnb = 32, ntiles = 0;
   bool x_half = false;   // every sphere plane has |m0| < n0/4 (band-limited x-synthesis input)
   int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
-      *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_lds = nullptr,
-      *d_up_ent = nullptr, *d_ent_slot = nullptr, *d_ent_brow = nullptr;
-  double *d_beta = nullptr, *d_beta_ent = nullptr, *d_kb = nullptr;
+      *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_key = nullptr,
+      *d_up_x = nullptr, *d_x_slot = nullptr;
+  double *d_beta = nullptr, *d_up_beta = nullptr, *d_x_beta = nullptr, *d_kb = nullptr;
 
   // workspace (one chunk of cb orbitals)
   int cb = 1;
