@@ -68,11 +68,12 @@ __global__ __launch_bounds__(NT) void unpack_kernel(const T* __restrict__ pk, in
 }
 
 // KB projections: P_Ip = sum over the (tile, atom) slots of atom I in
-// ascending order, DP = d_Ip P_Ip (Eq. vnl).  One wavefront per (atom, orbital):
-// lane = 8 * slot-lane + q; slot-lanes are combined in a fixed order.
+// ascending order, DP = scale d_Ip P_Ip (Eq. vnl; scale is the analysis
+// normalisation that the x-analysis leaves out).  One wavefront per (atom,
+// orbital): lane = 8 * slot-lane + q; slot-lanes are combined in a fixed order.
 template <typename C>
 __global__ __launch_bounds__(64) void proj_reduce_kernel(const C* __restrict__ partial, double2* __restrict__ DP,
-                                                         ProjTab pt) {
+                                                         ProjTab pt, double scale) {
   __shared__ double2 red[64];
   const int I = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
   const int q = lane & 7, sl = lane >> 3;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(64) void proj_reduce_kernel(const C* __restrict__ p
       tx += red[j * 8 + lane].x;
       ty += red[j * 8 + lane].y;
     }
-    const double dd = pt.d[I * np + q];
+    const double dd = pt.d[I * np + q] * scale;
     DP[((long long)o * pt.natoms + I) * np + q] = double2{dd * tx, dd * ty};
   }
 }
@@ -162,10 +163,11 @@ bool launch_unpack(const ks_system* s, int nb, const void* pk, bool pk_fp64, dou
 
 bool launch_proj_reduce(const ks_system* s, int nb, const void* partial, double2* DP, hipStream_t st) {
   if (s->natoms == 0 || nb == 0) return true;
+  const double scale = sqrt(s->omega) / (double)s->N;
   if (!mixed(s))
-    proj_reduce_kernel<double2><<<dim3(s->natoms, nb), 64, 0, st>>>((const double2*)partial, DP, proj_tab(s));
+    proj_reduce_kernel<double2><<<dim3(s->natoms, nb), 64, 0, st>>>((const double2*)partial, DP, proj_tab(s), scale);
   else
-    proj_reduce_kernel<float2><<<dim3(s->natoms, nb), 64, 0, st>>>((const float2*)partial, DP, proj_tab(s));
+    proj_reduce_kernel<float2><<<dim3(s->natoms, nb), 64, 0, st>>>((const float2*)partial, DP, proj_tab(s), scale);
   return true;
 }
 

@@ -57,44 +57,39 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
   if (ns == 0) return;  // no sphere point in this tile (uniform per block)
   for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
-  // Projections: items (segment, slot, projector); each sums beta * psi over
-  // its segment of the slot's points, then the segments of every (slot,
-  // projector) are added in order.  The partial sums are staged in X once all
-  // reads of psi are done.
+  // Projections: item i = pair*nseg + seg for the (slot, projector) pairs of
+  // the tile; each item sums beta * psi over its segment of the slot's points
+  // (in point order), and the nseg segments of a pair, adjacent lanes of one
+  // wave, are then added by a fixed butterfly over those lanes.
   const int np = pt.nproj;
-  const int pairs = ns * np;
-  int nseg = NT / pairs;
-  nseg = nseg < 1 ? 1 : (nseg > 16 ? 16 : nseg);
-  const int items = pairs * nseg;
-  // items <= max(NT, pairs) and pairs <= KB_TILE_DP, so PJ items per thread suffice
-  constexpr int PJ = ((NT > KB_TILE_DP ? NT : KB_TILE_DP) + NT - 1) / NT;
-  // The first KP points of every item (LDS position, beta) are the same for
+  const int pairs = ns * np;   // <= KB_TILE_DP <= NT
+  int lseg = 0;                // nseg = 2^lseg <= 16, nseg * pairs <= NT
+  while (lseg < 4 && (pairs << (lseg + 1)) <= NT) ++lseg;
+  const int nseg = 1 << lseg;
+  const int items = pairs << lseg;
+  const int pr = tid >> lseg, seg = tid & (nseg - 1);
+  // The first KP points of the item (LDS position, beta) are the same for
   // all orbitals of the block and stay in registers.
-  constexpr int KP = 8;
-  int ka[PJ], kb[PJ], kq[PJ];
-  int cpos[PJ][KP];
-  double cbeta[PJ][KP];
-#pragma unroll
-  for (int j = 0; j < PJ; ++j) {
-    const int i = tid + j * NT;
-    ka[j] = kb[j] = kq[j] = 0;
-    if (i < items) {
-      const int pr = i % pairs, seg = i / pairs;
-      const int sl = pr / np;
-      kq[j] = pr - sl * np;
-      const int k0 = pt.slot_pt[sA + sl], len = pt.slot_pt[sA + sl + 1] - k0;
-      ka[j] = k0 + (len * seg) / nseg;
-      kb[j] = k0 + (len * (seg + 1)) / nseg;
-    }
-#pragma unroll
-    for (int c = 0; c < KP; ++c) {
-      const int k = ka[j] + c;
-      const bool in = k < kb[j];
-      cpos[j][c] = in ? pt.pt_lds[k] : 0;
-      cbeta[j][c] = in ? pt.beta[(long long)k * np + kq[j]] : 0.0;
-    }
+  constexpr int KP = 16;
+  int ka = 0, kb = 0, kq = 0, sl = 0;
+  if (tid < items) {
+    sl = pr / np;
+    kq = pr - sl * np;
+    const int k0 = pt.slot_pt[sA + sl], len = pt.slot_pt[sA + sl + 1] - k0;
+    ka = k0 + (len * seg) / nseg;
+    kb = k0 + (len * (seg + 1)) / nseg;
   }
-  double2* red = reinterpret_cast<double2*>(X);   // holds >= 256 double2 for every supported N0, R
+  int cpos[KP];
+  double cbeta[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) {
+    const int k = ka + c;
+    const bool in = k < kb;
+    cpos[c] = in ? pt.pt_lds[k] : 0;
+    cbeta[c] = in ? pt.beta[(long long)k * np + kq] : 0.0;
+  }
+  C* pout = partial + (long long)(sA + sl) * np + kq;
+  const long long pstride = (long long)pt.nslots * np;
   FR pre;
   if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
@@ -103,43 +98,27 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
         fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     };
     fft_io<N0, +1, NB, NT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
-    double sx[PJ], sy[PJ];
+    double sx = 0.0, sy = 0.0;
 #pragma unroll
-    for (int j = 0; j < PJ; ++j) {
-      sx[j] = sy[j] = 0.0;
-#pragma unroll
-      for (int c = 0; c < KP; ++c) {
-        if (ka[j] + c < kb[j]) {
-          const C x = X[cpos[j][c]];
-          sx[j] += cbeta[j][c] * double(x.x);
-          sy[j] += cbeta[j][c] * double(x.y);
-        }
-      }
-      for (int k = ka[j] + KP; k < kb[j]; ++k) {
-        const double bv = pt.beta[(long long)k * np + kq[j]];
-        const C x = X[pt.pt_lds[k]];
-        sx[j] += bv * double(x.x);
-        sy[j] += bv * double(x.y);
+    for (int c = 0; c < KP; ++c) {
+      if (ka + c < kb) {
+        const C x = X[cpos[c]];
+        sx += cbeta[c] * double(x.x);
+        sy += cbeta[c] * double(x.y);
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PJ; ++j) {
-      const int i = tid + j * NT;
-      if (i < items) red[i] = double2{sx[j], sy[j]};
+    for (int k = ka + KP; k < kb; ++k) {
+      const double bv = pt.beta[(long long)k * np + kq];
+      const C x = X[pt.pt_lds[k]];
+      sx += bv * double(x.x);
+      sy += bv * double(x.y);
     }
-    __syncthreads();
-    for (int pr = tid; pr < pairs; pr += NT) {
-      double tx = 0.0, ty = 0.0;
-      for (int seg = 0; seg < nseg; ++seg) {
-        const double2 v = red[seg * pairs + pr];
-        tx += v.x;
-        ty += v.y;
-      }
-      const int sl = pr / np, q = pr - sl * np;
-      partial[((long long)o * pt.nslots + sA + sl) * np + q] = C{R(tx * scale), R(ty * scale)};
+    for (int m = 1; m < nseg; m <<= 1) {
+      sx += __shfl_xor(sx, m, 64);
+      sy += __shfl_xor(sy, m, 64);
     }
-    __syncthreads();   // red (= X) is rewritten by the next orbital's first stage
+    if (tid < items && seg == 0) pout[o * pstride] = C{R(sx * scale), R(sy * scale)};
+    __syncthreads();   // X is rewritten by the next orbital's first stage
   }
 }
 
@@ -226,7 +205,7 @@ template <int N0, typename R, bool HB>
 __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                     cplx<R>* __restrict__ Uout, const double* __restrict__ V,
                                                     const double2* __restrict__ DP, SphereTab tab, ProjTab pt,
-                                                    const cplx<R>* __restrict__ tw0, double sc_in, double sc_out) {
+                                                    const cplx<R>* __restrict__ tw0, double sc_v) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
   using LS = last_shape<N0, NB, NT>;
@@ -240,11 +219,12 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
-  // potential at the outputs of this thread's last synthesis stage (times Omega^-1/2)
+  // potential at the outputs of this thread's last synthesis stage, times the
+  // synthesis and analysis scales Omega^-1/2 Omega^1/2 / N = 1/N
   double vr[LS::items][LS::radix];
   const double* vbase = V + p0;
   last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
-    vr[it][q] = (p0 + t < npl) ? vbase[e * npl + t] * sc_in : 0.0;
+    vr[it][q] = (p0 + t < npl) ? vbase[e * npl + t] * sc_v : 0.0;
   });
   // KB coefficients d*P of this tile's slots: thread tid < ns*np stages one
   // (slot, projector) value per orbital.
@@ -286,7 +266,7 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     C* obase = Uout + (long long)o * nplanes * npl + p0;
     fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, [&](int t, int e, C v, int, int) {
       const int pi = fold(e, N0) - m0lo;
-      if (pi >= 0 && pi < nplanes && t < tvalid) obase[(unsigned)(pi * npl + t)] = C{R(double(v.x) * sc_out), R(double(v.y) * sc_out)};
+      if (pi >= 0 && pi < nplanes && t < tvalid) obase[(unsigned)(pi * npl + t)] = v;
     });
     __syncthreads();   // X and dps are rewritten for the next orbital
   }
@@ -384,17 +364,16 @@ bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipS
 
 template <int N0, bool HB>
 static void xapply_n(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
-  const double sc_in = 1.0 / sqrt(s->omega);
-  const double sc_out = sqrt(s->omega) / (double)s->N;
+  // synthesis scale Omega^-1/2 and analysis scale Omega^1/2/N folded into V
+  // (the KB coefficients carry the analysis scale from proj_reduce)
+  const double sc_v = 1.0 / (double)s->N;
   const int ng = x_groups(s, nb);
   if (!mixed(s))
     xapply_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, (double2*)U, s->d_v,
-                                                                   DP, sphere_tab(s), proj_tab(s), s->d_tw0, sc_in,
-                                                                   sc_out);
+                                                                   DP, sphere_tab(s), proj_tab(s), s->d_tw0, sc_v);
   else
     xapply_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, (float2*)U, s->d_v,
-                                                                  DP, sphere_tab(s), proj_tab(s), s->d_tw0f, sc_in,
-                                                                  sc_out);
+                                                                  DP, sphere_tab(s), proj_tab(s), s->d_tw0f, sc_v);
 }
 
 bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
