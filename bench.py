@@ -67,6 +67,34 @@ def alg_bytes(info, spec, kernel, S=16):
     return 0, 0
 
 
+def csrc_fingerprint():
+    """sha256 over the library's kernel and runtime sources (csrc/, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2106_03872_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, orbitals_per_pass):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by the copy-kernel
+    calibration), or None when the summary is missing or was taken on other
+    sources or another pass size."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_fp64.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("csrc_sha256") != csrc_fingerprint() or rec.get("orbitals_per_pass") != orbitals_per_pass:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
 def cpu_baseline(spec, sysm, norb_sample=128):
     """The FP64 oracle, unchanged, on a bounded sample of the workload:
     norb_sample orbitals through one Taylor-4 step and the density."""
@@ -209,9 +237,13 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dk = kernels[dom]
     po, pl = alg_bytes(info, spec, dom)
+    passes = -(-spec.norb // info["chunk"])
+    per_pass = -(-spec.norb // passes)          # orbitals per launch (balanced passes)
     roof = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dk["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_us": dk["avg_us"],
-            "alg_bytes_per_orbital": po, "alg_bytes_per_launch_shared": pl}
+            "frac": round(dk["alg_GBs"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, spec.name, per_pass), "avg_launch_us": dk["avg_us"],
+            "alg_bytes_per_orbital": po, "alg_bytes_per_launch_shared": pl,
+            "alg_bytes_per_launch": po * per_pass + pl, "orbitals_per_launch": per_pass}
     psi64 = state.download()
     state.close()
     gs.close()
@@ -273,7 +305,8 @@ def main():
                                f"projectors, E_cut={spec.ecut} Ha; step = Taylor-4 (dt={spec.dt}) + density + norms "
                                f"on HBM-resident orbitals",
                    "global_batch": spec.norb, "grid": list(spec.n), "npw": info["npw"],
-                   "chunk": info["chunk"], "hpsi_per_step": hpsi_per_step, "parallelism": "single GPU"},
+                   "chunk": info["chunk"], "orbitals_per_pass": per_pass, "hpsi_per_step": hpsi_per_step,
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": kernels,
         "physics": phys,

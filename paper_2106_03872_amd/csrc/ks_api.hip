@@ -357,6 +357,14 @@ int default_chunk(const ks_system* s) {
   return std::max(1, std::min(cb, s->max_norb));
 }
 
+// Orbitals per pass for a call over norb orbitals: the passes are balanced
+// (ceil(norb / cb) passes of equal size up to one), so no pass is a small
+// remainder that leaves most of the chip idle.
+int chunk_len(const ks_system* s, int norb) {
+  const int passes = (norb + s->cb - 1) / s->cb;
+  return passes > 0 ? (norb + passes - 1) / passes : s->cb;
+}
+
 ks_status check_common(ks_system* s, int norb) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (norb < 0 || norb > s->max_norb)
@@ -619,8 +627,9 @@ ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void
   if (a < b + bytes && b < a + bytes) return fail(s, KS_EINVAL, "psi and hpsi overlap");
   hipStream_t st = (hipStream_t)stream;
   Taylor none{{0.0, 0.0}, 0};
-  for (int o0 = 0; o0 < norb; o0 += s->cb) {
-    const int nb = std::min(s->cb, norb - o0);
+  const int cl = chunk_len(s, norb);
+  for (int o0 = 0; o0 < norb; o0 += cl) {
+    const int nb = std::min(cl, norb - o0);
     const double2* in = (const double2*)psi + (size_t)o0 * s->N;
     double2* out = (double2*)hpsi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, in, s->N, s->pk[0], st); })) != KS_OK) return r;
@@ -641,8 +650,9 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
   hipStream_t st = (hipStream_t)stream;
-  for (int o0 = 0; o0 < norb; o0 += s->cb) {
-    const int nb = std::min(s->cb, norb - o0);
+  const int cl = chunk_len(s, norb);
+  for (int o0 = 0; o0 < norb; o0 += cl) {
+    const int nb = std::min(cl, norb - o0);
     double2* box = (double2*)psi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
     if ((r = taylor_packed(s, nb, (double2*)s->pk[0], dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, st)) != KS_OK)
@@ -662,8 +672,9 @@ ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ,
     return KS_OK;
   }
   if (!psi || !occ) return fail(s, KS_EINVAL, "psi or occ is null");
-  for (int o0 = 0; o0 < norb; o0 += s->cb) {
-    const int nb = std::min(s->cb, norb - o0);
+  const int cl = chunk_len(s, norb);
+  for (int o0 = 0; o0 < norb; o0 += cl) {
+    const int nb = std::min(cl, norb - o0);
     const double2* box = (const double2*)psi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
     if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho, o0 > 0, st)) != KS_OK) return r;
@@ -683,8 +694,9 @@ ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, 
   }
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   Taylor none{{0.0, 0.0}, 0};
-  for (int o0 = 0; o0 < norb; o0 += s->cb) {
-    const int nb = std::min(s->cb, norb - o0);
+  const int cl = chunk_len(s, norb);
+  for (int o0 = 0; o0 < norb; o0 += cl) {
+    const int nb = std::min(cl, norb - o0);
     const double2* box = (const double2*)psi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
     if (energy && (r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return r;
@@ -856,8 +868,9 @@ ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* o
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
   hipStream_t st = (hipStream_t)stream;
   ks_status r;
-  for (int o0 = 0; o0 < t->norb; o0 += s->cb) {
-    const int nb = std::min(s->cb, t->norb - o0);
+  const int cl = chunk_len(s, t->norb);
+  for (int o0 = 0; o0 < t->norb; o0 += cl) {
+    const int nb = std::min(cl, t->norb - o0);
     double2* slice = t->data + (size_t)o0 * s->npw_stride;
     if ((r = taylor_packed(s, nb, slice, dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, st)) != KS_OK) return r;
   }
@@ -872,7 +885,7 @@ ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double*
   Taylor none{{0.0, 0.0}, 0};
   ks_status r;
   // norms only: one launch over every resident orbital
-  const int step = energy ? s->cb : t->norb;
+  const int step = energy ? chunk_len(s, t->norb) : t->norb;
   for (int o0 = 0; o0 < t->norb; o0 += step) {
     const int nb = std::min(step, t->norb - o0);
     const double2* slice = t->data + (size_t)o0 * s->npw_stride;
