@@ -191,7 +191,10 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
 /* Number of plane waves in the sphere (packed coefficients per orbital). */
 int ks_system_npw(const ks_system* sys);
 
-/* Orbitals processed per pass (chunk size of the internal pipeline). */
+/* Largest number of orbitals processed per pass (chunk size of the internal
+ * pipeline).  The default is min(max_norb, the count whose plane intermediate
+ * takes 4 GiB).  A call over norb orbitals runs ceil(norb / chunk) passes of
+ * equal size (up to one orbital). */
 int ks_system_chunk(const ks_system* sys);
 
 /* Set the chunk size (1 <= chunk <= max_norb); reallocates the workspace, so

@@ -55,12 +55,20 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
 }
 
 // ------------------------------------------------------------ plane analysis
-// Block (plane pi, orbital o): y-analysis of YB r2-columns of U at a time,
-// keeping the disk columns in Z; z-analysis of each column with the kinetic
-// term and the output mode applied to the outputs inside the sphere.
+// Block (plane pi, orbital group).  For each orbital of the group in order:
+// y-analysis of YB r2-columns of U at a time into the disk columns Z; the
+// z-analysis of every column in place; then the epilogue over the plane's
+// packed coefficients, which are contiguous, so its loads and stores
+// coalesce: + 1/2|G|^2 c and the output mode.  The next U chunk (also across
+// orbitals) is loaded while the current one is transformed, and an orbital's
+// epilogue operands are loaded before its transforms.
+// LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1] | column of each packed
+// coefficient of the plane [npp_max] (bytes).
+
+constexpr int EP_PRE = 4;   // epilogue coefficients per thread whose operands are prefetched
 
 template <int N, typename R, typename TW>
-__global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, const TW* win,
+__global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, int nb, const TW* win,
                                                         cplx<R>* __restrict__ wout, double2* acc, int pk_stride,
                                                         int acc_stride, SphereTab tab,
                                                         const cplx<R>* __restrict__ twN, int ncol_max, int mode,
@@ -71,56 +79,88 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
   C* tw = reinterpret_cast<C*>(smem_raw);
   C* Z = tw + N;
   C* Y = Z + ncol_max * (N + 1);
+  unsigned char* s_col = reinterpret_cast<unsigned char*>(Y + YB * (N + 1));
   __shared__ int s_off[130];
   __shared__ int s_m2lo[129];
-  const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int pi = blockIdx.x, tid = threadIdx.x;
+  int oa, ob;
+  orbital_range(nb, oa, ob);
   const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
   const int m1lo = tab.plane_m1lo[pi];
   for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
   for (int i = tid; i <= nc; i += NTP) s_off[i] = tab.col_off[c0 + i];
   for (int i = tid; i < nc; i += NTP) s_m2lo[i] = tab.col_m2lo[c0 + i];
   __syncthreads();
-  const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
-  // the U columns of the next chunk are loaded while the current one is transformed
+  const int e0 = s_off[0], npp = s_off[nc] - e0;
+  for (int c = tid; c < nc; c += NTP)
+    for (int k = s_off[c]; k < s_off[c + 1]; ++k) s_col[k - e0] = (unsigned char)c;
+  const double k0 = g0 * (tab.m0lo + pi);
+  const long long uplane = (long long)tab.nplanes * N * N;
   using FR = fft_regs<N, YB, NTP, C>;
   FR pre;
-  fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return u[e * N + t]; });
-  for (int w0 = 0; w0 < N; w0 += YB) {
-    const int w1 = w0 + YB;
-    auto next = [&] {
-      if (w1 < N) fft_preload<N, YB, NTP, C>(pre, N - w1, [&](int t, int e) -> C { return u[e * N + w1 + t]; });
-    };
-    fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, preloaded(pre, next), [&](int t, int e, C v, int, int) {
-      const int c = fold(e, N) - m1lo;
-      if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
-    });
-    __syncthreads();
+  if (oa < ob) {
+    const C* u = Uin + ((long long)oa * tab.nplanes + pi) * N * N;
+    fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return u[e * N + t]; });
   }
-  const double k0 = g0 * (tab.m0lo + pi);
-  const long long ob = (long long)o * pk_stride;
-  double2* accp = acc ? acc + (long long)o * acc_stride : nullptr;
-  for (int cb = 0; cb < nc; cb += YB) {
-    fft_io<N, -1, YB, NTP, SRC_LDS, DST_FN, C>(
-        Z + cb * (N + 1), N + 1, nc - cb, tw, no_load{}, [&](int t, int e, C ph, int, int) {
-          const int c = cb + t;
-          const int m2 = fold(e, N);
-          const int idx = m2 - s_m2lo[c];
-          if (idx < 0 || idx >= s_off[c + 1] - s_off[c]) return;
-          const int ep = s_off[c] + idx;
-          const double k1 = g1 * (m1lo + c), k2 = g2 * m2;
-          const double K = 0.5 * (k0 * k0 + k1 * k1 + k2 * k2);
-          const TW w = win[ob + ep];
-          const double2 hw{K * double(w.x) + double(ph.x), K * double(w.y) + double(ph.y)};
-          if (mode == H_OUT) {
-            wout[ob + ep] = to_c<C>(hw);
-          } else {
-            if (tay.write_w) wout[ob + ep] = to_c<C>(hw);
-            double2 av = accp[ep];
-            av.x += tay.coef.x * hw.x - tay.coef.y * hw.y;
-            av.y += tay.coef.x * hw.y + tay.coef.y * hw.x;
-            accp[ep] = av;
-          }
-        });
+  __syncthreads();
+  for (int o = oa; o < ob; ++o) {
+    const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
+    const long long obase = (long long)o * pk_stride + e0;
+    double2* accp = acc ? acc + (long long)o * acc_stride + e0 : nullptr;
+    // epilogue operands of this orbital
+    TW wv[EP_PRE];
+    double2 av[EP_PRE];
+#pragma unroll
+    for (int j = 0; j < EP_PRE; ++j) {
+      const int k = tid + j * NTP;
+      if (k < npp) {
+        wv[j] = win[obase + k];
+        if (mode != H_OUT) av[j] = accp[k];
+      }
+    }
+    for (int w0 = 0; w0 < N; w0 += YB) {
+      const int w1 = w0 + YB;
+      auto next = [&] {
+        if (w1 < N) {
+          fft_preload<N, YB, NTP, C>(pre, N - w1, [&](int t, int e) -> C { return u[e * N + w1 + t]; });
+        } else if (o + 1 < ob) {
+          const C* un = u + uplane;
+          fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return un[e * N + t]; });
+        }
+      };
+      fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, preloaded(pre, next),
+                                                 [&](int t, int e, C v, int, int) {
+                                                   const int c = fold(e, N) - m1lo;
+                                                   if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
+                                                 });
+      __syncthreads();
+    }
+    for (int cb = 0; cb < nc; cb += YB) fft_batch<N, -1, YB, NTP, C>(Z + cb * (N + 1), N + 1, nc - cb, tw);
+    auto epilogue = [&](int k, TW w, double2 av_in) {
+      const int c = s_col[k];
+      const int m2 = s_m2lo[c] + (k + e0 - s_off[c]);
+      const C ph = Z[c * (N + 1) + wrap(m2, N)];
+      const double k1 = g1 * (m1lo + c), k2 = g2 * m2;
+      const double K = 0.5 * (k0 * k0 + k1 * k1 + k2 * k2);
+      const double2 hw{K * double(w.x) + double(ph.x), K * double(w.y) + double(ph.y)};
+      if (mode == H_OUT) {
+        wout[obase + k] = to_c<C>(hw);
+      } else {
+        if (tay.write_w) wout[obase + k] = to_c<C>(hw);
+        double2 a = av_in;
+        a.x += tay.coef.x * hw.x - tay.coef.y * hw.y;
+        a.y += tay.coef.x * hw.y + tay.coef.y * hw.x;
+        accp[k] = a;
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < EP_PRE; ++j) {
+      const int k = tid + j * NTP;
+      if (k < npp) epilogue(k, wv[j], mode != H_OUT ? av[j] : double2{0.0, 0.0});
+    }
+    for (int k = tid + EP_PRE * NTP; k < npp; k += NTP)
+      epilogue(k, win[obase + k], mode != H_OUT ? accp[k] : double2{0.0, 0.0});
+    __syncthreads();   // Z is rewritten by the next orbital
   }
 }
 
@@ -130,7 +170,15 @@ size_t plane_lds_bytes(const ks_system* s) {
   const int N = s->n[1];
   const int yb = N <= 64 ? 64 : (N <= 96 ? 48 : (N <= 120 ? 24 : 16));   // pnb<N>
   const size_t es = s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2);
-  return es * ((size_t)N + (size_t)s->ncol_max * (N + 1) + (size_t)yb * (N + 1));
+  return es * ((size_t)N + (size_t)s->ncol_max * (N + 1) + (size_t)yb * (N + 1)) + ((size_t)s->npp_max + 15) / 16 * 16;
+}
+
+// Orbital groups per plane-pass launch: up to P_GROUP orbitals per block,
+// fewer when the launch would have fewer than about 4 blocks per CU.
+static int plane_groups(const ks_system* s, int nb) {
+  long long g = (long long)s->nplanes * nb / (256 * 4);
+  g = g < 1 ? 1 : (g > P_GROUP ? P_GROUP : g);
+  return (int)((nb + g - 1) / g);
 }
 
 template <int N, typename R, typename TIN>
@@ -160,8 +208,8 @@ template <int N, typename R, typename TW>
 static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, HMode mode,
                         Taylor tay, const void* tw, hipStream_t st) {
   const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
-  plane_fwd_kernel<N, R, TW><<<dim3(s->nplanes, nb), NTP, plane_lds_bytes(s), st>>>(
-      (const cplx<R>*)U, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
+  plane_fwd_kernel<N, R, TW><<<dim3(s->nplanes, plane_groups(s, nb)), NTP, plane_lds_bytes(s), st>>>(
+      (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
       sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
 }
 

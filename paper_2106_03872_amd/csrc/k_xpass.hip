@@ -35,11 +35,6 @@ __device__ __forceinline__ T wave_sum(T x) {
 // registers while the current one is transformed, and the per-tile data
 // (twiddles, potential, KB tables) is fetched once per block.
 
-__device__ __forceinline__ void orbital_range(int nb, int& oa, int& ob) {
-  oa = (int)((long long)blockIdx.y * nb / gridDim.y);
-  ob = (int)((long long)(blockIdx.y + 1) * nb / gridDim.y);
-}
-
 template <int N0, typename R, bool HB>
 __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    cplx<R>* __restrict__ partial, SphereTab tab, ProjTab pt,

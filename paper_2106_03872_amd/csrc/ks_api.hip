@@ -351,9 +351,13 @@ ks_status alloc_workspace(ks_system* s) {
   return alloc_proj_workspace(s);
 }
 
+// Default orbitals per pass: as many as give KS_CHUNK_BYTES of plane
+// intermediate T (larger passes mean fewer, fuller launches).
+constexpr double KS_CHUNK_BYTES = 4.0 * 1024 * 1024 * 1024;
+
 int default_chunk(const ks_system* s) {
   const double per = (double)s->nplanes * s->npl * (s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2));
-  int cb = (int)std::max(1.0, std::floor(1024.0 * 1024 * 1024 / per));
+  int cb = (int)std::max(1.0, std::floor(KS_CHUNK_BYTES / per));
   return std::max(1, std::min(cb, s->max_norb));
 }
 
@@ -479,6 +483,8 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   const int npw = sh.npw;
   s->m0lo = sh.m0lo;
   s->ncol_max = sh.ncol_max;
+  for (size_t pi = 0; pi + 1 < sh.plane_col0.size(); ++pi)
+    s->npp_max = std::max(s->npp_max, sh.col_off[sh.plane_col0[pi + 1]] - sh.col_off[sh.plane_col0[pi]]);
   s->nplanes = (int)plane_m1lo.size();
   s->ncols = (int)col_m2lo.size();
   s->npw = npw;
@@ -949,7 +955,7 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
   const double nplanes = (double)h.plane_m1lo.size();
   const double stride = (double)((h.npw + 63) / 64 * 64);
   int cb = chunk;
-  if (cb <= 0) cb = std::max(1, std::min(norb, (int)std::floor(1024.0 * 1024 * 1024 / (nplanes * npl * es))));
+  if (cb <= 0) cb = std::max(1, std::min(norb, (int)std::floor(KS_CHUNK_BYTES / (nplanes * npl * es))));
   const double np = std::max(1, nproj);
   double b = 0.0;
   b += (double)cb * stride * (16.0 + 2.0 * es);         // packed chunk buffers

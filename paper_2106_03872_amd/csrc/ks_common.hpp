@@ -8,6 +8,7 @@ namespace ks {
 constexpr int NT = 256;   // threads per x-pencil block
 constexpr int DENS_GROUP = 8;   // orbitals per density block
 constexpr int X_GROUP = 8;      // orbitals per x-pass block (upper bound)
+constexpr int P_GROUP = 8;      // orbitals per plane-pass block (upper bound)
 
 #define KS_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128)
 
@@ -78,5 +79,12 @@ inline ProjTab proj_tab(const ks_system* s) {
 
 
 inline bool mixed(const ks_system* s) { return s->prec == KS_MIXED; }
+
+// Orbital group of a block: the orbitals [y*nb/ng, (y+1)*nb/ng) with
+// y = blockIdx.y and ng = gridDim.y (group sizes differ by at most one).
+__device__ __forceinline__ void orbital_range(int nb, int& oa, int& ob) {
+  oa = (int)((long long)blockIdx.y * nb / gridDim.y);
+  ob = (int)((long long)(blockIdx.y + 1) * nb / gridDim.y);
+}
 
 }  // namespace ks

@@ -76,6 +76,7 @@ struct ks_system {
 
   // sphere
   int nplanes = 0, m0lo = 0, ncols = 0, npw = 0, npw_stride = 0, ncol_max = 0;
+  int npp_max = 0;   // largest number of packed coefficients in one m0 plane
   int* d_plane_col0 = nullptr;
   int* d_plane_m1lo = nullptr;
   int* d_col_off = nullptr;
