@@ -6,51 +6,97 @@
 
 namespace ks {
 
+constexpr int EP_PRE = 4;   // packed coefficients per thread whose loads are issued ahead
+
 // ----------------------------------------------------------- plane synthesis
-// Block (plane pi, orbital o).  LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1].
-// z-synthesis of each disk column straight from the packed coefficients into
-// Z; y-synthesis of YB r2-columns at a time straight from Z into T.
+// Block (plane pi, orbital group).  For each orbital of the group in order:
+// its packed coefficients of the plane (contiguous, so the loads coalesce;
+// fetched into registers one orbital ahead) are staged in LDS; z-synthesis of
+// each disk column from the staging area into Z; y-synthesis of YB
+// r2-columns at a time from Z straight into T.
+// LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1] (the staging area of the
+// packed coefficients, consumed before the y-synthesis, shares Y) | [npp_max]
+// bytes (unused here).  `stage` = 0 when a plane's coefficients do not fit in
+// Y: the z-synthesis then reads them from HBM directly.
 
 template <int N, typename R, typename TIN>
-__global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ pk, int pk_stride,
+__global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ pk, int nb, int pk_stride,
                                                         cplx<R>* __restrict__ Tout, SphereTab tab,
-                                                        const cplx<R>* __restrict__ twN, int ncol_max) {
+                                                        const cplx<R>* __restrict__ twN, int ncol_max, int stage) {
   using C = cplx<R>;
   constexpr int YB = pnb<N>::value;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* tw = reinterpret_cast<C*>(smem_raw);
   C* Z = tw + N;
   C* Y = Z + ncol_max * (N + 1);
+  C* S = Y;
   __shared__ int s_off[130];
   __shared__ int s_m2lo[129];
-  const int pi = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
+  const int pi = blockIdx.x, tid = threadIdx.x;
+  int oa, ob;
+  orbital_range(nb, oa, ob);
   const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
   const int m1lo = tab.plane_m1lo[pi];
   for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
   for (int i = tid; i <= nc; i += NTP) s_off[i] = tab.col_off[c0 + i];
   for (int i = tid; i < nc; i += NTP) s_m2lo[i] = tab.col_m2lo[c0 + i];
+  const int e0 = tab.col_off[c0], npp = tab.col_off[c0 + nc] - e0;
+  // this thread's first EP_PRE coefficients of the next orbital
+  TIN cin[EP_PRE];
+  auto fetch = [&](int o) {
+    const TIN* in = pk + (long long)o * pk_stride + e0;
+#pragma unroll
+    for (int j = 0; j < EP_PRE; ++j) {
+      const int k = tid + j * NTP;
+      if (k < npp) cin[j] = in[k];
+    }
+  };
+  if (stage && oa < ob) fetch(oa);
   __syncthreads();
-  const TIN* in = pk + (long long)o * pk_stride;
-  for (int cb = 0; cb < nc; cb += YB) {
-    fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
-        Z + cb * (N + 1), N + 1, nc - cb, tw,
-        [&](int t, int e) -> C {
-          const int c = cb + t;
-          const int idx = fold(e, N) - s_m2lo[c];
-          return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? cvt<C>(in[s_off[c] + idx]) : czero<C>();
-        },
-        no_store{});
-  }
-  C* out = Tout + ((long long)o * tab.nplanes + pi) * N * N;
-  for (int w0 = 0; w0 < N; w0 += YB) {
-    fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(
-        Y, N + 1, N - w0, tw,
-        [&](int t, int e) -> C {
-          const int c = fold(e, N) - m1lo;
-          return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
-        },
-        [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; });
-    __syncthreads();
+  for (int o = oa; o < ob; ++o) {
+    const TIN* in = pk + (long long)o * pk_stride;
+    if (stage) {
+#pragma unroll
+      for (int j = 0; j < EP_PRE; ++j) {
+        const int k = tid + j * NTP;
+        if (k < npp) S[k] = cvt<C>(cin[j]);
+      }
+      for (int k = tid + EP_PRE * NTP; k < npp; k += NTP) S[k] = cvt<C>(in[e0 + k]);
+      if (o + 1 < ob) fetch(o + 1);
+      __syncthreads();
+      for (int cb = 0; cb < nc; cb += YB) {
+        fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
+            Z + cb * (N + 1), N + 1, nc - cb, tw,
+            [&](int t, int e) -> C {
+              const int c = cb + t;
+              const int idx = fold(e, N) - s_m2lo[c];
+              return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? S[s_off[c] - e0 + idx] : czero<C>();
+            },
+            no_store{});
+      }
+    } else {
+      for (int cb = 0; cb < nc; cb += YB) {
+        fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
+            Z + cb * (N + 1), N + 1, nc - cb, tw,
+            [&](int t, int e) -> C {
+              const int c = cb + t;
+              const int idx = fold(e, N) - s_m2lo[c];
+              return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? cvt<C>(in[s_off[c] + idx]) : czero<C>();
+            },
+            no_store{});
+      }
+    }
+    C* out = Tout + ((long long)o * tab.nplanes + pi) * N * N;
+    for (int w0 = 0; w0 < N; w0 += YB) {
+      fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(
+          Y, N + 1, N - w0, tw,
+          [&](int t, int e) -> C {
+            const int c = fold(e, N) - m1lo;
+            return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
+          },
+          [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; });
+      __syncthreads();
+    }
   }
 }
 
@@ -64,8 +110,6 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
 // epilogue operands are loaded before its transforms.
 // LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1] | column of each packed
 // coefficient of the plane [npp_max] (bytes).
-
-constexpr int EP_PRE = 4;   // epilogue coefficients per thread whose operands are prefetched
 
 template <int N, typename R, typename TW>
 __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, int nb, const TW* win,
@@ -183,8 +227,10 @@ static int plane_groups(const ks_system* s, int nb) {
 
 template <int N, typename R, typename TIN>
 static void plane_inv_t(const ks_system* s, int nb, const void* pk, void* T, const void* tw, hipStream_t st) {
-  plane_inv_kernel<N, R, TIN><<<dim3(s->nplanes, nb), NTP, plane_lds_bytes(s), st>>>(
-      (const TIN*)pk, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max);
+  constexpr int YB = pnb<N>::value;
+  const int stage = s->npp_max <= YB * (N + 1) ? 1 : 0;
+  plane_inv_kernel<N, R, TIN><<<dim3(s->nplanes, plane_groups(s, nb)), NTP, plane_lds_bytes(s), st>>>(
+      (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage);
 }
 
 template <int N>
