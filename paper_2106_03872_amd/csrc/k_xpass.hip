@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   }
 }
 
-// density: block (tile, group of DENS_GROUP orbitals); |psi|^2 is accumulated
+// density: block (tile, orbital group); |psi|^2 is accumulated
 // straight from the last synthesis stage over the group's orbitals in order
 // and written to the group's partial density; dens_sum adds the groups in
 // order.
@@ -290,7 +290,8 @@ __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ T
   for (int it = 0; it < LS::items; ++it)
 #pragma unroll
     for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
-  const int oa = g * DENS_GROUP, ob = min(nb, oa + DENS_GROUP);
+  int oa, ob;
+  orbital_range(nb, oa, ob);
   // the next orbital's T is loaded once the first stage has consumed the current one
   using FR = fft_regs<N0, NB, NT, C, HB>;
   FR pre;
@@ -382,9 +383,18 @@ bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP,
   }
 }
 
+// Orbital groups of the density pass: each group writes one partial density
+// that dens_sum adds in order, so the groups are as large as keeps about 12
+// blocks per CU busy, and hold at least DENS_GROUP orbitals.
+static int dens_groups(const ks_system* s, int nb) {
+  const int by_size = (nb + DENS_GROUP - 1) / DENS_GROUP;
+  const int by_fill = (256 * 12 + s->ntiles - 1) / s->ntiles;
+  return std::max(1, std::min(by_size, by_fill));
+}
+
 template <int N0, bool HB>
 static void xdens_n(const ks_system* s, int nb, const void* T, const double* occ, double* part, hipStream_t st) {
-  const int ng = (nb + DENS_GROUP - 1) / DENS_GROUP;
+  const int ng = dens_groups(s, nb);
   if (!mixed(s))
     xdens_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, occ, part, sphere_tab(s),
                                                                   s->d_tw0, 1.0 / s->omega);
@@ -403,7 +413,7 @@ bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, 
     default:
       return false;
   }
-  const int ng = (nb + DENS_GROUP - 1) / DENS_GROUP;
+  const int ng = dens_groups(s, nb);
   dens_sum_kernel<<<(unsigned)((s->N + NT - 1) / NT), NT, 0, st>>>(s->dens_part, ng, s->N, rho, accumulate);
   return true;
 }

@@ -6,7 +6,7 @@
 namespace ks {
 
 constexpr int NT = 256;   // threads per x-pencil block
-constexpr int DENS_GROUP = 8;   // orbitals per density block
+constexpr int DENS_GROUP = 8;   // smallest orbital group of a density block
 constexpr int X_GROUP = 8;      // orbitals per x-pass block (upper bound)
 constexpr int P_GROUP = 8;      // orbitals per plane-pass block (upper bound)
 
