@@ -132,6 +132,7 @@ def setup_workload(spec, precision, chunk=0):
     state = ks.State(gs, spec.norb)
     state.upload(c)
     del c
+    gs.tuning = gs.autotune(spec.norb)   # launch schedule (orbital-group caps), timed on the device
     torch.cuda.synchronize()
     return sysm, gs, state
 
@@ -228,7 +229,7 @@ def main():
     log(f"[bench] workload {spec.name}: n={spec.n} L={spec.L} norb={spec.norb} natoms={spec.natoms}")
     sysm, gs, state = setup_workload(spec, ks.KS_FP64, args.chunk)
     info = gs.info()
-    log(f"[bench] FP64 set-up done, chunk {info['chunk']}, npw {info['npw']}")
+    log(f"[bench] FP64 set-up done, chunk {info['chunk']}, npw {info['npw']}, tuning {gs.tuning}")
     ms_step, ktimes, phys, rho64 = run_steps(spec, gs, state, args.steps, args.warmup)
     hpsi_per_step = 4 * spec.norb
     value = hpsi_per_step / (ms_step * 1e-3)
@@ -305,7 +306,9 @@ def main():
                                f"projectors, E_cut={spec.ecut} Ha; step = Taylor-4 (dt={spec.dt}) + density + norms "
                                f"on HBM-resident orbitals",
                    "global_batch": spec.norb, "grid": list(spec.n), "npw": info["npw"],
-                   "chunk": info["chunk"], "orbitals_per_pass": per_pass, "hpsi_per_step": hpsi_per_step,
+                   "chunk": info["chunk"], "orbitals_per_pass": per_pass,
+                   "tuning": {"x_group": gs.tuning["x_group"], "plane_group": gs.tuning["plane_group"]},
+                   "hpsi_per_step": hpsi_per_step,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernels": kernels,

@@ -247,10 +247,41 @@ typedef struct {
   int precision;    /* ks_precision */
   int x_half;       /* 1 if every sphere plane has |m0| < n0/4: the x-synthesis loads and
                        transforms only the nonzero half of its first-stage inputs */
+  int x_group;      /* largest orbital group of an x-pencil block (tuning) */
+  int plane_group;  /* largest orbital group of a plane block (tuning) */
 } ks_info;
 
 /* Fill *info for sys.  KS_EINVAL on null arguments. */
 ks_status ks_system_info(const ks_system* sys, ks_info* info);
+
+/* ------------------------------------------------------------------------
+ * Launch-schedule autotuning (set-up time; not on the hot path).
+ *
+ * Each plane and x-pencil block loops over a group of orbitals; the group
+ * caps trade the per-block set-up (twiddles, potential, KB tables, column
+ * tables, loaded once per block) against the number of blocks that fill the
+ * chip.  The results of H psi do not depend on them (every orbital is
+ * transformed by the same arithmetic in the same order).
+ */
+typedef struct {
+  int x_group;       /* cap on orbitals per x-pencil block, 1..64 */
+  int plane_group;   /* cap on orbitals per plane block, 1..64 */
+  double ms;         /* measured time of one H psi pass over the tuned orbital count (0 if not measured) */
+  int from_cache;    /* 1 if the result came from the process-wide cache */
+} ks_tuning;
+
+/* Time one H psi pass over min(norb, chunk) orbitals (zero coefficients; the
+ * kernels' timing does not depend on the values) for each candidate pair of
+ * group caps on `stream`, keep the fastest, and return it in *out (nullable).
+ * Results are cached per process by (grid, precision, number of sphere
+ * planes, orbitals per pass rounded up to a power of two): a later system of
+ * the same shape takes the cached caps without timing.  Synchronises `stream`; overwrites the
+ * system's internal workspace.  KS_EINVAL for norb outside [1, max_norb]. */
+ks_status ks_autotune(ks_system* sys, int norb, void* stream, ks_tuning* out);
+
+/* Set the group caps (x_group, plane_group in [1, 64]; ms and from_cache are
+ * ignored).  KS_EINVAL otherwise. */
+ks_status ks_system_set_tuning(ks_system* sys, const ks_tuning* t);
 
 /* Kernel classes reported by ks_kernel_time. */
 typedef enum {

@@ -217,11 +217,11 @@ size_t plane_lds_bytes(const ks_system* s) {
   return es * ((size_t)N + (size_t)s->ncol_max * (N + 1) + (size_t)yb * (N + 1)) + ((size_t)s->npp_max + 15) / 16 * 16;
 }
 
-// Orbital groups per plane-pass launch: up to P_GROUP orbitals per block,
+// Orbital groups per plane-pass launch: up to pg_max orbitals per block,
 // fewer when the launch would have fewer than about 4 blocks per CU.
 static int plane_groups(const ks_system* s, int nb) {
   long long g = (long long)s->nplanes * nb / (256 * 4);
-  g = g < 1 ? 1 : (g > P_GROUP ? P_GROUP : g);
+  g = g < 1 ? 1 : (g > s->pg_max ? s->pg_max : g);
   return (int)((nb + g - 1) / g);
 }
 

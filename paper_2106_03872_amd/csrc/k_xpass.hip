@@ -325,13 +325,13 @@ __global__ __launch_bounds__(NT) void dens_sum_kernel(const double* __restrict__
 
 // ------------------------------------------------------------------ launchers
 
-// Orbital groups per x-pass launch: groups of at most X_GROUP orbitals (sizes
+// Orbital groups per x-pass launch: groups of at most xg_max orbitals (sizes
 // differing by at most one), fewer orbitals per group when the launch would
 // otherwise have too few blocks to fill the chip (about 12 per CU).
 static int x_groups(const ks_system* s, int nb) {
   const long long blocks = (long long)s->ntiles * nb;
   long long g = blocks / (256 * 12);
-  g = g < 1 ? 1 : (g > X_GROUP ? X_GROUP : g);
+  g = g < 1 ? 1 : (g > s->xg_max ? s->xg_max : g);
   return (int)((nb + g - 1) / g);
 }
 

@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ks_internal.h"
@@ -433,6 +436,13 @@ ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nst
   }
   return KS_OK;
 }
+
+// process-wide autotuning results: (grid, precision, sphere planes, orbitals
+// per pass rounded up to a power of two) -> (x-pass group cap, plane-pass
+// group cap)
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
 }  // namespace
 
@@ -983,7 +993,87 @@ ks_status ks_system_info(const ks_system* s, ks_info* info) {
   info->x_tile = s->xnb;
   info->precision = s->prec;
   info->x_half = s->x_half ? 1 : 0;
+  info->x_group = s->xg_max;
+  info->plane_group = s->pg_max;
   return KS_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+ks_status ks_system_set_tuning(ks_system* s, const ks_tuning* t) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (!t || t->x_group < 1 || t->x_group > 64 || t->plane_group < 1 || t->plane_group > 64)
+    return fail(s, KS_EINVAL, "group caps must lie in [1, 64]");
+  s->xg_max = t->x_group;
+  s->pg_max = t->plane_group;
+  return KS_OK;
+}
+
+ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
+  ks_status r = check_common(s, norb);
+  if (r != KS_OK) return r;
+  if (norb < 1) return fail(s, KS_EINVAL, "norb must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = chunk_len(s, norb);
+  int nb2 = 1;
+  while (nb2 < nb) nb2 *= 2;
+  const TuneKey key{s->n[0], s->n[1], s->n[2], s->prec, s->nplanes, nb2};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      s->xg_max = it->second.first;
+      s->pg_max = it->second.second;
+      if (out) *out = ks_tuning{s->xg_max, s->pg_max, 0.0, 1};
+      return KS_OK;
+    }
+  }
+  const bool timing = s->timing;
+  s->timing = false;   // keep the search out of the kernel-time counters
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto done = [&](ks_status v) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    s->timing = timing;
+    return v;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return done(fail(s, KS_EDEVICE, "hipEventCreate failed"));
+  if (hipMemsetAsync(s->pk[0], 0, (size_t)nb * s->npw_stride * sizeof(double2), st) != hipSuccess)
+    return done(fail(s, KS_EDEVICE, "hipMemsetAsync failed"));
+  Taylor none{{0.0, 0.0}, 0};
+  const int xgs[] = {2, 4, 8, 16};
+  const int pgs[] = {1, 2, 4, 8};
+  int best_x = s->xg_max, best_p = s->pg_max;
+  float best = -1.0f;
+  for (int xg : xgs) {
+    for (int pg : pgs) {
+      s->xg_max = xg;
+      s->pg_max = pg;
+      if ((r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return done(r);
+      if (hipEventRecord(e0, st) != hipSuccess) return done(fail(s, KS_EDEVICE, "hipEventRecord failed"));
+      for (int rep = 0; rep < 2; ++rep)
+        if ((r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return done(r);
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+        return done(fail(s, KS_EDEVICE, "event timing failed"));
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return done(fail(s, KS_EDEVICE, "hipEventElapsedTime failed"));
+      ms *= 0.5f;
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        best_x = xg;
+        best_p = pg;
+      }
+    }
+  }
+  s->xg_max = best_x;
+  s->pg_max = best_p;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best_x, best_p};
+  }
+  if (out) *out = ks_tuning{best_x, best_p, (double)best, 0};
+  return done(KS_OK);
 }
 
 ks_status ks_set_kernel_timing(ks_system* s, int enable) {

@@ -7,8 +7,6 @@ namespace ks {
 
 constexpr int NT = 256;   // threads per x-pencil block
 constexpr int DENS_GROUP = 8;   // smallest orbital group of a density block
-constexpr int X_GROUP = 8;      // orbitals per x-pass block (upper bound)
-constexpr int P_GROUP = 8;      // orbitals per plane-pass block (upper bound)
 
 #define KS_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128)
 

@@ -24,10 +24,18 @@ KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "pla
 
 class Info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nruns",
-                                            "nslots", "npoints", "x_tile", "precision", "x_half")]
+                                            "nslots", "npoints", "x_tile", "precision", "x_half", "x_group",
+                                            "plane_group")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("x_group", ctypes.c_int), ("plane_group", ctypes.c_int), ("ms", ctypes.c_double),
+                ("from_cache", ctypes.c_int)]
+
+
 _STATUS = {1: "KS_EINVAL", 2: "KS_ENOMEM", 3: "KS_EDEVICE", 4: "KS_EUNSUPPORTED"}
 
 
@@ -74,6 +82,8 @@ def _load():
         "ks_plan_sphere": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, ctypes.POINTER(I), P]),
         "ks_plan_projectors": (I, [ctypes.POINTER(I), I, I, P, P, P, ctypes.POINTER(I), P, P, P, P]),
         "ks_set_kernel_timing": (I, [P, I]),
+        "ks_autotune": (I, [P, I, P, P]),
+        "ks_system_set_tuning": (I, [P, P]),
         "ks_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]),
     }
     for name, (res, args) in sig.items():
@@ -205,6 +215,18 @@ class System:
         inf = Info()
         self._check(_lib.ks_system_info(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def autotune(self, norb):
+        """Time the launch-schedule candidates (orbital-group caps) for H psi
+        over `norb` orbitals and keep the fastest (cached per process by
+        shape).  Returns {x_group, plane_group, ms, from_cache}."""
+        t = Tuning()
+        self._check(_lib.ks_autotune(self._h, int(norb), _stream(), ctypes.byref(t)))
+        return {"x_group": t.x_group, "plane_group": t.plane_group, "ms": t.ms, "from_cache": bool(t.from_cache)}
+
+    def set_tuning(self, x_group, plane_group):
+        t = Tuning(int(x_group), int(plane_group), 0.0, 0)
+        self._check(_lib.ks_system_set_tuning(self._h, ctypes.byref(t)))
 
     def set_kernel_timing(self, enable=True):
         self._check(_lib.ks_set_kernel_timing(self._h, int(bool(enable))))

@@ -6,8 +6,10 @@ the states of one system, and whole systems, are independent, which is what
 makes them batchable).  The loop
 
 * admits waiting requests in arrival order while their device footprint fits
-  the HBM budget (admission = system creation, uploads, Cholesky
-  orthonormalisation of the orbitals, one step captured into a HIP graph);
+  the HBM budget (admission = system creation, uploads, the launch schedule
+  from the library's autotuner (timed once per grid and pass-size bucket,
+  then cached), Cholesky orthonormalisation of the orbitals, one step
+  captured into a HIP graph);
 * keeps every admitted request's orbitals resident in HBM (packed layout)
   and issues its next step as soon as the previous one completed, on a pool
   of streams, so that the steps of many requests overlap on the device;
@@ -184,6 +186,7 @@ class HipBackend:
         self._next += 1
         with torch.cuda.stream(stream):
             gs = ks.system_from_synth(sysm, precision=self.precision)
+            gs.autotune(r.spec.norb)     # launch schedule; cached per grid and pass-size bucket
             c = torch.zeros((r.spec.norb, r.spec.npoints), dtype=torch.complex128, device="cuda")
             c[:, torch.from_numpy(sel).to("cuda")] = torch.from_numpy(vals).to("cuda")
             c = c.reshape((r.spec.norb,) + tuple(r.spec.n))

@@ -56,6 +56,8 @@ def test_null_system_calls_fail_cleanly():
     assert lib.ks_ham_apply(None, 1, None, None, None) == ks.KS_EINVAL
     assert lib.ks_density(None, 1, None, None, None, None) == ks.KS_EINVAL
     assert lib.ks_propagate_step(None, 1, None, 0.1, 1, None, None, None) == ks.KS_EINVAL
+    assert lib.ks_autotune(None, 1, None, None) == ks.KS_EINVAL
+    assert lib.ks_system_set_tuning(None, None) == ks.KS_EINVAL
     lib.ks_system_destroy(None)
 
 

@@ -62,6 +62,29 @@ def test_ham_apply_chunking_is_exact(ks):
     assert torch.equal(a, b)
 
 
+def test_autotune_keeps_results_and_caches(ks):
+    spec, sysm = _case("t48")
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    a = gs.ham_apply(c).clone()
+    t = gs.autotune(spec.norb)
+    assert t["x_group"] in (2, 4, 8, 16) and t["plane_group"] in (1, 2, 4, 8)
+    info = gs.info()
+    assert (info["x_group"], info["plane_group"]) == (t["x_group"], t["plane_group"])
+    assert torch.equal(a, gs.ham_apply(c))
+    # every launch schedule gives bit-identical results
+    for xg, pg in ((1, 1), (3, 5), (16, 8), (64, 64)):
+        gs.set_tuning(xg, pg)
+        assert torch.equal(a, gs.ham_apply(c))
+    with pytest.raises(ks.KSError):
+        gs.set_tuning(0, 1)
+    gs2 = ks.system_from_synth(sysm)
+    t2 = gs2.autotune(spec.norb)
+    assert t2["from_cache"] and (t2["x_group"], t2["plane_group"]) == (t["x_group"], t["plane_group"])
+    with pytest.raises(ks.KSError):
+        gs2.autotune(0)
+
+
 def test_ham_apply_deterministic(ks):
     spec, sysm = _case("t40")
     gs = ks.system_from_synth(sysm)
