@@ -27,11 +27,13 @@ HIPCC_FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-# Per-unit additions.  x-pencil passes: band-limited first-stage inputs are
-# literal zeros, and -fno-signed-zeros lets the compiler drop the additions of
-# those zeros (the only possible difference is the sign of a zero result).
+# Per-unit additions.  Plane and x-pencil passes: band-limited first-stage
+# inputs are literal zeros, and -fno-signed-zeros lets the compiler drop the
+# additions of those zeros (the only possible difference is the sign of a
+# zero result).
 UNIT_FLAGS = {
     "k_xpass.hip": ["-fno-signed-zeros"],
+    "k_plane.hip": ["-fno-signed-zeros"],
 }
 
 

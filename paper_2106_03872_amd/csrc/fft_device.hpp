@@ -22,6 +22,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace ks {
 
 template <typename R> struct cvec;
@@ -216,6 +218,34 @@ template <> struct plan<128> { using list = radix_list<8, 4, 4>; };
 enum { SRC_LDS = 0, SRC_FN = 1, SRC_PRE = 2 };   // SRC_PRE: inputs already in a register array (fft_preload)
 enum { DST_LDS = 0, DST_FN = 1, DST_FN_LDS = 2 };   // DST_FN_LDS: the functor writes the batch buffer
 
+// Band-limited operands.  A load or store functor derived from `band`
+// declares that the elements outside e < N/4 or e >= 3N/4 are zero (loads,
+// first stage) or not wanted (stores, last stage).  With a radix R divisible
+// by 4 those are the butterfly elements R/4 <= q < 3R/4 (first stage:
+// e = b + q N/R; last stage: e = k + q N/R); the stage then neither loads nor
+// stores them, and what only feeds the skipped stores is never computed.  For
+// other radices the declaration changes nothing.
+struct band {};
+template <class F>
+constexpr bool is_band = std::is_base_of<band, std::remove_cv_t<std::remove_reference_t<F>>>::value;
+template <int R>
+__device__ constexpr bool in_band(int q) {
+  return R % 4 != 0 || q < R / 4 || q >= 3 * R / 4;
+}
+template <class F>
+struct band_fn : band {
+  F f;
+  __device__ explicit band_fn(F g) : f(g) {}
+  template <class... A>
+  __device__ auto operator()(A... a) const {
+    return f(a...);
+  }
+};
+template <class F>
+__device__ band_fn<F> banded(F f) {
+  return band_fn<F>(f);
+}
+
 struct no_load {
   template <typename T> __device__ T operator()(int, int) const { return T{}; }
 };
@@ -255,9 +285,14 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
     if ((TOT % NT == 0 || i < TOT) && t < ntrans) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        if constexpr (SRC == SRC_FN) v[it][q] = load(t, b + q * NBF);
-        else if constexpr (SRC == SRC_PRE) v[it][q] = load.r.get(it, q);
-        else v[it][q] = buf[t * ts + b + q * NBF];
+        if constexpr (SRC == SRC_FN) {
+          if (!is_band<Load> || in_band<R>(q)) v[it][q] = load(t, b + q * NBF);
+          else v[it][q] = T{0, 0};
+        } else if constexpr (SRC == SRC_PRE) {
+          v[it][q] = load.r.get(it, q);
+        } else {
+          v[it][q] = buf[t * ts + b + q * NBF];
+        }
       }
     }
   }
@@ -280,7 +315,7 @@ __device__ __forceinline__ void stockham_stage(T* buf, int ts, int ntrans, const
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         if constexpr (DST == DST_LDS) buf[t * ts + o + q * NS] = v[it][q];
-        else store(t, o + q * NS, v[it][q], it, q);
+        else if (!is_band<Store> || in_band<R>(q)) store(t, o + q * NS, v[it][q], it, q);
       }
     }
   }

@@ -19,7 +19,7 @@ constexpr int EP_PRE = 4;   // packed coefficients per thread whose loads are is
 // bytes (unused here).  `stage` = 0 when a plane's coefficients do not fit in
 // Y: the z-synthesis then reads them from HBM directly.
 
-template <int N, typename R, typename TIN>
+template <int N, typename R, typename TIN, bool HB>
 __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ pk, int nb, int pk_stride,
                                                         cplx<R>* __restrict__ Tout, SphereTab tab,
                                                         const cplx<R>* __restrict__ twN, int ncol_max, int stage) {
@@ -65,36 +65,34 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
       if (o + 1 < ob) fetch(o + 1);
       __syncthreads();
       for (int cb = 0; cb < nc; cb += YB) {
-        fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
-            Z + cb * (N + 1), N + 1, nc - cb, tw,
-            [&](int t, int e) -> C {
-              const int c = cb + t;
-              const int idx = fold(e, N) - s_m2lo[c];
-              return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? S[s_off[c] - e0 + idx] : czero<C>();
-            },
-            no_store{});
+        auto load = [&](int t, int e) -> C {
+          const int c = cb + t;
+          const int idx = fold(e, N) - s_m2lo[c];
+          return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? S[s_off[c] - e0 + idx] : czero<C>();
+        };
+        if constexpr (HB) fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(Z + cb * (N + 1), N + 1, nc - cb, tw, banded(load), no_store{});
+        else fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(Z + cb * (N + 1), N + 1, nc - cb, tw, load, no_store{});
       }
     } else {
       for (int cb = 0; cb < nc; cb += YB) {
-        fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(
-            Z + cb * (N + 1), N + 1, nc - cb, tw,
-            [&](int t, int e) -> C {
-              const int c = cb + t;
-              const int idx = fold(e, N) - s_m2lo[c];
-              return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? cvt<C>(in[s_off[c] + idx]) : czero<C>();
-            },
-            no_store{});
+        auto load = [&](int t, int e) -> C {
+          const int c = cb + t;
+          const int idx = fold(e, N) - s_m2lo[c];
+          return (idx >= 0 && idx < s_off[c + 1] - s_off[c]) ? cvt<C>(in[s_off[c] + idx]) : czero<C>();
+        };
+        if constexpr (HB) fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(Z + cb * (N + 1), N + 1, nc - cb, tw, banded(load), no_store{});
+        else fft_io<N, +1, YB, NTP, SRC_FN, DST_LDS, C>(Z + cb * (N + 1), N + 1, nc - cb, tw, load, no_store{});
       }
     }
     C* out = Tout + ((long long)o * tab.nplanes + pi) * N * N;
     for (int w0 = 0; w0 < N; w0 += YB) {
-      fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(
-          Y, N + 1, N - w0, tw,
-          [&](int t, int e) -> C {
-            const int c = fold(e, N) - m1lo;
-            return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
-          },
-          [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; });
+      auto load = [&](int t, int e) -> C {
+        const int c = fold(e, N) - m1lo;
+        return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
+      };
+      auto store = [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; };
+      if constexpr (HB) fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(Y, N + 1, N - w0, tw, banded(load), store);
+      else fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(Y, N + 1, N - w0, tw, load, store);
       __syncthreads();
     }
   }
@@ -111,7 +109,7 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
 // LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1] | column of each packed
 // coefficient of the plane [npp_max] (bytes).
 
-template <int N, typename R, typename TW>
+template <int N, typename R, typename TW, bool HB>
 __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, int nb, const TW* win,
                                                         cplx<R>* __restrict__ wout, double2* acc, int pk_stride,
                                                         int acc_stride, SphereTab tab,
@@ -172,14 +170,23 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
           fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return un[e * N + t]; });
         }
       };
-      fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, preloaded(pre, next),
-                                                 [&](int t, int e, C v, int, int) {
-                                                   const int c = fold(e, N) - m1lo;
-                                                   if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
-                                                 });
+      auto store = [&](int t, int e, C v, int, int) {
+        const int c = fold(e, N) - m1lo;
+        if (c >= 0 && c < nc) Z[c * (N + 1) + w0 + t] = v;
+      };
+      if constexpr (HB) fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, preloaded(pre, next), banded(store));
+      else fft_io<N, -1, YB, NTP, SRC_PRE, DST_FN, C>(Y, N + 1, N - w0, tw, preloaded(pre, next), store);
       __syncthreads();
     }
-    for (int cb = 0; cb < nc; cb += YB) fft_batch<N, -1, YB, NTP, C>(Z + cb * (N + 1), N + 1, nc - cb, tw);
+    // z-analysis in place; with HB only the band |m2| < n2/4, which holds every column's run, is written
+    for (int cb = 0; cb < nc; cb += YB) {
+      C* zb = Z + cb * (N + 1);
+      if constexpr (HB)
+        fft_io<N, -1, YB, NTP, SRC_LDS, DST_FN_LDS, C>(zb, N + 1, nc - cb, tw, no_load{},
+                                                     banded([&](int t, int e, C v, int, int) { zb[t * (N + 1) + e] = v; }));
+      else
+        fft_batch<N, -1, YB, NTP, C>(zb, N + 1, nc - cb, tw);
+    }
     auto epilogue = [&](int k, TW w, double2 av_in) {
       const int c = s_col[k];
       const int m2 = s_m2lo[c] + (k + e0 - s_off[c]);
@@ -229,8 +236,13 @@ template <int N, typename R, typename TIN>
 static void plane_inv_t(const ks_system* s, int nb, const void* pk, void* T, const void* tw, hipStream_t st) {
   constexpr int YB = pnb<N>::value;
   const int stage = s->npp_max <= YB * (N + 1) ? 1 : 0;
-  plane_inv_kernel<N, R, TIN><<<dim3(s->nplanes, plane_groups(s, nb)), NTP, plane_lds_bytes(s), st>>>(
-      (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage);
+  const dim3 grid(s->nplanes, plane_groups(s, nb));
+  if (s->yz_half)
+    plane_inv_kernel<N, R, TIN, true><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage);
+  else
+    plane_inv_kernel<N, R, TIN, false><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage);
 }
 
 template <int N>
@@ -254,9 +266,15 @@ template <int N, typename R, typename TW>
 static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, HMode mode,
                         Taylor tay, const void* tw, hipStream_t st) {
   const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
-  plane_fwd_kernel<N, R, TW><<<dim3(s->nplanes, plane_groups(s, nb)), NTP, plane_lds_bytes(s), st>>>(
-      (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
-      sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
+  const dim3 grid(s->nplanes, plane_groups(s, nb));
+  if (s->yz_half)
+    plane_fwd_kernel<N, R, TW, true><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
+        sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
+  else
+    plane_fwd_kernel<N, R, TW, false><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
+        sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
 }
 
 template <int N>

@@ -259,10 +259,13 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
       __syncthreads();
     }
     C* obase = Uout + (long long)o * nplanes * npl + p0;
-    fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, [&](int t, int e, C v, int, int) {
+    auto store = [&](int t, int e, C v, int, int) {
       const int pi = fold(e, N0) - m0lo;
       if (pi >= 0 && pi < nplanes && t < tvalid) obase[(unsigned)(pi * npl + t)] = v;
-    });
+    };
+    // only the sphere's planes are stored; with HB they all lie in the band |m0| < n0/4
+    if constexpr (HB) fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, banded(store));
+    else fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, store);
     __syncthreads();   // X and dps are rewritten for the next orbital
   }
 }

@@ -502,6 +502,13 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   s->xnb = x_tile_nb(n[0]);
   s->ntiles = (s->npl + s->xnb - 1) / s->xnb;
   s->x_half = s->m0lo >= -(n[0] / 4) && s->m0lo + s->nplanes - 1 < n[0] / 4;
+  s->yz_half = true;
+  for (int pi = 0; pi < s->nplanes; ++pi) {
+    const int nc = plane_col0[pi + 1] - plane_col0[pi];
+    if (plane_m1lo[pi] < -(n[1] / 4) || plane_m1lo[pi] + nc - 1 >= n[1] / 4) s->yz_half = false;
+    for (int c = plane_col0[pi]; c < plane_col0[pi + 1]; ++c)
+      if (col_m2lo[c] < -(n[2] / 4) || col_m2lo[c] + (col_off[c + 1] - col_off[c]) - 1 >= n[2] / 4) s->yz_half = false;
+  }
 
   if (plane_lds_bytes(s) > 160 * 1024) {
     delete s;

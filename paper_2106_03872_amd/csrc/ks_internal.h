@@ -93,8 +93,9 @@ struct ks_system {
   // projectors
   int natoms = 0, nproj = 0, nslots = 0, nruns = 0, npoints = 0, nuniq = 0;
   int xnb = 32, ntiles = 0;
-  bool x_half = false;
-  int xg_max = 8, pg_max = 8;   // orbital-group caps of the x-pencil and plane passes (tunable)   // every sphere plane has |m0| < n0/4 (band-limited x-synthesis input)
+  bool x_half = false;   // every sphere plane has |m0| < n0/4 (band-limited x-synthesis input)
+  bool yz_half = false;  // every sphere point has |m1| < n1/4 and |m2| < n2/4 (band-limited y, z transforms)
+  int xg_max = 8, pg_max = 8;   // orbital-group caps of the x-pencil and plane passes (tunable)
   int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
       *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_key = nullptr,
       *d_up_x = nullptr, *d_x_slot = nullptr;
