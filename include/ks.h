@@ -167,8 +167,12 @@ void ks_state_destroy(ks_state* state);
 ks_status ks_state_upload(ks_state* state, const void* psi, void* stream);
 /* state -> psi (device complex128 box; zero outside chi). */
 ks_status ks_state_download(ks_state* state, void* psi, void* stream);
-/* As ks_propagate_step, on the resident orbitals. */
-ks_status ks_state_propagate(ks_state* state, double dt, int nsteps, const double* occ, double* rho, void* stream);
+/* As ks_propagate_step, on the resident orbitals; in addition, norms (NULL,
+ * or device float64 [nsteps][norb]) receives ||c_i||^2 after each step.
+ * Within one call the density of step s (s < nsteps-1) is taken from the
+ * first H psi of step s+1, which synthesises the same orbitals. */
+ks_status ks_state_propagate(ks_state* state, double dt, int nsteps, const double* occ, double* rho, double* norms,
+                             void* stream);
 /* As ks_reduce, on the resident orbitals. */
 ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, double* energy, void* stream);
 /*

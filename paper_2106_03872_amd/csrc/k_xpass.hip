@@ -35,13 +35,20 @@ __device__ __forceinline__ T wave_sum(T x) {
 // registers while the current one is transformed, and the per-tile data
 // (twiddles, potential, KB tables) is fetched once per block.
 
-template <int N0, typename R, bool HB>
+// DENS: the block also accumulates the density sum_o occ_o |psi_o|^2 / Omega
+// of its orbitals from the synthesis outputs and writes its group's partial
+// density (as xdens does), so a propagation step gets the density of its
+// input orbitals from its first H psi.
+template <int N0, typename R, bool HB, bool DENS>
 __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    cplx<R>* __restrict__ partial, SphereTab tab, ProjTab pt,
-                                                   const cplx<R>* __restrict__ tw0, double scale) {
+                                                   const cplx<R>* __restrict__ tw0, double scale,
+                                                   const double* __restrict__ occ, double* __restrict__ dpart,
+                                                   double inv_omega) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
   using FR = fft_regs<N0, NB, NT, C, HB>;
+  using LS = last_shape<N0, NB, NT>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ C tw[N0];
   const int tile = blockIdx.x, tid = threadIdx.x;
@@ -50,8 +57,15 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
-  if (ns == 0) return;  // no sphere point in this tile (uniform per block)
+  if (!DENS && ns == 0) return;  // no sphere point in this tile (uniform per block)
   for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
+  double a[DENS ? LS::items : 1][DENS ? LS::radix : 1];
+  if constexpr (DENS) {
+#pragma unroll
+    for (int it = 0; it < LS::items; ++it)
+#pragma unroll
+      for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
+  }
   // Projections: item i = pair*nseg + seg for the (slot, projector) pairs of
   // the tile; each item sums beta * psi over its segment of the slot's points
   // (in point order), and the nseg segments of a pair, adjacent lanes of one
@@ -92,7 +106,20 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
       if (o + 1 < ob)
         fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     };
-    fft_io<N0, +1, NB, NT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
+    if constexpr (DENS) {
+      const double f = occ[o] * inv_omega;
+      fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next),
+                                                   [&](int t, int e, C v, int it, int q) {
+                                                     X[t * (N0 + 1) + e] = v;
+                                                     a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
+                                                   });
+      if (ns == 0) {
+        __syncthreads();   // X is rewritten by the next orbital's first stage
+        continue;
+      }
+    } else {
+      fft_io<N0, +1, NB, NT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
+    }
     double sx = 0.0, sy = 0.0;
 #pragma unroll
     for (int c = 0; c < KP; ++c) {
@@ -114,6 +141,12 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
     }
     if (tid < items && seg == 0) pout[o * pstride] = C{R(sx * scale), R(sy * scale)};
     __syncthreads();   // X is rewritten by the next orbital's first stage
+  }
+  if constexpr (DENS) {
+    double* pb = dpart + (long long)blockIdx.y * tab.n0 * npl + p0;
+    last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+      if (p0 + t < npl) pb[e * npl + t] = a[it][q];
+    });
   }
 }
 
@@ -339,21 +372,41 @@ static int x_groups(const ks_system* s, int nb) {
 }
 
 template <int N0, bool HB>
-static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
+static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, const double* occ, double* rho,
+                    int accumulate, hipStream_t st) {
   const double scale = s->dV / sqrt(s->omega);
-  const int ng = x_groups(s, nb);
+  const double inv_omega = 1.0 / s->omega;
+  if (!rho) {
+    const int ng = x_groups(s, nb);
+    if (!mixed(s))
+      xproj_kernel<N0, double, HB, false><<<dim3(s->ntiles, ng), NT, 0, st>>>(
+          (const double2*)T, nb, (double2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0, scale, nullptr, nullptr,
+          inv_omega);
+    else
+      xproj_kernel<N0, float, HB, false><<<dim3(s->ntiles, ng), NT, 0, st>>>(
+          (const float2*)T, nb, (float2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0f, scale, nullptr, nullptr,
+          inv_omega);
+    return;
+  }
+  // groups of at least DENS_GROUP orbitals, so the partial densities fit their buffer
+  const int ng = std::min(x_groups(s, nb), (nb + DENS_GROUP - 1) / DENS_GROUP);
   if (!mixed(s))
-    xproj_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, (double2*)partial,
-                                                                  sphere_tab(s), proj_tab(s), s->d_tw0, scale);
+    xproj_kernel<N0, double, HB, true><<<dim3(s->ntiles, ng), NT, 0, st>>>(
+        (const double2*)T, nb, (double2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0, scale, occ, s->dens_part,
+        inv_omega);
   else
-    xproj_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, (float2*)partial,
-                                                                 sphere_tab(s), proj_tab(s), s->d_tw0f, scale);
+    xproj_kernel<N0, float, HB, true><<<dim3(s->ntiles, ng), NT, 0, st>>>(
+        (const float2*)T, nb, (float2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0f, scale, occ, s->dens_part,
+        inv_omega);
+  dens_sum_kernel<<<(unsigned)((s->N + NT - 1) / NT), NT, 0, st>>>(s->dens_part, ng, s->N, rho, accumulate);
 }
 
-bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st) {
+bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, const double* occ, double* rho,
+                  int accumulate, hipStream_t st) {
   switch (s->n[0]) {
 #define KS_CASE(v) \
-  case v: s->x_half ? xproj_n<v, true>(s, nb, T, partial, st) : xproj_n<v, false>(s, nb, T, partial, st); return true;
+  case v: s->x_half ? xproj_n<v, true>(s, nb, T, partial, occ, rho, accumulate, st) \
+                    : xproj_n<v, false>(s, nb, T, partial, occ, rho, accumulate, st); return true;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:

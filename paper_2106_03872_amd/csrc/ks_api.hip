@@ -381,12 +381,15 @@ ks_status check_common(ks_system* s, int norb) {
 
 // H applied to nb packed orbitals win; result per mode (see plane_fwd_kernel)
 // win_fp64: the input is the FP64 orbital state (else the working precision)
+// H applied to nb packed orbitals win.  With rho (only when natoms > 0), the
+// x-projection pass also writes (or adds, accumulate) the density
+// sum occ |win|^2 to rho.
 ks_status hpsi_packed(ks_system* s, int nb, const void* win, bool win_fp64, void* wout, void* acc, HMode mode, Taylor tay,
-                      hipStream_t st) {
+                      hipStream_t st, const double* occ = nullptr, double* rho = nullptr, int accumulate = 0) {
   ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, win, win_fp64, s->T, st); });
   if (r != KS_OK) return r;
   if (s->natoms > 0) {
-    r = kcall(s, KS_K_XPROJ, st, "xproj", [&] { return launch_xproj(s, nb, s->T, s->partial, st); });
+    r = kcall(s, KS_K_XPROJ, st, "xproj", [&] { return launch_xproj(s, nb, s->T, s->partial, occ, rho, accumulate, st); });
     if (r != KS_OK) return r;
     r = kcall(s, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] { return launch_proj_reduce(s, nb, s->partial, s->DP, st); });
     if (r != KS_OK) return r;
@@ -416,13 +419,17 @@ void taylor_coefficients(double dt, double2 coef[5]) {
 }
 
 // nsteps Taylor-4 steps on nb packed FP64 orbitals `state` (stride npw_stride),
-// in place; with rho, the density after step s is written (accumulate = 0) or
-// added (accumulate = 1) to rho + s*N.
+// in place.  With rho, the density after step s is written (accumulate = 0) or
+// added (accumulate = 1) to rho + s*N: for s < nsteps-1 by the first H psi of
+// step s+1, whose x-projection pass synthesises exactly those orbitals (when
+// there are projectors), for the last step by a density pass.  With norms,
+// ||c_o||^2 after step s goes to norms[s*norms_stride + o].
 ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nsteps, const double* occ, double* rho,
-                        int accumulate, hipStream_t st) {
+                        int accumulate, double* norms, int norms_stride, hipStream_t st) {
   double2 coef[5];
   taylor_coefficients(dt, coef);
   ks_status r;
+  const bool fuse = rho && s->natoms > 0;
   for (int step = 0; step < nsteps; ++step) {
     // w1 = H psi -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored; state += a_k w_k
     void* src[4] = {state, s->pk[1], s->pk[2], s->pk[1]};
@@ -430,9 +437,20 @@ ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nst
     for (int k = 1; k <= 4; ++k) {
       Taylor tay{coef[k], k < 4 ? 1 : 0};
       const bool in64 = k == 1 || s->prec == KS_FP64;
-      if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], state, H_TAYLOR, tay, st)) != KS_OK) return r;
+      double* rho_prev = (fuse && k == 1 && step > 0) ? rho + (size_t)(step - 1) * s->N : nullptr;
+      if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], state, H_TAYLOR, tay, st, occ, rho_prev,
+                           accumulate)) != KS_OK)
+        return r;
     }
-    if (rho && (r = density_packed(s, nb, state, occ, rho + (size_t)step * s->N, accumulate, st)) != KS_OK) return r;
+    if (rho && (!fuse || step == nsteps - 1) &&
+        (r = density_packed(s, nb, state, occ, rho + (size_t)step * s->N, accumulate, st)) != KS_OK)
+      return r;
+    if (norms) {
+      if ((r = kcall(s, KS_K_DOTS, st, "dots", [&] { return launch_dots(s, nb, state, nullptr, s->red, st); })) != KS_OK)
+        return r;
+      KS_HIP(s, hipMemcpy2DAsync(norms + (size_t)step * norms_stride, sizeof(double), s->red, 2 * sizeof(double),
+                                 sizeof(double), nb, hipMemcpyDeviceToDevice, st));
+    }
   }
   return KS_OK;
 }
@@ -678,7 +696,8 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
     const int nb = std::min(cl, norb - o0);
     double2* box = (double2*)psi + (size_t)o0 * s->N;
     if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, nb, box, s->N, s->pk[0], st); })) != KS_OK) return r;
-    if ((r = taylor_packed(s, nb, (double2*)s->pk[0], dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, st)) != KS_OK)
+    if ((r = taylor_packed(s, nb, (double2*)s->pk[0], dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, nullptr, 0,
+                           st)) != KS_OK)
       return r;
     if ((r = kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, nb, s->pk[0], true, box, s->N, st); })) != KS_OK) return r;
   }
@@ -883,7 +902,8 @@ ks_status ks_state_download(ks_state* t, void* psi, void* stream) {
   return kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, t->norb, t->data, true, box, s->N, st); });
 }
 
-ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* occ, double* rho, void* stream) {
+ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* occ, double* rho, double* norms,
+                             void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
   if (nsteps < 0) return fail(s, KS_EINVAL, "nsteps < 0");
@@ -895,7 +915,9 @@ ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* o
   for (int o0 = 0; o0 < t->norb; o0 += cl) {
     const int nb = std::min(cl, t->norb - o0);
     double2* slice = t->data + (size_t)o0 * s->npw_stride;
-    if ((r = taylor_packed(s, nb, slice, dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0, st)) != KS_OK) return r;
+    if ((r = taylor_packed(s, nb, slice, dt, nsteps, occ ? occ + o0 : nullptr, rho, o0 > 0,
+                           norms ? norms + o0 : nullptr, t->norb, st)) != KS_OK)
+      return r;
   }
   return KS_OK;
 }
@@ -935,7 +957,7 @@ ks_status ks_state_capture(ks_state* t, double dt, const double* occ, double* rh
   hipStream_t st = (hipStream_t)stream;
   state_drop_graph(t);
   KS_HIP(s, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  const ks_status r = ks_state_propagate(t, dt, 1, occ, rho, stream);
+  const ks_status r = ks_state_propagate(t, dt, 1, occ, rho, nullptr, stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(st, &g);
   if (r != KS_OK) {
@@ -1049,8 +1071,8 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
   if (hipMemsetAsync(s->pk[0], 0, (size_t)nb * s->npw_stride * sizeof(double2), st) != hipSuccess)
     return done(fail(s, KS_EDEVICE, "hipMemsetAsync failed"));
   Taylor none{{0.0, 0.0}, 0};
-  const int xgs[] = {2, 4, 8, 16};
-  const int pgs[] = {1, 2, 4, 8};
+  const int xgs[] = {2, 4, 8, 16, 32, 64};
+  const int pgs[] = {1, 2, 4, 8, 16};
   int best_x = s->xg_max, best_p = s->pg_max;
   float best = -1.0f;
   for (int xg : xgs) {

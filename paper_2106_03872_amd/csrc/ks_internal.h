@@ -148,7 +148,10 @@ bool launch_pack(const ks_system* s, int nb, const double2* box, long long box_s
 bool launch_unpack(const ks_system* s, int nb, const void* pk, bool pk_fp64, double2* box, long long box_stride,
                    hipStream_t st);
 bool launch_plane_inv(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, hipStream_t st);
-bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, hipStream_t st);
+// with rho: also the density of the synthesised orbitals (occ), written or
+// added (accumulate) to rho
+bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, const double* occ, double* rho,
+                  int accumulate, hipStream_t st);
 bool launch_proj_reduce(const ks_system* s, int nb, const void* partial, double2* DP, hipStream_t st);
 bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st);
 bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,

@@ -73,7 +73,7 @@ def _load():
         "ks_state_destroy": (None, [P]),
         "ks_state_upload": (I, [P, P, P]),
         "ks_state_download": (I, [P, P, P]),
-        "ks_state_propagate": (I, [P, D, I, P, P, P]),
+        "ks_state_propagate": (I, [P, D, I, P, P, P, P]),
         "ks_state_reduce": (I, [P, P, P, P, P]),
         "ks_state_capture": (I, [P, D, P, P, P]),
         "ks_state_replay": (I, [P, P]),
@@ -346,11 +346,18 @@ class State:
             self._h, _ptr(psi, torch.complex128, self.system.box_shape(self.norb), "psi"), self._st(stream)))
         return psi
 
-    def propagate(self, dt, nsteps=1, occ=None, rho=None, stream=None):
+    def propagate(self, dt, nsteps=1, occ=None, rho=None, norms=None, stream=None):
+        """nsteps Taylor-4 steps; rho [nsteps][n0][n1][n2] and norms
+        [nsteps][norb] (float64, optional) receive the density and the
+        orbital norms after each step."""
         import torch
+        if rho is not None and rho.numel() < int(nsteps) * int(np.prod(self.system.n)):
+            raise ValueError("rho must hold nsteps densities")
+        if norms is not None and norms.numel() < int(nsteps) * self.norb:
+            raise ValueError("norms must hold nsteps x norb values")
         self.system._check(_lib.ks_state_propagate(
             self._h, float(dt), int(nsteps), _ptr(occ, torch.float64, (self.norb,), "occ"),
-            _ptr(rho, torch.float64, None, "rho"), self._st(stream)))
+            _ptr(rho, torch.float64, None, "rho"), _ptr(norms, torch.float64, None, "norms"), self._st(stream)))
 
     def reduce(self, occ=None, want_energy=True, stream=None):
         import torch
