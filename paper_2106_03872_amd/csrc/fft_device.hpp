@@ -218,6 +218,26 @@ template <> struct plan<128> { using list = radix_list<8, 4, 4>; };
 enum { SRC_LDS = 0, SRC_FN = 1, SRC_PRE = 2 };   // SRC_PRE: inputs already in a register array (fft_preload)
 enum { DST_LDS = 0, DST_FN = 1, DST_FN_LDS = 2 };   // DST_FN_LDS: the functor writes the batch buffer
 
+// Streaming (non-temporal) global loads and stores for the plane
+// intermediates, which are written once and read once or twice per pass:
+// they then do not evict the small per-block tables (potential, projector and
+// scatter tables) that every orbital of a block re-reads from L2.
+template <typename T> struct native2;
+template <> struct native2<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct native2<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  using V = typename native2<T>::type;
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return T{v[0], v[1]};
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T x) {
+  using V = typename native2<T>::type;
+  const V v = {x.x, x.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
 // Band-limited operands.  A load or store functor derived from `band`
 // declares that the elements outside e < N/4 or e >= 3N/4 are zero (loads,
 // first stage) or not wanted (stores, last stage).  With a radix R divisible

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
         const int c = fold(e, N) - m1lo;
         return (c >= 0 && c < nc) ? Z[c * (N + 1) + w0 + t] : czero<C>();
       };
-      auto store = [&](int t, int e, C v, int, int) { out[e * N + w0 + t] = v; };
+      auto store = [&](int t, int e, C v, int, int) { st_stream(out + e * N + w0 + t, v); };
       if constexpr (HB) fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(Y, N + 1, N - w0, tw, banded(load), store);
       else fft_io<N, +1, YB, NTP, SRC_FN, DST_FN, C>(Y, N + 1, N - w0, tw, load, store);
       __syncthreads();
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
   FR pre;
   if (oa < ob) {
     const C* u = Uin + ((long long)oa * tab.nplanes + pi) * N * N;
-    fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return u[e * N + t]; });
+    fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return ld_stream(u + e * N + t); });
   }
   __syncthreads();
   for (int o = oa; o < ob; ++o) {
@@ -164,10 +164,10 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
       const int w1 = w0 + YB;
       auto next = [&] {
         if (w1 < N) {
-          fft_preload<N, YB, NTP, C>(pre, N - w1, [&](int t, int e) -> C { return u[e * N + w1 + t]; });
+          fft_preload<N, YB, NTP, C>(pre, N - w1, [&](int t, int e) -> C { return ld_stream(u + e * N + w1 + t); });
         } else if (o + 1 < ob) {
           const C* un = u + uplane;
-          fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return un[e * N + t]; });
+          fft_preload<N, YB, NTP, C>(pre, N, [&](int t, int e) -> C { return ld_stream(un + e * N + t); });
         }
       };
       auto store = [&](int t, int e, C v, int, int) {

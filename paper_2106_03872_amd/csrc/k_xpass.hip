@@ -19,7 +19,7 @@ struct TLoader {
         tvalid(npl_ - p0) {}
   __device__ C operator()(int t, int e) const {
     const int pi = fold(e, N0) - m0lo;
-    return (pi >= 0 && pi < nplanes && t < tvalid) ? base[(unsigned)(pi * npl + t)] : czero<C>();
+    return (pi >= 0 && pi < nplanes && t < tvalid) ? ld_stream(base + (unsigned)(pi * npl + t)) : czero<C>();
   }
 };
 
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     C* obase = Uout + (long long)o * nplanes * npl + p0;
     auto store = [&](int t, int e, C v, int, int) {
       const int pi = fold(e, N0) - m0lo;
-      if (pi >= 0 && pi < nplanes && t < tvalid) obase[(unsigned)(pi * npl + t)] = v;
+      if (pi >= 0 && pi < nplanes && t < tvalid) st_stream(obase + (unsigned)(pi * npl + t), v);
     };
     // only the sphere's planes are stored; with HB they all lie in the band |m0| < n0/4
     if constexpr (HB) fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, banded(store));
