@@ -27,6 +27,13 @@ or reordering:
 * Band energy ``sum_k f_k <psi_k|H|psi_k>`` and orbital norms.
 * Orthonormalisation by Cholesky of the overlap (the orthogonalisation step of
   Section "Ground-state solution").
+* Density-dependent local potential: the periodic Hartree potential solved in
+  Fourier space (Section "Poisson solver"), ``V_H(G) = 4 pi n(G) / |G|^2``
+  for ``G != 0`` and zero average, added to the static local potential.
+* The ETRS propagator (Eq. etrs, with the predictor of Eq. etrs0) whose two
+  exponentials of ``H(t)`` share the powers ``H(t)^k c`` (the shared-lambda
+  evaluation of the truncated Taylor series in Section "Real-time
+  propagation").
 
 Numerics: numpy FP64 / complex128; FFTs by ``scipy.fft`` (a library routine
 standing in for the DFT sums) using all host cores.
@@ -203,3 +210,56 @@ def orthonormalize(ham, c):
     Lc = np.linalg.cholesky(S)
     Cn = scipy.linalg.solve_triangular(Lc.conj(), C.T, lower=True)   # conj(L)^-1 C^T = (C L^-H)^T
     return Cn.reshape(c.shape)
+
+
+def hartree(grid, n):
+    """Periodic Hartree potential of the density ``n`` (Section "Poisson
+    solver", periodic boundary conditions): the Poisson equation
+    ``-lap V = 4 pi n`` becomes ``|G|^2 V(G) = 4 pi n(G)`` on the full box
+    (not the orbital sphere); the ``G = 0`` term is set to zero (a neutralising
+    background, so ``V_H`` has zero average).  ``n(G) = N^-1 sum_r n(r)
+    e^{-iG.r}`` and ``V(r) = sum_G V(G) e^{+iG.r}``."""
+    nG = scipy.fft.fftn(np.asarray(n, np.float64), norm="forward", workers=WORKERS)
+    G2 = 2.0 * grid.K
+    vG = np.zeros_like(nG)
+    nz = G2 > 0
+    vG[nz] = 4.0 * np.pi * nG[nz] / G2[nz]
+    return scipy.fft.ifftn(vG, norm="forward", workers=WORKERS).real
+
+
+def with_density(ham, n):
+    """The Hamiltonian of ``ham`` with local potential ``V_loc + V_H[n]``."""
+    h = Hamiltonian(ham.grid, ham.vloc + hartree(ham.grid, n))
+    h.atoms, h.d = ham.atoms, ham.d
+    return h
+
+
+def etrs_step(ham, c, dt, occ, nsteps=1):
+    """``nsteps`` ETRS steps (Eq. etrs) of the orbitals ``c`` under
+    ``H[n] = K + V_loc + V_H[n] + V_nl`` (``ham`` holds ``V_loc``).
+
+    One step from ``c(t)``:
+      1. ``H(t) = H[n(c(t))]``;
+      2. ``w_k = H(t)^k c`` for k = 1..4, shared by the two exponentials of
+         ``H(t)``: ``half = sum_k (-i dt/2)^k/k! w_k`` and the predictor
+         ``full = sum_k (-i dt)^k/k! w_k`` (Eq. etrs0);
+      3. ``H(t+dt) = H[n(full)]``;
+      4. ``c(t+dt) = sum_k (-i dt/2)^k/k! H(t+dt)^k half``.
+    Returns the orbitals and the densities ``n(c(t+dt))`` after each step."""
+    ah = taylor4_coefficients(0.5 * dt)
+    af = taylor4_coefficients(dt)
+    cur = np.where(ham.grid.chi, np.asarray(c, np.complex128), 0.0)
+    dens = []
+    for _ in range(nsteps):
+        h_t = with_density(ham, density(ham, cur, occ))
+        w = cur
+        half = cur.copy()
+        full = cur.copy()
+        for k in range(1, 5):
+            w = ham_apply(h_t, w)
+            half = half + ah[k] * w
+            full = full + af[k] * w
+        h_next = with_density(ham, density(ham, full, occ))
+        cur = taylor4_step(h_next, half, 0.5 * dt, 1)
+        dens.append(density(ham, cur, occ))
+    return cur, dens

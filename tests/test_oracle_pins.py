@@ -387,3 +387,78 @@ def test_generator_deterministic_and_normalised():
         np.testing.assert_allclose(dV * np.sum(beta ** 2, 0), 1.0, rtol=1e-13)
         assert np.all(np.diff(idx) > 0)
     assert a.vloc.min() < -1.5 and a.vloc.max() < 0
+
+
+# ----------------------------------------- Hartree potential and ETRS (NEXT rows)
+
+def test_hartree_single_mode_closed_form():
+    # -lap V = 4 pi n for n = n0 + a cos(G.r + p): V = 4 pi a / |G|^2 cos(G.r + p)
+    n, L = (8, 10, 12), (5.0, 6.0, 7.0)
+    g = ko.Grid(n, L, 0.0)
+    r = [np.arange(n[a]) * L[a] / n[a] for a in range(3)]
+    m = (1, -2, 3)
+    G = [2 * np.pi * m[a] / L[a] for a in range(3)]
+    ph = G[0] * r[0][:, None, None] + G[1] * r[1][None, :, None] + G[2] * r[2][None, None, :] + 0.4
+    dens = 1.3 + 0.25 * np.cos(ph)
+    v = ko.hartree(g, dens)
+    expect = 4 * np.pi * 0.25 / (G[0] ** 2 + G[1] ** 2 + G[2] ** 2) * np.cos(ph)
+    np.testing.assert_allclose(v, expect, atol=1e-13)
+
+
+def test_hartree_bruteforce_sums():
+    # explicit double sums over r and G (no FFT), zero G = 0 term
+    n, L = (4, 5, 6), (3.0, 3.5, 4.0)
+    g = ko.Grid(n, L, 0.0)
+    dens = _rng(41).random(n)
+    E0, E1, E2 = _phase_mats(n, L)
+    E = np.einsum("ad,be,cf->abcdef", E0, E1, E2).reshape(np.prod(n), np.prod(n))   # [r, G]
+    G2 = sum(np.meshgrid(*[(2 * np.pi * _folded(n[a]) / L[a]) ** 2 for a in range(3)], indexing="ij")).ravel()
+    nG = E.conj().T @ dens.ravel() / np.prod(n)
+    vG = np.where(G2 > 0, 4 * np.pi * nG / np.where(G2 > 0, G2, 1.0), 0.0)
+    expect = (E @ vG).real.reshape(n)
+    np.testing.assert_allclose(ko.hartree(g, dens), expect, atol=1e-12)
+    assert abs(ko.hartree(g, dens).mean()) < 1e-13
+
+
+def test_etrs_without_electrons_is_two_half_steps():
+    # no density -> no Hartree term -> H(t + dt) = H(t): ETRS = T4(-i dt/2)^2
+    g, ham = _tiny_system((4, 5, 6), (3.0, 3.5, 4.0), 9.0, seed=42)
+    c = np.where(g.chi, _rand_c(_rng(43), (2,) + g.n), 0)
+    out, dens = ko.etrs_step(ham, c, 0.05, np.zeros(2), nsteps=2)
+    np.testing.assert_allclose(out, ko.taylor4_step(ham, c, 0.025, 4), atol=1e-14 * np.abs(c).max())
+    assert len(dens) == 2 and np.abs(dens[-1]).max() == 0.0
+
+
+def test_etrs_free_electron_closed_form():
+    # one plane wave: uniform density, V_H = 0, so each step is T4(-i lam dt/2)^2
+    g = ko.Grid((8, 6, 10), (5.0, 4.0, 6.0), 0.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    c = np.zeros((1,) + g.n, complex)
+    c[0, 1, 2, 3] = 0.7 - 0.2j
+    lam = g.K[1, 2, 3]
+    dt, ns = 0.3 / lam, 3
+    out, dens = ko.etrs_step(ham, c, dt, np.array([2.0]), nsteps=ns)
+    expect = c * _t4(-1j * lam * dt / 2) ** (2 * ns)
+    np.testing.assert_allclose(out, expect, atol=1e-14)
+    np.testing.assert_allclose(dens[-1], np.full(g.n, 2.0 * abs(expect[0, 1, 2, 3]) ** 2 / g.omega), rtol=1e-13)
+
+
+def test_etrs_second_order_with_hartree():
+    # fixed final time, dt halved twice: with a density-dependent H the ETRS
+    # predictor makes the method second order (differences shrink 4x; taking
+    # H(t) for the second half-step instead gives a first-order method, 2x)
+    n, L = (6, 6, 6), (6.0, 6.0, 6.0)
+    g = ko.Grid(n, L, 2.0)
+    x = np.arange(n[0]) * L[0] / n[0]
+    ham = ko.Hamiltonian(g, 0.2 * np.cos(2 * np.pi * x / L[0])[:, None, None] * np.ones(n))
+    c = np.where(g.chi, _rand_c(_rng(44), (2,) + n), 0)
+    c = c / np.sqrt(np.sum(np.abs(c) ** 2, axis=(1, 2, 3)))[:, None, None, None]
+    occ = np.array([10.0, 10.0])
+    T = 1.0
+    outs = [ko.etrs_step(ham, c, T / k, occ, nsteps=k)[0] for k in (4, 8, 16)]
+    d1 = np.linalg.norm(outs[0] - outs[1])
+    d2 = np.linalg.norm(outs[1] - outs[2])
+    assert 3.6 < d1 / d2 < 4.4
+    # the Hartree term matters: without electrons the result is far away
+    free = ko.etrs_step(ham, c, T / 8, np.zeros(2), nsteps=8)[0]
+    assert np.linalg.norm(free - outs[1]) > 100 * d1
