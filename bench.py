@@ -188,6 +188,34 @@ def kernel_table(info, spec, ktimes, steps, ms_step):
     return kernels
 
 
+def run_etrs(spec, gs, state, steps):
+    """ETRS steps under the density-dependent Hamiltonian (V_loc + periodic
+    Hartree): 8 H psi, 2 densities and 2 Poisson solves per step."""
+    import torch
+    occ = torch.full((spec.norb,), float(spec.occ), dtype=torch.float64, device="cuda")
+    rho = torch.empty((steps,) + tuple(spec.n), dtype=torch.float64, device="cuda")
+    nrm = torch.empty((steps, spec.norb), dtype=torch.float64, device="cuda")
+    state.propagate_etrs(spec.dt, 1, occ)                      # warm-up (allocates the predictor)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    state.propagate_etrs(spec.dt, steps, occ, rho, nrm)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    # one Poisson solve (5 full-box FFT launches) timed on its own
+    v = torch.empty(tuple(spec.n), dtype=torch.float64, device="cuda")
+    gs.hartree(rho[-1], add_vloc=True, out=v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        gs.hartree(rho[-1], add_vloc=True, out=v)
+    torch.cuda.synchronize()
+    hms = (time.perf_counter() - t0) * 1e3 / 20
+    return {"ms_per_step": round(ms, 3), "hpsi_per_step": 8 * spec.norb,
+            "orbital_hpsi_per_s": round(8 * spec.norb / (ms * 1e-3), 1), "hartree_ms": round(hms, 4),
+            "electrons": float(occ.sum().item()), "norm_drift_max": float((nrm[-1] - 1.0).abs().max().item()),
+            "steps": steps, "density_dependent": "V_loc + periodic Hartree"}
+
+
 def run_serving(nreq, nsteps, budget_gb, log):
     from paper_2106_03872_amd import serve, synth
     trace = synth.serving_trace(nreq, 200.0, 2000)
@@ -214,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-etrs", action="store_true")
+    ap.add_argument("--etrs-steps", type=int, default=3)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=50)
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
@@ -250,6 +280,10 @@ def main():
             "alg_bytes_per_orbital": po, "alg_bytes_per_launch_shared": pl,
             "alg_bytes_per_launch": po * per_pass + pl, "orbitals_per_launch": per_pass}
     psi64 = state.download()
+    etrs = None if args.no_etrs else run_etrs(spec, gs, state, args.etrs_steps)
+    if etrs:
+        log(f"[bench] ETRS (V_loc + Hartree): {etrs['ms_per_step']:.2f} ms/step, "
+            f"{etrs['orbital_hpsi_per_s']:.1f} orbital.Hpsi/s, Hartree solve {etrs['hartree_ms']:.3f} ms")
     state.close()
     gs.close()
 
@@ -318,6 +352,7 @@ def main():
         "kernels": kernels,
         "physics": phys,
         "mixed": mixed,
+        "etrs": etrs,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -131,6 +131,17 @@ ks_status ks_density(ks_system* sys, int norb, const void* psi, const double* oc
                      void* stream);
 
 /*
+ * Periodic Hartree potential (Section "Poisson solver", periodic boundary
+ * conditions): v = V_H[rho] with V_H(G) = 4 pi rho(G) / |G|^2 for G != 0 and
+ * V_H(G = 0) = 0 (a neutralising background: V_H has zero average),
+ * rho(G) = N^-1 sum_r rho(r) e^{-iG.r}, V_H(r) = sum_G V_H(G) e^{+iG.r}, over
+ * the whole box.  With add_vloc != 0 the system's static V_loc is added.
+ * rho, v: device float64 [n0][n1][n2] (may be the same array).  KS_EINVAL on
+ * null arguments.
+ */
+ks_status ks_hartree(ks_system* sys, const double* rho, double* v, int add_vloc, void* stream);
+
+/*
  * Orbital norms and band energy (energy expression of Section "DFT and TDDFT
  * implementation" reduced to sum_k f_k <psi_k|H|psi_k> for a static potential):
  *   norms[i] = sum_G |c_iG|^2 over the sphere           (device float64 [norb])
@@ -173,6 +184,25 @@ ks_status ks_state_download(ks_state* state, void* psi, void* stream);
  * first H psi of step s+1, which synthesises the same orbitals. */
 ks_status ks_state_propagate(ks_state* state, double dt, int nsteps, const double* occ, double* rho, double* norms,
                              void* stream);
+/*
+ * nsteps steps of the enforced-time-reversal-symmetry propagator (Eq. etrs)
+ * under the density-dependent Hamiltonian H[n] = -1/2 lap + V_loc + V_H[n]
+ * + V_nl, V_H the periodic Hartree potential (see ks_hartree) and
+ * n = sum_i occ_i |psi_i|^2.  One step from psi(t):
+ *   H(t) = H[n(psi(t))];
+ *   w_k = H(t)^k psi for k = 1..4, shared by the two exponentials of H(t)
+ *   (Section "Real-time propagation"): half = sum_k (-i dt/2)^k/k! w_k and the
+ *   predictor full = sum_k (-i dt)^k/k! w_k (Eq. etrs0);
+ *   H(t+dt) = H[n(full)];  psi(t+dt) = sum_k (-i dt/2)^k/k! H(t+dt)^k half.
+ * That is 8 H psi and 2 densities per step.  occ is required; rho (NULL, or
+ * float64 [nsteps][n0][n1][n2]) and norms (NULL, or float64 [nsteps][norb])
+ * receive the density and ||c_i||^2 after each step.  The first call on a
+ * state allocates its predictor buffer (norb packed orbitals).  The system's
+ * potential is V_loc again when the call returns.  KS_EINVAL: null state or
+ * occ, nsteps < 0, non-finite dt.
+ */
+ks_status ks_state_propagate_etrs(ks_state* state, double dt, int nsteps, const double* occ, double* rho,
+                                  double* norms, void* stream);
 /* As ks_reduce, on the resident orbitals. */
 ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, double* energy, void* stream);
 /*

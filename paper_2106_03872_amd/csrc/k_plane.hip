@@ -111,7 +111,8 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
 
 template <int N, typename R, typename TW, bool HB>
 __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, int nb, const TW* win,
-                                                        cplx<R>* __restrict__ wout, double2* acc, int pk_stride,
+                                                        cplx<R>* __restrict__ wout, double2* acc, double2* acc2,
+                                                        int pk_stride,
                                                         int acc_stride, SphereTab tab,
                                                         const cplx<R>* __restrict__ twN, int ncol_max, int mode,
                                                         Taylor tay, double g0, double g1, double g2) {
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
     const C* u = Uin + ((long long)o * tab.nplanes + pi) * N * N;
     const long long obase = (long long)o * pk_stride + e0;
     double2* accp = acc ? acc + (long long)o * acc_stride + e0 : nullptr;
+    double2* acc2p = acc2 ? acc2 + (long long)o * acc_stride + e0 : nullptr;
     // epilogue operands of this orbital
     TW wv[EP_PRE];
     double2 av[EP_PRE];
@@ -187,6 +189,8 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
       else
         fft_batch<N, -1, YB, NTP, C>(zb, N + 1, nc - cb, tw);
     }
+    // the second accumulator (ETRS predictor) is read where it is updated,
+    // so the common single-accumulator path keeps its registers
     auto epilogue = [&](int k, TW w, double2 av_in) {
       const int c = s_col[k];
       const int m2 = s_m2lo[c] + (k + e0 - s_off[c]);
@@ -202,6 +206,12 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
         a.x += tay.coef.x * hw.x - tay.coef.y * hw.y;
         a.y += tay.coef.x * hw.y + tay.coef.y * hw.x;
         accp[k] = a;
+        if (acc2p) {
+          double2 b = acc2p[k];
+          b.x += tay.coef2.x * hw.x - tay.coef2.y * hw.y;
+          b.y += tay.coef2.x * hw.y + tay.coef2.y * hw.x;
+          acc2p[k] = b;
+        }
       }
     };
 #pragma unroll
@@ -263,32 +273,32 @@ bool launch_plane_inv(const ks_system* s, int nb, const void* pk, bool in_fp64, 
 }
 
 template <int N, typename R, typename TW>
-static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, HMode mode,
-                        Taylor tay, const void* tw, hipStream_t st) {
+static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, void* acc2,
+                        HMode mode, Taylor tay, const void* tw, hipStream_t st) {
   const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
   const dim3 grid(s->nplanes, plane_groups(s, nb));
   if (s->yz_half)
     plane_fwd_kernel<N, R, TW, true><<<grid, NTP, plane_lds_bytes(s), st>>>(
-        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
+        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, (double2*)acc2, s->npw_stride, s->npw_stride,
         sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
   else
     plane_fwd_kernel<N, R, TW, false><<<grid, NTP, plane_lds_bytes(s), st>>>(
-        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, s->npw_stride, s->npw_stride,
+        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, (double2*)acc2, s->npw_stride, s->npw_stride,
         sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
 }
 
 template <int N>
 static void plane_fwd_n(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
-                        void* acc, HMode mode, Taylor tay, hipStream_t st) {
-  if (!mixed(s)) plane_fwd_t<N, double, double2>(s, nb, U, win, wout, acc, mode, tay, s->d_tw1, st);
-  else if (win_fp64) plane_fwd_t<N, float, double2>(s, nb, U, win, wout, acc, mode, tay, s->d_tw1f, st);
-  else plane_fwd_t<N, float, float2>(s, nb, U, win, wout, acc, mode, tay, s->d_tw1f, st);
+                        void* acc, void* acc2, HMode mode, Taylor tay, hipStream_t st) {
+  if (!mixed(s)) plane_fwd_t<N, double, double2>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1, st);
+  else if (win_fp64) plane_fwd_t<N, float, double2>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1f, st);
+  else plane_fwd_t<N, float, float2>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1f, st);
 }
 
 bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
-                      void* acc, HMode mode, Taylor tay, hipStream_t st) {
+                      void* acc, void* acc2, HMode mode, Taylor tay, hipStream_t st) {
   switch (s->n[1]) {
-#define KS_CASE(v) case v: plane_fwd_n<v>(s, nb, U, win, win_fp64, wout, acc, mode, tay, st); return true;
+#define KS_CASE(v) case v: plane_fwd_n<v>(s, nb, U, win, win_fp64, wout, acc, acc2, mode, tay, st); return true;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:

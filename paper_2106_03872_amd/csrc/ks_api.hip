@@ -385,7 +385,8 @@ ks_status check_common(ks_system* s, int norb) {
 // x-projection pass also writes (or adds, accumulate) the density
 // sum occ |win|^2 to rho.
 ks_status hpsi_packed(ks_system* s, int nb, const void* win, bool win_fp64, void* wout, void* acc, HMode mode, Taylor tay,
-                      hipStream_t st, const double* occ = nullptr, double* rho = nullptr, int accumulate = 0) {
+                      hipStream_t st, const double* occ = nullptr, double* rho = nullptr, int accumulate = 0,
+                      void* acc2 = nullptr) {
   ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, win, win_fp64, s->T, st); });
   if (r != KS_OK) return r;
   if (s->natoms > 0) {
@@ -396,7 +397,8 @@ ks_status hpsi_packed(ks_system* s, int nb, const void* win, bool win_fp64, void
   }
   r = kcall(s, KS_K_XAPPLY, st, "xapply", [&] { return launch_xapply(s, nb, s->T, s->DP, s->U, st); });
   if (r != KS_OK) return r;
-  return kcall(s, KS_K_PLANE_FWD, st, "plane_fwd", [&] { return launch_plane_fwd(s, nb, s->U, win, win_fp64, wout, acc, mode, tay, st); });
+  return kcall(s, KS_K_PLANE_FWD, st, "plane_fwd",
+               [&] { return launch_plane_fwd(s, nb, s->U, win, win_fp64, wout, acc, acc2, mode, tay, st); });
 }
 
 ks_status density_packed(ks_system* s, int nb, const void* pk, const double* occ, double* rho, int accumulate,
@@ -435,7 +437,7 @@ ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nst
     void* src[4] = {state, s->pk[1], s->pk[2], s->pk[1]};
     void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
     for (int k = 1; k <= 4; ++k) {
-      Taylor tay{coef[k], k < 4 ? 1 : 0};
+      Taylor tay{coef[k], k < 4 ? 1 : 0, {0.0, 0.0}};
       const bool in64 = k == 1 || s->prec == KS_FP64;
       double* rho_prev = (fuse && k == 1 && step > 0) ? rho + (size_t)(step - 1) * s->N : nullptr;
       if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], state, H_TAYLOR, tay, st, occ, rho_prev,
@@ -461,6 +463,84 @@ ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nst
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+
+// Density of the nb-orbital passes of a resident state (all passes, in
+// order) into rho.
+ks_status state_density(ks_system* s, ks_state* t, const double2* orbitals, const double* occ, double* rho,
+                        hipStream_t st) {
+  const int cl = chunk_len(s, t->norb);
+  for (int o0 = 0; o0 < t->norb; o0 += cl) {
+    const int nb = std::min(cl, t->norb - o0);
+    const ks_status r = density_packed(s, nb, orbitals + (size_t)o0 * s->npw_stride, occ + o0, rho, o0 > 0, st);
+    if (r != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
+// d_v = V_loc + V_H[d_rho_w]
+ks_status update_potential(ks_system* s, hipStream_t st) {
+  if (!launch_hartree(s, s->d_rho_w, s->d_v, s->d_vloc, st)) return fail(s, KS_EUNSUPPORTED, "no Hartree kernel");
+  return launch_ok(s, true, "hartree");
+}
+
+// nsteps ETRS steps (Eq. etrs) of the resident orbitals under the
+// density-dependent H[n] = K + V_loc + V_H[n] + V_nl; see ks_state_propagate_etrs.
+ks_status etrs_packed(ks_system* s, ks_state* t, double dt, int nsteps, const double* occ, double* rho, double* norms,
+                      hipStream_t st) {
+  double2 ch[5], cf[5];
+  taylor_coefficients(0.5 * dt, ch);
+  taylor_coefficients(dt, cf);
+  const int cl = chunk_len(s, t->norb);
+  const size_t row = (size_t)s->npw_stride * sizeof(double2);
+  ks_status r;
+  // H(t): the potential of the current orbitals
+  if ((r = state_density(s, t, t->data, occ, s->d_rho_w, st)) != KS_OK) return r;
+  if ((r = update_potential(s, st)) != KS_OK) return r;
+  for (int step = 0; step < nsteps; ++step) {
+    // w_k = H(t)^k c, shared: c <- sum_k (-i dt/2)^k/k! w_k (in place), predictor <- sum_k (-i dt)^k/k! w_k
+    for (int o0 = 0; o0 < t->norb; o0 += cl) {
+      const int nb = std::min(cl, t->norb - o0);
+      double2* slice = t->data + (size_t)o0 * s->npw_stride;
+      double2* pred = t->aux + (size_t)o0 * s->npw_stride;
+      KS_HIP(s, hipMemcpyAsync(pred, slice, nb * row, hipMemcpyDeviceToDevice, st));
+      void* src[4] = {slice, s->pk[1], s->pk[2], s->pk[1]};
+      void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
+      for (int k = 1; k <= 4; ++k) {
+        Taylor tay{ch[k], k < 4 ? 1 : 0, cf[k]};
+        const bool in64 = k == 1 || s->prec == KS_FP64;
+        if ((r = hpsi_packed(s, nb, src[k - 1], in64, dst[k - 1], slice, H_TAYLOR, tay, st, nullptr, nullptr, 0,
+                             pred)) != KS_OK)
+          return r;
+      }
+    }
+    // H(t + dt) from the predictor's density (Eq. etrs0)
+    if ((r = state_density(s, t, t->aux, occ, s->d_rho_w, st)) != KS_OK) return r;
+    if ((r = update_potential(s, st)) != KS_OK) return r;
+    // second half-step with H(t + dt)
+    for (int o0 = 0; o0 < t->norb; o0 += cl) {
+      const int nb = std::min(cl, t->norb - o0);
+      if ((r = taylor_packed(s, nb, t->data + (size_t)o0 * s->npw_stride, 0.5 * dt, 1, nullptr, nullptr, 0, nullptr, 0,
+                             st)) != KS_OK)
+        return r;
+    }
+    // density (and potential) of the new orbitals
+    if ((r = state_density(s, t, t->data, occ, s->d_rho_w, st)) != KS_OK) return r;
+    if (rho)
+      KS_HIP(s, hipMemcpyAsync(rho + (size_t)step * s->N, s->d_rho_w, s->N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (norms) {
+      for (int o0 = 0; o0 < t->norb; o0 += cl) {
+        const int nb = std::min(cl, t->norb - o0);
+        const double2* slice = t->data + (size_t)o0 * s->npw_stride;
+        if ((r = kcall(s, KS_K_DOTS, st, "dots", [&] { return launch_dots(s, nb, slice, nullptr, s->red, st); })) != KS_OK)
+          return r;
+        KS_HIP(s, hipMemcpy2DAsync(norms + (size_t)step * t->norb + o0, sizeof(double), s->red, 2 * sizeof(double),
+                                   sizeof(double), nb, hipMemcpyDeviceToDevice, st));
+      }
+    }
+    if (step + 1 < nsteps && (r = update_potential(s, st)) != KS_OK) return r;
+  }
+  return KS_OK;
+}
 
 }  // namespace
 
@@ -544,12 +624,16 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
     return st;
   }
   if ((st = dalloc(s, reinterpret_cast<void**>(&s->d_v), s->N * sizeof(double))) != KS_OK ||
+      (st = dalloc(s, reinterpret_cast<void**>(&s->d_vloc), s->N * sizeof(double))) != KS_OK ||
+      (st = dalloc(s, reinterpret_cast<void**>(&s->d_hbox), s->N * sizeof(double2))) != KS_OK ||
+      (st = dalloc(s, reinterpret_cast<void**>(&s->d_rho_w), s->N * sizeof(double))) != KS_OK ||
       (st = dalloc(s, reinterpret_cast<void**>(&s->red), 2 * (size_t)max_norb * sizeof(double))) != KS_OK) {
     g_create_err = s->err;
     ks_system_destroy(s);
     return st;
   }
-  if (hipMemset(s->d_v, 0, s->N * sizeof(double)) != hipSuccess) {
+  if (hipMemset(s->d_v, 0, s->N * sizeof(double)) != hipSuccess ||
+      hipMemset(s->d_vloc, 0, s->N * sizeof(double)) != hipSuccess) {
     g_create_err = "hipMemset failed";
     ks_system_destroy(s);
     return KS_EDEVICE;
@@ -577,7 +661,7 @@ void ks_system_destroy(ks_system* s) {
   timing_free(s);
   free_workspace(s);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
-                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
+                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_vloc, s->d_hbox, s->d_rho_w, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
                   s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta,
                   s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
@@ -602,6 +686,7 @@ ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (!v) return fail(s, KS_EINVAL, "v is null");
   KS_HIP(s, hipMemcpyAsync(s->d_v, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  KS_HIP(s, hipMemcpyAsync(s->d_vloc, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   s->have_v = true;
   return KS_OK;
 }
@@ -667,7 +752,7 @@ ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void
   const char* b = (const char*)hpsi;
   if (a < b + bytes && b < a + bytes) return fail(s, KS_EINVAL, "psi and hpsi overlap");
   hipStream_t st = (hipStream_t)stream;
-  Taylor none{{0.0, 0.0}, 0};
+  Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   const int cl = chunk_len(s, norb);
   for (int o0 = 0; o0 < norb; o0 += cl) {
     const int nb = std::min(cl, norb - o0);
@@ -724,6 +809,15 @@ ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ,
   return KS_OK;
 }
 
+ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, void* stream) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (!rho || !v) return fail(s, KS_EINVAL, "rho or v is null");
+  hipStream_t st = (hipStream_t)stream;
+  if (!launch_hartree(s, rho, v, add_vloc ? s->d_vloc : nullptr, st))
+    return fail(s, KS_EUNSUPPORTED, "no Hartree kernel for this grid");
+  return launch_ok(s, true, "hartree");
+}
+
 ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, double* norms, double* energy,
                     void* stream) {
   ks_status r = check_common(s, norb);
@@ -735,7 +829,7 @@ ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, 
     return KS_OK;
   }
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
-  Taylor none{{0.0, 0.0}, 0};
+  Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   const int cl = chunk_len(s, norb);
   for (int o0 = 0; o0 < norb; o0 += cl) {
     const int nb = std::min(cl, norb - o0);
@@ -881,6 +975,8 @@ void ks_state_destroy(ks_state* t) {
   state_drop_graph(t);
   void* p = t->data;
   dfree(p);
+  void* q = t->aux;
+  dfree(q);
   delete t;
 }
 
@@ -922,12 +1018,34 @@ ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* o
   return KS_OK;
 }
 
+ks_status ks_state_propagate_etrs(ks_state* t, double dt, int nsteps, const double* occ, double* rho, double* norms,
+                                  void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (nsteps < 0) return fail(s, KS_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(s, KS_EINVAL, "dt must be finite");
+  if (!occ) return fail(s, KS_EINVAL, "occ is required (the Hamiltonian depends on the density)");
+  if (nsteps == 0) return KS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (!t->aux) {
+    ks_status r = dalloc(s, reinterpret_cast<void**>(&t->aux), (size_t)t->norb * s->npw_stride * sizeof(double2));
+    if (r != KS_OK) return r;
+  }
+  const ks_status r = etrs_packed(s, t, dt, nsteps, occ, rho, norms, st);
+  // the system's Hamiltonian is the static one again between calls
+  const hipError_t e =
+      hipMemcpyAsync(s->d_v, s->d_vloc, s->N * sizeof(double), hipMemcpyDeviceToDevice, st);
+  if (r != KS_OK) return r;
+  if (e != hipSuccess) return fail(s, KS_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  return KS_OK;
+}
+
 ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double* energy, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
   if (energy && !occ) return fail(s, KS_EINVAL, "energy requires occ");
   hipStream_t st = (hipStream_t)stream;
-  Taylor none{{0.0, 0.0}, 0};
+  Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   ks_status r;
   // norms only: one launch over every resident orbital
   const int step = energy ? chunk_len(s, t->norb) : t->norb;
@@ -1070,7 +1188,7 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
     return done(fail(s, KS_EDEVICE, "hipEventCreate failed"));
   if (hipMemsetAsync(s->pk[0], 0, (size_t)nb * s->npw_stride * sizeof(double2), st) != hipSuccess)
     return done(fail(s, KS_EDEVICE, "hipMemsetAsync failed"));
-  Taylor none{{0.0, 0.0}, 0};
+  Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   const int xgs[] = {2, 4, 8, 16, 32, 64};
   const int pgs[] = {1, 2, 4, 8, 16};
   int best_x = s->xg_max, best_p = s->pg_max;

@@ -58,8 +58,9 @@ constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-t
 enum HMode { H_OUT = 0, H_TAYLOR = 1 };
 
 struct Taylor {
-  double2 coef;  // (-i dt)^k / k!
-  int write_w;   // store w_k = H w_{k-1}
+  double2 coef;   // (-i dt)^k / k!
+  int write_w;    // store w_k = H w_{k-1}
+  double2 coef2;  // coefficient of the second accumulator (when one is given)
 };
 
 }  // namespace ks
@@ -86,9 +87,15 @@ struct ks_system {
   float2* d_tw0f = nullptr;
   float2* d_tw1f = nullptr;
 
-  // local potential
+  // local potential: d_v is the potential the Hamiltonian applies (V_loc,
+  // or V_loc + V_H[n] inside a density-dependent propagation), d_vloc the
+  // static V_loc
   double* d_v = nullptr;
+  double* d_vloc = nullptr;
   bool have_v = false;
+  // Hartree solve: complex work box [n0][n1][n2] and a density [n0][n1][n2]
+  double2* d_hbox = nullptr;
+  double* d_rho_w = nullptr;
 
   // projectors
   int natoms = 0, nproj = 0, nslots = 0, nruns = 0, npoints = 0, nuniq = 0;
@@ -136,6 +143,7 @@ struct ks_state {
   ks_system* sys = nullptr;
   int norb = 0;
   double2* data = nullptr;     // [norb][npw_stride]
+  double2* aux = nullptr;      // [norb][npw_stride] ETRS predictor (allocated on first use)
   hipGraph_t graph = nullptr;  // one captured propagation step
   hipGraphExec_t exec = nullptr;
 };
@@ -155,7 +163,7 @@ bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, cons
 bool launch_proj_reduce(const ks_system* s, int nb, const void* partial, double2* DP, hipStream_t st);
 bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st);
 bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
-                      void* acc, HMode mode, Taylor tay, hipStream_t st);
+                      void* acc, void* acc2, HMode mode, Taylor tay, hipStream_t st);
 bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
                   hipStream_t st);
 bool launch_dots(const ks_system* s, int nb, const void* a, const void* b, double* out, hipStream_t st);
@@ -164,6 +172,9 @@ bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hi
 bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st);
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st);
+
+// v = V_H[rho] (+ vloc when not null); uses the system's work box
+bool launch_hartree(const ks_system* s, const double* rho, double* v, const double* vloc, hipStream_t st);
 
 bool supported_size(int n);
 int x_tile_nb(int n0);

@@ -74,6 +74,8 @@ def _load():
         "ks_state_upload": (I, [P, P, P]),
         "ks_state_download": (I, [P, P, P]),
         "ks_state_propagate": (I, [P, D, I, P, P, P, P]),
+        "ks_state_propagate_etrs": (I, [P, D, I, P, P, P, P]),
+        "ks_hartree": (I, [P, P, P, I, P]),
         "ks_state_reduce": (I, [P, P, P, P, P]),
         "ks_state_capture": (I, [P, D, P, P, P]),
         "ks_state_replay": (I, [P, P]),
@@ -228,6 +230,16 @@ class System:
         t = Tuning(int(x_group), int(plane_group), 0.0, 0)
         self._check(_lib.ks_system_set_tuning(self._h, ctypes.byref(t)))
 
+    def hartree(self, rho, add_vloc=False, out=None):
+        """Periodic Hartree potential of the density rho (float64 box on the
+        device), plus the static V_loc when add_vloc."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self._check(_lib.ks_hartree(self._h, _ptr(rho, torch.float64, self.n, "rho"),
+                                    _ptr(out, torch.float64, self.n, "out"), int(bool(add_vloc)), _stream()))
+        return out
+
     def set_kernel_timing(self, enable=True):
         self._check(_lib.ks_set_kernel_timing(self._h, int(bool(enable))))
 
@@ -356,6 +368,19 @@ class State:
         if norms is not None and norms.numel() < int(nsteps) * self.norb:
             raise ValueError("norms must hold nsteps x norb values")
         self.system._check(_lib.ks_state_propagate(
+            self._h, float(dt), int(nsteps), _ptr(occ, torch.float64, (self.norb,), "occ"),
+            _ptr(rho, torch.float64, None, "rho"), _ptr(norms, torch.float64, None, "norms"), self._st(stream)))
+
+    def propagate_etrs(self, dt, nsteps, occ, rho=None, norms=None, stream=None):
+        """nsteps ETRS steps under the density-dependent Hamiltonian
+        (V_loc + Hartree); rho [nsteps][n0][n1][n2] and norms [nsteps][norb]
+        (float64, optional) receive the density and norms after each step."""
+        import torch
+        if rho is not None and rho.numel() < int(nsteps) * int(np.prod(self.system.n)):
+            raise ValueError("rho must hold nsteps densities")
+        if norms is not None and norms.numel() < int(nsteps) * self.norb:
+            raise ValueError("norms must hold nsteps x norb values")
+        self.system._check(_lib.ks_state_propagate_etrs(
             self._h, float(dt), int(nsteps), _ptr(occ, torch.float64, (self.norb,), "occ"),
             _ptr(rho, torch.float64, None, "rho"), _ptr(norms, torch.float64, None, "norms"), self._st(stream)))
 

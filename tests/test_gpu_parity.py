@@ -330,3 +330,56 @@ def test_single_orbital_and_max_chunk(ks):
     assert rel_err(gs.ham_apply(one).cpu().numpy(), ko.ham_apply(ham, one.cpu().numpy())) < TOL
     gs.set_chunk(1)
     assert rel_err(gs.ham_apply(c).cpu().numpy(), ko.ham_apply(ham, c.cpu().numpy())) < TOL
+
+
+# ------------------------------------------ Hartree potential and ETRS (NEXT rows)
+
+@pytest.mark.parametrize("name", ["t24", "t32x", "t48"])
+def test_hartree_parity(ks, name):
+    spec, sysm = _case(name)
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    rng = np.random.default_rng(5)
+    rho_np = rng.random(spec.n) + 0.5
+    rho = torch.from_numpy(rho_np).cuda()
+    v = gs.hartree(rho).cpu().numpy()
+    ref = ko.hartree(ham.grid, rho_np)
+    assert np.linalg.norm(v - ref) / np.linalg.norm(ref) < TOL
+    vt = gs.hartree(rho, add_vloc=True).cpu().numpy()
+    reft = ref + sysm.vloc.reshape(spec.n)
+    assert np.linalg.norm(vt - reft) / np.linalg.norm(reft) < TOL
+    # in place (rho and v the same array)
+    gs.hartree(rho, out=rho)
+    assert np.linalg.norm(rho.cpu().numpy() - ref) / np.linalg.norm(ref) < TOL
+
+
+@pytest.mark.parametrize("name", ["t24", "t48"])
+def test_etrs_parity(ks, name):
+    spec, sysm = _case(name)
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    # unit-norm orbitals, two electrons each: a physical density and Hartree potential
+    c = c / torch.sqrt(torch.from_numpy(ko.norms(ham, c.cpu().numpy())).cuda()).reshape(-1, 1, 1, 1)
+    c0 = c.cpu().numpy()
+    occ_np = np.full(spec.norb, 2.0)
+    occ = torch.from_numpy(occ_np).cuda()
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    K = 2
+    rho = torch.empty((K,) + spec.n, dtype=torch.float64, device="cuda")
+    nrm = torch.empty((K, spec.norb), dtype=torch.float64, device="cuda")
+    st.propagate_etrs(spec.dt, K, occ, rho, nrm)
+    torch.cuda.synchronize()
+    ref, dens = ko.etrs_step(ham, c0, spec.dt, occ_np, nsteps=K)
+    assert rel_err(st.download().cpu().numpy(), ref) < TOL
+    for s in range(K):
+        r = rho[s].cpu().numpy()
+        assert np.linalg.norm(r - dens[s]) / np.linalg.norm(dens[s]) < TOL
+    np.testing.assert_allclose(nrm[-1].cpu().numpy(), ko.norms(ham, ref), rtol=TOL)
+    # the density-dependent term is active: ETRS differs from two static half steps
+    assert rel_err(ref, ko.taylor4_step(ham, c0, spec.dt / 2, 2 * K)) > 1e-6
+    # the system's Hamiltonian is static again after the call
+    a = gs.ham_apply(c)
+    assert rel_err(a.cpu().numpy(), ko.ham_apply(ham, c0)) < TOL
+    st.close()
