@@ -30,6 +30,10 @@ or reordering:
 * Density-dependent local potential: the periodic Hartree potential solved in
   Fourier space (Section "Poisson solver"), ``V_H(G) = 4 pi n(G) / |G|^2``
   for ``G != 0`` and zero average, added to the static local potential.
+* The optical-response probe of Section "Results" (the water-molecule
+  spectrum): a field kick at t = 0, i.e. ``v_pert = -k.r delta(t)`` in
+  Eq. hamiltonian, which multiplies every orbital by ``exp(i k.r)``; and the
+  dipole moment, the first moment of the density.
 * The ETRS propagator (Eq. etrs, with the predictor of Eq. etrs0) whose two
   exponentials of ``H(t)`` share the powers ``H(t)^k c`` (the shared-lambda
   evaluation of the truncated Taylor series in Section "Real-time
@@ -263,3 +267,26 @@ def etrs_step(ham, c, dt, occ, nsteps=1):
         cur = taylor4_step(h_next, half, 0.5 * dt, 1)
         dens.append(density(ham, cur, occ))
     return cur, dens
+
+
+def positions(grid):
+    """Grid positions ``r_a = j_a L_a / n_a`` (cell origin at the corner)."""
+    return [np.arange(grid.n[a]) * grid.L[a] / grid.n[a] for a in range(3)]
+
+
+def kick(grid, c, k):
+    """Field kick at t = 0: ``psi(r) -> exp(i k.r) psi(r)`` (the propagator of
+    ``v_pert = -k.r delta(t)``), then projected on the plane-wave sphere."""
+    x = positions(grid)
+    phase = np.exp(1j * (k[0] * x[0][:, None, None] + k[1] * x[1][None, :, None] + k[2] * x[2][None, None, :]))
+    psi = synthesize(grid, np.asarray(c, np.complex128))
+    return np.where(grid.chi, analyze(grid, phase * psi), 0.0)
+
+
+def dipole(grid, n):
+    """Dipole moment, the first moment of the density: ``dV sum_r r n(r)``."""
+    x = positions(grid)
+    n = np.asarray(n, np.float64)
+    return np.array([grid.dV * np.sum(n * x[0][:, None, None]),
+                     grid.dV * np.sum(n * x[1][None, :, None]),
+                     grid.dV * np.sum(n * x[2][None, None, :])])

@@ -462,3 +462,49 @@ def test_etrs_second_order_with_hartree():
     # the Hartree term matters: without electrons the result is far away
     free = ko.etrs_step(ham, c, T / 8, np.zeros(2), nsteps=8)[0]
     assert np.linalg.norm(free - outs[1]) > 100 * d1
+
+
+# ------------------------------------------------- kick and dipole (NEXT-3)
+
+def test_kick_commensurate_is_index_shift():
+    # k = G_m: exp(i G_m.r) sum_G c_G exp(iG.r) = sum_G c_{G - G_m} exp(iG.r)
+    n, L = (8, 10, 12), (5.0, 6.0, 7.0)
+    g = ko.Grid(n, L, 0.0)
+    m = (1, -2, 3)
+    k = [2 * np.pi * m[a] / L[a] for a in range(3)]
+    c = np.zeros(n, complex)
+    rng = _rng(51)
+    for _ in range(6):   # a few coefficients with small |m|, so the shift stays inside the box
+        j = tuple(int(rng.integers(-2, 3)) % n[a] for a in range(3))
+        c[j] = rng.standard_normal() + 1j * rng.standard_normal()
+    out = ko.kick(g, c[None], k)[0]
+    expect = np.roll(c, m, axis=(0, 1, 2))
+    np.testing.assert_allclose(out, expect, atol=1e-13)
+    back = ko.kick(g, out[None], [-x for x in k])[0]
+    np.testing.assert_allclose(back, c, atol=1e-13)
+
+
+def test_kick_full_box_is_unitary_and_keeps_density():
+    g = ko.Grid((6, 8, 10), (4.0, 5.0, 6.0), 0.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    c = _rand_c(_rng(52), (3,) + g.n)
+    k = [0.013, -0.07, 0.2]                      # not commensurate with the cell
+    out = ko.kick(g, c, k)
+    np.testing.assert_allclose(ko.norms(ham, out), ko.norms(ham, c), rtol=1e-13)
+    occ = np.array([2.0, 1.0, 0.5])
+    np.testing.assert_allclose(ko.density(ham, out, occ), ko.density(ham, c, occ), rtol=1e-12, atol=1e-14)
+
+
+def test_dipole_closed_forms():
+    n, L = (6, 8, 10), (4.0, 5.0, 6.0)
+    g = ko.Grid(n, L, 0.0)
+    n0 = 0.3
+    # uniform density: d_a = n0 Omega (n_a - 1) L_a / (2 n_a)
+    d = ko.dipole(g, np.full(n, n0))
+    expect = [n0 * g.omega * (n[a] - 1) * L[a] / (2 * n[a]) for a in range(3)]
+    np.testing.assert_allclose(d, expect, rtol=1e-14)
+    # one occupied grid point: d = dV n_j r_j
+    rho = np.zeros(n)
+    rho[2, 5, 7] = 1.7
+    np.testing.assert_allclose(ko.dipole(g, rho), [g.dV * 1.7 * 2 * L[0] / n[0], g.dV * 1.7 * 5 * L[1] / n[1],
+                                                   g.dV * 1.7 * 7 * L[2] / n[2]], rtol=1e-14)
