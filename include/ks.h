@@ -142,6 +142,15 @@ ks_status ks_density(ks_system* sys, int norb, const void* psi, const double* oc
 ks_status ks_hartree(ks_system* sys, const double* rho, double* v, int add_vloc, void* stream);
 
 /*
+ * Dipole moment, the first moment of the density (Section "Results", the
+ * optical response of a kicked molecule): d_a = dV sum_r r_a rho(r) with grid
+ * positions r_a = j_a L_a / n_a.  rho: device float64 [n0][n1][n2]; d: device
+ * float64 [3].  Fixed summation order (deterministic).  KS_EINVAL on null
+ * arguments.
+ */
+ks_status ks_dipole(ks_system* sys, const double* rho, double* d, void* stream);
+
+/*
  * Orbital norms and band energy (energy expression of Section "DFT and TDDFT
  * implementation" reduced to sum_k f_k <psi_k|H|psi_k> for a static potential):
  *   norms[i] = sum_G |c_iG|^2 over the sphere           (device float64 [norb])
@@ -203,6 +212,15 @@ ks_status ks_state_propagate(ks_state* state, double dt, int nsteps, const doubl
  */
 ks_status ks_state_propagate_etrs(ks_state* state, double dt, int nsteps, const double* occ, double* rho,
                                   double* norms, void* stream);
+/*
+ * Field kick at t = 0 (the propagator of v_pert = -k.r delta(t) in Eq.
+ * hamiltonian): every resident orbital becomes exp(i k.r) psi(r) with grid
+ * positions r_a = j_a L_a / n_a, projected on the plane-wave sphere.  k: host
+ * array of 3 (bohr^-1).  One orbital at a time through the system's work box
+ * (a set-up operation, not the hot path).  KS_EINVAL: null state or k, or a
+ * non-finite k.
+ */
+ks_status ks_state_kick(ks_state* state, const double k[3], void* stream);
 /* As ks_reduce, on the resident orbitals. */
 ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, double* energy, void* stream);
 /*

@@ -1,4 +1,7 @@
-// Periodic Hartree potential of a density on the full FFT box (HIP, gfx950):
+// Full-box transforms (HIP, gfx950): the periodic Hartree potential of a
+// density, the field kick of the orbitals, and the dipole moment.
+//
+// Periodic Hartree potential of a density on the full FFT box:
 // V_H(G) = 4 pi n(G) / |G|^2 for G != 0 and 0 at G = 0 (Section "Poisson
 // solver", periodic boundary conditions), with n(G) = N^-1 sum_r n(r)
 // e^{-iG.r} and V_H(r) = sum_G V_H(G) e^{+iG.r}.
@@ -90,7 +93,103 @@ __global__ __launch_bounds__(NT) void hx_kernel(double2* __restrict__ W, int n1,
       X, N0 + 1, nt, tw, no_load{}, [&](int t, int e, double2 v, int, int) { base[(long long)e * npl + t] = v; });
 }
 
-// ------------------------------------------------------------------ launcher
+// z rows of a complex box in place (rows staged in LDS, coalesced).
+template <int N2, int SIGN>
+__global__ __launch_bounds__(NT) void hzc_kernel(double2* __restrict__ W, const double2* __restrict__ tw0,
+                                                 long long nrows) {
+  __shared__ double2 X[HNB * (N2 + 1)];
+  __shared__ double2 tw[N2];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N2; i += NT) tw[i] = tw0[i];
+  const long long row0 = (long long)blockIdx.x * HNB;
+  const int nr = (nrows - row0) < HNB ? (int)(nrows - row0) : HNB;
+  double2* base = W + row0 * N2;
+  for (int i = tid; i < nr * N2; i += NT) {
+    const int r = i / N2, e = i - r * N2;
+    X[r * (N2 + 1) + e] = base[i];
+  }
+  __syncthreads();
+  fft_batch<N2, SIGN, HNB, NT, double2>(X, N2 + 1, nr, tw);
+  for (int i = tid; i < nr * N2; i += NT) {
+    const int r = i / N2, e = i - r * N2;
+    base[i] = X[r * (N2 + 1) + e];
+  }
+}
+
+// Field kick, x part: synthesis along x, then psi(r) *= exp(i k.r) / N with
+// r = (j0 h0, j1 h1, j2 h2), then analysis along x; in place.  The y and z
+// transforms around it complete the 3-D synthesis and analysis.
+template <int N0>
+__global__ __launch_bounds__(NT) void hx_kick_kernel(double2* __restrict__ W, int n1, int n2, double k0, double k1,
+                                                     double k2, double h0, double h1, double h2, double scale,
+                                                     const double2* __restrict__ tw0) {
+  __shared__ double2 X[HNB * (N0 + 1)];
+  __shared__ double2 tw[N0];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
+  const int npl = n1 * n2;
+  const int p0 = blockIdx.x * HNB;
+  const int nt = npl - p0 < HNB ? npl - p0 : HNB;
+  double2* base = W + p0;
+  __syncthreads();
+  fft_io<N0, +1, HNB, NT, SRC_FN, DST_LDS, double2>(
+      X, N0 + 1, nt, tw, [&](int t, int e) -> double2 { return base[(long long)e * npl + t]; }, no_store{});
+  for (int i = tid; i < nt * N0; i += NT) {
+    const int t = i / N0, e = i - t * N0;
+    const int p = p0 + t, j1 = p / n2, j2 = p - j1 * n2;
+    const double th = k0 * (e * h0) + k1 * (j1 * h1) + k2 * (j2 * h2);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    double2& x = X[t * (N0 + 1) + e];
+    x = double2{scale * (x.x * cs - x.y * sn), scale * (x.x * sn + x.y * cs)};
+  }
+  __syncthreads();
+  fft_io<N0, -1, HNB, NT, SRC_LDS, DST_FN, double2>(
+      X, N0 + 1, nt, tw, no_load{}, [&](int t, int e, double2 v, int, int) { base[(long long)e * npl + t] = v; });
+}
+
+// Dipole moment: dV sum_r r_a rho(r).  Each block sums a contiguous range of
+// points (fixed order within the block: per-thread strided sums, then a tree
+// over the threads); dipole_sum adds the block partials in order.
+constexpr int DIP_BLOCKS = 256;
+
+__global__ __launch_bounds__(NT) void dipole_part_kernel(const double* __restrict__ rho, int n0, int n1, int n2,
+                                                         double h0, double h1, double h2,
+                                                         double* __restrict__ part) {
+  __shared__ double red[3][NT];
+  const long long N = (long long)n0 * n1 * n2;
+  const long long per = (N + DIP_BLOCKS - 1) / DIP_BLOCKS;
+  const long long a = blockIdx.x * per, b = a + per < N ? a + per : N;
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (long long i = a + threadIdx.x; i < b; i += NT) {
+    const long long j12 = i % ((long long)n1 * n2);
+    const int j0 = (int)(i / ((long long)n1 * n2)), j1 = (int)(j12 / n2), j2 = (int)(j12 % n2);
+    const double v = rho[i];
+    sx += v * (j0 * h0);
+    sy += v * (j1 * h1);
+    sz += v * (j2 * h2);
+  }
+  red[0][threadIdx.x] = sx;
+  red[1][threadIdx.x] = sy;
+  red[2][threadIdx.x] = sz;
+  __syncthreads();
+  for (int m = NT / 2; m > 0; m >>= 1) {
+    if ((int)threadIdx.x < m)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + m];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void dipole_sum_kernel(const double* __restrict__ part, double dV, double* __restrict__ d) {
+  const int c = threadIdx.x;
+  if (c >= 3) return;
+  double s = 0.0;
+  for (int b = 0; b < DIP_BLOCKS; ++b) s += part[b * 3 + c];
+  d[c] = dV * s;
+}
+
+// ------------------------------------------------------------------ launchers
 
 template <int N1>
 static void hartree_yz(const ks_system* s, const double* rho, double2* W, double* v, const double* vloc, int sign,
@@ -137,6 +236,62 @@ bool launch_hartree(const ks_system* s, const double* rho, double* v, const doub
       return false;
   }
   return yz_pass(s, nullptr, W, v, vloc, +1, st);
+}
+
+}  // namespace ks
+
+namespace ks {
+
+template <int N1>
+static void kick_yz(const ks_system* s, double2* W, int sign, hipStream_t st) {
+  const long long nrows = (long long)s->n[0] * s->n[1];
+  const unsigned zblocks = (unsigned)((nrows + HNB - 1) / HNB);
+  const unsigned yblocks = (unsigned)(s->n[0] * ((s->n[2] + HNB - 1) / HNB));
+  if (sign > 0) {
+    hzc_kernel<N1, +1><<<zblocks, NT, 0, st>>>(W, s->d_tw1, nrows);
+    hy_kernel<N1, +1><<<yblocks, NT, 0, st>>>(W, s->n[2], s->d_tw1);
+  } else {
+    hy_kernel<N1, -1><<<yblocks, NT, 0, st>>>(W, s->n[2], s->d_tw1);
+    hzc_kernel<N1, -1><<<zblocks, NT, 0, st>>>(W, s->d_tw1, nrows);
+  }
+}
+
+template <int N0>
+static void kick_x(const ks_system* s, double2* W, const double k[3], hipStream_t st) {
+  const int npl = s->n[1] * s->n[2];
+  hx_kick_kernel<N0><<<(unsigned)((npl + HNB - 1) / HNB), NT, 0, st>>>(
+      W, s->n[1], s->n[2], k[0], k[1], k[2], s->L[0] / s->n[0], s->L[1] / s->n[1], s->L[2] / s->n[2],
+      1.0 / (double)s->N, s->d_tw0);
+}
+
+static bool kick_yz_pass(const ks_system* s, double2* W, int sign, hipStream_t st) {
+  switch (s->n[1]) {
+#define KS_CASE(c) case c: kick_yz<c>(s, W, sign, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+bool launch_kick(const ks_system* s, double2* W, const double k[3], hipStream_t st) {
+  if (!kick_yz_pass(s, W, +1, st)) return false;
+  switch (s->n[0]) {
+#define KS_CASE(c) case c: kick_x<c>(s, W, k, st); break;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+  return kick_yz_pass(s, W, -1, st);
+}
+
+bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t st) {
+  double* part = reinterpret_cast<double*>(s->d_hbox);   // 3 * DIP_BLOCKS doubles of the work box
+  dipole_part_kernel<<<DIP_BLOCKS, NT, 0, st>>>(rho, s->n[0], s->n[1], s->n[2], s->L[0] / s->n[0],
+                                                s->L[1] / s->n[1], s->L[2] / s->n[2], part);
+  dipole_sum_kernel<<<1, 64, 0, st>>>(part, s->dV, d);
+  return true;
 }
 
 }  // namespace ks

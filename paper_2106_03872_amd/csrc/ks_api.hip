@@ -818,6 +818,12 @@ ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, v
   return launch_ok(s, true, "hartree");
 }
 
+ks_status ks_dipole(ks_system* s, const double* rho, double* d, void* stream) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (!rho || !d) return fail(s, KS_EINVAL, "rho or d is null");
+  return launch_ok(s, launch_dipole(s, rho, d, (hipStream_t)stream), "dipole");
+}
+
 ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, double* norms, double* energy,
                     void* stream) {
   ks_status r = check_common(s, norb);
@@ -1037,6 +1043,22 @@ ks_status ks_state_propagate_etrs(ks_state* t, double dt, int nsteps, const doub
       hipMemcpyAsync(s->d_v, s->d_vloc, s->N * sizeof(double), hipMemcpyDeviceToDevice, st);
   if (r != KS_OK) return r;
   if (e != hipSuccess) return fail(s, KS_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  return KS_OK;
+}
+
+ks_status ks_state_kick(ks_state* t, const double k[3], void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (!k || !std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
+    return fail(s, KS_EINVAL, "k must be three finite numbers");
+  hipStream_t st = (hipStream_t)stream;
+  ks_status r;
+  for (int o = 0; o < t->norb; ++o) {
+    double2* c = t->data + (size_t)o * s->npw_stride;
+    if ((r = launch_ok(s, launch_unpack(s, 1, c, true, s->d_hbox, s->N, st), "unpack")) != KS_OK) return r;
+    if ((r = launch_ok(s, launch_kick(s, s->d_hbox, k, st), "kick")) != KS_OK) return r;
+    if ((r = launch_ok(s, launch_pack(s, 1, s->d_hbox, s->N, c, st), "pack")) != KS_OK) return r;
+  }
   return KS_OK;
 }
 

@@ -176,6 +176,11 @@ bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, i
 // v = V_H[rho] (+ vloc when not null); uses the system's work box
 bool launch_hartree(const ks_system* s, const double* rho, double* v, const double* vloc, hipStream_t st);
 
+// psi <- chi exp(i k.r) psi for one orbital held on the complex box W (in place)
+bool launch_kick(const ks_system* s, double2* W, const double k[3], hipStream_t st);
+// d[0..2] = dV sum_r r rho(r) (device output; uses the work box for partial sums)
+bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t st);
+
 bool supported_size(int n);
 int x_tile_nb(int n0);
 size_t plane_lds_bytes(const ks_system* s);

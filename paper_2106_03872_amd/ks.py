@@ -76,6 +76,8 @@ def _load():
         "ks_state_propagate": (I, [P, D, I, P, P, P, P]),
         "ks_state_propagate_etrs": (I, [P, D, I, P, P, P, P]),
         "ks_hartree": (I, [P, P, P, I, P]),
+        "ks_dipole": (I, [P, P, P, P]),
+        "ks_state_kick": (I, [P, ctypes.POINTER(D), P]),
         "ks_state_reduce": (I, [P, P, P, P, P]),
         "ks_state_capture": (I, [P, D, P, P, P]),
         "ks_state_replay": (I, [P, P]),
@@ -240,6 +242,14 @@ class System:
                                     _ptr(out, torch.float64, self.n, "out"), int(bool(add_vloc)), _stream()))
         return out
 
+    def dipole(self, rho):
+        """Dipole moment dV sum_r r rho(r) of a density (float64 box on the
+        device); returns a float64 tensor of 3 on the device."""
+        import torch
+        d = torch.empty(3, dtype=torch.float64, device="cuda")
+        self._check(_lib.ks_dipole(self._h, _ptr(rho, torch.float64, self.n, "rho"), _ptr(d, torch.float64), _stream()))
+        return d
+
     def set_kernel_timing(self, enable=True):
         self._check(_lib.ks_set_kernel_timing(self._h, int(bool(enable))))
 
@@ -370,6 +380,11 @@ class State:
         self.system._check(_lib.ks_state_propagate(
             self._h, float(dt), int(nsteps), _ptr(occ, torch.float64, (self.norb,), "occ"),
             _ptr(rho, torch.float64, None, "rho"), _ptr(norms, torch.float64, None, "norms"), self._st(stream)))
+
+    def kick(self, k, stream=None):
+        """psi <- exp(i k.r) psi for every resident orbital (field kick at t = 0)."""
+        kk = (ctypes.c_double * 3)(*[float(x) for x in k])
+        self.system._check(_lib.ks_state_kick(self._h, kk, self._st(stream)))
 
     def propagate_etrs(self, dt, nsteps, occ, rho=None, norms=None, stream=None):
         """nsteps ETRS steps under the density-dependent Hamiltonian

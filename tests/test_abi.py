@@ -58,6 +58,8 @@ def test_null_system_calls_fail_cleanly():
     assert lib.ks_propagate_step(None, 1, None, 0.1, 1, None, None, None) == ks.KS_EINVAL
     assert lib.ks_autotune(None, 1, None, None) == ks.KS_EINVAL
     assert lib.ks_hartree(None, None, None, 0, None) == ks.KS_EINVAL
+    assert lib.ks_dipole(None, None, None, None) == ks.KS_EINVAL
+    assert lib.ks_state_kick(None, None, None) == ks.KS_EINVAL
     assert lib.ks_state_propagate_etrs(None, 0.1, 1, None, None, None, None) == ks.KS_EINVAL
     assert lib.ks_system_set_tuning(None, None) == ks.KS_EINVAL
     lib.ks_system_destroy(None)

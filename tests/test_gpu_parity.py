@@ -383,3 +383,50 @@ def test_etrs_parity(ks, name):
     a = gs.ham_apply(c)
     assert rel_err(a.cpu().numpy(), ko.ham_apply(ham, c0)) < TOL
     st.close()
+
+
+# --------------------------------------------------- kick and dipole (NEXT-3)
+
+@pytest.mark.parametrize("name", ["t24", "t32x", "t48"])
+def test_kick_and_dipole_parity(ks, name):
+    spec, sysm = _case(name)
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    c0 = c.cpu().numpy()
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    k = (0.05, -0.02, 0.11)
+    st.kick(k)
+    ref = ko.kick(ham.grid, c0, k)
+    got = st.download().cpu().numpy()
+    assert rel_err(got, ref) < TOL
+    occ_np = np.linspace(0.5, 2.0, spec.norb)
+    rho = gs.density(torch.from_numpy(got).cuda(), torch.from_numpy(occ_np).cuda())
+    d = gs.dipole(rho).cpu().numpy()
+    dr = ko.dipole(ham.grid, ko.density(ham, ref, occ_np))
+    assert np.max(np.abs(d - dr)) < TOL * np.max(np.abs(dr))
+    st.close()
+
+
+def test_kicked_etrs_dipole_series(ks):
+    # the optical-response workload: kick at t = 0, ETRS steps, dipole per step
+    spec, sysm = _case("t24")
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    c = c / torch.sqrt(torch.from_numpy(ko.norms(ham, c.cpu().numpy())).cuda()).reshape(-1, 1, 1, 1)
+    c0 = c.cpu().numpy()
+    occ_np = np.full(spec.norb, 2.0)
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    k = (0.0, 0.0, 0.01)
+    st.kick(k)
+    K = 3
+    rho = torch.empty((K,) + spec.n, dtype=torch.float64, device="cuda")
+    st.propagate_etrs(spec.dt, K, torch.from_numpy(occ_np).cuda(), rho)
+    d = torch.stack([gs.dipole(rho[s]) for s in range(K)]).cpu().numpy()
+    _, dens = ko.etrs_step(ham, ko.kick(ham.grid, c0, k), spec.dt, occ_np, nsteps=K)
+    dr = np.array([ko.dipole(ham.grid, x) for x in dens])
+    assert np.max(np.abs(d - dr)) < TOL * np.max(np.abs(dr))
+    st.close()
