@@ -290,3 +290,107 @@ def dipole(grid, n):
     return np.array([grid.dV * np.sum(n * x[0][:, None, None]),
                      grid.dV * np.sum(n * x[1][None, :, None]),
                      grid.dV * np.sum(n * x[2][None, None, :])])
+
+
+# ------------------------------------------------- ground state (Section "Ground-state solution")
+
+def teter(x):
+    """Preconditioner factor of Teter, Payne and Allan (applied in Fourier
+    space, Section "Ground-state solution"):
+    ``K(x) = (27 + 18x + 12x^2 + 8x^3) / (27 + 18x + 12x^2 + 8x^3 + 16x^4)``,
+    ``x`` the kinetic energy of a plane wave over a reference kinetic energy."""
+    x = np.asarray(x, np.float64)
+    num = 27.0 + 18.0 * x + 12.0 * x ** 2 + 8.0 * x ** 3
+    return num / (num + 16.0 * x ** 4)
+
+
+def canonical_phases(Q):
+    """Scale each column of ``Q`` by a unit phase so that its entry of largest
+    modulus (the first one on ties) is real and positive."""
+    Q = np.array(Q, np.complex128)
+    for j in range(Q.shape[1]):
+        k = int(np.argmax(np.abs(Q[:, j])))
+        m = abs(Q[k, j])
+        Q[:, j] *= np.conj(Q[k, j]) / m
+        Q[k, j] = m
+    return Q
+
+
+def subspace_rotation(ham, c, w):
+    """Subspace diagonalisation (Section "Ground-state solution"): the
+    Rayleigh-Ritz matrix ``Hs = C^H (H C)`` of the orthonormal orbitals ``c``
+    (``w = H c``), made exactly Hermitian, ``Hs = Q diag(e) Q^H`` with ``e``
+    ascending and the phases of :func:`canonical_phases`; returns
+    ``(C Q, W Q, e)``."""
+    nb = c.shape[0]
+    C = np.where(ham.grid.chi, c, 0.0).reshape(nb, -1)
+    W = np.asarray(w, np.complex128).reshape(nb, -1)
+    Hs = C.conj() @ W.T                       # Hs[i, j] = <c_i | H c_j>
+    Hs = 0.5 * (Hs + Hs.conj().T)
+    e, Q = np.linalg.eigh(Hs)
+    Q = canonical_phases(Q)
+    return (Q.T @ C).reshape(c.shape), (Q.T @ W).reshape(c.shape), e
+
+
+def sd_direction(ham, c, w, e):
+    """Preconditioned steepest-descent direction of each orbital:
+    residual ``r = H c - e c``; reference kinetic energy
+    ``T = sum K |r|^2 / sum |r|^2`` of the residual (``K = |G|^2/2``);
+    ``p = teter(K / T) r`` (``p = r`` when ``T = 0``, ``p = 0`` when
+    ``r = 0``); ``p <- p - <c|p> c``.  Returns ``(p, |r|)``."""
+    g = ham.grid
+    c = np.where(g.chi, c, 0.0)
+    r = np.where(g.chi, w - e[:, None, None, None] * c, 0.0)
+    ax = (-3, -2, -1)
+    rr = np.sum(np.abs(r) ** 2, axis=ax)
+    kr = np.sum(g.K * np.abs(r) ** 2, axis=ax)
+    p = np.zeros_like(r)
+    for i in range(c.shape[0]):
+        if rr[i] == 0.0:
+            continue
+        T = kr[i] / rr[i]
+        p[i] = r[i] if T <= 0.0 else teter(g.K / T) * r[i]
+        p[i] = np.where(g.chi, p[i], 0.0)
+        p[i] -= np.vdot(c[i], p[i]) * c[i]
+    return p, np.sqrt(rr)
+
+
+def sd_iteration(ham, c):
+    """One iteration of the preconditioned steepest-descent eigensolver
+    (Section "Ground-state solution") on orthonormal orbitals ``c``:
+
+    1. ``W = H C``; subspace diagonalisation (:func:`subspace_rotation`)
+       gives the Ritz values ``e``;
+    2. per orbital the direction ``p`` of :func:`sd_direction`, normalised
+       to ``q``;
+    3. exact line minimisation of the Rayleigh quotient over the span of
+       ``c`` and ``q``: the lowest eigenvector ``y`` (``|y| = 1``, ``y_0``
+       real and non-negative; ``y_1`` real and positive when ``y_0 = 0``) of
+       ``[[e, <c|Hq>], [<q|Hc>, <q|Hq>]]``, and ``c <- y_0 c + y_1 q``
+       (unchanged when ``p = 0``);
+    4. orthonormalisation (:func:`orthonormalize`).
+
+    Returns ``(c, e, |r|)``."""
+    g = ham.grid
+    c = np.where(g.chi, np.asarray(c, np.complex128), 0.0)
+    w = ham_apply(ham, c)
+    c, w, e = subspace_rotation(ham, c, w)
+    p, rn = sd_direction(ham, c, w, e)
+    ax = (-3, -2, -1)
+    u = np.sum(np.abs(p) ** 2, axis=ax)
+    live = u > 0.0
+    q = np.zeros_like(p)
+    q[live] = p[live] / np.sqrt(u[live])[:, None, None, None]
+    hq = ham_apply(ham, q)
+    out = c.copy()
+    for i in np.nonzero(live)[0]:
+        b = np.vdot(c[i], hq[i])
+        d = np.vdot(q[i], hq[i]).real
+        lam, Y = np.linalg.eigh(np.array([[e[i], b], [np.conj(b), d]]))
+        y = Y[:, 0]
+        if abs(y[0]) > 0.0:
+            y = y * np.conj(y[0]) / abs(y[0])
+        else:
+            y = y * np.conj(y[1]) / abs(y[1])
+        out[i] = y[0] * c[i] + y[1] * q[i]
+    return orthonormalize(ham, out), e, rn

@@ -508,3 +508,141 @@ def test_dipole_closed_forms():
     rho[2, 5, 7] = 1.7
     np.testing.assert_allclose(ko.dipole(g, rho), [g.dV * 1.7 * 2 * L[0] / n[0], g.dV * 1.7 * 5 * L[1] / n[1],
                                                    g.dV * 1.7 * 7 * L[2] / n[2]], rtol=1e-14)
+
+
+# ------------------------------------------------- ground-state SD eigensolver
+
+def test_teter_geometric_form_and_limits():
+    # 27 + 18x + 12x^2 + 8x^3 = 27 (1 + y + y^2 + y^3) and 16 x^4 = 81 y^4 with
+    # y = 2x/3, so K = (1 - y^4) / (1 + 2 y^4 - 3 y^5) away from y = 1
+    x = np.concatenate([np.linspace(0.0, 1.4, 57), np.linspace(1.6, 40.0, 97)])
+    y = 2.0 * x / 3.0
+    np.testing.assert_allclose(ko.teter(x), (1 - y ** 4) / (1 + 2 * y ** 4 - 3 * y ** 5), rtol=1e-13)
+    # K = 1 - (16/27) x^4 + O(x^5) at low energy, K ~ 1/(2x) at high energy
+    xs = 1e-3
+    assert abs((1.0 - ko.teter(xs)) / xs ** 4 - 16.0 / 27.0) < 1e-2
+    assert abs(2e6 * ko.teter(1e6) - 1.0) < 1e-5
+    assert ko.teter(0.0) == 1.0
+    assert np.all(np.diff(ko.teter(np.linspace(0, 50, 501))) < 0)
+
+
+def _chi_eigen(g, ham):
+    """Eigenpairs of the dense Hamiltonian on the sphere, embedded in the box."""
+    H = _dense_H(g, ham)
+    sel = g.chi.ravel()
+    lam, V = np.linalg.eigh(H[np.ix_(sel, sel)])
+    full = np.zeros((g.N, V.shape[1]), np.complex128)
+    full[sel] = V
+    return H, lam, full
+
+
+def _random_orthonormal(g, ham, norb, seed):
+    return ko.orthonormalize(ham, _rand_c(_rng(seed), (norb,) + g.n))
+
+
+def test_subspace_rotation_diagonalises_on_the_dense_hamiltonian():
+    g, ham = _tiny_system((6, 5, 6), (3.0, 3.5, 4.0), 10.0, seed=31)
+    H = _dense_H(g, ham)
+    c = _random_orthonormal(g, ham, 5, 32)
+    cr, wr, e = ko.subspace_rotation(ham, c, ko.ham_apply(ham, c))
+    C = cr.reshape(5, -1)
+    Hs = C.conj() @ H @ C.T
+    np.testing.assert_allclose(Hs, np.diag(e), atol=1e-11 * np.abs(H).max())
+    assert np.all(np.diff(e) > 0)
+    np.testing.assert_allclose(C.conj() @ C.T, np.eye(5), atol=1e-13)
+    np.testing.assert_allclose(wr.reshape(5, -1), C @ H.T, atol=1e-11 * np.abs(H).max())
+    # same span: the projectors on the two subspaces agree
+    C0 = c.reshape(5, -1)
+    np.testing.assert_allclose(C.T @ C.conj(), C0.T @ C0.conj(), atol=1e-12)
+
+
+def test_canonical_phases():
+    rng = _rng(33)
+    Q, _ = np.linalg.qr(_rand_c(rng, (7, 7)))
+    P = ko.canonical_phases(Q)
+    for j in range(7):
+        k = np.argmax(np.abs(P[:, j]))
+        assert P[k, j].imag == 0.0 and P[k, j].real > 0
+        ratio = P[:, j] / Q[:, j]
+        np.testing.assert_allclose(np.abs(ratio), 1.0, rtol=1e-14)
+        np.testing.assert_allclose(ratio, ratio[0], rtol=1e-13)
+
+
+def test_sd_direction_two_plane_waves_by_hand():
+    """Free electrons, c = a e1 + b e2: the Ritz value, residual, its kinetic
+    energy and the preconditioned, orthogonalised direction by hand."""
+    g = ko.Grid((8, 8, 8), (5.0, 5.0, 5.0), 12.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    j1, j2 = (1, 0, 0), (2, 1, 7)
+    K1 = 0.5 * (2 * np.pi / 5.0) ** 2 * 1
+    K2 = 0.5 * (2 * np.pi / 5.0) ** 2 * (4 + 1 + 1)
+    assert g.chi[j1] and g.chi[j2]
+    a, b = 0.8, 0.6j
+    c = np.zeros((1,) + g.n, np.complex128)
+    c[(0,) + j1], c[(0,) + j2] = a, b
+    e = abs(a) ** 2 * K1 + abs(b) ** 2 * K2
+    _, _, ee = ko.subspace_rotation(ham, c, ko.ham_apply(ham, c))
+    assert abs(ee[0] - e) < 1e-13
+    r1, r2 = a * (K1 - e), b * (K2 - e)
+    T = (K1 * abs(r1) ** 2 + K2 * abs(r2) ** 2) / (abs(r1) ** 2 + abs(r2) ** 2)
+    p1, p2 = ko.teter(K1 / T) * r1, ko.teter(K2 / T) * r2
+    cp = np.conj(a) * p1 + np.conj(b) * p2
+    p1, p2 = p1 - cp * a, p2 - cp * b
+    p, rn = ko.sd_direction(ham, c, ko.ham_apply(ham, c), np.array([e]))
+    assert abs(rn[0] - math.hypot(abs(r1), abs(r2))) < 1e-13
+    assert abs(p[(0,) + j1] - p1) < 1e-13 and abs(p[(0,) + j2] - p2) < 1e-13
+    p[(0,) + j1] = p[(0,) + j2] = 0
+    assert np.abs(p).max() == 0
+
+
+def test_sd_line_minimum_bruteforce():
+    """One orbital: the update minimises the Rayleigh quotient over the span of
+    the orbital and its direction (checked on a dense grid of complex steps)."""
+    g, ham = _tiny_system((6, 6, 5), (3.5, 3.5, 3.0), 12.0, seed=34)
+    H = _dense_H(g, ham)
+    c = _random_orthonormal(g, ham, 1, 35)
+    new, e, _ = ko.sd_iteration(ham, c)
+    p, _ = ko.sd_direction(ham, c, ko.ham_apply(ham, c), e)
+    cv, pv, nv = c.ravel(), p.ravel(), new.ravel()
+
+    def R(v):
+        return (np.vdot(v, H @ v) / np.vdot(v, v)).real
+
+    r_new = R(nv)
+    assert r_new < e[0]
+    # the new orbital lies in span{c, p}
+    B = np.stack([cv, pv], 1)
+    coef, *_ = np.linalg.lstsq(B, nv, rcond=None)
+    assert np.linalg.norm(B @ coef - nv) < 1e-12
+    s = np.linspace(-4, 4, 161) * abs(coef[1] / coef[0])
+    best = min(R(cv + (x + 1j * y) * pv) for x in s for y in s)
+    assert r_new <= best + 1e-12
+    assert best - r_new < 1e-3 * (e[0] - r_new)
+
+
+def test_sd_keeps_an_invariant_subspace():
+    g, ham = _tiny_system((5, 6, 6), (3.0, 3.5, 3.5), 11.0, seed=36)
+    _, lam, V = _chi_eigen(g, ham)
+    rng = _rng(37)
+    U, _ = np.linalg.qr(_rand_c(rng, (4, 4)))
+    c = (U.T @ V[:, :4].T).reshape((4,) + g.n)            # mixed exact eigenvectors
+    new, e, rn = ko.sd_iteration(ham, c)
+    np.testing.assert_allclose(e, lam[:4], atol=1e-11 * np.abs(lam).max())
+    assert rn.max() < 1e-10
+    ov = np.abs(new.reshape(4, -1).conj() @ V[:, :4])
+    np.testing.assert_allclose(ov, np.eye(4), atol=1e-10)
+
+
+def test_sd_converges_to_the_lowest_dense_eigenvalues():
+    g, ham = _tiny_system((6, 6, 6), (3.5, 3.5, 3.5), 9.0, seed=38, natoms=2, npts=20)
+    _, lam, V = _chi_eigen(g, ham)
+    c = _random_orthonormal(g, ham, 4, 39)
+    hist = []
+    for _ in range(150):
+        c, e, rn = ko.sd_iteration(ham, c)
+        hist.append(np.sum(e))
+    assert np.all(np.diff(hist[5:]) < 1e-10)                # settles monotonically
+    np.testing.assert_allclose(e, lam[:4], atol=1e-8)
+    assert rn.max() < 1e-4
+    ov = np.linalg.svd(c.reshape(4, -1).conj() @ V[:, :4], compute_uv=False)
+    assert ov.min() > 1 - 1e-8                               # same occupied subspace
