@@ -221,6 +221,33 @@ ks_status ks_state_propagate_etrs(ks_state* state, double dt, int nsteps, const 
  * non-finite k.
  */
 ks_status ks_state_kick(ks_state* state, const double k[3], void* stream);
+/*
+ * niter iterations of the preconditioned steepest-descent eigensolver
+ * (Section "Ground-state solution") for the lowest norb eigenstates of the
+ * system's static Hamiltonian, on the resident orbitals, which must be
+ * orthonormal on entry (ks_orthonormalize) and are orthonormal on return.
+ * One iteration:
+ *   1. W = H C; subspace diagonalisation: the Rayleigh-Ritz matrix
+ *      C^H W, made exactly Hermitian, = Q diag(e) Q^H with e ascending and
+ *      each column of Q scaled so that its entry of largest modulus (the
+ *      first on ties) is real and positive; C <- C Q, W <- W Q;
+ *   2. per orbital: residual r = w - e c; T = sum_G K|r|^2 / sum_G |r|^2
+ *      with K = |G|^2/2; direction p = t(K/T) r with the Teter-Payne-Allan
+ *      factor t(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4) (p = r
+ *      when T = 0, p = 0 when r = 0); p <- p - <c|p> c; q = p/|p|;
+ *   3. exact line minimisation of the Rayleigh quotient over span{c, q}:
+ *      c <- y0 c + y1 q with y the lowest normalised eigenvector of
+ *      [[e, <c|Hq>], [<q|Hc>, <q|Hq>]], y0 real >= 0 (c unchanged when p = 0);
+ *   4. Cholesky orthonormalisation.
+ * eig and resid (NULL, or device float64 [niter][norb]) receive e and |r|
+ * of each iteration (the values at step 1-2, before the update).  FP64
+ * systems only.  The first call on a state allocates three more orbital
+ * blocks and 6 norb^2 complex entries; every iteration synchronises the
+ * stream (Jacobi convergence and the Cholesky status).  Errors: KS_EINVAL
+ * (null state, niter < 0, linearly dependent orbitals), KS_EUNSUPPORTED
+ * (mixed precision), KS_EDEVICE (Jacobi sweeps not converged, HIP errors).
+ */
+ks_status ks_state_eigensolve(ks_state* state, int niter, double* eig, double* resid, void* stream);
 /* As ks_reduce, on the resident orbitals. */
 ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, double* energy, void* stream);
 /*
@@ -338,7 +365,7 @@ ks_status ks_system_set_tuning(ks_system* sys, const ks_tuning* t);
 /* Kernel classes reported by ks_kernel_time. */
 typedef enum {
   KS_K_PACK = 0, KS_K_UNPACK, KS_K_PLANE_INV, KS_K_XPROJ, KS_K_PROJ_REDUCE, KS_K_XAPPLY,
-  KS_K_PLANE_FWD, KS_K_XDENS, KS_K_DOTS, KS_K_COUNT
+  KS_K_PLANE_FWD, KS_K_XDENS, KS_K_DOTS, KS_K_GEMM, KS_K_EIG, KS_K_SD, KS_K_COUNT
 } ks_kernel_id;
 
 /*

@@ -1,0 +1,389 @@
+// Ground-state eigensolver kernels (Section "Ground-state solution"): the
+// subspace diagonalisation (a Hermitian eigenproblem of the orbitals'
+// Rayleigh-Ritz matrix, solved by parallel cyclic Jacobi rotations) and the
+// per-orbital steps of the preconditioned steepest descent (residual, Teter
+// preconditioner, exact line minimisation over the orbital and its
+// direction).  All reductions run in a fixed order.
+#include "ks_internal.h"
+
+namespace ks {
+
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ double2 cconj(double2 a) { return double2{a.x, -a.y}; }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return double2{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return double2{a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------- Jacobi rotations
+//
+// Round t of a sweep pairs the m = n + (n odd) indices by the round-robin
+// tournament: pair 0 is (m-1, t), pair k > 0 is ((t+k) mod (m-1),
+// (t-k) mod (m-1)); over the m-1 rounds every index meets every other once.
+// An index >= n (odd n) is a dummy and is never rotated.
+
+__device__ __forceinline__ void round_pair(int t, int k, int m, int& p, int& q) {
+  int a, b;
+  if (k == 0) {
+    a = m - 1;
+    b = t;
+  } else {
+    a = (t + k) % (m - 1);
+    b = (t - k + m - 1) % (m - 1);
+  }
+  p = min(a, b);
+  q = max(a, b);
+}
+
+// Rotation J (2x2, acting on indices p < q) with (J^H A J)_pq = 0 for the
+// Hermitian block [[a, b], [conj(b), c]]: with b = |b| e^{i phi}, the phase
+// D = diag(1, e^{-i phi}) makes the block real, and the real symmetric
+// rotation [[cs, sn], [-sn, cs]] with t = tan(theta) the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = (c - a) / (2|b|), zeroes it; J = D R.
+struct Rot {
+  double cs, sn;
+  double2 e;   // e^{-i phi}
+  bool id;
+};
+
+__device__ __forceinline__ Rot make_rot(const double2* __restrict__ A, int n, int p, int q) {
+  Rot r{1.0, 0.0, double2{1.0, 0.0}, true};
+  if (q >= n) return r;
+  const double a = A[(long long)p * n + p].x, c = A[(long long)q * n + q].x;
+  const double2 b = A[(long long)p * n + q];
+  const double ab = sqrt(b.x * b.x + b.y * b.y);
+  if (ab == 0.0) return r;
+  const double tau = (c - a) / (2.0 * ab);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  r.cs = 1.0 / sqrt(1.0 + t * t);
+  r.sn = t * r.cs;
+  r.e = double2{b.x / ab, -b.y / ab};
+  r.id = false;
+  return r;
+}
+
+// J entries: J00 = cs, J01 = sn, J10 = -sn e, J11 = cs e
+__device__ __forceinline__ double2 jent(const Rot& r, int i, int j) {
+  if (r.id) return double2{i == j ? 1.0 : 0.0, 0.0};
+  if (i == 0) return double2{j == 0 ? r.cs : r.sn, 0.0};
+  return cscale(r.e, j == 0 ? -r.sn : r.cs);
+}
+
+// One round: An = J^H A J, Vn = Vt rotated (rows of Vt are the columns of
+// the accumulated eigenvector matrix V, V <- V J).  Threads [0, P^2) own the
+// 2x2 block (pair I, pair K) of A; threads [P^2, P^2 + P n) own (pair I,
+// column j) of Vt.  Reads A and Vt only, so the rotations of a round all
+// come from the same matrix.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const double2* __restrict__ A, double2* __restrict__ An,
+                                                           const double2* __restrict__ Vt, double2* __restrict__ Vn,
+                                                           int n, int m, int t) {
+  const int P = m / 2;
+  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g < (long long)P * P) {
+    const int I = (int)(g / P), K = (int)(g % P);
+    int pi[2], pk[2];
+    round_pair(t, I, m, pi[0], pi[1]);
+    round_pair(t, K, m, pk[0], pk[1]);
+    const Rot ri = make_rot(A, n, pi[0], pi[1]);
+    const Rot rk = make_rot(A, n, pk[0], pk[1]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (pi[i] >= n) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (pk[j] >= n) continue;
+        double2 s{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          if (pi[k] >= n) continue;
+          const double2 jk = cconj(jent(ri, k, i));
+#pragma unroll
+          for (int l = 0; l < 2; ++l) {
+            if (pk[l] >= n) continue;
+            s = cadd(s, cmul(jk, cmul(A[(long long)pi[k] * n + pk[l]], jent(rk, l, j))));
+          }
+        }
+        An[(long long)pi[i] * n + pk[j]] = s;
+      }
+    }
+    return;
+  }
+  g -= (long long)P * P;
+  if (g >= (long long)P * n) return;
+  const int I = (int)(g / n), col = (int)(g % n);
+  int pi[2];
+  round_pair(t, I, m, pi[0], pi[1]);
+  const Rot ri = make_rot(A, n, pi[0], pi[1]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (pi[i] >= n) continue;
+    double2 s{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (pi[k] >= n) continue;
+      s = cadd(s, cmul(jent(ri, k, i), Vt[(long long)pi[k] * n + col]));
+    }
+    Vn[(long long)pi[i] * n + col] = s;
+  }
+}
+
+// A = (H + H^H) / 2, Vt = I
+__global__ __launch_bounds__(256) void hermitize_kernel(const double2* __restrict__ H, double2* __restrict__ A,
+                                                        double2* __restrict__ Vt, int n) {
+  const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)n * n) return;
+  const int i = (int)(g / n), j = (int)(g % n);
+  const double2 x = H[(long long)i * n + j], y = H[(long long)j * n + i];
+  A[g] = double2{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+  Vt[g] = double2{i == j ? 1.0 : 0.0, 0.0};
+}
+
+constexpr int RED_NT = 256;
+
+// out[0] = sum_{i != j} |A_ij|^2, out[1] = sum |A_ij|^2 (one block, fixed order)
+__global__ __launch_bounds__(RED_NT) void offdiag_kernel(const double2* __restrict__ A, int n, double* __restrict__ out) {
+  __shared__ double s0[RED_NT], s1[RED_NT];
+  const int tid = threadIdx.x;
+  double off = 0.0, all = 0.0;
+  for (long long g = tid; g < (long long)n * n; g += RED_NT) {
+    const double2 a = A[g];
+    const double v = a.x * a.x + a.y * a.y;
+    all += v;
+    if (g / n != g % n) off += v;
+  }
+  s0[tid] = off;
+  s1[tid] = all;
+  __syncthreads();
+  for (int h = RED_NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      s0[tid] += s0[tid + h];
+      s1[tid] += s1[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
+  }
+}
+
+// Block i: eigenvalue lambda_i = A_ii goes to rank r_i (ascending; equal
+// values by index); row r_i of Q receives eigenvector i scaled by the unit
+// phase that makes its entry of largest modulus (the first on ties) real and
+// positive.
+__global__ __launch_bounds__(RED_NT) void eig_finish_kernel(const double2* __restrict__ A,
+                                                            const double2* __restrict__ Vt, int n,
+                                                            double* __restrict__ eig, double2* __restrict__ Q) {
+  __shared__ double sm[RED_NT];
+  __shared__ int si[RED_NT], sc[RED_NT];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const double li = A[(long long)i * n + i].x;
+  const double2* v = Vt + (long long)i * n;
+  double best = -1.0;
+  int bi = n, cnt = 0;
+  for (int j = tid; j < n; j += RED_NT) {
+    const double2 x = v[j];
+    const double mg = x.x * x.x + x.y * x.y;
+    if (mg > best) {
+      best = mg;
+      bi = j;
+    }
+    const double lj = A[(long long)j * n + j].x;
+    cnt += (lj < li || (lj == li && j < i)) ? 1 : 0;
+  }
+  sm[tid] = best;
+  si[tid] = bi;
+  sc[tid] = cnt;
+  __syncthreads();
+  for (int h = RED_NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      const double mo = sm[tid + h];
+      const int io = si[tid + h];
+      if (mo > sm[tid] || (mo == sm[tid] && io < si[tid])) {
+        sm[tid] = mo;
+        si[tid] = io;
+      }
+      sc[tid] += sc[tid + h];
+    }
+    __syncthreads();
+  }
+  const int k = si[0], r = sc[0];
+  const double2 vk = v[k];
+  const double mk = sqrt(vk.x * vk.x + vk.y * vk.y);
+  const double2 ph{vk.x / mk, -vk.y / mk};
+  double2* out = Q + (long long)r * n;
+  for (int j = tid; j < n; j += RED_NT) out[j] = (j == k) ? double2{mk, 0.0} : cmul(v[j], ph);
+  if (tid == 0) eig[r] = li;
+}
+
+// ------------------------------------------------------ steepest descent
+
+constexpr int SD_NT = 512;
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*sh)[SD_NT]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int a = 0; a < NV; ++a) sh[a][tid] = v[a];
+  __syncthreads();
+  for (int h = SD_NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+#pragma unroll
+      for (int a = 0; a < NV; ++a) sh[a][tid] += sh[a][tid + h];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = sh[a][0];
+  __syncthreads();
+}
+
+// Teter-Payne-Allan factor (27 + 18x + 12x^2 + 8x^3) / (same + 16x^4)
+__device__ __forceinline__ double teter(double x) {
+  const double x2 = x * x, x3 = x2 * x;
+  const double num = 27.0 + 18.0 * x + 12.0 * x2 + 8.0 * x3;
+  return num / (num + 16.0 * x2 * x2);
+}
+
+// Block o (one orbital): r = w - e c, T = sum K|r|^2 / sum |r|^2,
+// p = teter(K/T) r (p = r when T = 0, p = 0 when r = 0), p <- p - <c|p> c,
+// q = p / |p| (q = 0 when p = 0).  resid[o] = |r|.
+__global__ __launch_bounds__(SD_NT) void sd_direction_kernel(const double2* __restrict__ C, const double2* __restrict__ W,
+                                                             const double* __restrict__ e, const double* __restrict__ kin,
+                                                             double2* __restrict__ Qd, double* __restrict__ resid,
+                                                             int npw, int stride) {
+  __shared__ double sh[2][SD_NT];
+  const int o = blockIdx.x, tid = threadIdx.x;
+  const double2* c = C + (long long)o * stride;
+  const double2* w = W + (long long)o * stride;
+  double2* q = Qd + (long long)o * stride;
+  const double eo = e[o];
+  double v[2] = {0.0, 0.0};
+  for (int g = tid; g < npw; g += SD_NT) {
+    const double2 cg = c[g], wg = w[g];
+    const double2 r{wg.x - eo * cg.x, wg.y - eo * cg.y};
+    const double rr = r.x * r.x + r.y * r.y;
+    v[0] += rr;
+    v[1] += kin[g] * rr;
+  }
+  block_sum<2>(v, sh);
+  const double rr = v[0], kr = v[1];
+  if (tid == 0) resid[o] = sqrt(rr);
+  if (rr == 0.0) {
+    for (int g = tid; g < npw; g += SD_NT) q[g] = double2{0.0, 0.0};
+    return;
+  }
+  const double T = kr / rr;
+  const bool flat = !(T > 0.0);
+  const double invT = flat ? 0.0 : 1.0 / T;
+  double u[2] = {0.0, 0.0};
+  for (int g = tid; g < npw; g += SD_NT) {
+    const double2 cg = c[g], wg = w[g];
+    const double f = flat ? 1.0 : teter(kin[g] * invT);
+    const double2 p{f * (wg.x - eo * cg.x), f * (wg.y - eo * cg.y)};
+    u[0] += cg.x * p.x + cg.y * p.y;   // <c|p>
+    u[1] += cg.x * p.y - cg.y * p.x;
+  }
+  block_sum<2>(u, sh);
+  const double2 cp{u[0], u[1]};
+  double nn[1] = {0.0};
+  for (int g = tid; g < npw; g += SD_NT) {
+    const double2 cg = c[g], wg = w[g];
+    const double f = flat ? 1.0 : teter(kin[g] * invT);
+    const double2 p{f * (wg.x - eo * cg.x) - (cp.x * cg.x - cp.y * cg.y),
+                    f * (wg.y - eo * cg.y) - (cp.x * cg.y + cp.y * cg.x)};
+    nn[0] += p.x * p.x + p.y * p.y;
+  }
+  block_sum<1>(nn, sh);
+  const double s = nn[0] > 0.0 ? 1.0 / sqrt(nn[0]) : 0.0;
+  for (int g = tid; g < npw; g += SD_NT) {
+    const double2 cg = c[g], wg = w[g];
+    const double f = flat ? 1.0 : teter(kin[g] * invT);
+    const double2 p{f * (wg.x - eo * cg.x) - (cp.x * cg.x - cp.y * cg.y),
+                    f * (wg.y - eo * cg.y) - (cp.x * cg.y + cp.y * cg.x)};
+    q[g] = double2{p.x * s, p.y * s};
+  }
+}
+
+// Block o: beta = <c|Hq>, d = <q|Hq>; the lowest eigenvector y of
+// [[e, beta], [conj(beta), d]] (|y| = 1, y0 real >= 0; y1 real > 0 when
+// y0 = 0) replaces c by y0 c + y1 q.  Nothing changes when q = 0.
+__global__ __launch_bounds__(SD_NT) void sd_update_kernel(double2* __restrict__ C, const double2* __restrict__ Qd,
+                                                          const double2* __restrict__ HQ, const double* __restrict__ e,
+                                                          int npw, int stride) {
+  __shared__ double sh[4][SD_NT];
+  const int o = blockIdx.x, tid = threadIdx.x;
+  double2* c = C + (long long)o * stride;
+  const double2* q = Qd + (long long)o * stride;
+  const double2* hq = HQ + (long long)o * stride;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = tid; g < npw; g += SD_NT) {
+    const double2 cg = c[g], qg = q[g], hg = hq[g];
+    v[0] += cg.x * hg.x + cg.y * hg.y;   // <c|Hq>
+    v[1] += cg.x * hg.y - cg.y * hg.x;
+    v[2] += qg.x * hg.x + qg.y * hg.y;   // Re <q|Hq>
+    v[3] += qg.x * qg.x + qg.y * qg.y;   // |q|^2
+  }
+  block_sum<4>(v, sh);
+  if (v[3] == 0.0) return;
+  const double a = e[o], d = v[2];
+  const double2 b{v[0], v[1]};
+  const double bb = sqrt(b.x * b.x + b.y * b.y);
+  const double h = 0.5 * (a - d), rad = sqrt(h * h + bb * bb);
+  double y0;
+  double2 y1;
+  if (bb == 0.0) {
+    y0 = a <= d ? 1.0 : 0.0;
+    y1 = double2{a <= d ? 0.0 : 1.0, 0.0};
+  } else if (h <= 0.0) {
+    // a <= d: y = (d - lambda, -conj(b)), d - lambda = rad - h >= 0
+    y0 = rad - h;
+    y1 = double2{-b.x, b.y};
+  } else {
+    // a > d: y = (|b|, -(a - lambda) conj(b) / |b|), a - lambda = h + rad
+    y0 = bb;
+    const double s = -(h + rad) / bb;
+    y1 = double2{s * b.x, -s * b.y};
+  }
+  const double nrm = sqrt(y0 * y0 + y1.x * y1.x + y1.y * y1.y);
+  y0 /= nrm;
+  y1 = double2{y1.x / nrm, y1.y / nrm};
+  for (int g = tid; g < npw; g += SD_NT) {
+    const double2 cg = c[g], qg = q[g];
+    c[g] = double2{y0 * cg.x + (y1.x * qg.x - y1.y * qg.y), y0 * cg.y + (y1.x * qg.y + y1.y * qg.x)};
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+void launch_hermitize(int n, const double2* H, double2* A, double2* Vt, hipStream_t st) {
+  hermitize_kernel<<<(unsigned)(((long long)n * n + 255) / 256), 256, 0, st>>>(H, A, Vt, n);
+}
+
+void launch_jacobi_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, int t, hipStream_t st) {
+  const int m = n + (n & 1), P = m / 2;
+  const long long threads = (long long)P * P + (long long)P * n;
+  jacobi_round_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(A, An, Vt, Vn, n, m, t);
+}
+
+void launch_offdiag(int n, const double2* A, double* out, hipStream_t st) {
+  offdiag_kernel<<<1, RED_NT, 0, st>>>(A, n, out);
+}
+
+void launch_eig_finish(int n, const double2* A, const double2* Vt, double* eig, double2* Q, hipStream_t st) {
+  eig_finish_kernel<<<n, RED_NT, 0, st>>>(A, Vt, n, eig, Q);
+}
+
+void launch_sd_direction(int norb, int npw, int stride, const double2* C, const double2* W, const double* e,
+                         const double* kin, double2* Qd, double* resid, hipStream_t st) {
+  sd_direction_kernel<<<norb, SD_NT, 0, st>>>(C, W, e, kin, Qd, resid, npw, stride);
+}
+
+void launch_sd_update(int norb, int npw, int stride, double2* C, const double2* Qd, const double2* HQ, const double* e,
+                      hipStream_t st) {
+  sd_update_kernel<<<norb, SD_NT, 0, st>>>(C, Qd, HQ, e, npw, stride);
+}
+
+}  // namespace ks

@@ -542,6 +542,85 @@ ks_status etrs_packed(ks_system* s, ks_state* t, double dt, int nsteps, const do
   return KS_OK;
 }
 
+// Small matrices of the Cholesky orthonormalisation (max_norb^2), allocated
+// on first use.
+ks_status ensure_ortho_mats(ks_system* s) {
+  if (s->ortho_S) return KS_OK;
+  const size_t n = (size_t)s->max_norb;
+  ks_status r;
+  if ((r = dalloc(s, reinterpret_cast<void**>(&s->ortho_S), n * n * sizeof(double2))) != KS_OK ||
+      (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_W), n * n * sizeof(double2))) != KS_OK ||
+      (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK ||
+      (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_diag), n * sizeof(double))) != KS_OK) {
+    void* p[] = {s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
+    for (void* q : p) dfree(q);
+    s->ortho_S = s->ortho_W = nullptr;
+    s->ortho_info = nullptr;
+    s->ortho_diag = nullptr;
+    return r;
+  }
+  return KS_OK;
+}
+
+// Cholesky orthonormalisation of n packed FP64 orbitals C (stride npw_stride)
+// in place, through Y (n orbitals of scratch).  Synchronises the stream to
+// read the factorisation's status.
+ks_status orthonormalize_packed(ks_system* s, int n, double2* C, double2* Y, hipStream_t st) {
+  ks_status r;
+  const size_t ld = s->npw_stride;
+  KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
+  if ((r = kcall(s, KS_K_GEMM, st, "overlap", [&] { return launch_overlap(n, s->npw, C, ld, s->ortho_S, st); })) != KS_OK)
+    return r;
+  if ((r = launch_ok(s, launch_cholesky(n, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_trtri(n, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
+  if ((r = kcall(s, KS_K_GEMM, st, "apply", [&] { return launch_apply_lower(n, s->npw, s->ortho_W, C, ld, Y, st); })) !=
+      KS_OK)
+    return r;
+  int info = 0;
+  KS_HIP(s, hipMemcpyAsync(&info, s->ortho_info, sizeof(int), hipMemcpyDeviceToHost, st));
+  KS_HIP(s, hipStreamSynchronize(st));
+  if (info) return fail(s, KS_EINVAL, "overlap matrix is not positive definite (orbitals linearly dependent)");
+  KS_HIP(s, hipMemcpy2DAsync(C, ld * sizeof(double2), Y, ld * sizeof(double2), s->npw * sizeof(double2), n,
+                             hipMemcpyDeviceToDevice, st));
+  return KS_OK;
+}
+
+// Jacobi sweeps stop once the off-diagonal Frobenius norm is at most
+// JACOBI_TOL of the whole matrix's.
+constexpr double JACOBI_TOL = 1e-14;
+constexpr int JACOBI_MAX_SWEEPS = 60;
+
+// Eigenvalues (ascending, into eig) and eigenvectors (rows of Q, the phase
+// of each fixed so that its largest entry is real and positive) of the
+// Hermitian part of the n x n matrix H.  work: 4 n^2; off: 2 doubles.
+// Synchronises the stream once per Jacobi sweep.
+ks_status subspace_eigh(ks_system* s, int n, const double2* H, double2* work, double* off, double* eig, double2* Q,
+                        hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  double2 *A = work, *An = work + nn, *V = work + 2 * nn, *Vn = work + 3 * nn;
+  ks_status r;
+  if ((r = kcall(s, KS_K_EIG, st, "hermitize", [&] { launch_hermitize(n, H, A, V, st); return true; })) != KS_OK)
+    return r;
+  const int m = n + (n & 1);
+  bool done = n < 2;
+  for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS && !done; ++sweep) {
+    for (int t = 0; t < m - 1; ++t) {
+      if ((r = kcall(s, KS_K_EIG, st, "jacobi", [&] { launch_jacobi_round(n, A, An, V, Vn, t, st); return true; })) !=
+          KS_OK)
+        return r;
+      std::swap(A, An);
+      std::swap(V, Vn);
+    }
+    if ((r = kcall(s, KS_K_EIG, st, "offdiag", [&] { launch_offdiag(n, A, off, st); return true; })) != KS_OK) return r;
+    double h[2] = {0.0, 0.0};
+    KS_HIP(s, hipMemcpyAsync(h, off, sizeof(h), hipMemcpyDeviceToHost, st));
+    KS_HIP(s, hipStreamSynchronize(st));
+    done = h[0] <= JACOBI_TOL * JACOBI_TOL * h[1];
+  }
+  if (!done) return fail(s, KS_EDEVICE, "subspace eigensolver: Jacobi sweeps did not converge");
+  return kcall(s, KS_K_EIG, st, "eig_finish", [&] { launch_eig_finish(n, A, V, eig, Q, st); return true; });
+}
+
 }  // namespace
 
 extern "C" {
@@ -623,6 +702,19 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
     ks_system_destroy(s);
     return st;
   }
+  {
+    // |G|^2/2 of each packed coefficient (preconditioner of the eigensolver)
+    std::vector<double> kp((size_t)npw);
+    for (int pi = 0; pi < s->nplanes; ++pi)
+      for (int c = plane_col0[pi]; c < plane_col0[pi + 1]; ++c)
+        for (int e = col_off[c]; e < col_off[c + 1]; ++e)
+          kp[e] = kin(L, s->m0lo + pi, plane_m1lo[pi] + (c - plane_col0[pi]), col_m2lo[c] + (e - col_off[c]));
+    if ((st = upload(s, &s->d_kin, kp)) != KS_OK) {
+      g_create_err = s->err;
+      ks_system_destroy(s);
+      return st;
+    }
+  }
   if ((st = dalloc(s, reinterpret_cast<void**>(&s->d_v), s->N * sizeof(double))) != KS_OK ||
       (st = dalloc(s, reinterpret_cast<void**>(&s->d_vloc), s->N * sizeof(double))) != KS_OK ||
       (st = dalloc(s, reinterpret_cast<void**>(&s->d_hbox), s->N * sizeof(double2))) != KS_OK ||
@@ -661,7 +753,7 @@ void ks_system_destroy(ks_system* s) {
   timing_free(s);
   free_workspace(s);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
-                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_vloc, s->d_hbox, s->d_rho_w, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
+                  s->d_tw0f, s->d_tw1f, s->d_v, s->d_vloc, s->d_kin, s->d_hbox, s->d_rho_w, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
                   s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta,
                   s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
@@ -860,17 +952,10 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   if (norb == 0) return KS_OK;
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   hipStream_t st = (hipStream_t)stream;
-  if (!s->ortho_pk) {
-    const size_t n = (size_t)s->max_norb;
-    if ((r = dalloc(s, &s->ortho_pk, 2 * n * s->npw_stride * sizeof(double2))) != KS_OK ||
-        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_S), n * n * sizeof(double2))) != KS_OK ||
-        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_W), n * n * sizeof(double2))) != KS_OK ||
-        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK ||
-        (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_diag), n * sizeof(double))) != KS_OK) {
-      dfree(s->ortho_pk);
-      return r;
-    }
-  }
+  if ((r = ensure_ortho_mats(s)) != KS_OK) return r;
+  if (!s->ortho_pk &&
+      (r = dalloc(s, &s->ortho_pk, 2 * (size_t)s->max_norb * s->npw_stride * sizeof(double2))) != KS_OK)
+    return r;
   double2* P = (double2*)s->ortho_pk;
   double2* Y = P + (size_t)s->max_norb * s->npw_stride;
   KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
@@ -981,8 +1066,8 @@ void ks_state_destroy(ks_state* t) {
   state_drop_graph(t);
   void* p = t->data;
   dfree(p);
-  void* q = t->aux;
-  dfree(q);
+  void* bufs[] = {t->aux, t->gs_buf[0], t->gs_buf[1], t->gs_mat, t->gs_vec};
+  for (void* q : bufs) dfree(q);
   delete t;
 }
 
@@ -1058,6 +1143,65 @@ ks_status ks_state_kick(ks_state* t, const double k[3], void* stream) {
     if ((r = launch_ok(s, launch_unpack(s, 1, c, true, s->d_hbox, s->N, st), "unpack")) != KS_OK) return r;
     if ((r = launch_ok(s, launch_kick(s, s->d_hbox, k, st), "kick")) != KS_OK) return r;
     if ((r = launch_ok(s, launch_pack(s, 1, s->d_hbox, s->N, c, st), "pack")) != KS_OK) return r;
+  }
+  return KS_OK;
+}
+
+ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid, void* stream) {
+  if (!t) return fail(nullptr, KS_EINVAL, "null state");
+  ks_system* s = t->sys;
+  if (niter < 0) return fail(s, KS_EINVAL, "niter < 0");
+  if (s->prec != KS_FP64) return fail(s, KS_EUNSUPPORTED, "the eigensolver runs on FP64 systems");
+  if (niter == 0) return KS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = t->norb;
+  const size_t ld = s->npw_stride, nn = (size_t)n * n, blk = (size_t)n * ld * sizeof(double2);
+  ks_status r;
+  if ((!t->aux && (r = dalloc(s, reinterpret_cast<void**>(&t->aux), blk)) != KS_OK) ||
+      (!t->gs_buf[0] && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_buf[0]), blk)) != KS_OK) ||
+      (!t->gs_buf[1] && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_buf[1]), blk)) != KS_OK) ||
+      (!t->gs_mat && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_mat), 6 * nn * sizeof(double2))) != KS_OK) ||
+      (!t->gs_vec && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_vec), (2 * (size_t)n + 2) * sizeof(double))) != KS_OK) ||
+      (r = ensure_ortho_mats(s)) != KS_OK)
+    return r;
+  double2 *C = t->data, *B1 = t->aux, *B2 = t->gs_buf[0], *B3 = t->gs_buf[1];
+  double2 *Hs = t->gs_mat, *Qm = t->gs_mat + nn, *work = t->gs_mat + 2 * nn;
+  double *e = t->gs_vec, *rn = t->gs_vec + n, *off = t->gs_vec + 2 * n;
+  const int cl = chunk_len(s, n);
+  const Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
+  const size_t row = ld * sizeof(double2), used = s->npw * sizeof(double2);
+  for (int it = 0; it < niter; ++it) {
+    // W = H C
+    for (int o0 = 0; o0 < n; o0 += cl)
+      if ((r = hpsi_packed(s, std::min(cl, n - o0), C + o0 * ld, true, B1 + o0 * ld, nullptr, H_OUT, none, st)) != KS_OK)
+        return r;
+    // subspace diagonalisation: Hs = C^H W = Q diag(e) Q^H; C <- Q^T C, W <- Q^T W
+    if ((r = kcall(s, KS_K_GEMM, st, "rayleigh_ritz", [&] { return launch_gemm_ch(n, s->npw, C, ld, B1, ld, Hs, st); })) !=
+        KS_OK)
+      return r;
+    if ((r = subspace_eigh(s, n, Hs, work, off, e, Qm, st)) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_GEMM, st, "rotate", [&] { return launch_rotate(n, s->npw, Qm, C, ld, B3, ld, st); })) != KS_OK ||
+        (r = kcall(s, KS_K_GEMM, st, "rotate", [&] { return launch_rotate(n, s->npw, Qm, B1, ld, B2, ld, st); })) != KS_OK)
+      return r;
+    KS_HIP(s, hipMemcpy2DAsync(C, row, B3, row, used, n, hipMemcpyDeviceToDevice, st));
+    // preconditioned directions q (B1) from the residuals of C, W (B2)
+    if ((r = kcall(s, KS_K_SD, st, "sd_direction", [&] {
+           launch_sd_direction(n, s->npw, (int)ld, C, B2, e, s->d_kin, B1, rn, st);
+           return true;
+         })) != KS_OK)
+      return r;
+    // H q (B3), line minimisation, orthonormalisation
+    for (int o0 = 0; o0 < n; o0 += cl)
+      if ((r = hpsi_packed(s, std::min(cl, n - o0), B1 + o0 * ld, true, B3 + o0 * ld, nullptr, H_OUT, none, st)) != KS_OK)
+        return r;
+    if ((r = kcall(s, KS_K_SD, st, "sd_update", [&] {
+           launch_sd_update(n, s->npw, (int)ld, C, B1, B3, e, st);
+           return true;
+         })) != KS_OK)
+      return r;
+    if ((r = orthonormalize_packed(s, n, C, B2, st)) != KS_OK) return r;
+    if (eig) KS_HIP(s, hipMemcpyAsync(eig + (size_t)it * n, e, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (resid) KS_HIP(s, hipMemcpyAsync(resid + (size_t)it * n, rn, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
   return KS_OK;
 }

@@ -92,6 +92,7 @@ struct ks_system {
   // static V_loc
   double* d_v = nullptr;
   double* d_vloc = nullptr;
+  double* d_kin = nullptr;   // |G|^2/2 of each packed coefficient [npw]
   bool have_v = false;
   // Hartree solve: complex work box [n0][n1][n2] and a density [n0][n1][n2]
   double2* d_hbox = nullptr;
@@ -143,7 +144,13 @@ struct ks_state {
   ks_system* sys = nullptr;
   int norb = 0;
   double2* data = nullptr;     // [norb][npw_stride]
-  double2* aux = nullptr;      // [norb][npw_stride] ETRS predictor (allocated on first use)
+  double2* aux = nullptr;      // [norb][npw_stride] ETRS predictor / eigensolver work (allocated on first use)
+  // eigensolver work (allocated on first use): two more orbital blocks, the
+  // Rayleigh-Ritz matrix and its Jacobi iterates [6][norb][norb], and
+  // [2*norb + 2] doubles (Ritz values, residual norms, off-diagonal norm)
+  double2* gs_buf[2] = {nullptr, nullptr};
+  double2* gs_mat = nullptr;
+  double* gs_vec = nullptr;
   hipGraph_t graph = nullptr;  // one captured propagation step
   hipGraphExec_t exec = nullptr;
 };
@@ -180,6 +187,25 @@ bool launch_hartree(const ks_system* s, const double* rho, double* v, const doub
 bool launch_kick(const ks_system* s, double2* W, const double k[3], hipStream_t st);
 // d[0..2] = dV sum_r r rho(r) (device output; uses the work box for partial sums)
 bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t st);
+
+// dense complex products for the eigensolver (MFMA FP64):
+// S[i][j] = sum_e conj(A[i][e]) B[j][e]   (norb x norb, rows of length npw)
+bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2* B, int ldb, double2* S, hipStream_t st);
+// Y[i][e] = sum_j Q[i][j] X[j][e]   (Q row-major norb x norb)
+bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ldx, double2* Y, int ldy, hipStream_t st);
+
+// subspace eigenproblem (k_ground.hip): A = (H + H^H)/2 and Vt = I; one
+// Jacobi round t (An, Vn from A, Vt); out = {off-diagonal |A|^2, |A|^2};
+// eigenvalues ascending and eigenvectors as the rows of Q, phase-fixed
+void launch_hermitize(int n, const double2* H, double2* A, double2* Vt, hipStream_t st);
+void launch_jacobi_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, int t, hipStream_t st);
+void launch_offdiag(int n, const double2* A, double* out, hipStream_t st);
+void launch_eig_finish(int n, const double2* A, const double2* Vt, double* eig, double2* Q, hipStream_t st);
+// steepest-descent steps over norb packed orbitals (one block per orbital)
+void launch_sd_direction(int norb, int npw, int stride, const double2* C, const double2* W, const double* e,
+                         const double* kin, double2* Qd, double* resid, hipStream_t st);
+void launch_sd_update(int norb, int npw, int stride, double2* C, const double2* Qd, const double2* HQ, const double* e,
+                      hipStream_t st);
 
 bool supported_size(int n);
 int x_tile_nb(int n0);

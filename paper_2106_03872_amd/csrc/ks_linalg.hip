@@ -317,4 +317,16 @@ bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, i
   return true;
 }
 
+bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2* B, int ldb, double2* S, hipStream_t st) {
+  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
+  zgemm_mfma_kernel<true, false, false, false><<<grid, 256, 0, st>>>(norb, norb, npw, A, lda, B, ldb, S, norb);
+  return true;
+}
+
+bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ldx, double2* Y, int ldy, hipStream_t st) {
+  dim3 grid((npw + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
+  zgemm_mfma_kernel<false, true, false, false><<<grid, 256, 0, st>>>(norb, npw, norb, Q, norb, X, ldx, Y, ldy);
+  return true;
+}
+
 }  // namespace ks

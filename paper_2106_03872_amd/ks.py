@@ -19,7 +19,8 @@ HEADER = os.path.join(HERE, "..", "include", "ks.h")
 
 KS_OK, KS_EINVAL, KS_ENOMEM, KS_EDEVICE, KS_EUNSUPPORTED = range(5)
 KS_FP64, KS_MIXED = 0, 1
-KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dots"]
+KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dots",
+           "gemm", "eig", "sd"]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +79,7 @@ def _load():
         "ks_hartree": (I, [P, P, P, I, P]),
         "ks_dipole": (I, [P, P, P, P]),
         "ks_state_kick": (I, [P, ctypes.POINTER(D), P]),
+        "ks_state_eigensolve": (I, [P, I, P, P, P]),
         "ks_state_reduce": (I, [P, P, P, P, P]),
         "ks_state_capture": (I, [P, D, P, P, P]),
         "ks_state_replay": (I, [P, P]),
@@ -398,6 +400,21 @@ class State:
         self.system._check(_lib.ks_state_propagate_etrs(
             self._h, float(dt), int(nsteps), _ptr(occ, torch.float64, (self.norb,), "occ"),
             _ptr(rho, torch.float64, None, "rho"), _ptr(norms, torch.float64, None, "norms"), self._st(stream)))
+
+    def eigensolve(self, niter, eig=None, resid=None, stream=None):
+        """niter preconditioned steepest-descent iterations towards the lowest
+        norb eigenstates (orthonormal orbitals in and out); returns the Ritz
+        values and residual norms of every iteration, float64 [niter][norb]."""
+        import torch
+        shape = (max(int(niter), 0), self.norb)
+        if eig is None:
+            eig = torch.empty(shape, dtype=torch.float64, device="cuda")
+        if resid is None:
+            resid = torch.empty(shape, dtype=torch.float64, device="cuda")
+        self.system._check(_lib.ks_state_eigensolve(
+            self._h, int(niter), _ptr(eig, torch.float64, shape, "eig"), _ptr(resid, torch.float64, shape, "resid"),
+            self._st(stream)))
+        return eig, resid
 
     def reduce(self, occ=None, want_energy=True, stream=None):
         import torch

@@ -61,6 +61,7 @@ def test_null_system_calls_fail_cleanly():
     assert lib.ks_dipole(None, None, None, None) == ks.KS_EINVAL
     assert lib.ks_state_kick(None, None, None) == ks.KS_EINVAL
     assert lib.ks_state_propagate_etrs(None, 0.1, 1, None, None, None, None) == ks.KS_EINVAL
+    assert lib.ks_state_eigensolve(None, 1, None, None, None) == ks.KS_EINVAL
     assert lib.ks_system_set_tuning(None, None) == ks.KS_EINVAL
     lib.ks_system_destroy(None)
 
