@@ -216,6 +216,41 @@ def run_etrs(spec, gs, state, steps):
             "steps": steps, "density_dependent": "V_loc + periodic Hartree"}
 
 
+def run_ground(spec, gs, state, iters):
+    """Steepest-descent eigensolver iterations on the resident orbitals: per
+    iteration 2 H psi per orbital, the Rayleigh-Ritz product, two rotation
+    products, the Jacobi subspace eigenproblem, the residual/preconditioner
+    and line-minimisation kernels and the Cholesky orthonormalisation."""
+    import torch
+    state.eigensolve(1)                                    # warm-up (allocates the work blocks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, resid = state.eigensolve(iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / iters
+    gs.set_kernel_timing(True)                             # per-class breakdown in a second timed run
+    state.eigensolve(iters)
+    torch.cuda.synchronize()
+    kt = gs.kernel_times()
+    gs.set_kernel_timing(False)
+    npw, n = gs.npw, spec.norb
+    # complex MACs of the dense products per iteration: Rayleigh-Ritz n^2 npw,
+    # two rotations 2 n^2 npw, overlap (lower half) n^2 npw / 2, triangular
+    # apply n^2 npw / 2; 8 real flops per complex MAC
+    gemm_flop = 8.0 * n * n * npw * 4.0
+    parts = {k: round(v[0] / iters, 3) for k, v in kt.items() if v[1] > 0}
+    launches = {k: v[1] // iters for k, v in kt.items() if v[1] > 0}
+    gemm_ms = kt["gemm"][0] / iters
+    return {"ms_per_iteration": round(ms, 3), "iterations": iters, "orbitals": n,
+            "ms_per_iteration_by_class": parts, "launches_per_iteration": launches,
+            "hpsi_ms_per_iteration": round(sum(parts.get(k, 0.0) for k in
+                                               ("plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd")), 3),
+            "gemm_tflops": round(gemm_flop / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms > 0 else None,
+            "gemm_peak_tflops": 78.6,
+            "ritz_sum_first_last": [float(eig[0].sum().item()), float(eig[-1].sum().item())],
+            "residual_max_last": float(resid[-1].max().item())}
+
+
 def run_serving(nreq, nsteps, budget_gb, log):
     from paper_2106_03872_amd import serve, synth
     trace = synth.serving_trace(nreq, 200.0, 2000)
@@ -244,6 +279,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-etrs", action="store_true")
     ap.add_argument("--etrs-steps", type=int, default=3)
+    ap.add_argument("--no-ground", action="store_true")
+    ap.add_argument("--ground-iters", type=int, default=2)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=50)
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
@@ -284,6 +321,10 @@ def main():
     if etrs:
         log(f"[bench] ETRS (V_loc + Hartree): {etrs['ms_per_step']:.2f} ms/step, "
             f"{etrs['orbital_hpsi_per_s']:.1f} orbital.Hpsi/s, Hartree solve {etrs['hartree_ms']:.3f} ms")
+    ground = None if args.no_ground else run_ground(spec, gs, state, args.ground_iters)
+    if ground:
+        log(f"[bench] ground state (steepest descent): {ground['ms_per_iteration']:.2f} ms/iteration, "
+            f"by class {ground['ms_per_iteration_by_class']}, products {ground['gemm_tflops']} TFLOP/s")
     state.close()
     gs.close()
 
@@ -353,6 +394,7 @@ def main():
         "physics": phys,
         "mixed": mixed,
         "etrs": etrs,
+        "ground_state": ground,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -34,6 +34,10 @@ or reordering:
   spectrum): a field kick at t = 0, i.e. ``v_pert = -k.r delta(t)`` in
   Eq. hamiltonian, which multiplies every orbital by ``exp(i k.r)``; and the
   dipole moment, the first moment of the density.
+* The ground-state eigensolver of Section "Ground-state solution":
+  preconditioned steepest descent (Teter preconditioner in Fourier space)
+  with subspace diagonalisation and Cholesky orthogonalisation, for a static
+  Hamiltonian.
 * The ETRS propagator (Eq. etrs, with the predictor of Eq. etrs0) whose two
   exponentials of ``H(t)`` share the powers ``H(t)^k c`` (the shared-lambda
   evaluation of the truncated Taylor series in Section "Real-time

@@ -551,10 +551,11 @@ ks_status ensure_ortho_mats(ks_system* s) {
   if ((r = dalloc(s, reinterpret_cast<void**>(&s->ortho_S), n * n * sizeof(double2))) != KS_OK ||
       (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_W), n * n * sizeof(double2))) != KS_OK ||
       (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK ||
-      (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_diag), n * sizeof(double))) != KS_OK) {
-    void* p[] = {s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
+      (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_diag), n * sizeof(double))) != KS_OK ||
+      (r = dalloc(s, reinterpret_cast<void**>(&s->gemm_part), GEMM_PART_BYTES)) != KS_OK) {
+    void* p[] = {s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag, s->gemm_part};
     for (void* q : p) dfree(q);
-    s->ortho_S = s->ortho_W = nullptr;
+    s->ortho_S = s->ortho_W = s->gemm_part = nullptr;
     s->ortho_info = nullptr;
     s->ortho_diag = nullptr;
     return r;
@@ -569,7 +570,7 @@ ks_status orthonormalize_packed(ks_system* s, int n, double2* C, double2* Y, hip
   ks_status r;
   const size_t ld = s->npw_stride;
   KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
-  if ((r = kcall(s, KS_K_GEMM, st, "overlap", [&] { return launch_overlap(n, s->npw, C, ld, s->ortho_S, st); })) != KS_OK)
+  if ((r = kcall(s, KS_K_GEMM, st, "overlap", [&] { return launch_overlap(n, s->npw, C, ld, s->ortho_S, s->gemm_part, st); })) != KS_OK)
     return r;
   if ((r = launch_ok(s, launch_cholesky(n, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(n, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
@@ -756,7 +757,7 @@ void ks_system_destroy(ks_system* s) {
                   s->d_tw0f, s->d_tw1f, s->d_v, s->d_vloc, s->d_kin, s->d_hbox, s->d_rho_w, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
                   s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta,
-                  s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag};
+                  s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag, s->gemm_part};
   for (void* p : ptrs) dfree(p);
   delete s;
 }
@@ -961,7 +962,7 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
   double2* box = (double2*)psi;
   if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, norb, box, s->N, P, st); })) != KS_OK) return r;
-  if ((r = launch_ok(s, launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, st), "overlap")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, s->gemm_part, st), "overlap")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(norb, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_apply_lower(norb, s->npw, s->ortho_W, P, s->npw_stride, Y, st), "apply")) != KS_OK)
@@ -1176,7 +1177,7 @@ ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid
       if ((r = hpsi_packed(s, std::min(cl, n - o0), C + o0 * ld, true, B1 + o0 * ld, nullptr, H_OUT, none, st)) != KS_OK)
         return r;
     // subspace diagonalisation: Hs = C^H W = Q diag(e) Q^H; C <- Q^T C, W <- Q^T W
-    if ((r = kcall(s, KS_K_GEMM, st, "rayleigh_ritz", [&] { return launch_gemm_ch(n, s->npw, C, ld, B1, ld, Hs, st); })) !=
+    if ((r = kcall(s, KS_K_GEMM, st, "rayleigh_ritz", [&] { return launch_gemm_ch(n, s->npw, C, ld, B1, ld, Hs, s->gemm_part, st); })) !=
         KS_OK)
       return r;
     if ((r = subspace_eigh(s, n, Hs, work, off, e, Qm, st)) != KS_OK) return r;

@@ -6,6 +6,8 @@
 //   C <- conj(X) C  (rows = orbitals), i.e. Psi <- Psi L^-H  (MFMA FP64)
 // The matrices are small (n = orbitals <= a few thousand); the two GEMMs are
 // the only large contractions and run on the matrix cores.
+#include <algorithm>
+
 #include "ks_internal.h"
 
 namespace ks {
@@ -20,6 +22,10 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 // k-tiles above the diagonal are skipped.  LOWER_OUT: only tiles with
 // m-tile >= n-tile are produced.
 //
+// Split K: block z of the grid's third dimension sums k in [z kchunk,
+// (z+1) kchunk) (kchunk a multiple of GBK) into Cout + z * cstride; a fixed-
+// order sum over z (sum_partials_kernel) completes the product.
+//
 // v_mfma_f64_16x16x4_f64 operand layout on gfx950 (64 lanes, measured):
 // A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
 // j + 16 (i mod 4), element i div 4 of the 4-double accumulator.
@@ -28,7 +34,8 @@ constexpr int GBM = 64, GBN = 64, GBK = 16;
 template <bool CONJ_A, bool B_KN, bool LOWER_A, bool LOWER_OUT>
 __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, const double2* __restrict__ A, long long lda,
                                                          const double2* __restrict__ Bm, long long ldb,
-                                                         double2* __restrict__ Cout, long long ldc) {
+                                                         double2* __restrict__ Cout, long long ldc, int kchunk,
+                                                         long long cstride) {
   __shared__ double2 As[GBK][GBM + 1];
   __shared__ double2 Bs[GBK][GBN + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -40,9 +47,11 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, co
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
-  const int kend = LOWER_A ? min(K, m0 + GBM) : K;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = LOWER_A ? min(min(K, kbeg + kchunk), m0 + GBM) : min(K, kbeg + kchunk);
+  Cout += blockIdx.z * cstride;
   const double sa = CONJ_A ? -1.0 : 1.0;
-  for (int k0 = 0; k0 < kend; k0 += GBK) {
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
     // A tile: 64 rows x 16 k, k fastest across threads
     for (int i = tid; i < GBM * GBK; i += 256) {
       const int kk = i % GBK, mm = i / GBK;
@@ -277,10 +286,53 @@ __global__ void zero_upper_kernel(double2* X, int n) {
 
 // ------------------------------------------------------------------ launchers
 
-bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, hipStream_t st) {
-  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
-  // S[i][j] = sum_e conj(P[i][e]) P[j][e]
-  zgemm_mfma_kernel<true, false, false, true><<<grid, 256, 0, st>>>(norb, norb, npw, P, ldp, P, ldp, S, norb);
+// Fixed-order sum of nz partial products [nz][n][n] (only tiles on or below
+// the diagonal when lower)
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __restrict__ part, int nz, int n, bool lower,
+                                                           double2* __restrict__ out) {
+  const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (g >= (long long)n * n) return;
+  const int i = (int)(g / n), j = (int)(g % n);
+  if (lower && j / GBN > i / GBM) return;
+  double2 s = part[g];
+  for (int z = 1; z < nz; ++z) {
+    const double2 v = part[(long long)z * n * n + g];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  out[g] = s;
+}
+
+// Split of the K = npw contraction for an n x n product: enough blocks to
+// fill the chip (about 2048), chunks of at least 256, partials within
+// GEMM_PART_BYTES.
+struct KSplit {
+  int nz, kchunk;
+};
+
+KSplit ksplit(int n, int K, bool lower) {
+  const long long t = (long long)((n + GBN - 1) / GBN) * ((n + GBM - 1) / GBM);
+  const long long tiles = lower ? (t + (n + GBM - 1) / GBM) / 2 : t;
+  long long nz = (2048 + tiles - 1) / tiles;
+  nz = std::min<long long>(nz, (long long)(GEMM_PART_BYTES / ((size_t)n * n * sizeof(double2))));
+  nz = std::min<long long>(nz, (K + 255) / 256);
+  nz = std::max<long long>(nz, 1);
+  int kchunk = (int)((K + nz - 1) / nz);
+  kchunk = (kchunk + GBK - 1) / GBK * GBK;
+  return KSplit{(K + kchunk - 1) / kchunk, kchunk};
+}
+
+bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, double2* part, hipStream_t st) {
+  // S[i][j] = sum_e conj(P[i][e]) P[j][e], tiles on and below the diagonal
+  const KSplit sp = ksplit(norb, npw, true);
+  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM, sp.nz);
+  if (sp.nz == 1) {
+    zgemm_mfma_kernel<true, false, false, true><<<grid, 256, 0, st>>>(norb, norb, npw, P, ldp, P, ldp, S, norb, sp.kchunk, 0);
+    return true;
+  }
+  zgemm_mfma_kernel<true, false, false, true><<<grid, 256, 0, st>>>(norb, norb, npw, P, ldp, P, ldp, part, norb, sp.kchunk,
+                                                                    (long long)norb * norb);
+  sum_partials_kernel<<<(unsigned)(((long long)norb * norb + 255) / 256), 256, 0, st>>>(part, sp.nz, norb, true, S);
   return true;
 }
 
@@ -313,19 +365,27 @@ bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st) {
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st) {
   dim3 grid((npw + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
   // Y[i][e] = sum_{j <= i} conj(X[i][j]) P[j][e]
-  zgemm_mfma_kernel<true, true, true, false><<<grid, 256, 0, st>>>(norb, npw, norb, X, norb, P, ldp, Y, ldp);
+  zgemm_mfma_kernel<true, true, true, false><<<grid, 256, 0, st>>>(norb, npw, norb, X, norb, P, ldp, Y, ldp, norb, 0);
   return true;
 }
 
-bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2* B, int ldb, double2* S, hipStream_t st) {
-  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
-  zgemm_mfma_kernel<true, false, false, false><<<grid, 256, 0, st>>>(norb, norb, npw, A, lda, B, ldb, S, norb);
+bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2* B, int ldb, double2* S, double2* part,
+                    hipStream_t st) {
+  const KSplit sp = ksplit(norb, npw, false);
+  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM, sp.nz);
+  if (sp.nz == 1) {
+    zgemm_mfma_kernel<true, false, false, false><<<grid, 256, 0, st>>>(norb, norb, npw, A, lda, B, ldb, S, norb, sp.kchunk, 0);
+    return true;
+  }
+  zgemm_mfma_kernel<true, false, false, false><<<grid, 256, 0, st>>>(norb, norb, npw, A, lda, B, ldb, part, norb, sp.kchunk,
+                                                                     (long long)norb * norb);
+  sum_partials_kernel<<<(unsigned)(((long long)norb * norb + 255) / 256), 256, 0, st>>>(part, sp.nz, norb, false, S);
   return true;
 }
 
 bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ldx, double2* Y, int ldy, hipStream_t st) {
   dim3 grid((npw + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
-  zgemm_mfma_kernel<false, true, false, false><<<grid, 256, 0, st>>>(norb, npw, norb, Q, norb, X, ldx, Y, ldy);
+  zgemm_mfma_kernel<false, true, false, false><<<grid, 256, 0, st>>>(norb, npw, norb, Q, norb, X, ldx, Y, ldy, norb, 0);
   return true;
 }
 
