@@ -66,28 +66,20 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
 #pragma unroll
       for (int q = 0; q < LS::radix; ++q) a[it][q] = 0.0;
   }
-  // Projections: item i = pair*nseg + seg for the (slot, projector) pairs of
-  // the tile; each item sums beta * psi over its segment of the slot's points
-  // (in point order), and the nseg segments of a pair, adjacent lanes of one
-  // wave, are then added by a fixed butterfly over those lanes.
+  // Projections: each lane sums beta * psi over its rows [ka, kb) of one
+  // (slot, projector) pair of the tile (in point order); the 2^g lanes of a
+  // pair, adjacent and aligned, are then added by a fixed butterfly and the
+  // group's first lane writes the pair (work planned per tile on the host).
+  static_assert(NT == KB_ITEM_LANES, "projection items are planned per block lane");
   const int np = pt.nproj;
-  const int pairs = ns * np;   // <= KB_TILE_DP <= NT
-  int lseg = 0;                // nseg = 2^lseg <= 16, nseg * pairs <= NT
-  while (lseg < 4 && (pairs << (lseg + 1)) <= NT) ++lseg;
-  const int nseg = 1 << lseg;
-  const int items = pairs << lseg;
-  const int pr = tid >> lseg, seg = tid & (nseg - 1);
+  const int4 item = pt.item[(long long)tile * NT + tid];
+  const int ka = item.x, kb = item.y;
+  const int sl = item.z / np, kq = item.z - sl * np;
+  const int glanes = 1 << (item.w & 0xff);
+  const bool writer = (item.w & 256) != 0;
   // The first KP points of the item (LDS position, beta) are the same for
   // all orbitals of the block and stay in registers.
-  constexpr int KP = 16;
-  int ka = 0, kb = 0, kq = 0, sl = 0;
-  if (tid < items) {
-    sl = pr / np;
-    kq = pr - sl * np;
-    const int k0 = pt.slot_pt[sA + sl], len = pt.slot_pt[sA + sl + 1] - k0;
-    ka = k0 + (len * seg) / nseg;
-    kb = k0 + (len * (seg + 1)) / nseg;
-  }
+  constexpr int KP = KB_CACHED_POINTS;
   int cpos[KP];
   double cbeta[KP];
 #pragma unroll
@@ -135,11 +127,14 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
       sx += bv * double(x.x);
       sy += bv * double(x.y);
     }
-    for (int m = 1; m < nseg; m <<= 1) {
-      sx += __shfl_xor(sx, m, 64);
-      sy += __shfl_xor(sy, m, 64);
+    for (int m = 1; m < (1 << KB_MAX_GROUP_LOG); m <<= 1) {
+      const double vx = __shfl_xor(sx, m, 64), vy = __shfl_xor(sy, m, 64);
+      if (m < glanes) {
+        sx += vx;
+        sy += vy;
+      }
     }
-    if (tid < items && seg == 0) pout[o * pstride] = C{R(sx * scale), R(sy * scale)};
+    if (writer) pout[o * pstride] = C{R(sx * scale), R(sy * scale)};
     __syncthreads();   // X is rewritten by the next orbital's first stage
   }
   if constexpr (DENS) {

@@ -194,6 +194,7 @@ struct ProjHost {
   std::vector<int> brow_input;   // input row of each beta row
   std::vector<int> pt_lds, slot_off, slot_atom, slot_pt, atom_slot_off, atom_slots;
   std::vector<int> up_off, up_lds, up_ent, ent_slot, ent_brow;
+  std::vector<int4> item;
 };
 
 ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* npts, const int* idx,
@@ -270,6 +271,44 @@ ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* 
       err = "too many atoms touch one x-tile (" + std::to_string(h.slot_off[t + 1] - h.slot_off[t]) + " x " +
             std::to_string(np) + " projectors > " + std::to_string(KB_TILE_DP) + ")";
       return KS_EUNSUPPORTED;
+    }
+  }
+  // Projection work of each lane of a tile's block: every (slot, projector)
+  // pair gets 2^g adjacent lanes (g = 0..4, aligned to 2^g), enough that each
+  // lane's share of the slot's beta rows fits the registers cached across
+  // orbitals; when a tile would need more lanes than the block has, the
+  // largest groups are halved (their lanes then loop over extra rows).
+  // item = (first row, end row, local slot * nproj + projector, g | 256 for
+  // the group's first lane).
+  h.item.assign((size_t)nt * KB_ITEM_LANES, make_int4(0, 0, 0, 0));
+  for (int t = 0; t < nt; ++t) {
+    const int s0 = h.slot_off[t], ns = h.slot_off[t + 1] - s0;
+    std::vector<int> lg(ns, 0);
+    for (int j = 0; j < ns; ++j) {
+      const int len = h.slot_pt[s0 + j + 1] - h.slot_pt[s0 + j];
+      const int need = (len + KB_CACHED_POINTS - 1) / KB_CACHED_POINTS;
+      while ((1 << lg[j]) < need && lg[j] < KB_MAX_GROUP_LOG) ++lg[j];
+    }
+    for (;;) {
+      long long lanes = 0;
+      for (int j = 0; j < ns; ++j) lanes += (long long)np << lg[j];
+      if (lanes <= KB_ITEM_LANES) break;
+      int jm = 0;
+      for (int j = 1; j < ns; ++j)
+        if (lg[j] > lg[jm]) jm = j;
+      --lg[jm];
+    }
+    std::vector<int> order(ns);
+    for (int j = 0; j < ns; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lg[a] > lg[b]; });
+    int base = 0;
+    for (int j : order) {
+      const int k0 = h.slot_pt[s0 + j], len = h.slot_pt[s0 + j + 1] - k0, g = 1 << lg[j];
+      for (int q = 0; q < np; ++q, base += g)
+        for (int sg = 0; sg < g; ++sg)
+          h.item[(size_t)t * KB_ITEM_LANES + base + sg] =
+              make_int4(k0 + (int)((long long)len * sg / g), k0 + (int)((long long)len * (sg + 1) / g), j * np + q,
+                        lg[j] | (sg == 0 ? 256 : 0));
     }
   }
   h.atom_slot_off.assign(natoms + 1, 0);
@@ -756,7 +795,7 @@ void ks_system_destroy(ks_system* s) {
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
                   s->d_tw0f, s->d_tw1f, s->d_v, s->d_vloc, s->d_kin, s->d_hbox, s->d_rho_w, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
-                  s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta,
+                  s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta, s->d_item,
                   s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag, s->gemm_part};
   for (void* p : ptrs) dfree(p);
   delete s;
@@ -824,7 +863,7 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
       (st = upload(s, &s->d_up_key, up_key)) != KS_OK || (st = upload(s, &s->d_up_x, up_x)) != KS_OK ||
       (st = upload(s, &s->d_x_slot, x_slot)) != KS_OK || (st = upload(s, &s->d_beta, ph.brows)) != KS_OK ||
       (st = upload(s, &s->d_up_beta, up_beta)) != KS_OK || (st = upload(s, &s->d_x_beta, x_beta)) != KS_OK ||
-      (st = upload(s, &s->d_kb, kb)) != KS_OK)
+      (st = upload(s, &s->d_kb, kb)) != KS_OK || (st = upload(s, &s->d_item, ph.item)) != KS_OK)
     return st;
   s->natoms = (natoms > 0 && ph.npoints > 0) ? natoms : 0;
   s->nproj = np;

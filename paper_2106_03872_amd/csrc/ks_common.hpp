@@ -69,6 +69,7 @@ inline ProjTab proj_tab(const ks_system* s) {
   c.x_beta = s->d_x_beta;
   c.beta = s->d_beta;
   c.d = s->d_kb;
+  c.item = s->d_item;
   c.natoms = s->natoms;
   c.nproj = s->nproj;
   c.nslots = s->nslots;

@@ -45,6 +45,7 @@ struct ProjTab {
   const double* x_beta;      // [nextra][nproj]
   const double* beta;        // [npoints][nproj], rows in slot order
   const double* d;           // [natoms][nproj]
+  const int4* item;          // [ntiles][KB_ITEM_LANES] projection work of each lane (see build_proj)
   int natoms, nproj, nslots;
 };
 
@@ -55,6 +56,9 @@ constexpr int UP_MAX_SLOT = (1 << UP_SLOT_BITS) - 1, UP_MAX_EXTRA = 127;
 constexpr int KB_MAX_NPROJ = 8;        // projectors per atom
 constexpr size_t GEMM_PART_BYTES = 64ull << 20;   // split-K partials of the n x n products
 constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-tile
+constexpr int KB_ITEM_LANES = 256;     // lanes of an x-pencil block (projection work items)
+constexpr int KB_CACHED_POINTS = 16;   // points of an item held in registers across orbitals
+constexpr int KB_MAX_GROUP_LOG = 4;    // at most 16 lanes per (slot, projector) pair
 
 enum HMode { H_OUT = 0, H_TAYLOR = 1 };
 
@@ -109,6 +113,7 @@ struct ks_system {
       *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_key = nullptr,
       *d_up_x = nullptr, *d_x_slot = nullptr;
   double *d_beta = nullptr, *d_up_beta = nullptr, *d_x_beta = nullptr, *d_kb = nullptr;
+  int4* d_item = nullptr;
 
   // workspace (one chunk of cb orbitals)
   int cb = 1;
