@@ -125,3 +125,37 @@ def test_mixed_etrs_vs_oracle(ks):
     assert rel_err(st.download().cpu().numpy(), ref) < TOL_H
     assert np.linalg.norm(rho[-1].cpu().numpy() - dens[-1]) / np.linalg.norm(dens[-1]) < TOL_H
     st.close()
+
+
+def test_mixed_full_size_120_sampled(ks):
+    """120^3 grid, 1024 orbitals, 256 atoms (several passes per call): mixed
+    H psi on sampled orbitals against the oracle, and the band energy after 50
+    Taylor-4 steps against the FP64 path on the same orthonormalised start."""
+    spec, sysm = _case("cfg4_120")
+    ham = oracle_ham(sysm)
+    g64 = ks.system_from_synth(sysm)
+    gmx = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
+    c = orbitals_device(spec)
+    g64.orthonormalize(c)
+    sample = [0, 511, spec.norb - 1]
+    hs = gmx.ham_apply(c)[sample].cpu().numpy()
+    err = rel_err(hs, ko.ham_apply(ham, c[sample].cpu().numpy()))
+    print(f"[mixed] 120^3 H psi rel err {err:.2e}", file=sys.stderr)
+    assert err < TOL_H
+    del hs
+    occ = torch.full((spec.norb,), 2.0, dtype=torch.float64, device="cuda")
+    s64, smx = ks.State(g64, spec.norb), ks.State(gmx, spec.norb)
+    s64.upload(c)
+    smx.upload(c)
+    del c
+    s64.propagate(spec.dt, 50)
+    smx.propagate(spec.dt, 50)
+    _, e64 = s64.reduce(occ)
+    b = smx.download()
+    s64.upload(b)                              # mixed-propagated orbitals, FP64 energy
+    _, e64m = s64.reduce(occ)
+    d_e = abs(e64m.item() - e64.item()) / float(occ.sum())
+    print(f"[mixed] 120^3 after 50 steps: |dE|/electron {d_e:.2e}", file=sys.stderr)
+    assert d_e < 1e-6
+    s64.close()
+    smx.close()
