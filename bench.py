@@ -251,6 +251,31 @@ def run_ground(spec, gs, state, iters):
             "residual_max_last": float(resid[-1].max().item())}
 
 
+def run_mixed_large(steps, log):
+    """The mixed-precision configuration's larger system (120^3 grid, 1024
+    orbitals, 256 atoms): FP64 and mixed steps from the same orthonormalised
+    start, the speedup and the orbital error of the mixed path."""
+    from paper_2106_03872_amd import ks, synth
+    spec = synth.CONFIGS["cfg4_120"]
+    sample = list(range(0, spec.norb, 64))
+    res, psi = {}, {}
+    for name, prec in (("fp64", ks.KS_FP64), ("mixed", ks.KS_MIXED)):
+        _, g, st = setup_workload(spec, prec)
+        ms, _, phys, _ = run_steps(spec, g, st, steps, 1, timing=False)
+        psi[name] = st.download()[sample].clone()
+        res[name] = {"ms_per_step": round(ms, 3), "value": round(4 * spec.norb / (ms * 1e-3), 1),
+                     "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"]}
+        log(f"[bench] 120^3 / {spec.norb} orbitals {name}: {ms:.2f} ms/step, {res[name]['value']:.0f} orbital.Hpsi/s")
+        st.close()
+        g.close()
+    a, b = psi["mixed"], psi["fp64"]
+    d = (a - b).reshape(len(sample), -1).norm(dim=1) / b.reshape(len(sample), -1).norm(dim=1)
+    return {"workload": f"{spec.n[0]}^3, {spec.norb} orbitals, {spec.natoms} atoms", "steps": 1 + steps,
+            "fp64": res["fp64"], "mixed": res["mixed"],
+            "speedup_vs_fp64": round(res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"], 3),
+            "orbital_rel_err_vs_fp64_max": float(d.max().item()), "orbitals_compared": len(sample)}
+
+
 def run_serving(nreq, nsteps, budget_gb, log):
     from paper_2106_03872_amd import serve, synth
     trace = synth.serving_trace(nreq, 200.0, 2000)
@@ -280,6 +305,7 @@ def main():
     ap.add_argument("--no-etrs", action="store_true")
     ap.add_argument("--etrs-steps", type=int, default=3)
     ap.add_argument("--no-ground", action="store_true")
+    ap.add_argument("--no-mixed-120", action="store_true")
     ap.add_argument("--ground-iters", type=int, default=2)
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=50)
@@ -346,6 +372,8 @@ def main():
         del psim
     del psi64
 
+    mixed_120 = None if (args.no_mixed or args.no_mixed_120) else run_mixed_large(3, log)
+
     serving = None
     if not args.no_serving:
         serving = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log)
@@ -393,6 +421,7 @@ def main():
         "kernels": kernels,
         "physics": phys,
         "mixed": mixed,
+        "mixed_120": mixed_120,
         "etrs": etrs,
         "ground_state": ground,
         "serving": serving,
