@@ -242,7 +242,7 @@ ks_status ks_state_kick(ks_state* state, const double k[3], void* stream);
  * eig and resid (NULL, or device float64 [niter][norb]) receive e and |r|
  * of each iteration (the values at step 1-2, before the update).  FP64
  * systems only.  The first call on a state allocates three more orbital
- * blocks and 6 norb^2 complex entries; every iteration synchronises the
+ * blocks and about 6 norb^2 complex entries; every iteration synchronises the
  * stream (Jacobi convergence and the Cholesky status).  Errors: KS_EINVAL
  * (null state, niter < 0, linearly dependent orbitals), KS_EUNSUPPORTED
  * (mixed precision), KS_EDEVICE (Jacobi sweeps not converged, HIP errors).

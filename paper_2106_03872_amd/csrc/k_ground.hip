@@ -17,10 +17,15 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) { return double2{
 
 // ---------------------------------------------------------- Jacobi rotations
 //
-// Round t of a sweep pairs the m = n + (n odd) indices by the round-robin
-// tournament: pair 0 is (m-1, t), pair k > 0 is ((t+k) mod (m-1),
-// (t-k) mod (m-1)); over the m-1 rounds every index meets every other once.
-// An index >= n (odd n) is a dummy and is never rotated.
+// Blocked cyclic Jacobi.  The (zero-padded) matrix of order N2 = a multiple
+// of 2 BJ_B is cut into nblk = N2 / BJ_B index blocks.  Round t of a sweep
+// pairs the blocks by the round-robin tournament (pair 0 is (m-1, t), pair
+// k > 0 is ((t+k) mod (m-1), (t-k) mod (m-1)), m = nblk): over the m-1
+// rounds every block meets every other once.  Each pair's 2 BJ_B x 2 BJ_B
+// sub-problem gets one cyclic sweep of 2x2 rotations (same tournament inside)
+// giving a unitary U; then A <- U^H A U and V <- V U with U block diagonal
+// over the round's pairs.  Padding rows and columns are zero, so they are
+// never rotated and stay decoupled.
 
 __device__ __forceinline__ void round_pair(int t, int k, int m, int& p, int& q) {
   int a, b;
@@ -35,6 +40,11 @@ __device__ __forceinline__ void round_pair(int t, int k, int m, int& p, int& q) 
   q = max(a, b);
 }
 
+constexpr int BJ_B = 16;            // index block
+constexpr int BJ_M = 2 * BJ_B;      // sub-problem order
+constexpr int BJ_NT = 256;
+static_assert(BJ_B * BJ_B == BJ_NT, "one thread per 2x2 block of a sub-problem");
+
 // Rotation J (2x2, acting on indices p < q) with (J^H A J)_pq = 0 for the
 // Hermitian block [[a, b], [conj(b), c]]: with b = |b| e^{i phi}, the phase
 // D = diag(1, e^{-i phi}) makes the block real, and the real symmetric
@@ -43,14 +53,10 @@ __device__ __forceinline__ void round_pair(int t, int k, int m, int& p, int& q) 
 struct Rot {
   double cs, sn;
   double2 e;   // e^{-i phi}
-  bool id;
 };
 
-__device__ __forceinline__ Rot make_rot(const double2* __restrict__ A, int n, int p, int q) {
-  Rot r{1.0, 0.0, double2{1.0, 0.0}, true};
-  if (q >= n) return r;
-  const double a = A[(long long)p * n + p].x, c = A[(long long)q * n + q].x;
-  const double2 b = A[(long long)p * n + q];
+__device__ __forceinline__ Rot make_rot(double a, double c, double2 b) {
+  Rot r{1.0, 0.0, double2{1.0, 0.0}};
   const double ab = sqrt(b.x * b.x + b.y * b.y);
   if (ab == 0.0) return r;
   const double tau = (c - a) / (2.0 * ab);
@@ -58,83 +64,168 @@ __device__ __forceinline__ Rot make_rot(const double2* __restrict__ A, int n, in
   r.cs = 1.0 / sqrt(1.0 + t * t);
   r.sn = t * r.cs;
   r.e = double2{b.x / ab, -b.y / ab};
-  r.id = false;
   return r;
 }
 
 // J entries: J00 = cs, J01 = sn, J10 = -sn e, J11 = cs e
 __device__ __forceinline__ double2 jent(const Rot& r, int i, int j) {
-  if (r.id) return double2{i == j ? 1.0 : 0.0, 0.0};
   if (i == 0) return double2{j == 0 ? r.cs : r.sn, 0.0};
   return cscale(r.e, j == 0 ? -r.sn : r.cs);
 }
 
-// One round: An = J^H A J, Vn = Vt rotated (rows of Vt are the columns of
-// the accumulated eigenvector matrix V, V <- V J).  Threads [0, P^2) own the
-// 2x2 block (pair I, pair K) of A; threads [P^2, P^2 + P n) own (pair I,
-// column j) of Vt.  Reads A and Vt only, so the rotations of a round all
-// come from the same matrix.
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const double2* __restrict__ A, double2* __restrict__ An,
-                                                           const double2* __restrict__ Vt, double2* __restrict__ Vn,
-                                                           int n, int m, int t) {
-  const int P = m / 2;
-  long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g < (long long)P * P) {
-    const int I = (int)(g / P), K = (int)(g % P);
+// global index of local index l of block pair (I, J)
+__device__ __forceinline__ int bj_index(int I, int J, int l) { return l < BJ_B ? I * BJ_B + l : J * BJ_B + (l - BJ_B); }
+
+// Block k of round t: one cyclic sweep on the sub-problem of block pair k;
+// its unitary goes to Ublk[k] (row-major BJ_M x BJ_M).
+__global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restrict__ A, int N2, int t,
+                                                         double2* __restrict__ Ublk) {
+  __shared__ double2 S[BJ_M][BJ_M + 1];
+  __shared__ double2 U[BJ_M][BJ_M + 1];
+  __shared__ Rot rot[BJ_B];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  int I, J;
+  round_pair(t, k, N2 / BJ_B, I, J);
+  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) {
+    const int r = e / BJ_M, c = e % BJ_M;
+    S[r][c] = A[(long long)bj_index(I, J, r) * N2 + bj_index(I, J, c)];
+    U[r][c] = double2{r == c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  const int P2 = tid / BJ_B, Q2 = tid % BJ_B;
+  for (int r = 0; r < BJ_M - 1; ++r) {
+    if (tid < BJ_B) {
+      int p, q;
+      round_pair(r, tid, BJ_M, p, q);
+      rot[tid] = make_rot(S[p][p].x, S[q][q].x, S[p][q]);
+    }
+    __syncthreads();
+    // 2x2 block (P2, Q2) of S <- J^H S J (each block has one owner)
     int pi[2], pk[2];
-    round_pair(t, I, m, pi[0], pi[1]);
-    round_pair(t, K, m, pk[0], pk[1]);
-    const Rot ri = make_rot(A, n, pi[0], pi[1]);
-    const Rot rk = make_rot(A, n, pk[0], pk[1]);
+    round_pair(r, P2, BJ_M, pi[0], pi[1]);
+    round_pair(r, Q2, BJ_M, pk[0], pk[1]);
+    const Rot ri = rot[P2], rk = rot[Q2];
+    double2 blk[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      if (pi[i] >= n) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        if (pk[j] >= n) continue;
         double2 s{0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          if (pi[k] >= n) continue;
-          const double2 jk = cconj(jent(ri, k, i));
+        for (int a = 0; a < 2; ++a) {
+          const double2 ja = cconj(jent(ri, a, i));
 #pragma unroll
-          for (int l = 0; l < 2; ++l) {
-            if (pk[l] >= n) continue;
-            s = cadd(s, cmul(jk, cmul(A[(long long)pi[k] * n + pk[l]], jent(rk, l, j))));
-          }
+          for (int b = 0; b < 2; ++b) s = cadd(s, cmul(ja, cmul(S[pi[a]][pk[b]], jent(rk, b, j))));
         }
-        An[(long long)pi[i] * n + pk[j]] = s;
+        blk[i][j] = s;
       }
+    // columns (p, q) of U <- U J: rows P2 and P2 + BJ_B of the pair Q2
+    double2 u[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = P2 + h * BJ_B;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        u[h][j] = cadd(cmul(U[row][pk[0]], jent(rk, 0, j)), cmul(U[row][pk[1]], jent(rk, 1, j)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) S[pi[i]][pk[j]] = blk[i][j];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) U[P2 + h * BJ_B][pk[j]] = u[h][j];
+    __syncthreads();
+  }
+  double2* out = Ublk + (long long)k * BJ_M * BJ_M;
+  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) out[e] = U[e / BJ_M][e % BJ_M];
+}
+
+constexpr int BJ_VCOLS = 64;   // columns of V per block of the V update
+
+// Round t: blocks [0, P^2) form An[rows of pair a][columns of pair b] =
+// U_a^H A U_b; the remaining blocks form the rows of pair a of Vn = (V U)^T
+// over BJ_VCOLS columns: Vn[g(i)][c] = sum_k U_a[k][i] Vt[g(k)][c].
+__global__ __launch_bounds__(BJ_NT) void bj_apply_kernel(const double2* __restrict__ A, double2* __restrict__ An,
+                                                         const double2* __restrict__ Vt, double2* __restrict__ Vn,
+                                                         int N2, int t, const double2* __restrict__ Ublk) {
+  __shared__ double2 Ua[BJ_M][BJ_M + 1];
+  __shared__ double2 Ub[BJ_M][BJ_M + 1];
+  __shared__ double2 X[BJ_M][BJ_M + 1];
+  const int tid = threadIdx.x, nblk = N2 / BJ_B, P = nblk / 2;
+  constexpr int PER = BJ_M * BJ_M / BJ_NT;
+  if ((int)blockIdx.x < P * P) {
+    const int ka = blockIdx.x / P, kb = blockIdx.x % P;
+    int Ia, Ja, Ib, Jb;
+    round_pair(t, ka, nblk, Ia, Ja);
+    round_pair(t, kb, nblk, Ib, Jb);
+    const double2* ua = Ublk + (long long)ka * BJ_M * BJ_M;
+    const double2* ub = Ublk + (long long)kb * BJ_M * BJ_M;
+    for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) {
+      const int r = e / BJ_M, c = e % BJ_M;
+      Ua[r][c] = ua[e];
+      Ub[r][c] = ub[e];
+      X[r][c] = A[(long long)bj_index(Ia, Ja, r) * N2 + bj_index(Ib, Jb, c)];
+    }
+    __syncthreads();
+    double2 tmp[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + s * BJ_NT, r = e / BJ_M, c = e % BJ_M;
+      double2 acc{0.0, 0.0};
+      #pragma unroll 4
+      for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(X[r][l], Ub[l][c]));
+      tmp[s] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + s * BJ_NT;
+      X[e / BJ_M][e % BJ_M] = tmp[s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int e = tid + s * BJ_NT, r = e / BJ_M, c = e % BJ_M;
+      double2 acc{0.0, 0.0};
+      #pragma unroll 4
+      for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(cconj(Ua[l][r]), X[l][c]));
+      An[(long long)bj_index(Ia, Ja, r) * N2 + bj_index(Ib, Jb, c)] = acc;
     }
     return;
   }
-  g -= (long long)P * P;
-  if (g >= (long long)P * n) return;
-  const int I = (int)(g / n), col = (int)(g % n);
-  int pi[2];
-  round_pair(t, I, m, pi[0], pi[1]);
-  const Rot ri = make_rot(A, n, pi[0], pi[1]);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    if (pi[i] >= n) continue;
-    double2 s{0.0, 0.0};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      if (pi[k] >= n) continue;
-      s = cadd(s, cmul(jent(ri, k, i), Vt[(long long)pi[k] * n + col]));
-    }
-    Vn[(long long)pi[i] * n + col] = s;
+  const int nch = (N2 + BJ_VCOLS - 1) / BJ_VCOLS;
+  const int w = blockIdx.x - P * P, ka = w / nch, c0 = (w % nch) * BJ_VCOLS;
+  if (ka >= P) return;
+  int Ia, Ja;
+  round_pair(t, ka, nblk, Ia, Ja);
+  const double2* ua = Ublk + (long long)ka * BJ_M * BJ_M;
+  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) Ua[e / BJ_M][e % BJ_M] = ua[e];
+  __syncthreads();
+  for (int e = tid; e < BJ_M * BJ_VCOLS; e += BJ_NT) {
+    const int i = e / BJ_VCOLS, c = c0 + e % BJ_VCOLS;
+    if (c >= N2) continue;
+    double2 acc{0.0, 0.0};
+    #pragma unroll 4
+    for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(Ua[l][i], Vt[(long long)bj_index(Ia, Ja, l) * N2 + c]));
+    Vn[(long long)bj_index(Ia, Ja, i) * N2 + c] = acc;
   }
 }
 
-// A = (H + H^H) / 2, Vt = I
-__global__ __launch_bounds__(256) void hermitize_kernel(const double2* __restrict__ H, double2* __restrict__ A,
-                                                        double2* __restrict__ Vt, int n) {
+// A = (H + H^H) / 2 padded with zeros to order N2, Vt = I (order N2)
+__global__ __launch_bounds__(256) void hermitize_kernel(const double2* __restrict__ H, int n, double2* __restrict__ A,
+                                                        double2* __restrict__ Vt, int N2) {
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (g >= (long long)n * n) return;
-  const int i = (int)(g / n), j = (int)(g % n);
-  const double2 x = H[(long long)i * n + j], y = H[(long long)j * n + i];
-  A[g] = double2{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+  if (g >= (long long)N2 * N2) return;
+  const int i = (int)(g / N2), j = (int)(g % N2);
+  double2 a{0.0, 0.0};
+  if (i < n && j < n) {
+    const double2 x = H[(long long)i * n + j], y = H[(long long)j * n + i];
+    a = double2{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+  }
+  A[g] = a;
   Vt[g] = double2{i == j ? 1.0 : 0.0, 0.0};
 }
 
@@ -172,13 +263,13 @@ __global__ __launch_bounds__(RED_NT) void offdiag_kernel(const double2* __restri
 // phase that makes its entry of largest modulus (the first on ties) real and
 // positive.
 __global__ __launch_bounds__(RED_NT) void eig_finish_kernel(const double2* __restrict__ A,
-                                                            const double2* __restrict__ Vt, int n,
+                                                            const double2* __restrict__ Vt, int n, int ld,
                                                             double* __restrict__ eig, double2* __restrict__ Q) {
   __shared__ double sm[RED_NT];
   __shared__ int si[RED_NT], sc[RED_NT];
   const int i = blockIdx.x, tid = threadIdx.x;
-  const double li = A[(long long)i * n + i].x;
-  const double2* v = Vt + (long long)i * n;
+  const double li = A[(long long)i * ld + i].x;
+  const double2* v = Vt + (long long)i * ld;
   double best = -1.0;
   int bi = n, cnt = 0;
   for (int j = tid; j < n; j += RED_NT) {
@@ -188,7 +279,7 @@ __global__ __launch_bounds__(RED_NT) void eig_finish_kernel(const double2* __res
       best = mg;
       bi = j;
     }
-    const double lj = A[(long long)j * n + j].x;
+    const double lj = A[(long long)j * ld + j].x;
     cnt += (lj < li || (lj == li && j < i)) ? 1 : 0;
   }
   sm[tid] = best;
@@ -358,14 +449,25 @@ __global__ __launch_bounds__(SD_NT) void sd_update_kernel(double2* __restrict__ 
 
 // ------------------------------------------------------------------ launchers
 
-void launch_hermitize(int n, const double2* H, double2* A, double2* Vt, hipStream_t st) {
-  hermitize_kernel<<<(unsigned)(((long long)n * n + 255) / 256), 256, 0, st>>>(H, A, Vt, n);
+int bj_order(int n) { return (n + BJ_M - 1) / BJ_M * BJ_M; }
+
+int bj_rounds(int n) { return bj_order(n) / BJ_B - 1; }
+
+size_t bj_work_elems(int n) {
+  const size_t N2 = (size_t)bj_order(n);
+  return 4 * N2 * N2 + (N2 / BJ_M) * BJ_M * BJ_M;
 }
 
-void launch_jacobi_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, int t, hipStream_t st) {
-  const int m = n + (n & 1), P = m / 2;
-  const long long threads = (long long)P * P + (long long)P * n;
-  jacobi_round_kernel<<<(unsigned)((threads + 255) / 256), 256, 0, st>>>(A, An, Vt, Vn, n, m, t);
+void launch_hermitize(int n, const double2* H, double2* A, double2* Vt, hipStream_t st) {
+  const int N2 = bj_order(n);
+  hermitize_kernel<<<(unsigned)(((long long)N2 * N2 + 255) / 256), 256, 0, st>>>(H, n, A, Vt, N2);
+}
+
+void launch_bj_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, double2* Ublk, int t,
+                     hipStream_t st) {
+  const int N2 = bj_order(n), P = N2 / BJ_M, nch = (N2 + BJ_VCOLS - 1) / BJ_VCOLS;
+  bj_solve_kernel<<<P, BJ_NT, 0, st>>>(A, N2, t, Ublk);
+  bj_apply_kernel<<<P * P + P * nch, BJ_NT, 0, st>>>(A, An, Vt, Vn, N2, t, Ublk);
 }
 
 void launch_offdiag(int n, const double2* A, double* out, hipStream_t st) {
@@ -373,7 +475,7 @@ void launch_offdiag(int n, const double2* A, double* out, hipStream_t st) {
 }
 
 void launch_eig_finish(int n, const double2* A, const double2* Vt, double* eig, double2* Q, hipStream_t st) {
-  eig_finish_kernel<<<n, RED_NT, 0, st>>>(A, Vt, n, eig, Q);
+  eig_finish_kernel<<<n, RED_NT, 0, st>>>(A, Vt, n, bj_order(n), eig, Q);
 }
 
 void launch_sd_direction(int norb, int npw, int stride, const double2* C, const double2* W, const double* e,

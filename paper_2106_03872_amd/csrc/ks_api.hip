@@ -632,26 +632,27 @@ constexpr int JACOBI_MAX_SWEEPS = 60;
 
 // Eigenvalues (ascending, into eig) and eigenvectors (rows of Q, the phase
 // of each fixed so that its largest entry is real and positive) of the
-// Hermitian part of the n x n matrix H.  work: 4 n^2; off: 2 doubles.
-// Synchronises the stream once per Jacobi sweep.
+// Hermitian part of the n x n matrix H, by blocked Jacobi sweeps.  work:
+// bj_work_elems(n); off: 2 doubles.  Synchronises the stream once per sweep.
 ks_status subspace_eigh(ks_system* s, int n, const double2* H, double2* work, double* off, double* eig, double2* Q,
                         hipStream_t st) {
-  const size_t nn = (size_t)n * n;
-  double2 *A = work, *An = work + nn, *V = work + 2 * nn, *Vn = work + 3 * nn;
+  const int N2 = bj_order(n);
+  const size_t nn = (size_t)N2 * N2;
+  double2 *A = work, *An = work + nn, *V = work + 2 * nn, *Vn = work + 3 * nn, *Ublk = work + 4 * nn;
   ks_status r;
   if ((r = kcall(s, KS_K_EIG, st, "hermitize", [&] { launch_hermitize(n, H, A, V, st); return true; })) != KS_OK)
     return r;
-  const int m = n + (n & 1);
   bool done = n < 2;
   for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS && !done; ++sweep) {
-    for (int t = 0; t < m - 1; ++t) {
-      if ((r = kcall(s, KS_K_EIG, st, "jacobi", [&] { launch_jacobi_round(n, A, An, V, Vn, t, st); return true; })) !=
+    for (int t = 0; t < bj_rounds(n); ++t) {
+      if ((r = kcall(s, KS_K_EIG, st, "jacobi", [&] { launch_bj_round(n, A, An, V, Vn, Ublk, t, st); return true; })) !=
           KS_OK)
         return r;
       std::swap(A, An);
       std::swap(V, Vn);
     }
-    if ((r = kcall(s, KS_K_EIG, st, "offdiag", [&] { launch_offdiag(n, A, off, st); return true; })) != KS_OK) return r;
+    if ((r = kcall(s, KS_K_EIG, st, "offdiag", [&] { launch_offdiag(N2, A, off, st); return true; })) != KS_OK)
+      return r;
     double h[2] = {0.0, 0.0};
     KS_HIP(s, hipMemcpyAsync(h, off, sizeof(h), hipMemcpyDeviceToHost, st));
     KS_HIP(s, hipStreamSynchronize(st));
@@ -1200,7 +1201,8 @@ ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid
   if ((!t->aux && (r = dalloc(s, reinterpret_cast<void**>(&t->aux), blk)) != KS_OK) ||
       (!t->gs_buf[0] && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_buf[0]), blk)) != KS_OK) ||
       (!t->gs_buf[1] && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_buf[1]), blk)) != KS_OK) ||
-      (!t->gs_mat && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_mat), 6 * nn * sizeof(double2))) != KS_OK) ||
+      (!t->gs_mat &&
+       (r = dalloc(s, reinterpret_cast<void**>(&t->gs_mat), (2 * nn + bj_work_elems(n)) * sizeof(double2))) != KS_OK) ||
       (!t->gs_vec && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_vec), (2 * (size_t)n + 2) * sizeof(double))) != KS_OK) ||
       (r = ensure_ortho_mats(s)) != KS_OK)
     return r;

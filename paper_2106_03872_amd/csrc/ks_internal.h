@@ -153,7 +153,8 @@ struct ks_state {
   double2* data = nullptr;     // [norb][npw_stride]
   double2* aux = nullptr;      // [norb][npw_stride] ETRS predictor / eigensolver work (allocated on first use)
   // eigensolver work (allocated on first use): two more orbital blocks, the
-  // Rayleigh-Ritz matrix and its Jacobi iterates [6][norb][norb], and
+  // Rayleigh-Ritz matrix, its eigenvectors and the Jacobi work (2 norb^2 +
+  // bj_work_elems(norb) entries), and
   // [2*norb + 2] doubles (Ritz values, residual norms, off-diagonal norm)
   double2* gs_buf[2] = {nullptr, nullptr};
   double2* gs_mat = nullptr;
@@ -203,11 +204,18 @@ bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2*
 // Y[i][e] = sum_j Q[i][j] X[j][e]   (Q row-major norb x norb)
 bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ldx, double2* Y, int ldy, hipStream_t st);
 
-// subspace eigenproblem (k_ground.hip): A = (H + H^H)/2 and Vt = I; one
-// Jacobi round t (An, Vn from A, Vt); out = {off-diagonal |A|^2, |A|^2};
-// eigenvalues ascending and eigenvectors as the rows of Q, phase-fixed
+// subspace eigenproblem (k_ground.hip), blocked Jacobi on the matrix padded
+// to order bj_order(n): A = (H + H^H)/2 (padded with zeros) and Vt = I; one
+// round t (An, Vn from A, Vt; Ublk: the round's block unitaries); out =
+// {off-diagonal |A|^2, |A|^2} over the padded order; eigenvalues ascending
+// and eigenvectors as the rows of Q (n x n), phase-fixed.  Work elements:
+// bj_work_elems(n) (A, An, Vt, Vn, Ublk).
+int bj_order(int n);
+size_t bj_work_elems(int n);
+int bj_rounds(int n);
 void launch_hermitize(int n, const double2* H, double2* A, double2* Vt, hipStream_t st);
-void launch_jacobi_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, int t, hipStream_t st);
+void launch_bj_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, double2* Ublk, int t,
+                     hipStream_t st);
 void launch_offdiag(int n, const double2* A, double* out, hipStream_t st);
 void launch_eig_finish(int n, const double2* A, const double2* Vt, double* eig, double2* Q, hipStream_t st);
 // steepest-descent steps over norb packed orbitals (one block per orbital)
