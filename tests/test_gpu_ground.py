@@ -1,8 +1,9 @@
 """Steepest-descent eigensolver (Section "Ground-state solution") on the
 device against the FP64 oracle: orbitals, Ritz values and residual norms
 after every iteration, from orthonormalised random orbitals; ragged orbital
-counts (one orbital, an odd count, several passes), a longer run that
-converges, and the error paths.
+counts (one orbital, an odd count, several passes; 33 and 128 orbitals,
+whose subspace problems span several padded Jacobi blocks), a longer run
+that converges, and the error paths.
 
 Tolerance: the iteration is FP64 throughout; its operations (H psi at 1e-12,
 reductions, dense products, Jacobi rotations) each round at 1e-15 -- 1e-12,
@@ -59,7 +60,8 @@ def _oracle_run(ham, c0, K):
 
 
 @pytest.mark.parametrize("name,norb,chunk", [("t24", None, None), ("cfg1_16", None, None), ("t32x", 5, None),
-                                             ("t24", 1, None), ("t24", None, 4), ("t48", 12, None)])
+                                             ("t24", 1, None), ("t24", None, 4), ("t48", 12, None),
+                                             ("t48", None, None), ("cfg2_64", None, None)])
 def test_sd_iterations_vs_oracle(ks, name, norb, chunk):
     spec, ham, gs, st, c0 = _start(ks, name, norb, chunk)
     K = 3
