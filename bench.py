@@ -108,10 +108,29 @@ def cpu_baseline(spec, sysm, norb_sample=128):
     c1 = ko.taylor4_step(ham, c, spec.dt, 1)
     ko.density(ham, c1, np.full(norb_sample, spec.occ))
     dt = time.perf_counter() - t0
-    return {"value": 4 * norb_sample / dt, "unit": "orbital·Hψ/s", "cores": ko.WORKERS,
+    # the same on one thread, over a smaller slice
+    n1 = max(1, norb_sample // 16)
+    workers = ko.WORKERS
+    ko.WORKERS = 1
+    try:
+        t0 = time.perf_counter()
+        c1 = ko.taylor4_step(ham, c[:n1], spec.dt, 1)
+        ko.density(ham, c1, np.full(n1, spec.occ))
+        dt1 = time.perf_counter() - t0
+    finally:
+        ko.WORKERS = workers
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": 4 * norb_sample / dt, "unit": "orbital·Hψ/s", "cores": workers,
             "kind": "oracle",
             "sample": f"{norb_sample} of {spec.norb} orbitals, one Taylor-4 step (4 H psi each) + density, "
-                      f"{spec.n[0]}^3 grid, {spec.natoms} atoms; {dt:.1f} s"}
+                      f"{spec.n[0]}^3 grid, {spec.natoms} atoms; {dt:.1f} s",
+            "one_thread": {"value": 4 * n1 / dt1, "sample": f"{n1} orbitals, same step; {dt1:.1f} s"},
+            "cpu_model": model}
 
 
 def setup_workload(spec, precision, chunk=0):
@@ -129,7 +148,20 @@ def setup_workload(spec, precision, chunk=0):
     c[:, torch.from_numpy(sel).to(dev)] = torch.from_numpy(vals).to(dev)
     c = c.reshape((spec.norb,) + tuple(spec.n))
     del vals
+    torch.cuda.synchronize()
+    gs.set_kernel_timing(True)
+    t0 = time.perf_counter()
     gs.orthonormalize(c)                 # Cholesky of the overlap (set-up)
+    torch.cuda.synchronize()
+    ortho_ms = (time.perf_counter() - t0) * 1e3
+    gemm_ms = gs.kernel_times()["gemm"][0]
+    gs.set_kernel_timing(False)
+    # overlap (tiles on and below the diagonal) and triangular apply: about
+    # n^2 npw complex MACs together, 8 real flops each
+    flop = 8.0 * spec.norb ** 2 * gs.npw
+    gs.ortho = {"ms": round(ortho_ms, 3), "gemm_ms": round(gemm_ms, 3),
+                "gemm_tflops": round(flop / (gemm_ms * 1e-3) / 1e12, 2) if gemm_ms > 0 else None,
+                "gemm_peak_tflops": 78.6, "orbitals": spec.norb}
     state = ks.State(gs, spec.norb)
     state.upload(c)
     del c
@@ -328,6 +360,9 @@ def main():
     sysm, gs, state = setup_workload(spec, ks.KS_FP64, args.chunk)
     info = gs.info()
     log(f"[bench] FP64 set-up done, chunk {info['chunk']}, npw {info['npw']}, tuning {gs.tuning}")
+    ortho = gs.ortho
+    log(f"[bench] orthonormalisation of {spec.norb} orbitals: {ortho['ms']:.2f} ms, "
+        f"products {ortho['gemm_tflops']} TFLOP/s")
     ms_step, ktimes, phys, rho64 = run_steps(spec, gs, state, args.steps, args.warmup)
     hpsi_per_step = 4 * spec.norb
     value = hpsi_per_step / (ms_step * 1e-3)
@@ -424,6 +459,7 @@ def main():
         "mixed_120": mixed_120,
         "etrs": etrs,
         "ground_state": ground,
+        "orthonormalisation": ortho,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -1002,10 +1002,13 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
   double2* box = (double2*)psi;
   if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, norb, box, s->N, P, st); })) != KS_OK) return r;
-  if ((r = launch_ok(s, launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, s->gemm_part, st), "overlap")) != KS_OK) return r;
+  if ((r = kcall(s, KS_K_GEMM, st, "overlap",
+                 [&] { return launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, s->gemm_part, st); })) != KS_OK)
+    return r;
   if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(norb, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
-  if ((r = launch_ok(s, launch_apply_lower(norb, s->npw, s->ortho_W, P, s->npw_stride, Y, st), "apply")) != KS_OK)
+  if ((r = kcall(s, KS_K_GEMM, st, "apply",
+                 [&] { return launch_apply_lower(norb, s->npw, s->ortho_W, P, s->npw_stride, Y, st); })) != KS_OK)
     return r;
   int info = 0;
   KS_HIP(s, hipMemcpyAsync(&info, s->ortho_info, sizeof(int), hipMemcpyDeviceToHost, st));
