@@ -82,7 +82,6 @@ __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restri
                                                          double2* __restrict__ Ublk) {
   __shared__ double2 S[BJ_M][BJ_M + 1];
   __shared__ double2 U[BJ_M][BJ_M + 1];
-  __shared__ Rot rot[BJ_B];
   const int k = blockIdx.x, tid = threadIdx.x;
   int I, J;
   round_pair(t, k, N2 / BJ_B, I, J);
@@ -94,17 +93,13 @@ __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restri
   __syncthreads();
   const int P2 = tid / BJ_B, Q2 = tid % BJ_B;
   for (int r = 0; r < BJ_M - 1; ++r) {
-    if (tid < BJ_B) {
-      int p, q;
-      round_pair(r, tid, BJ_M, p, q);
-      rot[tid] = make_rot(S[p][p].x, S[q][q].x, S[p][q]);
-    }
-    __syncthreads();
-    // 2x2 block (P2, Q2) of S <- J^H S J (each block has one owner)
+    // 2x2 block (P2, Q2) of S <- J^H S J (each block has one owner); every
+    // thread forms the two rotations it needs from the diagonal blocks
     int pi[2], pk[2];
     round_pair(r, P2, BJ_M, pi[0], pi[1]);
     round_pair(r, Q2, BJ_M, pk[0], pk[1]);
-    const Rot ri = rot[P2], rk = rot[Q2];
+    const Rot ri = make_rot(S[pi[0]][pi[0]].x, S[pi[1]][pi[1]].x, S[pi[0]][pi[1]]);
+    const Rot rk = make_rot(S[pk[0]][pk[0]].x, S[pk[1]][pk[1]].x, S[pk[0]][pk[1]]);
     double2 blk[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -231,16 +226,44 @@ __global__ __launch_bounds__(256) void hermitize_kernel(const double2* __restric
 
 constexpr int RED_NT = 256;
 
-// out[0] = sum_{i != j} |A_ij|^2, out[1] = sum |A_ij|^2 (one block, fixed order)
-__global__ __launch_bounds__(RED_NT) void offdiag_kernel(const double2* __restrict__ A, int n, double* __restrict__ out) {
+// Row i: part[2i] = sum_{j != i} |A_ij|^2, part[2i+1] = sum_j |A_ij|^2
+// (fixed order); offdiag_sum_kernel adds the rows in order into out[0..1].
+__global__ __launch_bounds__(RED_NT) void offdiag_rows_kernel(const double2* __restrict__ A, int n,
+                                                              double* __restrict__ part) {
+  __shared__ double s0[RED_NT], s1[RED_NT];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const double2* row = A + (long long)i * n;
+  double off = 0.0, all = 0.0;
+  for (int j = tid; j < n; j += RED_NT) {
+    const double2 a = row[j];
+    const double v = a.x * a.x + a.y * a.y;
+    all += v;
+    if (j != i) off += v;
+  }
+  s0[tid] = off;
+  s1[tid] = all;
+  __syncthreads();
+  for (int h = RED_NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      s0[tid] += s0[tid + h];
+      s1[tid] += s1[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[2 * i] = s0[0];
+    part[2 * i + 1] = s1[0];
+  }
+}
+
+__global__ __launch_bounds__(RED_NT) void offdiag_sum_kernel(const double* __restrict__ part, int n,
+                                                             double* __restrict__ out) {
   __shared__ double s0[RED_NT], s1[RED_NT];
   const int tid = threadIdx.x;
   double off = 0.0, all = 0.0;
-  for (long long g = tid; g < (long long)n * n; g += RED_NT) {
-    const double2 a = A[g];
-    const double v = a.x * a.x + a.y * a.y;
-    all += v;
-    if (g / n != g % n) off += v;
+  for (int i = tid; i < n; i += RED_NT) {
+    off += part[2 * i];
+    all += part[2 * i + 1];
   }
   s0[tid] = off;
   s1[tid] = all;
@@ -470,8 +493,9 @@ void launch_bj_round(int n, const double2* A, double2* An, const double2* Vt, do
   bj_apply_kernel<<<P * P + P * nch, BJ_NT, 0, st>>>(A, An, Vt, Vn, N2, t, Ublk);
 }
 
-void launch_offdiag(int n, const double2* A, double* out, hipStream_t st) {
-  offdiag_kernel<<<1, RED_NT, 0, st>>>(A, n, out);
+void launch_offdiag(int n, const double2* A, double* part, double* out, hipStream_t st) {
+  offdiag_rows_kernel<<<n, RED_NT, 0, st>>>(A, n, part);
+  offdiag_sum_kernel<<<1, RED_NT, 0, st>>>(part, n, out);
 }
 
 void launch_eig_finish(int n, const double2* A, const double2* Vt, double* eig, double2* Q, hipStream_t st) {

@@ -633,7 +633,8 @@ constexpr int JACOBI_MAX_SWEEPS = 60;
 // Eigenvalues (ascending, into eig) and eigenvectors (rows of Q, the phase
 // of each fixed so that its largest entry is real and positive) of the
 // Hermitian part of the n x n matrix H, by blocked Jacobi sweeps.  work:
-// bj_work_elems(n); off: 2 doubles.  Synchronises the stream once per sweep.
+// bj_work_elems(n); off: 2 + 2 bj_order(n) doubles.  Synchronises the stream
+// once per sweep.
 ks_status subspace_eigh(ks_system* s, int n, const double2* H, double2* work, double* off, double* eig, double2* Q,
                         hipStream_t st) {
   const int N2 = bj_order(n);
@@ -651,7 +652,7 @@ ks_status subspace_eigh(ks_system* s, int n, const double2* H, double2* work, do
       std::swap(A, An);
       std::swap(V, Vn);
     }
-    if ((r = kcall(s, KS_K_EIG, st, "offdiag", [&] { launch_offdiag(N2, A, off, st); return true; })) != KS_OK)
+    if ((r = kcall(s, KS_K_EIG, st, "offdiag", [&] { launch_offdiag(N2, A, off + 2, off, st); return true; })) != KS_OK)
       return r;
     double h[2] = {0.0, 0.0};
     KS_HIP(s, hipMemcpyAsync(h, off, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -1206,7 +1207,8 @@ ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid
       (!t->gs_buf[1] && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_buf[1]), blk)) != KS_OK) ||
       (!t->gs_mat &&
        (r = dalloc(s, reinterpret_cast<void**>(&t->gs_mat), (2 * nn + bj_work_elems(n)) * sizeof(double2))) != KS_OK) ||
-      (!t->gs_vec && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_vec), (2 * (size_t)n + 2) * sizeof(double))) != KS_OK) ||
+      (!t->gs_vec && (r = dalloc(s, reinterpret_cast<void**>(&t->gs_vec),
+                                 (2 * (size_t)n + 2 + 2 * (size_t)bj_order(n)) * sizeof(double))) != KS_OK) ||
       (r = ensure_ortho_mats(s)) != KS_OK)
     return r;
   double2 *C = t->data, *B1 = t->aux, *B2 = t->gs_buf[0], *B3 = t->gs_buf[1];

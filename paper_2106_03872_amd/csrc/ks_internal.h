@@ -154,8 +154,8 @@ struct ks_state {
   double2* aux = nullptr;      // [norb][npw_stride] ETRS predictor / eigensolver work (allocated on first use)
   // eigensolver work (allocated on first use): two more orbital blocks, the
   // Rayleigh-Ritz matrix, its eigenvectors and the Jacobi work (2 norb^2 +
-  // bj_work_elems(norb) entries), and
-  // [2*norb + 2] doubles (Ritz values, residual norms, off-diagonal norm)
+  // bj_work_elems(norb) entries), and [2*norb + 2 + 2*bj_order(norb)]
+  // doubles (Ritz values, residual norms, off-diagonal norm, its row partials)
   double2* gs_buf[2] = {nullptr, nullptr};
   double2* gs_mat = nullptr;
   double* gs_vec = nullptr;
@@ -207,7 +207,8 @@ bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ld
 // subspace eigenproblem (k_ground.hip), blocked Jacobi on the matrix padded
 // to order bj_order(n): A = (H + H^H)/2 (padded with zeros) and Vt = I; one
 // round t (An, Vn from A, Vt; Ublk: the round's block unitaries); out =
-// {off-diagonal |A|^2, |A|^2} over the padded order; eigenvalues ascending
+// {off-diagonal |A|^2, |A|^2} over the padded order (per-row partials in
+// part, 2 per row); eigenvalues ascending
 // and eigenvectors as the rows of Q (n x n), phase-fixed.  Work elements:
 // bj_work_elems(n) (A, An, Vt, Vn, Ublk).
 int bj_order(int n);
@@ -216,7 +217,7 @@ int bj_rounds(int n);
 void launch_hermitize(int n, const double2* H, double2* A, double2* Vt, hipStream_t st);
 void launch_bj_round(int n, const double2* A, double2* An, const double2* Vt, double2* Vn, double2* Ublk, int t,
                      hipStream_t st);
-void launch_offdiag(int n, const double2* A, double* out, hipStream_t st);
+void launch_offdiag(int n, const double2* A, double* part /*2n*/, double* out, hipStream_t st);
 void launch_eig_finish(int n, const double2* A, const double2* Vt, double* eig, double2* Q, hipStream_t st);
 // steepest-descent steps over norb packed orbitals (one block per orbital)
 void launch_sd_direction(int norb, int npw, int stride, const double2* C, const double2* W, const double* e,
