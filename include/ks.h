@@ -230,7 +230,9 @@ ks_status ks_state_kick(ks_state* state, const double k[3], void* stream);
  *   1. W = H C; subspace diagonalisation: the Rayleigh-Ritz matrix
  *      C^H W, made exactly Hermitian, = Q diag(e) Q^H with e ascending and
  *      each column of Q scaled so that its entry of largest modulus (the
- *      first on ties) is real and positive; C <- C Q, W <- W Q;
+ *      first on ties) is real and positive; C <- C Q, W <- W Q (the
+ *      eigenproblem by blocked Jacobi sweeps until the off-diagonal
+ *      Frobenius norm is at most 1e-14 of the matrix's, at most 60 sweeps);
  *   2. per orbital: residual r = w - e c; T = sum_G K|r|^2 / sum_G |r|^2
  *      with K = |G|^2/2; direction p = t(K/T) r with the Teter-Payne-Allan
  *      factor t(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4) (p = r
