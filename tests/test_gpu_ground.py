@@ -142,3 +142,17 @@ def test_sd_full_size_cfg3(ks):
     S = (out.conj() @ out.T).cpu().numpy()
     assert np.abs(S - np.eye(spec.norb)).max() < 1e-11
     st.close()
+
+
+def test_sd_is_deterministic(ks):
+    """Fixed-order reductions everywhere: two runs from the same start give
+    bit-identical orbitals, Ritz values and residual norms."""
+    spec, ham, gs, st, c0 = _start(ks, "t48")
+    st2 = ks.State(gs, spec.norb)
+    st2.upload(torch.from_numpy(c0).cuda())
+    e1, r1 = st.eigensolve(3)
+    e2, r2 = st2.eigensolve(3)
+    assert torch.equal(e1, e2) and torch.equal(r1, r2)
+    assert torch.equal(st.download(), st2.download())
+    st.close()
+    st2.close()
