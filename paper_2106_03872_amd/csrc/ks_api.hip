@@ -591,10 +591,12 @@ ks_status ensure_ortho_mats(ks_system* s) {
       (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_W), n * n * sizeof(double2))) != KS_OK ||
       (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_info), sizeof(int))) != KS_OK ||
       (r = dalloc(s, reinterpret_cast<void**>(&s->ortho_diag), n * sizeof(double))) != KS_OK ||
-      (r = dalloc(s, reinterpret_cast<void**>(&s->gemm_part), GEMM_PART_BYTES)) != KS_OK) {
+      ((s->gemm_part_bytes = gemm_part_bytes(s->max_norb, s->npw)) > 0 &&
+       (r = dalloc(s, reinterpret_cast<void**>(&s->gemm_part), s->gemm_part_bytes)) != KS_OK)) {
     void* p[] = {s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag, s->gemm_part};
     for (void* q : p) dfree(q);
     s->ortho_S = s->ortho_W = s->gemm_part = nullptr;
+    s->gemm_part_bytes = 0;
     s->ortho_info = nullptr;
     s->ortho_diag = nullptr;
     return r;
@@ -609,7 +611,7 @@ ks_status orthonormalize_packed(ks_system* s, int n, double2* C, double2* Y, hip
   ks_status r;
   const size_t ld = s->npw_stride;
   KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
-  if ((r = kcall(s, KS_K_GEMM, st, "overlap", [&] { return launch_overlap(n, s->npw, C, ld, s->ortho_S, s->gemm_part, st); })) != KS_OK)
+  if ((r = kcall(s, KS_K_GEMM, st, "overlap", [&] { return launch_overlap(n, s->npw, C, ld, s->ortho_S, s->gemm_part, s->gemm_part_bytes, st); })) != KS_OK)
     return r;
   if ((r = launch_ok(s, launch_cholesky(n, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(n, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
@@ -1004,7 +1006,7 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   double2* box = (double2*)psi;
   if ((r = kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, norb, box, s->N, P, st); })) != KS_OK) return r;
   if ((r = kcall(s, KS_K_GEMM, st, "overlap",
-                 [&] { return launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, s->gemm_part, st); })) != KS_OK)
+                 [&] { return launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, s->gemm_part, s->gemm_part_bytes, st); })) != KS_OK)
     return r;
   if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(norb, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
@@ -1223,7 +1225,7 @@ ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid
       if ((r = hpsi_packed(s, std::min(cl, n - o0), C + o0 * ld, true, B1 + o0 * ld, nullptr, H_OUT, none, st)) != KS_OK)
         return r;
     // subspace diagonalisation: Hs = C^H W = Q diag(e) Q^H; C <- Q^T C, W <- Q^T W
-    if ((r = kcall(s, KS_K_GEMM, st, "rayleigh_ritz", [&] { return launch_gemm_ch(n, s->npw, C, ld, B1, ld, Hs, s->gemm_part, st); })) !=
+    if ((r = kcall(s, KS_K_GEMM, st, "rayleigh_ritz", [&] { return launch_gemm_ch(n, s->npw, C, ld, B1, ld, Hs, s->gemm_part, s->gemm_part_bytes, st); })) !=
         KS_OK)
       return r;
     if ((r = subspace_eigh(s, n, Hs, work, off, e, Qm, st)) != KS_OK) return r;
@@ -1335,6 +1337,7 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
   b += npoints * (np * 8.0 + 4 * 4.0) + 64.0 * 1024;    // KB tables
   b += (double)cb * npoints * np * 16.0 / 8.0;          // projection partials (upper bound)
   b += (double)norb * stride * 16.0;                    // resident state
+  b += 2.0 * norb * norb * 16.0 + (double)gemm_part_bytes(norb, h.npw);   // orthonormalisation
   *bytes = (unsigned long long)b;
   return KS_OK;
 }

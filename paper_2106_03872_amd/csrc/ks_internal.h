@@ -54,7 +54,7 @@ constexpr int UP_POS_BITS = 16, UP_SLOT_BITS = 8;
 constexpr int UP_MAX_SLOT = (1 << UP_SLOT_BITS) - 1, UP_MAX_EXTRA = 127;
 
 constexpr int KB_MAX_NPROJ = 8;        // projectors per atom
-constexpr size_t GEMM_PART_BYTES = 64ull << 20;   // split-K partials of the n x n products
+constexpr size_t GEMM_PART_MAX = 256ull << 20;    // largest split-K partial buffer of the n x n products
 constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-tile
 constexpr int KB_ITEM_LANES = 256;     // lanes of an x-pencil block (projection work items)
 constexpr int KB_CACHED_POINTS = 16;   // points of an item held in registers across orbitals
@@ -132,7 +132,8 @@ struct ks_system {
   double2* ortho_W = nullptr;
   int* ortho_info = nullptr;
   double* ortho_diag = nullptr;
-  double2* gemm_part = nullptr;   // GEMM_PART_BYTES of split-K partials
+  double2* gemm_part = nullptr;   // split-K partials of the n x n products (gemm_part_bytes)
+  size_t gemm_part_bytes = 0;
   int ortho_cap = 0;
 
   // kernel timing (ks_set_kernel_timing)
@@ -183,8 +184,11 @@ bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, 
                   hipStream_t st);
 bool launch_dots(const ks_system* s, int nb, const void* a, const void* b, double* out, hipStream_t st);
 bool launch_energy_sum(int norb, const double* occ, const double* red, double* energy, hipStream_t st);
-// part: split-K partial products (GEMM_PART_BYTES)
-bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, double2* part, hipStream_t st);
+// part: split-K partial products (part_bytes of them; NULL: no split)
+bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, double2* part, size_t part_bytes,
+                    hipStream_t st);
+// bytes of split-K partials the products of up to n orbitals over K use
+size_t gemm_part_bytes(int n, int K);
 bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st);
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st);
@@ -200,7 +204,7 @@ bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t
 // dense complex products for the eigensolver (MFMA FP64):
 // S[i][j] = sum_e conj(A[i][e]) B[j][e]   (norb x norb, rows of length npw)
 bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2* B, int ldb, double2* S, double2* part,
-                    hipStream_t st);
+                    size_t part_bytes, hipStream_t st);
 // Y[i][e] = sum_j Q[i][j] X[j][e]   (Q row-major norb x norb)
 bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ldx, double2* Y, int ldy, hipStream_t st);
 

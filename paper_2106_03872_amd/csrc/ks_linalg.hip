@@ -22,14 +22,24 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 // k-tiles above the diagonal are skipped.  LOWER_OUT: only tiles with
 // m-tile >= n-tile are produced.
 //
-// Split K: block z of the grid's third dimension sums k in [z kchunk,
-// (z+1) kchunk) (kchunk a multiple of GBK) into Cout + z * cstride; a fixed-
-// order sum over z (sum_partials_kernel) completes the product.
+// Split K: chunk z sums k in [z kchunk, (z+1) kchunk) (kchunk a multiple of
+// GBK) into Cout + z * cstride; a fixed-order sum over z
+// (sum_partials_kernel) completes the product.
+//
+// Block order (one-dimensional grid of mt * nt * nz tiles, rounded up to a
+// multiple of XCDS): the hardware hands workgroup w to XCD w mod XCDS, so
+// logical tile l = (w mod XCDS) * G/XCDS + w / XCDS gives each XCD a
+// contiguous run of logical tiles, and the logical order puts tiles that
+// read the same operand next to each other, so that its L2 serves the
+// repeats: with B_KN, the m-tiles of one n-tile (which share B's column
+// block); otherwise the tiles of one K chunk (which share that chunk of A
+// and B).
 //
 // v_mfma_f64_16x16x4_f64 operand layout on gfx950 (64 lanes, measured):
 // A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane
 // j + 16 (i mod 4), element i div 4 of the 4-double accumulator.
 constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int XCDS = 8;   // accelerator dies (each with its own L2)
 
 template <bool CONJ_A, bool B_KN, bool LOWER_A, bool LOWER_OUT>
 __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, const double2* __restrict__ A, long long lda,
@@ -39,7 +49,23 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, co
   __shared__ double2 As[GBK][GBM + 1];
   __shared__ double2 Bs[GBK][GBN + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int mt = (M + GBM - 1) / GBM, nt = (N + GBN - 1) / GBN;
+  const int nz = (K + kchunk - 1) / kchunk;
+  const long long tiles = (long long)mt * nt * nz;
+  const long long per = gridDim.x / XCDS;
+  const long long l = (long long)(blockIdx.x % XCDS) * per + blockIdx.x / XCDS;
+  if (l >= tiles) return;
+  int mi, ni, z;
+  if (B_KN) {
+    mi = (int)(l % mt);
+    ni = (int)((l / mt) % nt);
+    z = (int)(l / ((long long)mt * nt));
+  } else {
+    ni = (int)(l % nt);
+    mi = (int)((l / nt) % mt);
+    z = (int)(l / ((long long)mt * nt));
+  }
+  const int m0 = mi * GBM, n0 = ni * GBN;
   if (LOWER_OUT && n0 > m0) return;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   dvec4 re[2][2], im[2][2];
@@ -47,9 +73,9 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, co
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) re[a][b] = im[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
-  const int kbeg = blockIdx.z * kchunk;
+  const int kbeg = z * kchunk;
   const int kend = LOWER_A ? min(min(K, kbeg + kchunk), m0 + GBM) : min(K, kbeg + kchunk);
-  Cout += blockIdx.z * cstride;
+  Cout += z * cstride;
   const double sa = CONJ_A ? -1.0 : 1.0;
   for (int k0 = kbeg; k0 < kend; k0 += GBK) {
     // A tile: 64 rows x 16 k, k fastest across threads
@@ -286,6 +312,12 @@ __global__ void zero_upper_kernel(double2* X, int n) {
 
 // ------------------------------------------------------------------ launchers
 
+// one-dimensional grid of the mt * nt * nz tiles, a multiple of XCDS
+unsigned gemm_grid(int M, int N, int nz) {
+  const long long t = (long long)((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN) * nz;
+  return (unsigned)((t + XCDS - 1) / XCDS * XCDS);
+}
+
 // Fixed-order sum of nz partial products [nz][n][n] (only tiles on or below
 // the diagonal when lower)
 __global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __restrict__ part, int nz, int n, bool lower,
@@ -304,17 +336,17 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __rest
 }
 
 // Split of the K = npw contraction for an n x n product: enough blocks to
-// fill the chip (about 2048), chunks of at least 256, partials within
-// GEMM_PART_BYTES.
+// fill the chip (about 2048 working blocks), chunks of at least 256,
+// partials within part_bytes.
 struct KSplit {
   int nz, kchunk;
 };
 
-KSplit ksplit(int n, int K, bool lower) {
+KSplit ksplit(int n, int K, bool lower, size_t part_bytes) {
   const long long t = (long long)((n + GBN - 1) / GBN) * ((n + GBM - 1) / GBM);
   const long long tiles = lower ? (t + (n + GBM - 1) / GBM) / 2 : t;
   long long nz = (2048 + tiles - 1) / tiles;
-  nz = std::min<long long>(nz, (long long)(GEMM_PART_BYTES / ((size_t)n * n * sizeof(double2))));
+  nz = std::min<long long>(nz, (long long)(part_bytes / ((size_t)n * n * sizeof(double2))));
   nz = std::min<long long>(nz, (K + 255) / 256);
   nz = std::max<long long>(nz, 1);
   int kchunk = (int)((K + nz - 1) / nz);
@@ -322,10 +354,20 @@ KSplit ksplit(int n, int K, bool lower) {
   return KSplit{(K + kchunk - 1) / kchunk, kchunk};
 }
 
-bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, double2* part, hipStream_t st) {
+size_t gemm_part_bytes(int n, int K) {
+  size_t b = 0;
+  for (bool lower : {true, false}) {
+    const KSplit sp = ksplit(n, K, lower, GEMM_PART_MAX);
+    if (sp.nz > 1) b = std::max(b, (size_t)sp.nz * n * n * sizeof(double2));
+  }
+  return b;
+}
+
+bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, double2* part, size_t part_bytes,
+                    hipStream_t st) {
   // S[i][j] = sum_e conj(P[i][e]) P[j][e], tiles on and below the diagonal
-  const KSplit sp = ksplit(norb, npw, true);
-  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM, sp.nz);
+  const KSplit sp = ksplit(norb, npw, true, part ? part_bytes : 0);
+  const unsigned grid = gemm_grid(norb, norb, sp.nz);
   if (sp.nz == 1) {
     zgemm_mfma_kernel<true, false, false, true><<<grid, 256, 0, st>>>(norb, norb, npw, P, ldp, P, ldp, S, norb, sp.kchunk, 0);
     return true;
@@ -363,16 +405,16 @@ bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st) {
 }
 
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st) {
-  dim3 grid((npw + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
+  const unsigned grid = gemm_grid(norb, npw, 1);
   // Y[i][e] = sum_{j <= i} conj(X[i][j]) P[j][e]
   zgemm_mfma_kernel<true, true, true, false><<<grid, 256, 0, st>>>(norb, npw, norb, X, norb, P, ldp, Y, ldp, norb, 0);
   return true;
 }
 
 bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2* B, int ldb, double2* S, double2* part,
-                    hipStream_t st) {
-  const KSplit sp = ksplit(norb, npw, false);
-  dim3 grid((norb + GBN - 1) / GBN, (norb + GBM - 1) / GBM, sp.nz);
+                    size_t part_bytes, hipStream_t st) {
+  const KSplit sp = ksplit(norb, npw, false, part ? part_bytes : 0);
+  const unsigned grid = gemm_grid(norb, norb, sp.nz);
   if (sp.nz == 1) {
     zgemm_mfma_kernel<true, false, false, false><<<grid, 256, 0, st>>>(norb, norb, npw, A, lda, B, ldb, S, norb, sp.kchunk, 0);
     return true;
@@ -384,7 +426,7 @@ bool launch_gemm_ch(int norb, int npw, const double2* A, int lda, const double2*
 }
 
 bool launch_rotate(int norb, int npw, const double2* Q, const double2* X, int ldx, double2* Y, int ldy, hipStream_t st) {
-  dim3 grid((npw + GBN - 1) / GBN, (norb + GBM - 1) / GBM);
+  const unsigned grid = gemm_grid(norb, npw, 1);
   zgemm_mfma_kernel<false, true, false, false><<<grid, 256, 0, st>>>(norb, npw, norb, Q, norb, X, ldx, Y, ldy, norb, 0);
   return true;
 }
