@@ -77,27 +77,42 @@ __global__ __launch_bounds__(256) void zgemm_mfma_kernel(int M, int N, int K, co
   const int kend = LOWER_A ? min(min(K, kbeg + kchunk), m0 + GBM) : min(K, kbeg + kchunk);
   Cout += z * cstride;
   const double sa = CONJ_A ? -1.0 : 1.0;
-  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
-    // A tile: 64 rows x 16 k, k fastest across threads
-    for (int i = tid; i < GBM * GBK; i += 256) {
-      const int kk = i % GBK, mm = i / GBK;
-      const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? A[(long long)m * lda + k] : double2{0.0, 0.0};
-    }
-    if (B_KN) {
-      for (int i = tid; i < GBN * GBK; i += 256) {
+  // The next k-tile is loaded into registers while the current one is
+  // multiplied from LDS.  A tile: 64 rows x 16 k, k fastest across threads.
+  constexpr int PT = GBM * GBK / 256;
+  static_assert(GBN * GBK / 256 == PT, "equal A and B tile shares");
+  double2 ra[PT], rb[PT];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int i = tid + j * 256;
+      {
+        const int kk = i % GBK, mm = i / GBK;
+        const int m = m0 + mm, k = k0 + kk;
+        ra[j] = (m < M && k < K) ? A[(long long)m * lda + k] : double2{0.0, 0.0};
+      }
+      if (B_KN) {
         const int nn = i % GBN, kk = i / GBN;
         const int n = n0 + nn, k = k0 + kk;
-        Bs[kk][nn] = (n < N && k < K) ? Bm[(long long)k * ldb + n] : double2{0.0, 0.0};
-      }
-    } else {
-      for (int i = tid; i < GBN * GBK; i += 256) {
+        rb[j] = (n < N && k < K) ? Bm[(long long)k * ldb + n] : double2{0.0, 0.0};
+      } else {
         const int kk = i % GBK, nn = i / GBK;
         const int n = n0 + nn, k = k0 + kk;
-        Bs[kk][nn] = (n < N && k < K) ? Bm[(long long)n * ldb + k] : double2{0.0, 0.0};
+        rb[j] = (n < N && k < K) ? Bm[(long long)n * ldb + k] : double2{0.0, 0.0};
       }
     }
+  };
+  if (kbeg < kend) load_tile(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int i = tid + j * 256;
+      As[i % GBK][i / GBK] = ra[j];
+      if (B_KN) Bs[i / GBN][i % GBN] = rb[j];
+      else Bs[i % GBK][i / GBK] = rb[j];
+    }
     __syncthreads();
+    if (k0 + GBK < kend) load_tile(k0 + GBK);
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 4) {
       const int kr = ks + (lane >> 4), c = lane & 15;
