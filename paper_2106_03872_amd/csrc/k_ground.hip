@@ -82,6 +82,7 @@ __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restri
                                                          double2* __restrict__ Ublk) {
   __shared__ double2 S[BJ_M][BJ_M + 1];
   __shared__ double2 U[BJ_M][BJ_M + 1];
+  __shared__ Rot rot[BJ_B];
   const int k = blockIdx.x, tid = threadIdx.x;
   int I, J;
   round_pair(t, k, N2 / BJ_B, I, J);
@@ -93,13 +94,19 @@ __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restri
   __syncthreads();
   const int P2 = tid / BJ_B, Q2 = tid % BJ_B;
   for (int r = 0; r < BJ_M - 1; ++r) {
-    // 2x2 block (P2, Q2) of S <- J^H S J (each block has one owner); every
-    // thread forms the two rotations it needs from the diagonal blocks
+    // the round's BJ_B rotations, one per thread of the first wave (forming
+    // them in every thread instead costs more than this barrier)
+    if (tid < BJ_B) {
+      int p, q;
+      round_pair(r, tid, BJ_M, p, q);
+      rot[tid] = make_rot(S[p][p].x, S[q][q].x, S[p][q]);
+    }
+    __syncthreads();
+    // 2x2 block (P2, Q2) of S <- J^H S J (each block has one owner)
     int pi[2], pk[2];
     round_pair(r, P2, BJ_M, pi[0], pi[1]);
     round_pair(r, Q2, BJ_M, pk[0], pk[1]);
-    const Rot ri = make_rot(S[pi[0]][pi[0]].x, S[pi[1]][pi[1]].x, S[pi[0]][pi[1]]);
-    const Rot rk = make_rot(S[pk[0]][pk[0]].x, S[pk[1]][pk[1]].x, S[pk[0]][pk[1]]);
+    const Rot ri = rot[P2], rk = rot[Q2];
     double2 blk[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
