@@ -156,3 +156,28 @@ def test_sd_is_deterministic(ks):
     assert torch.equal(st.download(), st2.download())
     st.close()
     st2.close()
+
+
+def test_sd_local_only_system(ks):
+    """No projectors (the x-projection pass is skipped): 3 iterations against
+    the oracle on the t24 grid with its local potential only."""
+    print("[case] ground t24 local only", file=sys.stderr, flush=True)
+    spec = synth.CONFIGS["t24"]
+    sysm = synth.system(spec)
+    g = ko.Grid(spec.n, spec.L, spec.ecut)
+    ham = ko.Hamiltonian(g, sysm.vloc)
+    gs = ks.System(spec.n, spec.L, spec.ecut, spec.norb)
+    gs.set_vloc(torch.from_numpy(sysm.vloc).cuda())
+    c = orbitals_device(spec)
+    gs.orthonormalize(c)
+    c0 = c.cpu().numpy()
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    eig, resid = st.eigensolve(3)
+    ref, E, RN = _oracle_run(ham, c0, 3)
+    got = st.download().cpu().numpy()
+    print(f"[ground] t24 local only: orbital rel err {rel_err(got, ref):.2e}", file=sys.stderr)
+    assert rel_err(got, ref) < TOL_C
+    assert np.abs(eig.cpu().numpy() - E).max() < TOL_E * np.abs(E).max()
+    np.testing.assert_allclose(resid.cpu().numpy(), RN, rtol=1e-8)
+    st.close()
