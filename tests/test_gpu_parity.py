@@ -430,3 +430,28 @@ def test_kicked_etrs_dipole_series(ks):
     dr = np.array([ko.dipole(ham.grid, x) for x in dens])
     assert np.max(np.abs(d - dr)) < TOL * np.max(np.abs(dr))
     st.close()
+
+
+def test_etrs_local_only_system(ks):
+    """ETRS under V_loc + V_H[n] on a system without projectors (density
+    passes only, no x-projection pass) against the oracle."""
+    print("[case] etrs t24 local only", file=sys.stderr, flush=True)
+    spec = synth.CONFIGS["t24"]
+    sysm = synth.system(spec)
+    g = ko.Grid(spec.n, spec.L, spec.ecut)
+    ham = ko.Hamiltonian(g, sysm.vloc)
+    gs = ks.System(spec.n, spec.L, spec.ecut, spec.norb)
+    gs.set_vloc(torch.from_numpy(sysm.vloc).cuda())
+    c = orbitals_device(spec)
+    c = c / torch.sqrt(torch.from_numpy(ko.norms(ham, c.cpu().numpy())).cuda()).reshape(-1, 1, 1, 1)
+    c0 = c.cpu().numpy()
+    occ_np = np.full(spec.norb, 2.0)
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    K = 2
+    rho = torch.empty((K,) + spec.n, dtype=torch.float64, device="cuda")
+    st.propagate_etrs(spec.dt, K, torch.from_numpy(occ_np).cuda(), rho)
+    ref, dens = ko.etrs_step(ham, c0, spec.dt, occ_np, nsteps=K)
+    assert rel_err(st.download().cpu().numpy(), ref) < TOL
+    assert np.linalg.norm(rho[-1].cpu().numpy() - dens[-1]) / np.linalg.norm(dens[-1]) < TOL
+    st.close()
