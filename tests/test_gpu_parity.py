@@ -473,3 +473,21 @@ def test_hartree_and_dipole_full_size(ks):
     d = gs.dipole(rho).cpu().numpy()
     dr = ko.dipole(g, n)
     assert np.abs(d - dr).max() < TOL * np.abs(dr).max()
+
+
+def test_kick_full_size_sampled(ks):
+    """96^3 grid, 512 resident orbitals: the field kick on every orbital, with
+    sampled orbitals recomputed by the oracle one by one."""
+    print("[case] kick cfg3_96 sampled", file=sys.stderr, flush=True)
+    spec, sysm = _case("cfg3_96")
+    gs = ks.system_from_synth(sysm)
+    c = orbitals_device(spec)
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    k = (0.0, 0.01, -0.02)
+    st.kick(k)
+    sample = [0, 301, spec.norb - 1]
+    got = st.download()[sample].cpu().numpy()
+    ref = ko.kick(ko.Grid(spec.n, spec.L, spec.ecut), c[sample].cpu().numpy(), k)
+    assert rel_err(got, ref) < TOL
+    st.close()
