@@ -62,11 +62,17 @@ typedef struct ks_system ks_system;
  * ecut (Ha; ecut <= 0 means the whole FFT box, no sphere).  Builds the
  * plane-wave sphere tables (kinetic energies |G|^2/2 and the mask, from the
  * plane-wave basis of Section "DFT and TDDFT implementation") and allocates
- * the workspace, sized so that no later call allocates device memory (except
- * the first ks_orthonormalize).  max_norb bounds norb in every later call.
- * Errors: KS_EINVAL (null, n < 1, L <= 0, max_norb < 1, n1 != n2, sphere
- * reaching the Nyquist plane), KS_EUNSUPPORTED (size without a kernel, sphere
- * too large for LDS), KS_ENOMEM.  On error *out is NULL.
+ * the workspace of the H psi, propagation, density and reduction calls, so
+ * that these allocate nothing.  Calls that do allocate device memory:
+ * ks_system_set_projectors (its tables and projection workspace),
+ * ks_system_set_chunk, the first ks_orthonormalize or ks_state_eigensolve of
+ * a system (overlap matrices), ks_state_create, and the first
+ * ks_state_propagate_etrs / ks_state_eigensolve of a state (extra orbital
+ * blocks).  max_norb bounds norb in every later call.
+ * Errors: KS_EINVAL (null, n < 1, L <= 0, max_norb < 1, n1 != n2, ecut > 0
+ * with a sphere that contains a point of the Nyquist plane m_a = -n_a/2 of an
+ * even n_a), KS_EUNSUPPORTED (size without a kernel, sphere too large for
+ * LDS), KS_ENOMEM.  On error *out is NULL.
  */
 ks_status ks_system_create(const int n[3], const double L[3], double ecut, int precision,
                            int max_norb, ks_system** out);

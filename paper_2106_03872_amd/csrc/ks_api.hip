@@ -158,6 +158,13 @@ ks_status build_sphere(const int n[3], const double L[3], double ecut, SphereHos
       }
       if (cnt == 0) continue;
       if (cnt != hi - lo + 1) { err = "sphere column is not contiguous"; return KS_EUNSUPPORTED; }
+      // a sphere (not the whole box) must stay clear of the Nyquist planes
+      // m_a = -n_a/2 of even sizes, where G and -G fold onto one box index
+      if (ecut > 0.0 && ((n[0] % 2 == 0 && m0 == mlo(0)) || (n[1] % 2 == 0 && m1 == mlo(1)) ||
+                         (n[2] % 2 == 0 && lo == mlo(2)))) {
+        err = "the plane-wave sphere reaches a Nyquist plane of the grid";
+        return KS_EINVAL;
+      }
       if (have_col && m1 != prev_m1 + 1) { err = "sphere plane is not contiguous"; return KS_EUNSUPPORTED; }
       if (!have_col) first_col = m1;
       have_col = true;
@@ -1332,7 +1339,8 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
   double b = 0.0;
   b += (double)cb * stride * (16.0 + 2.0 * es);         // packed chunk buffers
   b += 2.0 * cb * nplanes * npl * es;                   // plane intermediates
-  b += N * 8.0 + 2.0 * norb * 8.0;                      // potential, reductions
+  b += N * 40.0 + 2.0 * norb * 8.0;                     // potential, static potential, density and complex
+                                                        // work box of the Hartree solve; reductions
   b += (double)((cb + 7) / 8) * N * 8.0;                // partial densities
   b += npoints * (np * 8.0 + 4 * 4.0) + 64.0 * 1024;    // KB tables
   b += (double)cb * npoints * np * 16.0 / 8.0;          // projection partials (upper bound)

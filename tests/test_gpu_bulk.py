@@ -1,0 +1,147 @@
+"""Parity at bulk sizes, through the C ABI, against the FP64 oracle.
+
+* 64^3 grid, 128 orbitals, 32 atoms x 4 projectors (H psi at bulk scale):
+  every orbital's H psi, one Taylor-4 step and its density at 1e-12, the
+  resident-state propagation whose first density comes from the fused
+  projection pass, and the mixed-precision path at 1e-5.
+* 96^3 grid, 512 orbitals, 128 atoms: a three-step propagation of the
+  resident state in the benchmark's launch configuration, so that the
+  densities of steps 0 and 1 come from the fused density variant of the
+  x-projection pass; occupations are one-hot on sampled orbitals, so the
+  oracle recomputes only those.
+
+The orbitals are orthonormalised by the oracle on the host (the bulk
+configuration's recipe), never by the library, so no oracle input comes from
+the HIP path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ks_oracle as ko
+from paper_2106_03872_amd import synth
+
+from gpu_common import oracle_ham, orbitals_device, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-12
+TOL_MIXED = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2106_03872_amd import ks as ksmod
+    return ksmod
+
+
+def _case(name):
+    print(f"[case] {name}", file=sys.stderr, flush=True)
+    spec = synth.CONFIGS[name]
+    return spec, synth.system(spec)
+
+
+def _dens_err(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def cfg2(ks):
+    spec, sysm = _case("cfg2_64")
+    ham = oracle_ham(sysm)
+    c0 = ko.orthonormalize(ham, synth.orbitals_box(spec))
+    return spec, sysm, ham, c0
+
+
+def test_cfg2_ham_apply_all_orbitals(ks, cfg2):
+    spec, sysm, ham, c0 = cfg2
+    gs = ks.system_from_synth(sysm)
+    c = torch.from_numpy(c0).cuda()
+    got = gs.ham_apply(c).cpu().numpy()
+    ref = ko.ham_apply(ham, c0)
+    err = rel_err(got, ref)
+    print(f"[cfg2] H psi rel err {err:.2e}", file=sys.stderr, flush=True)
+    assert err < TOL
+    assert np.all(got[:, ~ham.grid.chi] == 0)
+    gs.close()
+
+
+def test_cfg2_taylor_step_density_and_resident_state(ks, cfg2):
+    spec, sysm, ham, c0 = cfg2
+    gs = ks.system_from_synth(sysm)
+    occ_np = np.full(spec.norb, 2.0)
+    occ = torch.from_numpy(occ_np).cuda()
+    # box interface: one step with the density (separate density pass)
+    c = torch.from_numpy(c0).cuda()
+    rho = torch.empty((1,) + spec.n, dtype=torch.float64, device="cuda")
+    gs.propagate_step(c, spec.dt, 1, occ, rho)
+    ref1 = ko.taylor4_step(ham, c0, spec.dt, 1)
+    assert rel_err(c.cpu().numpy(), ref1) < TOL
+    rr1 = ko.density(ham, ref1, occ_np)
+    assert _dens_err(rho[0].cpu().numpy(), rr1) < TOL
+    # resident state, two steps in one call: the density of step 0 comes
+    # from the fused projection pass of step 1's first H psi
+    st = ks.State(gs, spec.norb)
+    st.upload(torch.from_numpy(c0).cuda())
+    rho2 = torch.empty((2,) + spec.n, dtype=torch.float64, device="cuda")
+    nrm = torch.empty((2, spec.norb), dtype=torch.float64, device="cuda")
+    st.propagate(spec.dt, 2, occ, rho2, nrm)
+    ref2 = ko.taylor4_step(ham, ref1, spec.dt, 1)
+    assert _dens_err(rho2[0].cpu().numpy(), rr1) < TOL
+    assert _dens_err(rho2[1].cpu().numpy(), ko.density(ham, ref2, occ_np)) < TOL
+    np.testing.assert_allclose(nrm[0].cpu().numpy(), ko.norms(ham, ref1), rtol=TOL)
+    np.testing.assert_allclose(nrm[1].cpu().numpy(), ko.norms(ham, ref2), rtol=TOL)
+    assert rel_err(st.download().cpu().numpy(), ref2) < TOL
+    st.close()
+    gs.close()
+
+
+def test_cfg2_mixed_precision(ks, cfg2):
+    spec, sysm, ham, c0 = cfg2
+    gm = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
+    c = torch.from_numpy(c0).cuda()
+    err = rel_err(gm.ham_apply(c).cpu().numpy(), ko.ham_apply(ham, c0))
+    print(f"[cfg2] mixed H psi rel err {err:.2e}", file=sys.stderr, flush=True)
+    assert err < TOL_MIXED
+    occ_np = np.full(spec.norb, 2.0)
+    rho = torch.empty((1,) + spec.n, dtype=torch.float64, device="cuda")
+    gm.propagate_step(c, spec.dt, 1, torch.from_numpy(occ_np).cuda(), rho)
+    ref1 = ko.taylor4_step(ham, c0, spec.dt, 1)
+    assert rel_err(c.cpu().numpy(), ref1) < TOL_MIXED
+    assert _dens_err(rho[0].cpu().numpy(), ko.density(ham, ref1, occ_np)) < TOL_MIXED
+    gm.close()
+
+
+def test_cfg3_resident_fused_density_three_steps(ks):
+    spec, sysm = _case("cfg3_96")
+    ham = oracle_ham(sysm)
+    gs = ks.system_from_synth(sysm)
+    assert gs.chunk == spec.norb                  # one pass of 512 orbitals, as timed
+    sample = [5, 300]
+    occ_s = np.array([2.0, 1.5])
+    occ = torch.zeros(spec.norb, dtype=torch.float64, device="cuda")
+    occ[sample] = torch.from_numpy(occ_s).cuda()
+    c = orbitals_device(spec)
+    cs = c[sample].cpu().numpy()
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    del c
+    K = 3
+    rho = torch.empty((K,) + spec.n, dtype=torch.float64, device="cuda")
+    nrm = torch.empty((K, spec.norb), dtype=torch.float64, device="cuda")
+    st.propagate(spec.dt, K, occ, rho, nrm)
+    out = st.download()[sample].cpu().numpy()
+    ref = cs
+    for s in range(K):
+        ref = ko.taylor4_step(ham, ref, spec.dt, 1)
+        e = _dens_err(rho[s].cpu().numpy(), ko.density(ham, ref, occ_s))
+        print(f"[cfg3] step {s} density rel err {e:.2e}", file=sys.stderr, flush=True)
+        assert e < TOL
+        np.testing.assert_allclose(nrm[s, sample].cpu().numpy(), ko.norms(ham, ref), rtol=TOL)
+    assert rel_err(out, ref) < TOL
+    st.close()
+    gs.close()

@@ -11,7 +11,7 @@ from paper_2106_03872_amd import ks, synth
     ((16, 16, 16), (10, 10, 10), 10.0), ((24, 24, 24), (10, 10, 10), 10.0),
     ((32, 32, 32), (10.0, 11.0, 12.0), 10.0), ((60, 60, 60), (19.8,) * 3, 10.0),
     ((96, 96, 96), (30,) * 3, 10.0), ((20, 16, 16), (7.0, 5.0, 6.0), 0.0),
-    ((12, 8, 8), (4.0, 3.0, 3.5), 3.0), ((8, 8, 8), (3.0, 3.0, 3.0), 100.0),
+    ((12, 8, 8), (4.0, 3.0, 3.5), 3.0), ((8, 8, 8), (3.0, 3.0, 3.0), 20.0),
 ])
 def test_sphere_matches_oracle_mask(n, L, ecut):
     m = ks.plan_sphere(n, L, ecut)
@@ -25,6 +25,19 @@ def test_sphere_matches_oracle_mask(n, L, ecut):
     assert np.all(np.diff(key) > 0)
     same_col = (np.diff(m[:, 0]) == 0) & (np.diff(m[:, 1]) == 0)
     assert np.all(np.diff(m[:, 2])[same_col] == 1)
+
+
+@pytest.mark.parametrize("n,L,ecut", [((8, 8, 8), (3.0, 3.0, 3.0), 100.0), ((16, 12, 12), (4.0, 6.0, 6.0), 40.0),
+                                       ((24, 16, 16), (6.0, 6.0, 6.0), 40.0)])
+def test_sphere_reaching_nyquist_is_rejected(n, L, ecut):
+    # the oracle's mask contains a point with m_a = -n_a/2 on an even axis
+    g = ko.Grid(n, L, ecut)
+    assert any(np.any(g.chi.take([n[a] // 2], axis=a)) for a in range(3) if n[a] % 2 == 0)
+    with pytest.raises(ks.KSError) as e:
+        ks.plan_sphere(n, L, ecut)
+    assert e.value.status == ks.KS_EINVAL
+    # the whole box (no sphere) includes the Nyquist planes by definition
+    assert len(ks.plan_sphere(n, L, 0.0)) == int(np.prod(n))
 
 
 def test_sphere_rejects_bad_arguments():

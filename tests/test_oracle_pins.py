@@ -620,6 +620,26 @@ def test_sd_line_minimum_bruteforce():
     assert best - r_new < 1e-3 * (e[0] - r_new)
 
 
+def test_sd_line_minimum_phase():
+    """The lowest eigenvector of the 2x2 line-minimisation problem is fixed
+    only up to a phase; the reading taken is y0 real and non-negative, so the
+    updated orbital keeps the phase of the old one: with one orbital (no
+    subspace mixing, and Cholesky is a positive scaling) <c|c_new> is real and
+    positive.  The coupling <c|Hq> is made complex by a random global phase of
+    the projector coefficients' orbital, so an eigensolver's own phase choice
+    would not satisfy this by accident."""
+    g, ham = _tiny_system((6, 6, 5), (3.5, 3.5, 3.0), 12.0, seed=34)
+    for k, ph in enumerate((0.3, 1.1, 2.0, -2.7)):
+        c = _random_orthonormal(g, ham, 1, 40 + k) * np.exp(1j * ph)
+        new, e, _ = ko.sd_iteration(ham, c)
+        ov = np.vdot(c.ravel(), new.ravel())
+        assert ov.real > 0.5
+        assert abs(ov.imag) < 1e-13 * abs(ov)
+        # the same orbital with another global phase gives the same update up to that phase
+        new2, _, _ = ko.sd_iteration(ham, c * np.exp(0.7j))
+        np.testing.assert_allclose(new2, new * np.exp(0.7j), atol=1e-12)
+
+
 def test_sd_keeps_an_invariant_subspace():
     g, ham = _tiny_system((5, 6, 6), (3.0, 3.5, 3.5), 11.0, seed=36)
     _, lam, V = _chi_eigen(g, ham)
