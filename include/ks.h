@@ -77,8 +77,39 @@ typedef struct ks_system ks_system;
 ks_status ks_system_create(const int n[3], const double L[3], double ecut, int precision,
                            int max_norb, ks_system** out);
 
-/* Free the system and its device memory after synchronising the device. */
+/*
+ * Free the system and its device memory.  Waits for the work the system's
+ * calls enqueued (on any stream, including replays of its states' captured
+ * steps), not for the rest of the device.  With a pool the memory returns to
+ * the pool and no HIP free is called.
+ */
 void ks_system_destroy(ks_system* sys);
+
+/*
+ * Device memory pool for many short-lived systems (serving): one device
+ * allocation of `bytes`, sub-allocated on the host, so that creating and
+ * destroying pooled systems and their states calls no hipMalloc / hipFree
+ * (which may synchronise the device).  A pool belongs to the device current
+ * at its creation.  Errors: KS_EINVAL (null, bytes == 0), KS_ENOMEM.
+ */
+typedef struct ks_pool ks_pool;
+ks_status ks_pool_create(unsigned long long bytes, ks_pool** out);
+/* Free the pool's device memory; every system created in it must have been
+ * destroyed. */
+void ks_pool_destroy(ks_pool* pool);
+/* Bytes in use, the most ever in use, and the largest free range (each
+ * output nullable).  KS_EINVAL on a null pool. */
+ks_status ks_pool_usage(ks_pool* pool, unsigned long long* used, unsigned long long* peak,
+                        unsigned long long* largest_free);
+/*
+ * As ks_system_create, with every device buffer of the system and of its
+ * states taken from `pool` (the pool's device must be current).  An
+ * exhausted pool gives KS_ENOMEM, at creation or at the call that allocates
+ * (see ks_system_create); the pool is not grown.  The message of a failed
+ * creation is ks_last_error(NULL).
+ */
+ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
+                              int max_norb, ks_system** out);
 
 /* Message of the last failing call on sys (or of the last failing create
  * when sys is NULL).  Valid until the next call on sys. */
@@ -156,6 +187,7 @@ ks_status ks_hartree(ks_system* sys, const double* rho, double* v, int add_vloc,
  */
 ks_status ks_dipole(ks_system* sys, const double* rho, double* d, void* stream);
 
+
 /*
  * Orbital norms and band energy (energy expression of Section "DFT and TDDFT
  * implementation" reduced to sum_k f_k <psi_k|H|psi_k> for a static potential):
@@ -187,7 +219,7 @@ typedef struct ks_state ks_state;
 
 /* Allocate the state (device memory for norb packed orbitals). */
 ks_status ks_state_create(ks_system* sys, int norb, ks_state** out);
-/* Free the state (synchronises the device). */
+/* Free the state (waits for its system's enqueued work only). */
 void ks_state_destroy(ks_state* state);
 /* psi (device complex128 box [norb][n0][n1][n2]) -> state; outside chi ignored. */
 ks_status ks_state_upload(ks_state* state, const void* psi, void* stream);
@@ -263,6 +295,12 @@ ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, dou
  * given dt, occ, rho) into a HIP graph owned by the state; stream must not be
  * the default stream and kernel timing must be off.  Replaces an earlier
  * capture.  ks_state_replay launches the captured step on any stream.
+ * The graph holds the system's workspace and tables and its launch shapes:
+ * after ks_system_set_projectors, ks_system_set_chunk, ks_system_set_tuning
+ * or ks_autotune on the system, ks_state_replay returns KS_EINVAL until the
+ * step is captured again.  The occ and rho buffers given at capture must
+ * stay allocated while the graph is replayed (ks_system_set_vloc is fine:
+ * replays read the current potential).
  */
 ks_status ks_state_capture(ks_state* state, double dt, const double* occ, double* rho, void* stream);
 ks_status ks_state_replay(ks_state* state, void* stream);

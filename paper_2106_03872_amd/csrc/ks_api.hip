@@ -32,9 +32,58 @@ ks_status fail(ks_system* s, ks_status st, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                          \
   } while (0)
 
+// ------------------------------------------------------------ device pool
+
+constexpr size_t POOL_ALIGN = 256;
+
+void* pool_alloc(ks_pool* p, size_t bytes) {
+  bytes = (bytes + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
+  std::lock_guard<std::mutex> lk(p->mu);
+  for (auto it = p->free_ranges.begin(); it != p->free_ranges.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, rest = it->second - bytes;
+    p->free_ranges.erase(it);
+    if (rest) p->free_ranges[off + bytes] = rest;
+    p->live[off] = bytes;
+    p->used += bytes;
+    p->peak = std::max(p->peak, p->used);
+    return p->base + off;
+  }
+  return nullptr;
+}
+
+void pool_free(ks_pool* p, void* ptr) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  const size_t off = (size_t)((char*)ptr - p->base);
+  auto it = p->live.find(off);
+  if (it == p->live.end()) return;
+  size_t start = off, len = it->second;
+  p->used -= len;
+  p->live.erase(it);
+  auto nx = p->free_ranges.lower_bound(start);
+  if (nx != p->free_ranges.end() && nx->first == start + len) {   // merge with the next free range
+    len += nx->second;
+    nx = p->free_ranges.erase(nx);
+  }
+  if (nx != p->free_ranges.begin()) {                               // and with the previous one
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == start) {
+      start = pv->first;
+      len += pv->second;
+      p->free_ranges.erase(pv);
+    }
+  }
+  p->free_ranges[start] = len;
+}
+
 ks_status dalloc(ks_system* s, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (s && s->pool) {
+    *p = pool_alloc(s->pool, bytes);
+    if (!*p) return fail(s, KS_ENOMEM, "device pool exhausted (" + std::to_string(bytes) + " B requested)");
+    return KS_OK;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -44,13 +93,40 @@ ks_status dalloc(ks_system* s, void** p, size_t bytes) {
   return KS_OK;
 }
 
-void dfree(void*& p) {
-  if (p) (void)hipFree(p);
+// The caller makes sure no enqueued work still uses p.
+void dfree(ks_system* s, void*& p) {
+  if (p) {
+    if (s && s->pool) pool_free(s->pool, p);
+    else (void)hipFree(p);
+  }
   p = nullptr;
 }
 
+// Record the system's completion event on st after the work a call enqueued
+// (not while st is being captured into a graph: the capture's replays
+// record it instead).
+void track(ks_system* s, hipStream_t st) {
+  if (!s || !s->done) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+    (void)hipEventRecord(s->done, st);
+}
+
+// Records the completion event when the enclosing call returns.
+struct Track {
+  ks_system* s;
+  hipStream_t st;
+  Track(ks_system* s_, void* stream) : s(s_), st((hipStream_t)stream) {}
+  ~Track() { track(s, st); }
+};
+
+// Wait until the work the system enqueued has finished (its own work only).
+void wait_own(ks_system* s) {
+  if (s && s->done) (void)hipEventSynchronize(s->done);
+}
+
 template <typename T> ks_status upload(ks_system* s, T** dst, const std::vector<T>& v) {
-  dfree(reinterpret_cast<void*&>(*dst));
+  dfree(s, reinterpret_cast<void*&>(*dst));
   ks_status st = dalloc(s, reinterpret_cast<void**>(dst), v.size() * sizeof(T));
   if (st != KS_OK) return st;
   if (!v.empty()) KS_HIP(s, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -356,18 +432,18 @@ ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* 
 }
 
 void free_workspace(ks_system* s) {
-  for (auto& p : s->pk) dfree(p);
-  dfree(s->T);
-  dfree(s->U);
-  dfree(s->partial);
-  dfree(reinterpret_cast<void*&>(s->DP));
-  dfree(reinterpret_cast<void*&>(s->dens_part));
+  for (auto& p : s->pk) dfree(s, p);
+  dfree(s, s->T);
+  dfree(s, s->U);
+  dfree(s, s->partial);
+  dfree(s, reinterpret_cast<void*&>(s->DP));
+  dfree(s, reinterpret_cast<void*&>(s->dens_part));
   s->partial_cap = s->dp_cap = 0;
 }
 
 ks_status alloc_proj_workspace(ks_system* s) {
-  dfree(s->partial);
-  dfree(reinterpret_cast<void*&>(s->DP));
+  dfree(s, s->partial);
+  dfree(s, reinterpret_cast<void*&>(s->DP));
   const size_t pbytes = (size_t)s->cb * std::max(1, s->nslots) * std::max(1, s->nproj) * sizeof(double2);
   const size_t dbytes = (size_t)s->cb * std::max(1, s->natoms) * std::max(1, s->nproj) * sizeof(double2);
   ks_status st = dalloc(s, &s->partial, pbytes);
@@ -601,7 +677,7 @@ ks_status ensure_ortho_mats(ks_system* s) {
       ((s->gemm_part_bytes = gemm_part_bytes(s->max_norb, s->npw)) > 0 &&
        (r = dalloc(s, reinterpret_cast<void**>(&s->gemm_part), s->gemm_part_bytes)) != KS_OK)) {
     void* p[] = {s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag, s->gemm_part};
-    for (void* q : p) dfree(q);
+    for (void* q : p) dfree(s, q);
     s->ortho_S = s->ortho_W = s->gemm_part = nullptr;
     s->gemm_part_bytes = 0;
     s->ortho_info = nullptr;
@@ -676,8 +752,72 @@ ks_status subspace_eigh(ks_system* s, int n, const double2* H, double2* work, do
 
 extern "C" {
 
+static ks_status system_create(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
+                               int max_norb, ks_system** out);
+
 ks_status ks_system_create(const int n[3], const double L[3], double ecut, int precision, int max_norb,
                            ks_system** out) {
+  return system_create(nullptr, n, L, ecut, precision, max_norb, out);
+}
+
+ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
+                              int max_norb, ks_system** out) {
+  if (!pool) {
+    if (out) *out = nullptr;
+    return fail(nullptr, KS_EINVAL, "pool is null");
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pool->device) {
+    if (out) *out = nullptr;
+    return fail(nullptr, KS_EINVAL, "the pool belongs to another device");
+  }
+  return system_create(pool, n, L, ecut, precision, max_norb, out);
+}
+
+ks_status ks_pool_create(unsigned long long bytes, ks_pool** out) {
+  if (!out) return fail(nullptr, KS_EINVAL, "out is null");
+  *out = nullptr;
+  if (bytes == 0) return fail(nullptr, KS_EINVAL, "pool size must be positive");
+  ks_pool* p = new ks_pool();
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(nullptr, KS_EDEVICE, "hipGetDevice failed");
+  }
+  p->bytes = (size_t)(bytes + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
+  void* b = nullptr;
+  const hipError_t e = hipMalloc(&b, p->bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return fail(nullptr, KS_ENOMEM, "hipMalloc(" + std::to_string(bytes) + " B): " + hipGetErrorString(e));
+  }
+  p->base = (char*)b;
+  p->free_ranges[0] = p->bytes;
+  *out = p;
+  return KS_OK;
+}
+
+void ks_pool_destroy(ks_pool* p) {
+  if (!p) return;
+  (void)hipFree(p->base);
+  delete p;
+}
+
+ks_status ks_pool_usage(ks_pool* p, unsigned long long* used, unsigned long long* peak, unsigned long long* largest_free) {
+  if (!p) return fail(nullptr, KS_EINVAL, "pool is null");
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (used) *used = p->used;
+  if (peak) *peak = p->peak;
+  if (largest_free) {
+    size_t m = 0;
+    for (const auto& f : p->free_ranges) m = std::max(m, f.second);
+    *largest_free = m;
+  }
+  return KS_OK;
+}
+
+static ks_status system_create(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
+                               int max_norb, ks_system** out) {
   if (!out) return fail(nullptr, KS_EINVAL, "out is null");
   *out = nullptr;
   if (!n || !L) return fail(nullptr, KS_EINVAL, "n or L is null");
@@ -693,6 +833,12 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   if (!std::isfinite(ecut)) return fail(nullptr, KS_EINVAL, "ecut must be finite");
 
   ks_system* s = new ks_system();
+  s->pool = pool;
+  if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
+    s->done = nullptr;
+    delete s;
+    return fail(nullptr, KS_EDEVICE, "hipEventCreateWithFlags failed");
+  }
   for (int a = 0; a < 3; ++a) {
     s->n[a] = n[a];
     s->L[a] = L[a];
@@ -710,7 +856,7 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
     std::string msg;
     const ks_status r = build_sphere(n, L, ecut, sh, msg);
     if (r != KS_OK) {
-      delete s;
+      ks_system_destroy(s);
       return fail(nullptr, r, msg);
     }
   }
@@ -739,7 +885,7 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
   }
 
   if (plane_lds_bytes(s) > 160 * 1024) {
-    delete s;
+    ks_system_destroy(s);
     return fail(nullptr, KS_EUNSUPPORTED, "plane-wave sphere too large for the plane pass LDS budget");
   }
 
@@ -800,7 +946,7 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
 
 void ks_system_destroy(ks_system* s) {
   if (!s) return;
-  (void)hipDeviceSynchronize();
+  wait_own(s);
   timing_free(s);
   free_workspace(s);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
@@ -808,7 +954,8 @@ void ks_system_destroy(ks_system* s) {
                   s->d_atom_slot_off, s->d_atom_slots,
                   s->d_up_off, s->d_up_key, s->d_up_x, s->d_x_slot, s->d_beta, s->d_up_beta, s->d_x_beta, s->d_item,
                   s->d_kb, s->red, s->ortho_pk, s->ortho_S, s->ortho_W, s->ortho_info, s->ortho_diag, s->gemm_part};
-  for (void* p : ptrs) dfree(p);
+  for (void* p : ptrs) dfree(s, p);
+  if (s->done) (void)hipEventDestroy(s->done);
   delete s;
 }
 
@@ -820,14 +967,16 @@ int ks_system_chunk(const ks_system* s) { return s ? s->cb : 0; }
 ks_status ks_system_set_chunk(ks_system* s, int chunk) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (chunk < 1 || chunk > s->max_norb) return fail(s, KS_EINVAL, "chunk outside [1, max_norb]");
-  KS_HIP(s, hipDeviceSynchronize());
+  wait_own(s);
   s->cb = chunk;
+  ++s->gen;
   return alloc_workspace(s);
 }
 
 ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (!v) return fail(s, KS_EINVAL, "v is null");
+  Track tk(s, stream);
   KS_HIP(s, hipMemcpyAsync(s->d_v, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   KS_HIP(s, hipMemcpyAsync(s->d_vloc, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   s->have_v = true;
@@ -845,6 +994,8 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
     if (r != KS_OK) return fail(s, r, msg);
   }
   KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
+  wait_own(s);   // the old tables may still be read by work on another stream
+  ++s->gen;
   const int np = ph.nproj;
   std::vector<double> kb((size_t)natoms * np);
   for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
@@ -895,6 +1046,7 @@ ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void
   const char* b = (const char*)hpsi;
   if (a < b + bytes && b < a + bytes) return fail(s, KS_EINVAL, "psi and hpsi overlap");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   const int cl = chunk_len(s, norb);
   for (int o0 = 0; o0 < norb; o0 += cl) {
@@ -919,6 +1071,7 @@ ks_status ks_propagate_step(ks_system* s, int norb, void* psi, double dt, int ns
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   const int cl = chunk_len(s, norb);
   for (int o0 = 0; o0 < norb; o0 += cl) {
     const int nb = std::min(cl, norb - o0);
@@ -937,6 +1090,7 @@ ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ,
   if (r != KS_OK) return r;
   if (!rho) return fail(s, KS_EINVAL, "rho is null");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   if (norb == 0) {
     KS_HIP(s, hipMemsetAsync(rho, 0, s->N * sizeof(double), st));
     return KS_OK;
@@ -956,6 +1110,7 @@ ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, v
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (!rho || !v) return fail(s, KS_EINVAL, "rho or v is null");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   if (!launch_hartree(s, rho, v, add_vloc ? s->d_vloc : nullptr, st))
     return fail(s, KS_EUNSUPPORTED, "no Hartree kernel for this grid");
   return launch_ok(s, true, "hartree");
@@ -964,6 +1119,7 @@ ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, v
 ks_status ks_dipole(ks_system* s, const double* rho, double* d, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (!rho || !d) return fail(s, KS_EINVAL, "rho or d is null");
+  Track tk(s, stream);
   return launch_ok(s, launch_dipole(s, rho, d, (hipStream_t)stream), "dipole");
 }
 
@@ -973,6 +1129,7 @@ ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, 
   if (r != KS_OK) return r;
   if (energy && !occ) return fail(s, KS_EINVAL, "energy requires occ");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   if (norb == 0) {
     if (energy) KS_HIP(s, hipMemsetAsync(energy, 0, sizeof(double), st));
     return KS_OK;
@@ -1003,6 +1160,7 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   if (norb == 0) return KS_OK;
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   if ((r = ensure_ortho_mats(s)) != KS_OK) return r;
   if (!s->ortho_pk &&
       (r = dalloc(s, &s->ortho_pk, 2 * (size_t)s->max_norb * s->npw_stride * sizeof(double2))) != KS_OK)
@@ -1116,12 +1274,13 @@ static void state_drop_graph(ks_state* t) {
 
 void ks_state_destroy(ks_state* t) {
   if (!t) return;
-  (void)hipDeviceSynchronize();
+  ks_system* s = t->sys;
+  wait_own(s);
   state_drop_graph(t);
   void* p = t->data;
-  dfree(p);
+  dfree(s, p);
   void* bufs[] = {t->aux, t->gs_buf[0], t->gs_buf[1], t->gs_mat, t->gs_vec};
-  for (void* q : bufs) dfree(q);
+  for (void* q : bufs) dfree(s, q);
   delete t;
 }
 
@@ -1130,6 +1289,7 @@ ks_status ks_state_upload(ks_state* t, const void* psi, void* stream) {
   ks_system* s = t->sys;
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   const double2* box = (const double2*)psi;
   return kcall(s, KS_K_PACK, st, "pack", [&] { return launch_pack(s, t->norb, box, s->N, t->data, st); });
 }
@@ -1139,6 +1299,7 @@ ks_status ks_state_download(ks_state* t, void* psi, void* stream) {
   ks_system* s = t->sys;
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   double2* box = (double2*)psi;
   return kcall(s, KS_K_UNPACK, st, "unpack", [&] { return launch_unpack(s, t->norb, t->data, true, box, s->N, st); });
 }
@@ -1151,6 +1312,7 @@ ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* o
   if (!std::isfinite(dt)) return fail(s, KS_EINVAL, "dt must be finite");
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   ks_status r;
   const int cl = chunk_len(s, t->norb);
   for (int o0 = 0; o0 < t->norb; o0 += cl) {
@@ -1172,6 +1334,7 @@ ks_status ks_state_propagate_etrs(ks_state* t, double dt, int nsteps, const doub
   if (!occ) return fail(s, KS_EINVAL, "occ is required (the Hamiltonian depends on the density)");
   if (nsteps == 0) return KS_OK;
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   if (!t->aux) {
     ks_status r = dalloc(s, reinterpret_cast<void**>(&t->aux), (size_t)t->norb * s->npw_stride * sizeof(double2));
     if (r != KS_OK) return r;
@@ -1191,6 +1354,7 @@ ks_status ks_state_kick(ks_state* t, const double k[3], void* stream) {
   if (!k || !std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
     return fail(s, KS_EINVAL, "k must be three finite numbers");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   ks_status r;
   for (int o = 0; o < t->norb; ++o) {
     double2* c = t->data + (size_t)o * s->npw_stride;
@@ -1208,6 +1372,7 @@ ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid
   if (s->prec != KS_FP64) return fail(s, KS_EUNSUPPORTED, "the eigensolver runs on FP64 systems");
   if (niter == 0) return KS_OK;
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   const int n = t->norb;
   const size_t ld = s->npw_stride, nn = (size_t)n * n, blk = (size_t)n * ld * sizeof(double2);
   ks_status r;
@@ -1267,6 +1432,7 @@ ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double*
   ks_system* s = t->sys;
   if (energy && !occ) return fail(s, KS_EINVAL, "energy requires occ");
   hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
   Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   ks_status r;
   // norms only: one launch over every resident orbital
@@ -1311,6 +1477,7 @@ ks_status ks_state_capture(ks_state* t, double dt, const double* occ, double* rh
     state_drop_graph(t);
     return fail(s, KS_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
   }
+  t->graph_gen = s->gen;
   return KS_OK;
 }
 
@@ -1318,6 +1485,9 @@ ks_status ks_state_replay(ks_state* t, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
   if (!t->exec) return fail(s, KS_EINVAL, "no captured step");
+  if (t->graph_gen != s->gen)
+    return fail(s, KS_EINVAL, "the system's buffers or launch shapes changed since the capture; capture again");
+  Track tk(s, stream);
   KS_HIP(s, hipGraphLaunch(t->exec, (hipStream_t)stream));
   return KS_OK;
 }
@@ -1377,6 +1547,7 @@ ks_status ks_system_set_tuning(ks_system* s, const ks_tuning* t) {
     return fail(s, KS_EINVAL, "group caps must lie in [1, 64]");
   s->xg_max = t->x_group;
   s->pg_max = t->plane_group;
+  ++s->gen;
   return KS_OK;
 }
 
@@ -1395,6 +1566,7 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
     if (it != g_tune_cache.end()) {
       s->xg_max = it->second.first;
       s->pg_max = it->second.second;
+      ++s->gen;
       if (out) *out = ks_tuning{s->xg_max, s->pg_max, 0.0, 1};
       return KS_OK;
     }
@@ -1439,6 +1611,7 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
   }
   s->xg_max = best_x;
   s->pg_max = best_p;
+  ++s->gen;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = {best_x, best_p};

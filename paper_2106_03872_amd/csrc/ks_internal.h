@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +71,17 @@ struct Taylor {
 };
 
 }  // namespace ks
+
+// Device memory pool (ks_pool_create): one device allocation, sub-allocated
+// on the host (first fit, 256-byte aligned, neighbouring free ranges merged).
+struct ks_pool {
+  char* base = nullptr;
+  size_t bytes = 0, used = 0, peak = 0;
+  int device = 0;
+  std::map<size_t, size_t> free_ranges;   // offset -> size
+  std::map<size_t, size_t> live;          // offset -> size
+  std::mutex mu;
+};
 
 struct ks_system {
   int n[3];
@@ -145,6 +158,15 @@ struct ks_system {
   long long kt_n[16] = {0};
 
   std::string err;
+
+  // device memory source (nullptr: hipMalloc / hipFree per buffer)
+  ks_pool* pool = nullptr;
+  // recorded on the stream of every call that enqueues work (outside stream
+  // capture): destroying the system or one of its states waits for it
+  // instead of the whole device
+  hipEvent_t done = nullptr;
+  // bumped whenever buffers or launch shapes that a captured graph holds change
+  unsigned long long gen = 0;
 };
 
 // Orbitals kept resident on the device in the packed FP64 layout.
@@ -162,6 +184,7 @@ struct ks_state {
   double* gs_vec = nullptr;
   hipGraph_t graph = nullptr;  // one captured propagation step
   hipGraphExec_t exec = nullptr;
+  unsigned long long graph_gen = 0;   // system generation at capture
 };
 
 namespace ks {

@@ -58,6 +58,11 @@ def _load():
     sig = {
         "ks_system_create": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, ctypes.POINTER(P)]),
         "ks_system_destroy": (None, [P]),
+        "ks_system_create_in": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, ctypes.POINTER(P)]),
+        "ks_pool_create": (I, [ctypes.c_ulonglong, ctypes.POINTER(P)]),
+        "ks_pool_destroy": (None, [P]),
+        "ks_pool_usage": (I, [P, ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong),
+                              ctypes.POINTER(ctypes.c_ulonglong)]),
         "ks_last_error": (ctypes.c_char_p, [P]),
         "ks_system_set_vloc": (I, [P, P, P]),
         "ks_system_set_projectors": (I, [P, I, I, P, P, P, P, P]),
@@ -175,18 +180,55 @@ def _ptr(t, dtype, shape=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
-class System:
-    """One Kohn-Sham system (grid, cell, cutoff, potential, projectors)."""
+class Pool:
+    """Device memory pool (ks_pool_create): systems created in it allocate
+    and free without hipMalloc / hipFree."""
 
-    def __init__(self, n, L, ecut, max_norb, precision=KS_FP64):
+    def __init__(self, nbytes):
+        h = ctypes.c_void_p()
+        st = _lib.ks_pool_create(int(nbytes), ctypes.byref(h))
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_last_error(None).decode())
+        self._h = h
+        self.nbytes = int(nbytes)
+
+    def usage(self):
+        """(used, peak, largest free range) in bytes."""
+        u, p, f = ctypes.c_ulonglong(), ctypes.c_ulonglong(), ctypes.c_ulonglong()
+        st = _lib.ks_pool_usage(self._h, ctypes.byref(u), ctypes.byref(p), ctypes.byref(f))
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_last_error(None).decode())
+        return u.value, p.value, f.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ks_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    """One Kohn-Sham system (grid, cell, cutoff, potential, projectors);
+    with `pool`, its device memory comes from that Pool."""
+
+    def __init__(self, n, L, ecut, max_norb, precision=KS_FP64, pool=None):
         self.n = tuple(int(x) for x in n)
         self.L = tuple(float(x) for x in L)
         self.ecut = float(ecut)
         self.max_norb = int(max_norb)
         self.N = int(np.prod(self.n))
+        self.pool = pool
         h = ctypes.c_void_p()
-        st = _lib.ks_system_create((ctypes.c_int * 3)(*self.n), (ctypes.c_double * 3)(*self.L),
-                                   self.ecut, int(precision), self.max_norb, ctypes.byref(h))
+        nn, LL = (ctypes.c_int * 3)(*self.n), (ctypes.c_double * 3)(*self.L)
+        if pool is None:
+            st = _lib.ks_system_create(nn, LL, self.ecut, int(precision), self.max_norb, ctypes.byref(h))
+        else:
+            st = _lib.ks_system_create_in(pool._h, nn, LL, self.ecut, int(precision), self.max_norb, ctypes.byref(h))
         if st != KS_OK:
             raise KSError(st, _lib.ks_last_error(None).decode())
         self._h = h
@@ -426,11 +468,14 @@ class State:
         return norms, energy
 
     def capture(self, dt, occ=None, rho=None, stream=None):
+        """Capture one step into a graph.  The graph holds occ and rho, so
+        they stay referenced here until the next capture or close."""
         import torch
         if stream is None:
             raise ValueError("capture needs an explicit non-default stream")
         self.system._check(_lib.ks_state_capture(self._h, float(dt), _ptr(occ, torch.float64, (self.norb,), "occ"),
                                                  _ptr(rho, torch.float64, None, "rho"), self._st(stream)))
+        self._captured = (occ, rho)
 
     def replay(self, stream=None):
         self.system._check(_lib.ks_state_replay(self._h, self._st(stream)))
@@ -468,11 +513,11 @@ def orthonormalize(system, psi):
     return system.orthonormalize(psi)
 
 
-def system_from_synth(sysm, max_norb=None, ecut=None, precision=KS_FP64):
+def system_from_synth(sysm, max_norb=None, ecut=None, precision=KS_FP64, pool=None):
     """Create a System from a synth.System (potential + projectors uploaded)."""
     import torch
     spec = sysm.spec
-    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb, precision)
+    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb, precision, pool)
     s.set_vloc(torch.from_numpy(sysm.vloc).to("cuda"))
     p = sysm.proj
     s.set_projectors(p.npts, p.idx, p.beta, p.d)

@@ -6,26 +6,33 @@ the states of one system, and whole systems, are independent, which is what
 makes them batchable).  The loop
 
 * admits waiting requests in arrival order while their device footprint fits
-  the HBM budget (admission = system creation, uploads, the launch schedule
-  from the library's autotuner (timed once per grid and pass-size bucket,
-  then cached), Cholesky orthonormalisation of the orbitals, one step
-  captured into a HIP graph);
+  the HBM budget.  Admission (system creation in a device memory pool, table
+  and orbital uploads, Cholesky orthonormalisation, one step captured into a
+  HIP graph) runs on worker threads, each with its own stream, so it never
+  holds up the issue loop; launch schedules are tuned per grid and pass-size bucket
+  before the trace starts;
 * keeps every admitted request's orbitals resident in HBM (packed layout)
   and issues its next step as soon as the previous one completed, on a pool
   of streams, so that the steps of many requests overlap on the device;
-* retires finished requests (final energy, norms, orbitals on request) and
-  frees their memory, which admits more.
+* retires finished requests without blocking: the final norms and energy
+  are copied to pinned host memory behind an event, and the system is freed
+  (back into the pool, waiting for its own work only) once that event has
+  completed, which admits more;
+* isolates failures: a request whose admission or step fails is reported
+  failed and its memory released; the others carry on.
 
 Per-step latency is the time between the completions of consecutive steps of
-one request (the first step: from admission); time-to-first-step is from
-arrival.  The scheduler is written against a small backend interface so that
-its admission and ordering logic can be tested on the CPU with a simulated
-device (``FakeBackend``).
+one request (the first step: from the end of its admission); time-to-first-
+step is from arrival.  The scheduler is written against a small backend
+interface so that its admission and ordering logic can be tested on the CPU
+with a simulated device (``FakeBackend``).
 """
 from __future__ import annotations
 
+import threading
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -39,10 +46,12 @@ class Request:
     nsteps: int = 50
     # filled in by the server
     footprint: int = 0
-    t_admit: float = -1.0
+    t_submit: float = -1.0    # admission started
+    t_admit: float = -1.0     # admission finished: steps may be issued
     t_done: float = -1.0
     step_times: list = field(default_factory=list)
     result: dict = field(default_factory=dict)
+    error: str = ""
 
 
 def percentile(x, q):
@@ -58,6 +67,8 @@ class Server:
         self.max_active = int(max_active)
         self.keep_orbitals = keep_orbitals
         self.max_used = 0
+        self.max_resident = 0
+        self.failed = []
 
     def run(self, requests):
         be = self.be
@@ -66,52 +77,101 @@ class Server:
             r.footprint = be.footprint(r)
             if r.footprint > self.budget:
                 raise ValueError(f"request {r.rid} needs {r.footprint} B, more than the budget {self.budget} B")
-        waiting, active, done = deque(), [], []
+        waiting, admitting, active, retiring, done = deque(), [], [], [], []
+        self.failed = []
         used = 0
+
+        def fail(r, exc):
+            nonlocal used
+            r.error = f"{type(exc).__name__}: {exc}"
+            r.t_done = be.now()
+            used -= r.footprint
+            be.discard(getattr(r, "handle", None))
+            r.handle = None
+            self.failed.append(r)
+
         be.start()
-        while pending or waiting or active:
+        while pending or waiting or admitting or active or retiring:
             progressed = False
             now = be.now()
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
                 progressed = True
-            while waiting and len(active) < self.max_active and used + waiting[0].footprint <= self.budget:
+            while (waiting and len(active) + len(admitting) < self.max_active
+                   and used + waiting[0].footprint <= self.budget):
                 r = waiting.popleft()
                 used += r.footprint
                 self.max_used = max(self.max_used, used)
+                r.t_submit = be.now()
+                r.handle = None
+                r.admit_tok = be.admit_submit(r)
+                admitting.append(r)
+                progressed = True
+            still = []
+            for r in admitting:
+                try:
+                    h = be.admit_poll(r.admit_tok)
+                except Exception as exc:      # this request fails alone
+                    fail(r, exc)
+                    progressed = True
+                    continue
+                if h is None:
+                    still.append(r)
+                    continue
+                r.handle = h
                 r.t_admit = be.now()
-                r.handle = be.admit(r)
                 r.inflight = None
                 active.append(r)
                 progressed = True
+            admitting = still
+            self.max_resident = max(self.max_resident, len(active))
             for r in active:
                 if r.inflight is None and len(r.step_times) < r.nsteps:
-                    r.inflight = be.issue_step(r.handle)
+                    try:
+                        r.inflight = be.issue_step(r.handle)
+                    except Exception as exc:
+                        r.inflight = exc
                     progressed = True
             still = []
             for r in active:
+                if isinstance(r.inflight, Exception):
+                    fail(r, r.inflight)
+                    continue
                 if r.inflight is not None and be.is_done(r.inflight):
                     r.step_times.append(be.done_time(r.inflight))
                     r.inflight = None
                     progressed = True
                 if len(r.step_times) == r.nsteps and r.inflight is None:
-                    r.result = be.retire(r.handle, self.keep_orbitals)
-                    r.t_done = be.now()
-                    r.handle = None
-                    used -= r.footprint
-                    done.append(r)
+                    r.retire_tok = be.retire_submit(r.handle, self.keep_orbitals)
+                    retiring.append(r)
+                    progressed = True
                 else:
                     still.append(r)
             active = still
+            still = []
+            for r in retiring:
+                res = be.retire_poll(r.retire_tok)
+                if res is None:
+                    still.append(r)
+                    continue
+                r.result = res
+                r.t_done = be.now()
+                r.handle = None
+                used -= r.footprint
+                done.append(r)
+                progressed = True
+            retiring = still
             if not progressed:
                 be.idle(pending[0].arrival if pending else None)
         self.elapsed = be.now()
+        self.used_at_end = used
+        be.finish()
         return done
 
     @staticmethod
     def report(done, elapsed, hpsi_per_step):
         """Latency percentiles and aggregate throughput of a finished run."""
-        lat, ttfs = [], []
+        lat, ttfs, adm = [], [], []
         total_hpsi = 0
         for r in done:
             prev = r.t_admit
@@ -119,6 +179,7 @@ class Server:
                 lat.append(t - prev)
                 prev = t
             ttfs.append(r.step_times[0] - r.arrival if r.step_times else float("nan"))
+            adm.append(r.t_admit - r.t_submit)
             total_hpsi += hpsi_per_step(r) * len(r.step_times)
         return {
             "requests": len(done),
@@ -127,6 +188,8 @@ class Server:
             "step_latency_ms_p99": 1e3 * percentile(lat, 99),
             "time_to_first_step_ms_p50": 1e3 * percentile(ttfs, 50),
             "time_to_first_step_ms_p99": 1e3 * percentile(ttfs, 99),
+            "admission_ms_p50": 1e3 * percentile(adm, 50),
+            "admission_ms_p99": 1e3 * percentile(adm, 99),
             "makespan_s": elapsed,
             "orbital_hpsi_per_s": total_hpsi / elapsed if elapsed > 0 else float("nan"),
         }
@@ -139,10 +202,11 @@ def hpsi_per_step(r):
 # ------------------------------------------------------------------ backends
 
 class HipBackend:
-    """Runs requests on the MI355X through the C ABI (one system + resident
-    state per request, steps replayed from a captured graph on a stream pool)."""
+    """Runs requests on the MI355X through the C ABI: one pooled system +
+    resident state per request, steps replayed from a captured graph on a
+    stream pool; admissions on worker threads, each with its own stream."""
 
-    def __init__(self, precision=None, nstreams=4, use_graphs=True, dt=0.05):
+    def __init__(self, precision=None, nstreams=4, use_graphs=True, dt=0.05, pool_bytes=None, admit_workers=4):
         import torch
 
         from paper_2106_03872_amd import ks
@@ -150,54 +214,103 @@ class HipBackend:
         self.ks = ks
         self.precision = ks.KS_MIXED if precision is None else precision
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.admit_workers = int(admit_workers)
+        self._tls = threading.local()     # one admission stream per worker thread
         self.use_graphs = use_graphs
         self.dt = dt
         self._next = 0
         self.inputs = {}
+        self.pool_bytes = pool_bytes
+        self.pool = None
+        self.tuning_s = 0.0
+        self._exec = None
 
-    def prepare(self, requests):
-        """Draw every request's inputs on the host (the request payload)."""
+    def prepare(self, requests, pretune=True):
+        """Draw every request's inputs on the host (the request payload) and,
+        with pretune, tune the launch schedule of every grid and pass-size
+        bucket of the trace before it starts (cached by the library)."""
         from paper_2106_03872_amd import synth
         for r in requests:
             sysm = synth.system(r.spec)
             sel, vals = synth.orbital_values(r.spec)
             self.inputs[r.rid] = (sysm, sel, vals)
+        if pretune:
+            t0 = time.perf_counter()
+            seen = set()
+            for r in sorted(requests, key=lambda q: -q.spec.norb):
+                key = (tuple(r.spec.n), 1 << max(0, (r.spec.norb - 1).bit_length()))
+                if key in seen:
+                    continue
+                seen.add(key)
+                gs = self.ks.system_from_synth(self.inputs[r.rid][0], precision=self.precision)
+                gs.autotune(r.spec.norb)
+                gs.close()
+            self.torch.cuda.synchronize()
+            self.tuning_s = time.perf_counter() - t0
 
     def footprint(self, r):
         sysm = self.inputs[r.rid][0]
         s = r.spec
         base = self.ks.plan_footprint(s.n, s.L, s.ecut, s.norb, int(sysm.proj.npts.sum()), 4, self.precision)
         npw_stride = len(self.ks.plan_sphere(s.n, s.L, s.ecut)) + 64
-        box = s.norb * s.npoints * 16                       # transient box copy at admission
-        ortho = 2 * s.norb * npw_stride * 16 + 2 * s.norb * s.norb * 16 + 256
-        return base + box + ortho
+        ortho = 2 * s.norb * npw_stride * 16 + 2 * s.norb * s.norb * 16
+        return base + ortho + 64 * 256        # pool alignment of the system's buffers
 
     def start(self):
         self.torch.cuda.synchronize()
+        if self.pool is None and self.pool_bytes:
+            self.pool = self.ks.Pool(self.pool_bytes)
+        self._exec = ThreadPoolExecutor(max_workers=self.admit_workers)
         self.t0 = time.perf_counter()
+
+    def finish(self):
+        if self._exec is not None:
+            self._exec.shutdown(wait=True)
+            self._exec = None
 
     def now(self):
         return time.perf_counter() - self.t0
 
-    def admit(self, r):
+    def _admit(self, r, sysm, sel, vals):
         torch, ks = self.torch, self.ks
+        if getattr(self._tls, "stream", None) is None:
+            self._tls.stream = torch.cuda.Stream()
+        stream = self._tls.stream
+        h = {"stream": self.streams[r.rid % len(self.streams)]}
+        try:
+            with torch.cuda.stream(stream):
+                gs = ks.system_from_synth(sysm, precision=self.precision, pool=self.pool)
+                h["system"] = gs
+                gs.autotune(r.spec.norb)     # cached: tuned before the trace
+                c = torch.zeros((r.spec.norb, r.spec.npoints), dtype=torch.complex128, device="cuda")
+                c[:, torch.from_numpy(sel).to("cuda", non_blocking=False)] = torch.from_numpy(vals).to("cuda")
+                c = c.reshape((r.spec.norb,) + tuple(r.spec.n))
+                gs.orthonormalize(c)
+                st = ks.State(gs, r.spec.norb)
+                h["state"] = st
+                st.upload(c, stream)
+                occ = torch.full((r.spec.norb,), float(r.spec.occ), dtype=torch.float64, device="cuda")
+                h["occ"] = occ
+                h["occ_sum"] = float(r.spec.occ) * r.spec.norb
+                if self.use_graphs:
+                    st.capture(self.dt, stream=stream)
+                ready = torch.cuda.Event()
+                ready.record(stream)
+                del c
+            ready.synchronize()              # the worker waits; the issue loop does not
+        except Exception:
+            self.discard(h)
+            raise
+        return h
+
+    def admit_submit(self, r):
         sysm, sel, vals = self.inputs.pop(r.rid)
-        stream = self.streams[self._next % len(self.streams)]
-        self._next += 1
-        with torch.cuda.stream(stream):
-            gs = ks.system_from_synth(sysm, precision=self.precision)
-            gs.autotune(r.spec.norb)     # launch schedule; cached per grid and pass-size bucket
-            c = torch.zeros((r.spec.norb, r.spec.npoints), dtype=torch.complex128, device="cuda")
-            c[:, torch.from_numpy(sel).to("cuda")] = torch.from_numpy(vals).to("cuda")
-            c = c.reshape((r.spec.norb,) + tuple(r.spec.n))
-            gs.orthonormalize(c)
-            st = ks.State(gs, r.spec.norb)
-            st.upload(c, stream)
-            occ = torch.full((r.spec.norb,), float(r.spec.occ), dtype=torch.float64, device="cuda")
-            if self.use_graphs:
-                st.capture(self.dt, stream=stream)
-            del c
-        return {"system": gs, "state": st, "stream": stream, "occ": occ}
+        return self._exec.submit(self._admit, r, sysm, sel, vals)
+
+    def admit_poll(self, tok):
+        if not tok.done():
+            return None
+        return tok.result()                  # raises the admission's error
 
     def issue_step(self, h):
         with self.torch.cuda.stream(h["stream"]):
@@ -217,17 +330,44 @@ class HipBackend:
     def done_time(self, tok):
         return tok[1]
 
-    def retire(self, h, keep_orbitals):
+    def retire_submit(self, h, keep_orbitals):
         torch = self.torch
         with torch.cuda.stream(h["stream"]):
             norms, energy = h["state"].reduce(h["occ"], stream=h["stream"])
-            out = {"norms": norms.cpu().numpy(), "energy": energy.item(),
-                   "electrons": float(h["occ"].sum().item())}
+            out = {"norms": torch.empty(norms.shape, dtype=norms.dtype, pin_memory=True),
+                   "energy": torch.empty(1, dtype=torch.float64, pin_memory=True)}
+            out["norms"].copy_(norms, non_blocking=True)
+            out["energy"].copy_(energy, non_blocking=True)
             if keep_orbitals:
-                out["orbitals"] = h["state"].download(stream=h["stream"]).cpu().numpy()
-        h["state"].close()
-        h["system"].close()
-        return out
+                psi = h["state"].download(stream=h["stream"])
+                out["orbitals"] = torch.empty(psi.shape, dtype=psi.dtype, pin_memory=True)
+                out["orbitals"].copy_(psi, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(h["stream"])
+        h["retire"] = (ev, out, (norms, energy))
+        return h
+
+    def retire_poll(self, h):
+        ev, out, _ = h["retire"]
+        if not ev.query():
+            return None
+        res = {"norms": out["norms"].numpy().copy(), "energy": float(out["energy"][0]),
+               "electrons": float(h["occ_sum"])}
+        if "orbitals" in out:
+            res["orbitals"] = out["orbitals"].numpy().copy()
+        self.discard(h)
+        return res
+
+    def discard(self, h):
+        """Free a request's state and system (each waits for its own work)."""
+        if not h:
+            return
+        if h.get("state") is not None:
+            h["state"].close()
+            h["state"] = None
+        if h.get("system") is not None:
+            h["system"].close()
+            h["system"] = None
 
     def idle(self, next_arrival):
         time.sleep(20e-6)
@@ -238,7 +378,7 @@ class FakeBackend:
     per-request step durations from a cost model, and `lanes` steps that can
     run at once (a step waits for the earliest free lane)."""
 
-    def __init__(self, lanes=4, cost_per_hpsi=1e-6, footprint_fn=None):
+    def __init__(self, lanes=4, cost_per_hpsi=1e-6, footprint_fn=None, fail_admit=(), fail_step=()):
         self.lanes = lanes
         self.cost = cost_per_hpsi
         self.footprint_fn = footprint_fn or (lambda r: r.spec.norb * r.spec.npoints * 16)
@@ -247,6 +387,9 @@ class FakeBackend:
         self.running = []
         self.admitted = []
         self.retired = []
+        self.discarded = []
+        self.fail_admit = set(fail_admit)
+        self.fail_step = set(fail_step)
 
     def footprint(self, r):
         return self.footprint_fn(r)
@@ -257,11 +400,27 @@ class FakeBackend:
     def now(self):
         return self.t
 
-    def admit(self, r):
+    def admit_submit(self, r):
         self.admitted.append(r.rid)
+        if r.rid in self.fail_admit:
+            return RuntimeError(f"admission of request {r.rid} failed")
         return {"rid": r.rid, "cost": self.cost * 4 * r.spec.norb * (r.spec.npoints / 1e5)}
 
+    def admit_poll(self, tok):
+        if isinstance(tok, Exception):
+            raise tok
+        return tok
+
+    def finish(self):
+        pass
+
+    def discard(self, h):
+        if h:
+            self.discarded.append(h["rid"])
+
     def issue_step(self, h):
+        if h["rid"] in self.fail_step:
+            raise RuntimeError(f"step of request {h['rid']} failed")
         i = min(range(self.lanes), key=lambda k: self.lane_free[k])
         end = max(self.t, self.lane_free[i]) + h["cost"]
         self.lane_free[i] = end
@@ -274,7 +433,10 @@ class FakeBackend:
     def done_time(self, tok):
         return tok
 
-    def retire(self, h, keep_orbitals):
+    def retire_submit(self, h, keep_orbitals):
+        return h
+
+    def retire_poll(self, h):
         self.retired.append(h["rid"])
         return {"rid": h["rid"]}
 

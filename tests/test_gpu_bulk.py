@@ -53,7 +53,7 @@ def _dens_err(a, b):
 def cfg2(ks):
     spec, sysm = _case("cfg2_64")
     ham = oracle_ham(sysm)
-    c0 = ko.orthonormalize(ham, synth.orbitals_box(spec))
+    c0 = np.ascontiguousarray(ko.orthonormalize(ham, synth.orbitals_box(spec)))
     return spec, sysm, ham, c0
 
 

@@ -9,20 +9,16 @@ import pytest
 from paper_2106_03872_amd import serve, synth
 
 pytestmark = pytest.mark.gpu
+NSTEPS = 50
 torch = pytest.importorskip("torch")
 
 
 def _requests():
-    specs = [
-        synth.cubic_spec("s0", 24, 7.92, 8, 2, 3100, nsteps=4),
-        synth.cubic_spec("s1", 32, 10.56, 12, 3, 3101, nsteps=4),
-        synth.cubic_spec("s2", 24, 7.92, 16, 2, 3102, nsteps=4),
-        synth.cubic_spec("s3", 40, 13.2, 8, 4, 3103, nsteps=4),
-        synth.cubic_spec("s4", 32, 10.56, 10, 2, 3104, nsteps=4),
-        synth.cubic_spec("s5", 24, 7.92, 9, 3, 3105, nsteps=4),
-    ]
+    sizes = [(40, 48, 2), (32, 40, 3), (48, 32, 2), (40, 56, 4), (32, 64, 2), (48, 40, 3),
+             (40, 36, 2), (32, 48, 3), (48, 44, 4), (40, 60, 2), (32, 52, 2), (48, 36, 3)]
+    specs = [synth.cubic_spec(f"s{i}", n, 0.33 * n, norb, nat, 3100 + i) for i, (n, norb, nat) in enumerate(sizes)]
     arrivals = np.cumsum(np.random.default_rng(9).exponential(0.002, len(specs)))
-    return [serve.Request(rid=i, arrival=float(t), spec=s, nsteps=4) for i, (t, s) in enumerate(zip(arrivals, specs))]
+    return [serve.Request(rid=i, arrival=float(t), spec=s, nsteps=NSTEPS) for i, (t, s) in enumerate(zip(arrivals, specs))]
 
 
 @pytest.fixture(scope="module")
@@ -31,25 +27,30 @@ def gpu():
         pytest.skip("no HIP device")
 
 
-def _run(reqs, budget=None, use_graphs=True):
-    be = serve.HipBackend(use_graphs=use_graphs)
+def _run(reqs, budget=None, use_graphs=True, pool_bytes=None):
+    be = serve.HipBackend(use_graphs=use_graphs, pool_bytes=pool_bytes)
     be.prepare(reqs)
     if budget is None:
         budget = sum(be.footprint(r) for r in reqs) * 2
     srv = serve.Server(be, budget, keep_orbitals=True)
     done = srv.run(reqs)
+    assert not srv.failed, [r.error for r in srv.failed]
     return {r.rid: r for r in done}, srv
 
 
 def test_serving_alone_equals_mix(gpu):
+    """Twelve requests on 4 streams with a budget that keeps at least 8 of
+    them resident at once but not all (so the rest queue); systems come from a
+    device pool.  Every result is bit-identical to the request run alone."""
     print("[case] serving mix", file=sys.stderr, flush=True)
     reqs = _requests()
     be = serve.HipBackend()
-    be.prepare(reqs)
+    be.prepare(reqs, pretune=False)
     fps = sorted(be.footprint(r) for r in reqs)
-    budget = fps[-1] + fps[-2]                       # at most ~2 resident: forces queueing
-    mix, srv = _run(_requests(), budget)
+    budget = sum(fps[-9:])                           # any 9 fit, not all 12
+    mix, srv = _run(_requests(), budget, pool_bytes=budget + (64 << 20))
     assert len(mix) == len(reqs) and srv.max_used <= budget
+    assert srv.max_resident >= 8, srv.max_resident
     rep = serve.Server.report(list(mix.values()), srv.elapsed, serve.hpsi_per_step)
     print(f"[serve] {rep}", file=sys.stderr)
     for r in _requests():
@@ -68,3 +69,50 @@ def test_graph_replay_equals_direct_steps(gpu):
     d, _ = _run(_requests()[:3], use_graphs=False)
     for rid in g:
         assert np.array_equal(g[rid].result["orbitals"], d[rid].result["orbitals"])
+
+
+def test_pooled_system_equals_plain_and_releases(gpu):
+    from paper_2106_03872_amd import ks
+    print("[case] pooled system", file=sys.stderr, flush=True)
+    spec = synth.CONFIGS["t24"]
+    sysm = synth.system(spec)
+    pool = ks.Pool(256 << 20)
+    a = ks.system_from_synth(sysm)
+    b = ks.system_from_synth(sysm, pool=pool)
+    c = torch.from_numpy(synth.orbitals_box(spec)).cuda()
+    assert torch.equal(a.ham_apply(c), b.ham_apply(c))
+    st = ks.State(b, spec.norb)
+    st.upload(c)
+    st.propagate(0.05, 2)
+    used, peak, _ = pool.usage()
+    assert 0 < used <= peak <= 256 << 20
+    st.close()
+    b.close()
+    used, _, largest = pool.usage()
+    assert used == 0 and largest == pool.nbytes       # every range returned and merged
+    with pytest.raises(ks.KSError) as e:              # an exhausted pool fails cleanly
+        ks.System((64, 64, 64), (20.0,) * 3, 10.0, 512, pool=ks.Pool(1 << 20))
+    assert e.value.status == ks.KS_ENOMEM
+    a.close()
+    pool.close()
+
+
+def test_replay_after_retune_is_rejected(gpu):
+    from paper_2106_03872_amd import ks
+    print("[case] stale graph", file=sys.stderr, flush=True)
+    spec = synth.CONFIGS["t24"]
+    gs = ks.system_from_synth(synth.system(spec))
+    st = ks.State(gs, spec.norb)
+    st.upload(torch.from_numpy(synth.orbitals_box(spec)).cuda())
+    s = torch.cuda.Stream()
+    st.capture(0.05, stream=s)
+    st.replay(s)
+    gs.set_tuning(4, 2)                               # launch shapes changed: the graph is stale
+    with pytest.raises(ks.KSError) as e:
+        st.replay(s)
+    assert e.value.status == ks.KS_EINVAL
+    st.capture(0.05, stream=s)                        # captured again: replays work
+    st.replay(s)
+    torch.cuda.synchronize()
+    st.close()
+    gs.close()

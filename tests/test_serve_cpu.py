@@ -38,8 +38,8 @@ def test_backpressure_limits_concurrency():
     srv = serve.Server(be, hbm_budget=250)         # at most two resident requests
     done = srv.run(reqs)
     assert srv.max_used <= 250 and len(done) == 20
-    # intervals [admit, done] never overlap more than twice
-    ev = sorted([(r.t_admit, 1) for r in done] + [(r.t_done, -1) for r in done], key=lambda x: (x[0], x[1]))
+    # intervals [admission start, done] never overlap more than twice
+    ev = sorted([(r.t_submit, 1) for r in done] + [(r.t_done, -1) for r in done], key=lambda x: (x[0], x[1]))
     level = 0
     for _, d in ev:
         level += d
@@ -59,3 +59,18 @@ def test_more_lanes_finish_sooner():
     t4 = serve.Server(serve.FakeBackend(lanes=4), 10 ** 13)
     t4.run(_trace(30))
     assert t4.elapsed < t1.elapsed
+
+
+def test_failing_requests_fail_alone():
+    reqs = _trace(24)
+    be = serve.FakeBackend(lanes=3, fail_admit={3, 11}, fail_step={7})
+    budget = 4 * max(be.footprint(r) for r in reqs)
+    srv = serve.Server(be, budget)
+    done = srv.run(reqs)
+    failed = {r.rid for r in srv.failed}
+    assert failed == {3, 7, 11}
+    assert sorted(r.rid for r in done) == sorted(set(range(24)) - failed)
+    assert all(len(r.step_times) == 5 and not r.error for r in done)
+    assert all(r.error for r in srv.failed)
+    assert 7 in be.discarded                       # the failed step's request was freed
+    assert srv.used_at_end == 0                    # every reservation was released
