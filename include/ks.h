@@ -86,6 +86,17 @@ ks_status ks_system_create(const int n[3], const double L[3], double ecut, int p
 void ks_system_destroy(ks_system* sys);
 
 /*
+ * A non-blocking stream (hipStreamNonBlocking, default priority) on the
+ * current device.  Work on it never waits for, and is never waited for by,
+ * the legacy default stream, so a graph can be captured on it (ks_state_capture,
+ * ks_batch_capture) while other threads use the default stream, as they do
+ * for blocking host transfers.  KS_EINVAL on null, KS_EDEVICE.
+ */
+ks_status ks_stream_create(void** stream);
+/* Destroy a stream from ks_stream_create (after its work has completed). */
+void ks_stream_destroy(void* stream);
+
+/*
  * Device memory pool for many short-lived systems (serving): one device
  * allocation of `bytes`, sub-allocated on the host, so that creating and
  * destroying pooled systems and their states calls no hipMalloc / hipFree
@@ -187,6 +198,23 @@ ks_status ks_hartree(ks_system* sys, const double* rho, double* v, int add_vloc,
  */
 ks_status ks_dipole(ks_system* sys, const double* rho, double* d, void* stream);
 
+/*
+ * Absorption spectrum of a kicked propagation (Section "Results": the
+ * spectrum is the Fourier transform of the dipole moments after the kick):
+ *   x(t_n) = (d(t_n) - d(0)) . k / |k|,  t_n = n dt,
+ *   alpha(w) = |k|^-1 dt sum_{n=0}^{nt-1} c_n x(t_n) exp(i w t_n - damping t_n)
+ *              (trapezoid weights: c_0 = c_{nt-1} = 1/2, else 1),
+ *   S(w) = (2 w / pi) Im alpha(w)   (its integral over w is the number of
+ *                                    electrons: the f-sum rule).
+ * dipoles: device float64 [nt][3] with d(0), the dipole right after the kick,
+ * first; k: host [3], the kick (bohr^-1); omegas: device float64 [nw] (Ha);
+ * alpha: device float64 [nw][2] (re, im); strength: device float64 [nw].
+ * Fixed summation order (deterministic).  No system needed.  KS_EINVAL:
+ * null arguments, nt < 1, nw < 0, dt <= 0, non-finite damping, k zero or
+ * non-finite; the message is ks_last_error(NULL).
+ */
+ks_status ks_spectrum(const double* dipoles, int nt, double dt, const double k[3], const double* omegas, int nw,
+                      double damping, double* alpha, double* strength, void* stream);
 
 /*
  * Orbital norms and band energy (energy expression of Section "DFT and TDDFT
@@ -304,6 +332,42 @@ ks_status ks_state_reduce(ks_state* state, const double* occ, double* norms, dou
  */
 ks_status ks_state_capture(ks_state* state, double dt, const double* occ, double* rho, void* stream);
 ks_status ks_state_replay(ks_state* state, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched steps (serving): resident states of several distinct systems of
+ * one grid (same n, L, ecut and precision, hence one plane-wave sphere) are
+ * propagated together, one launch per kernel and H psi for all of them.
+ * States are independent (Section "Real-time propagation"), and every
+ * orbital goes through the same arithmetic as in its own ks_state_propagate,
+ * so the results are bit-identical to stepping each state alone.
+ *
+ * ks_batch_create: states[nstates] (host array), distinct systems, each
+ * state's norb at most its system's chunk.  Allocates a small device table
+ * (from the first system's pool when it has one).  KS_EINVAL (null, empty,
+ * systems that differ in grid / cell / cutoff / precision, two states of one
+ * system), KS_EUNSUPPORTED (a state larger than its system's pass).
+ * The batch holds the systems' buffers: after ks_system_set_projectors,
+ * set_chunk, set_tuning or autotune on any of them, the batch calls return
+ * KS_EINVAL (create it again).  Destroy the batch before its states.
+ */
+typedef struct ks_batch ks_batch;
+ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out);
+/* Waits for the work of the batch's systems, frees the table. */
+void ks_batch_destroy(ks_batch* batch);
+/* nsteps Taylor-4 steps (as ks_state_propagate without density or norms) of
+ * every state of the batch, on `stream`. */
+ks_status ks_batch_propagate(ks_batch* batch, double dt, int nsteps, void* stream);
+/* Capture one batched step into a graph owned by the batch (non-default
+ * stream, kernel timing off); ks_batch_replay launches it on any stream. */
+ks_status ks_batch_capture(ks_batch* batch, double dt, void* stream);
+ks_status ks_batch_replay(ks_batch* batch, void* stream);
+/* Message of the last failing batch call (or of a failed ks_batch_create on
+ * NULL). */
+const char* ks_batch_last_error(const ks_batch* batch);
+/* One-shot form: create a batch of the states, nsteps steps, destroy it
+ * (waits for the steps).  Errors as ks_batch_create / ks_batch_propagate;
+ * the message is ks_batch_last_error(NULL). */
+ks_status ks_propagate_batch(ks_state* const* states, int nstates, double dt, int nsteps, void* stream);
 
 /*
  * Device bytes a system of this shape plus a resident state of norb orbitals

@@ -296,6 +296,26 @@ def dipole(grid, n):
                      grid.dV * np.sum(n * x[2][None, None, :])])
 
 
+def spectrum(dipoles, dt, k, omegas, damping):
+    """Absorption of a kicked propagation (Section "Results": the spectrum is
+    the Fourier transform of the dipole moments recorded after the kick).
+    ``dipoles[n]`` is d(t_n), t_n = n dt, with d(0) right after the kick;
+    x(t) = (d(t) - d(0)) . k/|k|; alpha(w) = |k|^-1 int x(t) e^{iwt - eta t} dt
+    by the trapezoidal rule over the recorded times; S(w) = (2w/pi) Im alpha(w),
+    whose integral over w is the number of electrons.  Returns (alpha, S)."""
+    d = np.asarray(dipoles, np.float64)
+    k = np.asarray(k, np.float64)
+    kn = float(np.sqrt(np.sum(k * k)))
+    x = (d - d[0]) @ (k / kn)
+    t = dt * np.arange(len(x))
+    w = np.asarray(omegas, np.float64)
+    alpha = np.zeros(len(w), np.complex128)
+    for i in range(len(w)):
+        f = x * np.exp(1j * w[i] * t - damping * t)
+        alpha[i] = dt * (np.sum(f) - 0.5 * (f[0] + f[-1])) / kn
+    return alpha, 2.0 * w / np.pi * alpha.imag
+
+
 # ------------------------------------------------- ground state (Section "Ground-state solution")
 
 def teter(x):

@@ -71,11 +71,24 @@ __global__ __launch_bounds__(NT) void unpack_kernel(const T* __restrict__ pk, in
 // ascending order, DP = scale d_Ip P_Ip (Eq. vnl; scale is the analysis
 // normalisation that the x-analysis leaves out).  One wavefront per (atom,
 // orbital): lane = 8 * slot-lane + q; slot-lanes are combined in a fixed order.
-template <typename C>
+// BATCH: block (I, y) reduces orbital rows[y].y of job rows[y].x (its
+// partial sums, coefficients and tables); atoms beyond the job's count exit.
+template <typename C, bool BATCH = false>
 __global__ __launch_bounds__(64) void proj_reduce_kernel(const C* __restrict__ partial, double2* __restrict__ DP,
-                                                         ProjTab pt, double scale) {
+                                                         ProjTab pt, double scale,
+                                                         const BatchJob* __restrict__ jobs = nullptr,
+                                                         const int4* __restrict__ rows = nullptr) {
   __shared__ double2 red[64];
-  const int I = blockIdx.x, o = blockIdx.y, lane = threadIdx.x;
+  const int I = blockIdx.x, lane = threadIdx.x;
+  int o = blockIdx.y;
+  if constexpr (BATCH) {
+    const int4 r = rows[blockIdx.y];
+    partial = static_cast<const C*>(jobs[r.x].partial);
+    DP = jobs[r.x].DP;
+    pt = jobs[r.x].pt;
+    o = r.y;
+    if (I >= pt.natoms) return;   // uniform per block
+  }
   const int q = lane & 7, sl = lane >> 3;
   const int np = pt.nproj;
   double sx = 0.0, sy = 0.0;
@@ -168,6 +181,19 @@ bool launch_proj_reduce(const ks_system* s, int nb, const void* partial, double2
     proj_reduce_kernel<double2><<<dim3(s->natoms, nb), 64, 0, st>>>((const double2*)partial, DP, proj_tab(s), scale);
   else
     proj_reduce_kernel<float2><<<dim3(s->natoms, nb), 64, 0, st>>>((const float2*)partial, DP, proj_tab(s), scale);
+  return true;
+}
+
+bool launch_proj_reduce_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, int max_natoms,
+                              hipStream_t st) {
+  if (max_natoms == 0 || nrows == 0) return true;
+  const double scale = sqrt(s->omega) / (double)s->N;
+  if (!mixed(s))
+    proj_reduce_kernel<double2, true><<<dim3(max_natoms, nrows), 64, 0, st>>>(nullptr, nullptr, ProjTab{}, scale, jobs,
+                                                                             rows);
+  else
+    proj_reduce_kernel<float2, true><<<dim3(max_natoms, nrows), 64, 0, st>>>(nullptr, nullptr, ProjTab{}, scale, jobs,
+                                                                            rows);
   return true;
 }
 

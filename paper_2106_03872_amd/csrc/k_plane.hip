@@ -19,10 +19,14 @@ constexpr int EP_PRE = 4;   // packed coefficients per thread whose loads are is
 // bytes (unused here).  `stage` = 0 when a plane's coefficients do not fit in
 // Y: the z-synthesis then reads them from HBM directly.
 
-template <int N, typename R, typename TIN, bool HB>
+// BATCH: one launch over several systems of the grid; the block's system
+// (its input, T and orbital count) comes from jobs[rows[blockIdx.y].x].
+template <int N, typename R, typename TIN, bool HB, bool BATCH = false>
 __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ pk, int nb, int pk_stride,
                                                         cplx<R>* __restrict__ Tout, SphereTab tab,
-                                                        const cplx<R>* __restrict__ twN, int ncol_max, int stage) {
+                                                        const cplx<R>* __restrict__ twN, int ncol_max, int stage,
+                                                        const BatchJob* __restrict__ jobs = nullptr,
+                                                        const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
   constexpr int YB = pnb<N>::value;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -34,7 +38,15 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
   __shared__ int s_m2lo[129];
   const int pi = blockIdx.x, tid = threadIdx.x;
   int oa, ob;
-  orbital_range(nb, oa, ob);
+  if constexpr (BATCH) {
+    const int4 r = rows[blockIdx.y];
+    pk = static_cast<const TIN*>(jobs[r.x].win);
+    Tout = static_cast<cplx<R>*>(jobs[r.x].T);
+    nb = jobs[r.x].nb;
+    group_range(nb, r.y, r.z, oa, ob);
+  } else {
+    orbital_range(nb, oa, ob);
+  }
   const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
   const int m1lo = tab.plane_m1lo[pi];
   for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
@@ -109,13 +121,17 @@ __global__ __launch_bounds__(NTP) void plane_inv_kernel(const TIN* __restrict__ 
 // LDS: twiddles [N] | Z [ncol][N+1] | Y [YB][N+1] | column of each packed
 // coefficient of the plane [npp_max] (bytes).
 
-template <int N, typename R, typename TW, bool HB>
+// BATCH: as plane_inv_kernel; U, win, wout, acc and the orbital count come
+// from the block's job (no second accumulator).
+template <int N, typename R, typename TW, bool HB, bool BATCH = false>
 __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restrict__ Uin, int nb, const TW* win,
                                                         cplx<R>* __restrict__ wout, double2* acc, double2* acc2,
                                                         int pk_stride,
                                                         int acc_stride, SphereTab tab,
                                                         const cplx<R>* __restrict__ twN, int ncol_max, int mode,
-                                                        Taylor tay, double g0, double g1, double g2) {
+                                                        Taylor tay, double g0, double g1, double g2,
+                                                        const BatchJob* __restrict__ jobs = nullptr,
+                                                        const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
   constexpr int YB = pnb<N>::value;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -127,7 +143,18 @@ __global__ __launch_bounds__(NTP) void plane_fwd_kernel(const cplx<R>* __restric
   __shared__ int s_m2lo[129];
   const int pi = blockIdx.x, tid = threadIdx.x;
   int oa, ob;
-  orbital_range(nb, oa, ob);
+  if constexpr (BATCH) {
+    const int4 r = rows[blockIdx.y];
+    Uin = static_cast<const cplx<R>*>(jobs[r.x].U);
+    win = static_cast<const TW*>(jobs[r.x].win);
+    wout = static_cast<cplx<R>*>(jobs[r.x].wout);
+    acc = jobs[r.x].acc;
+    acc2 = nullptr;
+    nb = jobs[r.x].nb;
+    group_range(nb, r.y, r.z, oa, ob);
+  } else {
+    orbital_range(nb, oa, ob);
+  }
   const int c0 = tab.plane_col0[pi], nc = tab.plane_col0[pi + 1] - c0;
   const int m1lo = tab.plane_m1lo[pi];
   for (int i = tid; i < N; i += NTP) tw[i] = twN[i];
@@ -242,29 +269,42 @@ static int plane_groups(const ks_system* s, int nb) {
   return (int)((nb + g - 1) / g);
 }
 
-template <int N, typename R, typename TIN>
-static void plane_inv_t(const ks_system* s, int nb, const void* pk, void* T, const void* tw, hipStream_t st) {
+// Batched launches pass (rows, jobs, nrows): the grid's y extent is nrows
+// and every per-system argument comes from the jobs; nb and the pointers
+// below are then unused.
+struct BatchRef {
+  const BatchJob* jobs = nullptr;
+  const int4* rows = nullptr;
+  int nrows = 0;
+};
+
+template <int N, typename R, typename TIN, bool B>
+static void plane_inv_t(const ks_system* s, int nb, const void* pk, void* T, const void* tw, const BatchRef& b,
+                        hipStream_t st) {
   constexpr int YB = pnb<N>::value;
   const int stage = s->npp_max <= YB * (N + 1) ? 1 : 0;
-  const dim3 grid(s->nplanes, plane_groups(s, nb));
+  const dim3 grid(s->nplanes, B ? b.nrows : plane_groups(s, nb));
   if (s->yz_half)
-    plane_inv_kernel<N, R, TIN, true><<<grid, NTP, plane_lds_bytes(s), st>>>(
-        (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage);
+    plane_inv_kernel<N, R, TIN, true, B><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage, b.jobs,
+        b.rows);
   else
-    plane_inv_kernel<N, R, TIN, false><<<grid, NTP, plane_lds_bytes(s), st>>>(
-        (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage);
+    plane_inv_kernel<N, R, TIN, false, B><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const TIN*)pk, nb, s->npw_stride, (cplx<R>*)T, sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, stage, b.jobs,
+        b.rows);
 }
 
-template <int N>
-static void plane_inv_n(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, hipStream_t st) {
-  if (!mixed(s)) plane_inv_t<N, double, double2>(s, nb, pk, T, s->d_tw1, st);
-  else if (in_fp64) plane_inv_t<N, float, double2>(s, nb, pk, T, s->d_tw1f, st);
-  else plane_inv_t<N, float, float2>(s, nb, pk, T, s->d_tw1f, st);
+template <int N, bool B>
+static void plane_inv_n(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, const BatchRef& b,
+                        hipStream_t st) {
+  if (!mixed(s)) plane_inv_t<N, double, double2, B>(s, nb, pk, T, s->d_tw1, b, st);
+  else if (in_fp64) plane_inv_t<N, float, double2, B>(s, nb, pk, T, s->d_tw1f, b, st);
+  else plane_inv_t<N, float, float2, B>(s, nb, pk, T, s->d_tw1f, b, st);
 }
 
 bool launch_plane_inv(const ks_system* s, int nb, const void* pk, bool in_fp64, void* T, hipStream_t st) {
   switch (s->n[1]) {
-#define KS_CASE(v) case v: plane_inv_n<v>(s, nb, pk, in_fp64, T, st); return true;
+#define KS_CASE(v) case v: plane_inv_n<v, false>(s, nb, pk, in_fp64, T, BatchRef{}, st); return true;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:
@@ -272,38 +312,67 @@ bool launch_plane_inv(const ks_system* s, int nb, const void* pk, bool in_fp64, 
   }
 }
 
-template <int N, typename R, typename TW>
-static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, void* acc2,
-                        HMode mode, Taylor tay, const void* tw, hipStream_t st) {
-  const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
-  const dim3 grid(s->nplanes, plane_groups(s, nb));
-  if (s->yz_half)
-    plane_fwd_kernel<N, R, TW, true><<<grid, NTP, plane_lds_bytes(s), st>>>(
-        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, (double2*)acc2, s->npw_stride, s->npw_stride,
-        sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
-  else
-    plane_fwd_kernel<N, R, TW, false><<<grid, NTP, plane_lds_bytes(s), st>>>(
-        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, (double2*)acc2, s->npw_stride, s->npw_stride,
-        sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2);
+bool launch_plane_inv_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool in_fp64,
+                            hipStream_t st) {
+  const BatchRef b{jobs, rows, nrows};
+  switch (s->n[1]) {
+#define KS_CASE(v) case v: plane_inv_n<v, true>(s, 0, nullptr, in_fp64, nullptr, b, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
 }
 
-template <int N>
+template <int N, typename R, typename TW, bool B>
+static void plane_fwd_t(const ks_system* s, int nb, const void* U, const void* win, void* wout, void* acc, void* acc2,
+                        HMode mode, Taylor tay, const void* tw, const BatchRef& b, hipStream_t st) {
+  const double g0 = 2.0 * M_PI / s->L[0], g1 = 2.0 * M_PI / s->L[1], g2 = 2.0 * M_PI / s->L[2];
+  const dim3 grid(s->nplanes, B ? b.nrows : plane_groups(s, nb));
+  if (s->yz_half)
+    plane_fwd_kernel<N, R, TW, true, B><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, (double2*)acc2, s->npw_stride, s->npw_stride,
+        sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2, b.jobs, b.rows);
+  else
+    plane_fwd_kernel<N, R, TW, false, B><<<grid, NTP, plane_lds_bytes(s), st>>>(
+        (const cplx<R>*)U, nb, (const TW*)win, (cplx<R>*)wout, (double2*)acc, (double2*)acc2, s->npw_stride, s->npw_stride,
+        sphere_tab(s), (const cplx<R>*)tw, s->ncol_max, (int)mode, tay, g0, g1, g2, b.jobs, b.rows);
+}
+
+template <int N, bool B>
 static void plane_fwd_n(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
-                        void* acc, void* acc2, HMode mode, Taylor tay, hipStream_t st) {
-  if (!mixed(s)) plane_fwd_t<N, double, double2>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1, st);
-  else if (win_fp64) plane_fwd_t<N, float, double2>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1f, st);
-  else plane_fwd_t<N, float, float2>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1f, st);
+                        void* acc, void* acc2, HMode mode, Taylor tay, const BatchRef& b, hipStream_t st) {
+  if (!mixed(s)) plane_fwd_t<N, double, double2, B>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1, b, st);
+  else if (win_fp64) plane_fwd_t<N, float, double2, B>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1f, b, st);
+  else plane_fwd_t<N, float, float2, B>(s, nb, U, win, wout, acc, acc2, mode, tay, s->d_tw1f, b, st);
 }
 
 bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win, bool win_fp64, void* wout,
                       void* acc, void* acc2, HMode mode, Taylor tay, hipStream_t st) {
   switch (s->n[1]) {
-#define KS_CASE(v) case v: plane_fwd_n<v>(s, nb, U, win, win_fp64, wout, acc, acc2, mode, tay, st); return true;
+#define KS_CASE(v) case v: plane_fwd_n<v, false>(s, nb, U, win, win_fp64, wout, acc, acc2, mode, tay, BatchRef{}, st); return true;
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:
       return false;
   }
+}
+
+bool launch_plane_fwd_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool win_fp64,
+                            Taylor tay, hipStream_t st) {
+  const BatchRef b{jobs, rows, nrows};
+  switch (s->n[1]) {
+#define KS_CASE(v) case v: plane_fwd_n<v, true>(s, 0, nullptr, nullptr, win_fp64, nullptr, nullptr, nullptr, H_TAYLOR, tay, b, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+int plane_group_size(const ks_system* s, long long total_orbitals) {
+  long long g = (long long)s->nplanes * total_orbitals / (256 * 4);
+  return (int)(g < 1 ? 1 : (g > s->pg_max ? s->pg_max : g));
 }
 
 }  // namespace ks

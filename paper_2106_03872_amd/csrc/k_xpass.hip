@@ -39,13 +39,18 @@ __device__ __forceinline__ T wave_sum(T x) {
 // of its orbitals from the synthesis outputs and writes its group's partial
 // density (as xdens does), so a propagation step gets the density of its
 // input orbitals from its first H psi.
-template <int N0, typename R, bool HB, bool DENS>
+// BATCH: one launch over several systems of the grid (no density); the
+// block's system (T, partial sums, projector tables, orbital count) comes
+// from jobs[rows[blockIdx.y].x].
+template <int N0, typename R, bool HB, bool DENS, bool BATCH = false>
 __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    cplx<R>* __restrict__ partial, SphereTab tab, ProjTab pt,
                                                    const cplx<R>* __restrict__ tw0, double scale,
                                                    const double* __restrict__ occ, double* __restrict__ dpart,
-                                                   double inv_omega) {
+                                                   double inv_omega, const BatchJob* __restrict__ jobs = nullptr,
+                                                   const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
+  static_assert(!(BATCH && DENS), "batched launches carry no density");
   constexpr int NB = xnb<N0>::value;
   using FR = fft_regs<N0, NB, NT, C, HB>;
   using LS = last_shape<N0, NB, NT>;
@@ -53,7 +58,16 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   __shared__ C tw[N0];
   const int tile = blockIdx.x, tid = threadIdx.x;
   int oa, ob;
-  orbital_range(nb, oa, ob);
+  if constexpr (BATCH) {
+    const int4 r = rows[blockIdx.y];
+    Tin = static_cast<const C*>(jobs[r.x].T);
+    partial = static_cast<C*>(jobs[r.x].partial);
+    pt = jobs[r.x].pt;
+    nb = jobs[r.x].nb;
+    group_range(nb, r.y, r.z, oa, ob);
+  } else {
+    orbital_range(nb, oa, ob);
+  }
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
@@ -224,11 +238,15 @@ __device__ __forceinline__ void kb_scatter_any(C* X, const double2* dps, const P
   }
 }
 
-template <int N0, typename R, bool HB>
+// BATCH: as xproj_kernel (T, U, V, d P, projector tables and orbital count
+// from the block's job).
+template <int N0, typename R, bool HB, bool BATCH = false>
 __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                     cplx<R>* __restrict__ Uout, const double* __restrict__ V,
                                                     const double2* __restrict__ DP, SphereTab tab, ProjTab pt,
-                                                    const cplx<R>* __restrict__ tw0, double sc_v) {
+                                                    const cplx<R>* __restrict__ tw0, double sc_v,
+                                                    const BatchJob* __restrict__ jobs = nullptr,
+                                                    const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
   constexpr int NB = xnb<N0>::value;
   using LS = last_shape<N0, NB, NT>;
@@ -238,7 +256,18 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   __shared__ C tw[N0];
   const int tile = blockIdx.x, tid = threadIdx.x;
   int oa, ob;
-  orbital_range(nb, oa, ob);
+  if constexpr (BATCH) {
+    const int4 r = rows[blockIdx.y];
+    Tin = static_cast<const C*>(jobs[r.x].T);
+    Uout = static_cast<C*>(jobs[r.x].U);
+    V = jobs[r.x].V;
+    DP = jobs[r.x].DP;
+    pt = jobs[r.x].pt;
+    nb = jobs[r.x].nb;
+    group_range(nb, r.y, r.z, oa, ob);
+  } else {
+    orbital_range(nb, oa, ob);
+  }
   for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
@@ -432,6 +461,48 @@ bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP,
     default:
       return false;
   }
+}
+
+// Batched launches: one x-pass launch over several systems of the grid.
+template <int N0, bool HB>
+static void x_batch_n(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool apply,
+                      hipStream_t st) {
+  const dim3 grid(s->ntiles, nrows);
+  if (!apply) {
+    const double scale = s->dV / sqrt(s->omega);
+    if (!mixed(s))
+      xproj_kernel<N0, double, HB, false, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, sphere_tab(s), ProjTab{},
+                                                                   s->d_tw0, scale, nullptr, nullptr, 0.0, jobs, rows);
+    else
+      xproj_kernel<N0, float, HB, false, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, sphere_tab(s), ProjTab{},
+                                                                  s->d_tw0f, scale, nullptr, nullptr, 0.0, jobs, rows);
+    return;
+  }
+  const double sc_v = 1.0 / (double)s->N;
+  if (!mixed(s))
+    xapply_kernel<N0, double, HB, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, nullptr, nullptr, sphere_tab(s),
+                                                           ProjTab{}, s->d_tw0, sc_v, jobs, rows);
+  else
+    xapply_kernel<N0, float, HB, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, nullptr, nullptr, sphere_tab(s),
+                                                          ProjTab{}, s->d_tw0f, sc_v, jobs, rows);
+}
+
+bool launch_x_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool apply,
+                    hipStream_t st) {
+  switch (s->n[0]) {
+#define KS_CASE(v) \
+  case v: s->x_half ? x_batch_n<v, true>(s, jobs, rows, nrows, apply, st) \
+                    : x_batch_n<v, false>(s, jobs, rows, nrows, apply, st); return true;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+int x_group_size(const ks_system* s, long long total_orbitals) {
+  long long g = (long long)s->ntiles * total_orbitals / (256 * 12);
+  return (int)(g < 1 ? 1 : (g > s->xg_max ? s->xg_max : g));
 }
 
 // Orbital groups of the density pass: each group writes one partial density

@@ -79,6 +79,7 @@ void pool_free(ks_pool* p, void* ptr) {
 ks_status dalloc(ks_system* s, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (s && s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (s && s->pool) {
     *p = pool_alloc(s->pool, bytes);
     if (!*p) return fail(s, KS_ENOMEM, "device pool exhausted (" + std::to_string(bytes) + " B requested)");
@@ -97,7 +98,7 @@ ks_status dalloc(ks_system* s, void** p, size_t bytes) {
 void dfree(ks_system* s, void*& p) {
   if (p) {
     if (s && s->pool) pool_free(s->pool, p);
-    else (void)hipFree(p);
+    else if (!(s && s->pool_lost)) (void)hipFree(p);
   }
   p = nullptr;
 }
@@ -496,6 +497,7 @@ int chunk_len(const ks_system* s, int norb) {
 
 ks_status check_common(ks_system* s, int norb) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (norb < 0 || norb > s->max_norb)
     return fail(s, KS_EINVAL, "norb " + std::to_string(norb) + " outside [0, " + std::to_string(s->max_norb) + "]");
   return KS_OK;
@@ -774,6 +776,20 @@ ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], 
   return system_create(pool, n, L, ecut, precision, max_norb, out);
 }
 
+ks_status ks_stream_create(void** out) {
+  if (!out) return fail(nullptr, KS_EINVAL, "out is null");
+  *out = nullptr;
+  hipStream_t st = nullptr;
+  const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(nullptr, KS_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+  *out = st;
+  return KS_OK;
+}
+
+void ks_stream_destroy(void* stream) {
+  if (stream) (void)hipStreamDestroy((hipStream_t)stream);
+}
+
 ks_status ks_pool_create(unsigned long long bytes, ks_pool** out) {
   if (!out) return fail(nullptr, KS_EINVAL, "out is null");
   *out = nullptr;
@@ -799,6 +815,13 @@ ks_status ks_pool_create(unsigned long long bytes, ks_pool** out) {
 
 void ks_pool_destroy(ks_pool* p) {
   if (!p) return;
+  // systems still alive lose their pool: their buffers go with it, and their
+  // later frees do nothing
+  for (ks_system* s : p->systems) {
+    wait_own(s);
+    s->pool = nullptr;
+    s->pool_lost = true;
+  }
   (void)hipFree(p->base);
   delete p;
 }
@@ -834,6 +857,10 @@ static ks_status system_create(ks_pool* pool, const int n[3], const double L[3],
 
   ks_system* s = new ks_system();
   s->pool = pool;
+  if (pool) {
+    std::lock_guard<std::mutex> lk(pool->mu);
+    pool->systems.push_back(s);
+  }
   if (hipEventCreateWithFlags(&s->done, hipEventDisableTiming) != hipSuccess) {
     s->done = nullptr;
     delete s;
@@ -944,9 +971,19 @@ static ks_status system_create(ks_pool* pool, const int n[3], const double L[3],
   return KS_OK;
 }
 
+static void batch_release(ks_batch* b);
+static void state_release(ks_state* t);
+
 void ks_system_destroy(ks_system* s) {
   if (!s) return;
   wait_own(s);
+  while (!s->batches.empty()) batch_release(s->batches.back());
+  while (!s->states.empty()) state_release(s->states.back());
+  if (s->pool) {
+    std::lock_guard<std::mutex> lk(s->pool->mu);
+    auto& v = s->pool->systems;
+    v.erase(std::remove(v.begin(), v.end(), s), v.end());
+  }
   timing_free(s);
   free_workspace(s);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
@@ -975,6 +1012,7 @@ ks_status ks_system_set_chunk(ks_system* s, int chunk) {
 
 ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!v) return fail(s, KS_EINVAL, "v is null");
   Track tk(s, stream);
   KS_HIP(s, hipMemcpyAsync(s->d_v, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -986,6 +1024,7 @@ ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
 ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
                                    const double* beta, const double* d, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (natoms > 0 && !d) return fail(s, KS_EINVAL, "d is null");
   ProjHost ph;
   {
@@ -1108,6 +1147,7 @@ ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ,
 
 ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!rho || !v) return fail(s, KS_EINVAL, "rho or v is null");
   hipStream_t st = (hipStream_t)stream;
   Track tk(s, st);
@@ -1118,9 +1158,26 @@ ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, v
 
 ks_status ks_dipole(ks_system* s, const double* rho, double* d, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!rho || !d) return fail(s, KS_EINVAL, "rho or d is null");
   Track tk(s, stream);
   return launch_ok(s, launch_dipole(s, rho, d, (hipStream_t)stream), "dipole");
+}
+
+ks_status ks_spectrum(const double* dipoles, int nt, double dt, const double k[3], const double* omegas, int nw,
+                      double damping, double* alpha, double* strength, void* stream) {
+  if (!dipoles || !k || (nw > 0 && (!omegas || !alpha || !strength))) return fail(nullptr, KS_EINVAL, "null argument");
+  if (nt < 1 || nw < 0) return fail(nullptr, KS_EINVAL, "nt must be >= 1 and nw >= 0");
+  if (!std::isfinite(dt) || !(dt > 0.0) || !std::isfinite(damping))
+    return fail(nullptr, KS_EINVAL, "dt must be positive and damping finite");
+  if (!std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]) ||
+      k[0] * k[0] + k[1] * k[1] + k[2] * k[2] == 0.0)
+    return fail(nullptr, KS_EINVAL, "the kick must be finite and non-zero");
+  launch_spectrum(dipoles, nt, dt, k, omegas, nw, damping, reinterpret_cast<double2*>(alpha), strength,
+                  (hipStream_t)stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, KS_EDEVICE, std::string("spectrum: ") + hipGetErrorString(e));
+  return KS_OK;
 }
 
 ks_status ks_reduce(ks_system* s, int norb, const void* psi, const double* occ, double* norms, double* energy,
@@ -1261,6 +1318,7 @@ ks_status ks_state_create(ks_system* s, int norb, ks_state** out) {
     delete t;
     return r;
   }
+  s->states.push_back(t);
   *out = t;
   return KS_OK;
 }
@@ -1272,21 +1330,39 @@ static void state_drop_graph(ks_state* t) {
   t->graph = nullptr;
 }
 
-void ks_state_destroy(ks_state* t) {
-  if (!t) return;
+// Free a state's device memory and graph and detach it from its system
+// (after its system's enqueued work); the handle stays valid but empty.
+static void state_release(ks_state* t) {
   ks_system* s = t->sys;
+  if (!s) return;
   wait_own(s);
+  // batches holding this state hold freed buffers from now on
+  for (size_t i = s->batches.size(); i-- > 0;) {
+    ks_batch* b = s->batches[i];
+    if (std::find(b->states.begin(), b->states.end(), t) != b->states.end()) batch_release(b);
+  }
   state_drop_graph(t);
   void* p = t->data;
   dfree(s, p);
   void* bufs[] = {t->aux, t->gs_buf[0], t->gs_buf[1], t->gs_mat, t->gs_vec};
   for (void* q : bufs) dfree(s, q);
+  t->data = t->aux = t->gs_buf[0] = t->gs_buf[1] = t->gs_mat = nullptr;
+  t->gs_vec = nullptr;
+  s->states.erase(std::remove(s->states.begin(), s->states.end(), t), s->states.end());
+  t->sys = nullptr;
+}
+
+void ks_state_destroy(ks_state* t) {
+  if (!t) return;
+  state_release(t);
   delete t;
 }
 
 ks_status ks_state_upload(ks_state* t, const void* psi, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   hipStream_t st = (hipStream_t)stream;
   Track tk(s, st);
@@ -1297,6 +1373,8 @@ ks_status ks_state_upload(ks_state* t, const void* psi, void* stream) {
 ks_status ks_state_download(ks_state* t, void* psi, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!psi) return fail(s, KS_EINVAL, "psi is null");
   hipStream_t st = (hipStream_t)stream;
   Track tk(s, st);
@@ -1308,6 +1386,8 @@ ks_status ks_state_propagate(ks_state* t, double dt, int nsteps, const double* o
                              void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (nsteps < 0) return fail(s, KS_EINVAL, "nsteps < 0");
   if (!std::isfinite(dt)) return fail(s, KS_EINVAL, "dt must be finite");
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
@@ -1329,6 +1409,8 @@ ks_status ks_state_propagate_etrs(ks_state* t, double dt, int nsteps, const doub
                                   void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (nsteps < 0) return fail(s, KS_EINVAL, "nsteps < 0");
   if (!std::isfinite(dt)) return fail(s, KS_EINVAL, "dt must be finite");
   if (!occ) return fail(s, KS_EINVAL, "occ is required (the Hamiltonian depends on the density)");
@@ -1351,6 +1433,8 @@ ks_status ks_state_propagate_etrs(ks_state* t, double dt, int nsteps, const doub
 ks_status ks_state_kick(ks_state* t, const double k[3], void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!k || !std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
     return fail(s, KS_EINVAL, "k must be three finite numbers");
   hipStream_t st = (hipStream_t)stream;
@@ -1368,6 +1452,8 @@ ks_status ks_state_kick(ks_state* t, const double k[3], void* stream) {
 ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (niter < 0) return fail(s, KS_EINVAL, "niter < 0");
   if (s->prec != KS_FP64) return fail(s, KS_EUNSUPPORTED, "the eigensolver runs on FP64 systems");
   if (niter == 0) return KS_OK;
@@ -1430,6 +1516,8 @@ ks_status ks_state_eigensolve(ks_state* t, int niter, double* eig, double* resid
 ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double* energy, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (energy && !occ) return fail(s, KS_EINVAL, "energy requires occ");
   hipStream_t st = (hipStream_t)stream;
   Track tk(s, st);
@@ -1457,6 +1545,8 @@ ks_status ks_state_reduce(ks_state* t, const double* occ, double* norms, double*
 ks_status ks_state_capture(ks_state* t, double dt, const double* occ, double* rho, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!stream) return fail(s, KS_EINVAL, "capture needs a non-default stream");
   if (s->timing) return fail(s, KS_EINVAL, "kernel timing must be off while capturing");
   if (rho && !occ) return fail(s, KS_EINVAL, "rho requires occ");
@@ -1484,12 +1574,259 @@ ks_status ks_state_capture(ks_state* t, double dt, const double* occ, double* rh
 ks_status ks_state_replay(ks_state* t, void* stream) {
   if (!t) return fail(nullptr, KS_EINVAL, "null state");
   ks_system* s = t->sys;
+  if (!s) return fail(nullptr, KS_EINVAL, "the state's system was destroyed");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
   if (!t->exec) return fail(s, KS_EINVAL, "no captured step");
   if (t->graph_gen != s->gen)
     return fail(s, KS_EINVAL, "the system's buffers or launch shapes changed since the capture; capture again");
   Track tk(s, stream);
   KS_HIP(s, hipGraphLaunch(t->exec, (hipStream_t)stream));
   return KS_OK;
+}
+
+// ------------------------------------------------------------ batched steps
+
+static void batch_drop_graph(ks_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+static bool same_grid(const ks_system* a, const ks_system* b) {
+  for (int i = 0; i < 3; ++i)
+    if (a->n[i] != b->n[i] || a->L[i] != b->L[i]) return false;
+  return a->ecut == b->ecut && a->prec == b->prec;
+}
+
+static ks_status batch_check(ks_batch* b) {
+  for (size_t j = 0; j < b->states.size(); ++j)
+    if (b->states[j]->sys->pool_lost) return fail(b->s0, KS_EINVAL, "a system's pool was destroyed");
+  for (size_t j = 0; j < b->states.size(); ++j)
+    if (b->states[j]->sys->gen != b->gens[j])
+      return fail(b->s0, KS_EINVAL, "a system of the batch changed its buffers or launch shapes; create the batch again");
+  return KS_OK;
+}
+
+ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out) {
+  if (!out) return fail(nullptr, KS_EINVAL, "out is null");
+  *out = nullptr;
+  if (!states || nstates < 1) return fail(nullptr, KS_EINVAL, "a batch needs at least one state");
+  ks_system* s0 = states[0] ? states[0]->sys : nullptr;
+  if (!s0) return fail(nullptr, KS_EINVAL, "null state");
+  std::vector<int4> rx, rp, rr;
+  int max_natoms = 0;
+  long long total = 0;
+  for (int j = 0; j < nstates; ++j) {
+    const ks_state* t = states[j];
+    if (!t) return fail(nullptr, KS_EINVAL, "null state");
+    if (!same_grid(t->sys, s0))
+      return fail(nullptr, KS_EINVAL, "the states' systems differ in grid, cell, cutoff or precision");
+    for (int i = 0; i < j; ++i)
+      if (states[i]->sys == t->sys) return fail(nullptr, KS_EINVAL, "two states of one system (they share its workspace)");
+    if (t->norb > t->sys->cb)
+      return fail(nullptr, KS_EUNSUPPORTED, "a state holds more orbitals than its system's pass (chunk)");
+    total += t->norb;
+    max_natoms = std::max(max_natoms, t->sys->natoms);
+  }
+  const int gx = x_group_size(s0, total), gp = plane_group_size(s0, total);
+  for (int j = 0; j < nstates; ++j) {
+    const int nb = states[j]->norb;
+    const int ngx = (nb + gx - 1) / gx, ngp = (nb + gp - 1) / gp;
+    for (int g = 0; g < ngx; ++g) rx.push_back(make_int4(j, g, ngx, 0));
+    for (int g = 0; g < ngp; ++g) rp.push_back(make_int4(j, g, ngp, 0));
+    if (states[j]->sys->natoms > 0)
+      for (int o = 0; o < nb; ++o) rr.push_back(make_int4(j, o, 0, 0));
+  }
+  ks_batch* b = new ks_batch();
+  b->s0 = s0;
+  b->max_natoms = max_natoms;
+  b->nrows_x = (int)rx.size();
+  b->nrows_p = (int)rp.size();
+  b->nrows_r = (int)rr.size();
+  for (int j = 0; j < nstates; ++j) {
+    b->states.push_back(states[j]);
+    b->gens.push_back(states[j]->sys->gen);
+  }
+  // jobs of the four Taylor sub-steps: w1 = H c -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored
+  std::vector<BatchJob> jobs((size_t)4 * nstates);
+  for (int k = 0; k < 4; ++k) {
+    for (int j = 0; j < nstates; ++j) {
+      ks_state* t = states[j];
+      ks_system* s = t->sys;
+      BatchJob& q = jobs[(size_t)k * nstates + j];
+      const void* src[4] = {t->data, s->pk[1], s->pk[2], s->pk[1]};
+      void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
+      q.win = src[k];
+      q.wout = dst[k];
+      q.acc = t->data;
+      q.T = s->T;
+      q.U = s->U;
+      q.partial = s->partial;
+      q.DP = s->DP;
+      q.V = s->d_v;
+      q.pt = proj_tab(s);
+      q.nb = t->norb;
+    }
+  }
+  const size_t jb = jobs.size() * sizeof(BatchJob);
+  const size_t rb = (rx.size() + rp.size() + std::max<size_t>(rr.size(), 1)) * sizeof(int4);
+  b->dev_bytes = jb + rb;
+  void* dev = nullptr;
+  ks_status r = dalloc(s0, &dev, b->dev_bytes);
+  if (r != KS_OK) {
+    delete b;
+    return fail(nullptr, r, s0->err);
+  }
+  b->dev = (char*)dev;
+  std::vector<char> host(b->dev_bytes, 0);
+  memcpy(host.data(), jobs.data(), jb);
+  memcpy(host.data() + jb, rx.data(), rx.size() * sizeof(int4));
+  memcpy(host.data() + jb + rx.size() * sizeof(int4), rp.data(), rp.size() * sizeof(int4));
+  if (!rr.empty()) memcpy(host.data() + jb + (rx.size() + rp.size()) * sizeof(int4), rr.data(), rr.size() * sizeof(int4));
+  const hipError_t e = hipMemcpy(b->dev, host.data(), b->dev_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    ks_batch_destroy(b);
+    return fail(nullptr, KS_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  for (int k = 0; k < 4; ++k) b->jobs[k] = reinterpret_cast<BatchJob*>(b->dev) + (size_t)k * nstates;
+  b->rows_x = reinterpret_cast<int4*>(b->dev + jb);
+  b->rows_p = b->rows_x + rx.size();
+  b->rows_r = b->rows_p + rp.size();
+  for (ks_state* t : b->states) t->sys->batches.push_back(b);
+  *out = b;
+  return KS_OK;
+}
+
+// Free a batch's table and graph and detach it from its systems (after their
+// enqueued work); the handle stays valid but empty.
+static void batch_release(ks_batch* b) {
+  if (!b->s0) return;
+  for (ks_state* t : b->states) wait_own(t->sys);
+  batch_drop_graph(b);
+  void* p = b->dev;
+  dfree(b->s0, p);
+  b->dev = nullptr;
+  for (ks_state* t : b->states) {
+    auto& v = t->sys->batches;
+    v.erase(std::remove(v.begin(), v.end(), b), v.end());
+  }
+  b->states.clear();
+  b->gens.clear();
+  b->s0 = nullptr;
+}
+
+void ks_batch_destroy(ks_batch* b) {
+  if (!b) return;
+  batch_release(b);
+  delete b;
+}
+
+// nsteps Taylor-4 steps of every state of the batch, one launch per kernel
+// and H psi for all of them.
+static ks_status batch_taylor(ks_batch* b, double dt, int nsteps, hipStream_t st) {
+  ks_system* s0 = b->s0;
+  double2 coef[5];
+  taylor_coefficients(dt, coef);
+  ks_status r;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int k = 1; k <= 4; ++k) {
+      const BatchJob* jobs = b->jobs[k - 1];
+      const bool in64 = k == 1 || s0->prec == KS_FP64;
+      const Taylor tay{coef[k], k < 4 ? 1 : 0, {0.0, 0.0}};
+      if ((r = kcall(s0, KS_K_PLANE_INV, st, "plane_inv",
+                     [&] { return launch_plane_inv_batch(s0, jobs, b->rows_p, b->nrows_p, in64, st); })) != KS_OK)
+        return r;
+      if (b->max_natoms > 0) {
+        if ((r = kcall(s0, KS_K_XPROJ, st, "xproj",
+                       [&] { return launch_x_batch(s0, jobs, b->rows_x, b->nrows_x, false, st); })) != KS_OK)
+          return r;
+        if ((r = kcall(s0, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] {
+               return launch_proj_reduce_batch(s0, jobs, b->rows_r, b->nrows_r, b->max_natoms, st);
+             })) != KS_OK)
+          return r;
+      }
+      if ((r = kcall(s0, KS_K_XAPPLY, st, "xapply",
+                     [&] { return launch_x_batch(s0, jobs, b->rows_x, b->nrows_x, true, st); })) != KS_OK)
+        return r;
+      if ((r = kcall(s0, KS_K_PLANE_FWD, st, "plane_fwd",
+                     [&] { return launch_plane_fwd_batch(s0, jobs, b->rows_p, b->nrows_p, in64, tay, st); })) != KS_OK)
+        return r;
+    }
+  }
+  return KS_OK;
+}
+
+static void batch_track(ks_batch* b, hipStream_t st) {
+  for (ks_state* t : b->states) track(t->sys, st);
+}
+
+ks_status ks_batch_propagate(ks_batch* b, double dt, int nsteps, void* stream) {
+  if (!b) return fail(nullptr, KS_EINVAL, "null batch");
+  if (!b->s0) return fail(nullptr, KS_EINVAL, "a state or system of the batch was destroyed");
+  if (nsteps < 0) return fail(b->s0, KS_EINVAL, "nsteps < 0");
+  if (!std::isfinite(dt)) return fail(b->s0, KS_EINVAL, "dt must be finite");
+  ks_status r = batch_check(b);
+  if (r != KS_OK) return r;
+  const hipStream_t st = (hipStream_t)stream;
+  r = batch_taylor(b, dt, nsteps, st);
+  batch_track(b, st);
+  return r;
+}
+
+ks_status ks_batch_capture(ks_batch* b, double dt, void* stream) {
+  if (!b) return fail(nullptr, KS_EINVAL, "null batch");
+  if (!b->s0) return fail(nullptr, KS_EINVAL, "a state or system of the batch was destroyed");
+  ks_system* s0 = b->s0;
+  if (!stream) return fail(s0, KS_EINVAL, "capture needs a non-default stream");
+  if (!std::isfinite(dt)) return fail(s0, KS_EINVAL, "dt must be finite");
+  if (s0->timing) return fail(s0, KS_EINVAL, "kernel timing must be off while capturing");
+  ks_status r = batch_check(b);
+  if (r != KS_OK) return r;
+  const hipStream_t st = (hipStream_t)stream;
+  batch_drop_graph(b);
+  KS_HIP(s0, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  r = batch_taylor(b, dt, 1, st);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &g);
+  if (r != KS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return fail(s0, KS_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  b->graph = g;
+  const hipError_t e2 = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    batch_drop_graph(b);
+    return fail(s0, KS_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  }
+  return KS_OK;
+}
+
+ks_status ks_batch_replay(ks_batch* b, void* stream) {
+  if (!b) return fail(nullptr, KS_EINVAL, "null batch");
+  if (!b->s0) return fail(nullptr, KS_EINVAL, "a state or system of the batch was destroyed");
+  if (!b->exec) return fail(b->s0, KS_EINVAL, "no captured step");
+  ks_status r = batch_check(b);
+  if (r != KS_OK) return r;
+  const hipStream_t st = (hipStream_t)stream;
+  KS_HIP(b->s0, hipGraphLaunch(b->exec, st));
+  batch_track(b, st);
+  return KS_OK;
+}
+
+const char* ks_batch_last_error(const ks_batch* b) {
+  return (b && b->s0) ? b->s0->err.c_str() : ks_last_error(nullptr);
+}
+
+ks_status ks_propagate_batch(ks_state* const* states, int nstates, double dt, int nsteps, void* stream) {
+  ks_batch* b = nullptr;
+  ks_status r = ks_batch_create(states, nstates, &b);
+  if (r != KS_OK) return r;
+  r = ks_batch_propagate(b, dt, nsteps, stream);
+  if (r != KS_OK) g_create_err = b->s0->err;
+  ks_batch_destroy(b);   // waits for the systems' own work, which includes these steps
+  return r;
 }
 
 ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int precision, int norb, int npoints,

@@ -38,45 +38,6 @@ __device__ __forceinline__ int find_col(const int* off, int nc, int e) {
 
 template <int N> struct pnb { static constexpr int value = N <= 64 ? 64 : (N <= 96 ? 48 : (N <= 120 ? 24 : 16)); };
 
-inline SphereTab sphere_tab(const ks_system* s) {
-
-  SphereTab t;
-  t.plane_col0 = s->d_plane_col0;
-  t.plane_m1lo = s->d_plane_m1lo;
-  t.col_off = s->d_col_off;
-  t.col_m2lo = s->d_col_m2lo;
-  t.nplanes = s->nplanes;
-  t.m0lo = s->m0lo;
-  t.n0 = s->n[0];
-  t.n1 = s->n[1];
-  t.n2 = s->n[2];
-  return t;
-}
-
-inline ProjTab proj_tab(const ks_system* s) {
-  ProjTab c;
-  c.pt_lds = s->d_pt_lds;
-  c.slot_off = s->d_slot_off;
-  c.slot_atom = s->d_slot_atom;
-  c.slot_pt = s->d_slot_pt;
-  c.atom_slot_off = s->d_atom_slot_off;
-  c.atom_slots = s->d_atom_slots;
-  c.up_off = s->d_up_off;
-  c.up_key = s->d_up_key;
-  c.up_x = s->d_up_x;
-  c.up_beta = s->d_up_beta;
-  c.x_slot = s->d_x_slot;
-  c.x_beta = s->d_x_beta;
-  c.beta = s->d_beta;
-  c.d = s->d_kb;
-  c.item = s->d_item;
-  c.natoms = s->natoms;
-  c.nproj = s->nproj;
-  c.nslots = s->nslots;
-  return c;
-}
-
-
 inline bool mixed(const ks_system* s) { return s->prec == KS_MIXED; }
 
 // Orbital group of a block: the orbitals [y*nb/ng, (y+1)*nb/ng) with
@@ -84,6 +45,12 @@ inline bool mixed(const ks_system* s) { return s->prec == KS_MIXED; }
 __device__ __forceinline__ void orbital_range(int nb, int& oa, int& ob) {
   oa = (int)((long long)blockIdx.y * nb / gridDim.y);
   ob = (int)((long long)(blockIdx.y + 1) * nb / gridDim.y);
+}
+
+// The same for group g of ng over nb orbitals (a batched launch's row).
+__device__ __forceinline__ void group_range(int nb, int g, int ng, int& oa, int& ob) {
+  oa = (int)((long long)g * nb / ng);
+  ob = (int)((long long)(g + 1) * nb / ng);
 }
 
 }  // namespace ks

@@ -9,6 +9,8 @@
 
 #include "../../include/ks.h"
 
+struct ks_batch;
+
 namespace ks {
 
 // Plane-wave sphere in packed order: planes m0 = m0lo .. m0lo+nplanes-1, in
@@ -51,6 +53,24 @@ struct ProjTab {
   int natoms, nproj, nslots;
 };
 
+// One system of a batched launch (several systems of one grid, hence one
+// sphere and one tiling, in one launch of each H psi kernel): its buffers
+// and projector tables.  Block row y of a batched launch belongs to job
+// rows[y].x, orbital group rows[y].y of rows[y].z (proj_reduce: orbital
+// rows[y].y).
+struct BatchJob {
+  const void* win;    // packed input orbitals of the H psi (plane synthesis; kinetic term)
+  void* wout;         // packed H psi (working precision), or null
+  double2* acc;       // Taylor accumulator (the FP64 state)
+  void* T;            // plane intermediates
+  void* U;
+  void* partial;      // projection partial sums
+  double2* DP;        // KB coefficients times projections
+  const double* V;    // local potential
+  ProjTab pt;
+  int nb;             // orbitals
+};
+
 // up_key fields
 constexpr int UP_POS_BITS = 16, UP_SLOT_BITS = 8;
 constexpr int UP_MAX_SLOT = (1 << UP_SLOT_BITS) - 1, UP_MAX_EXTRA = 127;
@@ -80,6 +100,7 @@ struct ks_pool {
   int device = 0;
   std::map<size_t, size_t> free_ranges;   // offset -> size
   std::map<size_t, size_t> live;          // offset -> size
+  std::vector<ks_system*> systems;        // systems created in the pool (released if the pool goes first)
   std::mutex mu;
 };
 
@@ -161,12 +182,18 @@ struct ks_system {
 
   // device memory source (nullptr: hipMalloc / hipFree per buffer)
   ks_pool* pool = nullptr;
+  bool pool_lost = false;   // the pool was destroyed first: buffers are gone, frees do nothing
   // recorded on the stream of every call that enqueues work (outside stream
   // capture): destroying the system or one of its states waits for it
   // instead of the whole device
   hipEvent_t done = nullptr;
   // bumped whenever buffers or launch shapes that a captured graph holds change
   unsigned long long gen = 0;
+  // live states and batches of the system: destroying the system releases
+  // their device memory and leaves them as empty handles, so handles may be
+  // destroyed in any order
+  std::vector<ks_state*> states;
+  std::vector<ks_batch*> batches;
 };
 
 // Orbitals kept resident on the device in the packed FP64 layout.
@@ -187,6 +214,23 @@ struct ks_state {
   unsigned long long graph_gen = 0;   // system generation at capture
 };
 
+// Several resident states of distinct systems of one grid, stepped together
+// by one launch per H psi kernel (ks_batch_create).
+struct ks_batch {
+  std::vector<ks_state*> states;
+  std::vector<unsigned long long> gens;   // each system's generation at creation
+  ks_system* s0 = nullptr;                // the first system: sphere, twiddles, precision, caps
+  char* dev = nullptr;                    // device tables (jobs of the 4 Taylor sub-steps, rows)
+  size_t dev_bytes = 0;
+  ks::BatchJob* jobs[4] = {nullptr, nullptr, nullptr, nullptr};
+  int4* rows_x = nullptr;                 // x-pass rows (job, group, groups)
+  int4* rows_p = nullptr;                 // plane-pass rows
+  int4* rows_r = nullptr;                 // projection-reduce rows (job, orbital)
+  int nrows_x = 0, nrows_p = 0, nrows_r = 0, max_natoms = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace ks {
 
 // launchers (ks_kernels.hip); return false when the size has no kernel
@@ -205,6 +249,23 @@ bool launch_plane_fwd(const ks_system* s, int nb, const void* U, const void* win
                       void* acc, void* acc2, HMode mode, Taylor tay, hipStream_t st);
 bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,
                   hipStream_t st);
+// Batched launches over several systems of s's grid (s supplies the sphere,
+// twiddles, precision and launch caps); jobs and rows in device memory, see
+// BatchJob.  x-passes: rows of orbital groups (apply = false: projections,
+// true: local potential, scatter and analysis); proj_reduce: one row per
+// (job, orbital) and max_natoms blocks per row; plane passes: rows of orbital
+// groups, Taylor mode with the jobs' acc and wout.
+bool launch_plane_inv_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool in_fp64,
+                            hipStream_t st);
+bool launch_x_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool apply, hipStream_t st);
+bool launch_proj_reduce_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, int max_natoms,
+                              hipStream_t st);
+bool launch_plane_fwd_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool win_fp64,
+                            Taylor tay, hipStream_t st);
+// orbitals per block of the x-pencil and plane passes for a launch over
+// total_orbitals orbitals (the same rule as the single-system launches)
+int x_group_size(const ks_system* s, long long total_orbitals);
+int plane_group_size(const ks_system* s, long long total_orbitals);
 bool launch_dots(const ks_system* s, int nb, const void* a, const void* b, double* out, hipStream_t st);
 bool launch_energy_sum(int norb, const double* occ, const double* red, double* energy, hipStream_t st);
 // part: split-K partial products (part_bytes of them; NULL: no split)
@@ -221,6 +282,9 @@ bool launch_hartree(const ks_system* s, const double* rho, double* v, const doub
 
 // psi <- chi exp(i k.r) psi for one orbital held on the complex box W (in place)
 bool launch_kick(const ks_system* s, double2* W, const double k[3], hipStream_t st);
+// absorption spectrum of a dipole series (see k_response.hip); k: host, |k| > 0
+void launch_spectrum(const double* d, int nt, double dt, const double k[3], const double* omegas, int nw,
+                     double eta, double2* alpha, double* strength, hipStream_t st);
 // d[0..2] = dV sum_r r rho(r) (device output; uses the work box for partial sums)
 bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t st);
 
@@ -255,5 +319,44 @@ void launch_sd_update(int norb, int npw, int stride, double2* C, const double2* 
 bool supported_size(int n);
 int x_tile_nb(int n0);
 size_t plane_lds_bytes(const ks_system* s);
+
+// kernel-side views of a system's sphere and projector tables
+inline SphereTab sphere_tab(const ks_system* s) {
+
+  SphereTab t;
+  t.plane_col0 = s->d_plane_col0;
+  t.plane_m1lo = s->d_plane_m1lo;
+  t.col_off = s->d_col_off;
+  t.col_m2lo = s->d_col_m2lo;
+  t.nplanes = s->nplanes;
+  t.m0lo = s->m0lo;
+  t.n0 = s->n[0];
+  t.n1 = s->n[1];
+  t.n2 = s->n[2];
+  return t;
+}
+
+inline ProjTab proj_tab(const ks_system* s) {
+  ProjTab c;
+  c.pt_lds = s->d_pt_lds;
+  c.slot_off = s->d_slot_off;
+  c.slot_atom = s->d_slot_atom;
+  c.slot_pt = s->d_slot_pt;
+  c.atom_slot_off = s->d_atom_slot_off;
+  c.atom_slots = s->d_atom_slots;
+  c.up_off = s->d_up_off;
+  c.up_key = s->d_up_key;
+  c.up_x = s->d_up_x;
+  c.up_beta = s->d_up_beta;
+  c.x_slot = s->d_x_slot;
+  c.x_beta = s->d_x_beta;
+  c.beta = s->d_beta;
+  c.d = s->d_kb;
+  c.item = s->d_item;
+  c.natoms = s->natoms;
+  c.nproj = s->nproj;
+  c.nslots = s->nslots;
+  return c;
+}
 
 }  // namespace ks

@@ -7,6 +7,7 @@ current torch stream is passed to every call.  Importing this module loads
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
@@ -60,6 +61,15 @@ def _load():
         "ks_system_destroy": (None, [P]),
         "ks_system_create_in": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, ctypes.POINTER(P)]),
         "ks_pool_create": (I, [ctypes.c_ulonglong, ctypes.POINTER(P)]),
+        "ks_stream_create": (I, [ctypes.POINTER(P)]),
+        "ks_stream_destroy": (None, [P]),
+        "ks_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P)]),
+        "ks_batch_destroy": (None, [P]),
+        "ks_batch_propagate": (I, [P, D, I, P]),
+        "ks_batch_capture": (I, [P, D, P]),
+        "ks_batch_replay": (I, [P, P]),
+        "ks_batch_last_error": (ctypes.c_char_p, [P]),
+        "ks_propagate_batch": (I, [ctypes.POINTER(P), I, D, I, P]),
         "ks_pool_destroy": (None, [P]),
         "ks_pool_usage": (I, [P, ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_ulonglong),
                               ctypes.POINTER(ctypes.c_ulonglong)]),
@@ -83,6 +93,7 @@ def _load():
         "ks_state_propagate_etrs": (I, [P, D, I, P, P, P, P]),
         "ks_hartree": (I, [P, P, P, I, P]),
         "ks_dipole": (I, [P, P, P, P]),
+        "ks_spectrum": (I, [P, I, D, ctypes.POINTER(D), P, I, D, P, P, P]),
         "ks_state_kick": (I, [P, ctypes.POINTER(D), P]),
         "ks_state_eigensolve": (I, [P, I, P, P, P]),
         "ks_state_reduce": (I, [P, P, P, P, P]),
@@ -105,6 +116,19 @@ def _load():
 
 
 _lib = _load()
+
+# At interpreter exit the process releases every device resource itself;
+# finalisers that run after this point (objects collected during shutdown, in
+# no particular order) do not call into the runtime.
+_exiting = False
+
+
+def _mark_exiting():
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_mark_exiting)
 
 
 def header_symbols():
@@ -180,6 +204,106 @@ def _ptr(t, dtype, shape=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+class Stream:
+    """A non-blocking HIP stream (ks_stream_create) usable as a torch stream
+    (``.torch``): graphs can be captured on it while other threads use the
+    legacy default stream.  torch may keep the raw stream in its allocators'
+    bookkeeping (events of pinned or cross-stream blocks), so the stream is
+    destroyed only by an explicit close(), never by garbage collection; long-
+    lived users take streams from ``stream_pool``."""
+
+    def __init__(self):
+        import torch
+        h = ctypes.c_void_p()
+        st = _lib.ks_stream_create(ctypes.byref(h))
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_last_error(None).decode())
+        self._h = h
+        self.torch = torch.cuda.ExternalStream(h.value)
+
+    def close(self):
+        """Destroy the stream after its work (the caller makes sure nothing
+        refers to it any more)."""
+        if getattr(self, "_h", None):
+            self.torch.synchronize()
+            _lib.ks_stream_destroy(self._h)
+            self._h = None
+
+
+_stream_pool = []
+_stream_pool_lock = None
+
+
+def stream_pool(i):
+    """The i-th process-wide non-blocking Stream (created on first use, kept
+    until the process ends), so that repeated users reuse streams."""
+    import threading
+    global _stream_pool_lock
+    if _stream_pool_lock is None:
+        _stream_pool_lock = threading.Lock()
+    with _stream_pool_lock:
+        while len(_stream_pool) <= i:
+            _stream_pool.append(Stream())
+        return _stream_pool[i]
+
+
+class Batch:
+    """Resident states of distinct systems of one grid stepped together,
+    one launch per kernel for all of them (ks_batch_create).  The batch
+    keeps the states (and their systems) referenced."""
+
+    def __init__(self, states):
+        self.states = list(states)
+        arr = (ctypes.c_void_p * len(self.states))(*[s._h.value for s in self.states])
+        h = ctypes.c_void_p()
+        st = _lib.ks_batch_create(arr, len(self.states), ctypes.byref(h))
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_batch_last_error(None).decode())
+        self._h = h
+        self._captured = None
+
+    def _check(self, st):
+        if st != KS_OK:
+            raise KSError(st, _lib.ks_batch_last_error(self._h).decode())
+
+    @staticmethod
+    def _st(stream):
+        return ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream()
+
+    def propagate(self, dt, nsteps=1, stream=None):
+        self._check(_lib.ks_batch_propagate(self._h, float(dt), int(nsteps), self._st(stream)))
+
+    def capture(self, dt, stream):
+        if stream is None:
+            raise ValueError("capture needs an explicit non-default stream")
+        self._check(_lib.ks_batch_capture(self._h, float(dt), self._st(stream)))
+
+    def replay(self, stream=None):
+        self._check(_lib.ks_batch_replay(self._h, self._st(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ks_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if _exiting:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def propagate_batch(states, dt, nsteps=1, stream=None):
+    """ks_propagate_batch: nsteps Taylor-4 steps of the states together."""
+    arr = (ctypes.c_void_p * len(states))(*[s._h.value for s in states])
+    st = _lib.ks_propagate_batch(arr, len(states), float(dt), int(nsteps),
+                                 ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream())
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_batch_last_error(None).decode())
+
+
 class Pool:
     """Device memory pool (ks_pool_create): systems created in it allocate
     and free without hipMalloc / hipFree."""
@@ -206,6 +330,8 @@ class Pool:
             self._h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -243,6 +369,8 @@ class System:
             self._h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -391,6 +519,8 @@ class State:
             self._h = None
 
     def __del__(self):
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:

@@ -1,35 +1,40 @@
-"""Optical absorption from a kicked propagation (host side).
+"""Optical absorption from a kicked propagation: binding of ks_spectrum.
 
 After a field kick ``exp(i k.r)`` at t = 0 (``State.kick``; the electrons
 gain momentum k) the dipole moment ``d(t)`` (``System.dipole`` of each step's
-density, the first moment of the electron number density) responds linearly
-for a small kick; the absorption (dipole strength) along the kick direction is
-``S(w) = (2 w / pi) Im[alpha(w)]`` with
-``alpha(w) = (1/|k|) int_0^T (d(t) - d(0)) . k_hat e^{i w t} e^{-eta t} dt``,
-normalised so that the integral of S over w is the number of electrons
-(f-sum rule)
-(Section "Results": the spectrum is the Fourier transform of the dipole
-moments recorded after the kick).  The time integral is the trapezoidal rule
-over the recorded steps.
+density) responds linearly for a small kick; the absorption along the kick
+direction is ``S(w) = (2 w / pi) Im alpha(w)`` with
+``alpha(w) = |k|^-1 int (d(t) - d(0)) . k_hat e^{i w t - eta t} dt``
+(trapezoidal rule over the recorded steps), normalised so that the integral
+of S over w is the number of electrons (Section "Results": the spectrum is
+the Fourier transform of the dipole moments recorded after the kick).  The
+sums run on the device (``ks_spectrum``); this module only marshals.
 """
 from __future__ import annotations
+
+import ctypes
 
 import numpy as np
 
 
 def absorption_spectrum(dipoles, dt, k, omegas, damping=0.005):
-    """dipoles: [nsteps + 1, 3] with d(0) first (the density right after the
-    kick); dt: time step; k: kick vector; omegas: frequencies (Ha).  Returns
-    (alpha(w) complex, S(w))."""
-    d = np.asarray(dipoles, np.float64)
-    k = np.asarray(k, np.float64)
-    kn = float(np.linalg.norm(k))
-    if kn == 0.0:
-        raise ValueError("the kick must be non-zero")
-    x = (d - d[0]) @ (k / kn)
-    t = dt * np.arange(len(x))
-    w = np.asarray(omegas, np.float64)[:, None]
-    f = x[None, :] * np.exp(1j * w * t[None, :] - damping * t[None, :])
-    integral = dt * (f.sum(axis=1) - 0.5 * (f[:, 0] + f[:, -1]))
-    alpha = integral / kn
-    return alpha, 2.0 * w[:, 0] / np.pi * alpha.imag
+    """dipoles: [nsteps + 1, 3] float64 (torch tensor on the device, or an
+    array that is copied there) with d(0) first, the dipole right after the
+    kick; dt: time step; k: kick vector; omegas: frequencies (Ha).  Returns
+    (alpha, S) as device tensors: complex128 [nw] and float64 [nw]."""
+    import torch
+
+    from paper_2106_03872_amd import ks
+    d = torch.as_tensor(np.asarray(dipoles.cpu() if hasattr(dipoles, "cpu") else dipoles, np.float64)).to("cuda")
+    w = torch.as_tensor(np.asarray(omegas.cpu() if hasattr(omegas, "cpu") else omegas, np.float64)).to("cuda")
+    d = d.reshape(-1, 3).contiguous()
+    w = w.reshape(-1).contiguous()
+    alpha = torch.empty((w.numel(), 2), dtype=torch.float64, device="cuda")
+    S = torch.empty(w.numel(), dtype=torch.float64, device="cuda")
+    kk = (ctypes.c_double * 3)(*[float(x) for x in k])
+    st = ks.library().ks_spectrum(ctypes.c_void_p(d.data_ptr()), int(d.shape[0]), float(dt), kk,
+                                  ctypes.c_void_p(w.data_ptr()), int(w.numel()), float(damping),
+                                  ctypes.c_void_p(alpha.data_ptr()), ctypes.c_void_p(S.data_ptr()), ks._stream())
+    if st != ks.KS_OK:
+        raise ks.KSError(st, ks.library().ks_last_error(None).decode())
+    return torch.view_as_complex(alpha), S

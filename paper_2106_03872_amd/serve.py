@@ -54,6 +54,44 @@ class Request:
     error: str = ""
 
 
+class _RWLock:
+    """Shared/exclusive lock with writer preference: admission workers hold
+    it shared while they make HIP calls; the issue loop holds it exclusively
+    while it captures a graph, so that no other thread touches the runtime
+    during a capture."""
+
+    def __init__(self):
+        self._c = threading.Condition()
+        self._readers = 0
+        self._writer = False
+        self._waiting = 0
+
+    def acquire_read(self):
+        with self._c:
+            while self._writer or self._waiting:
+                self._c.wait()
+            self._readers += 1
+
+    def release_read(self):
+        with self._c:
+            self._readers -= 1
+            if self._readers == 0:
+                self._c.notify_all()
+
+    def acquire_write(self):
+        with self._c:
+            self._waiting += 1
+            while self._writer or self._readers:
+                self._c.wait()
+            self._waiting -= 1
+            self._writer = True
+
+    def release_write(self):
+        with self._c:
+            self._writer = False
+            self._c.notify_all()
+
+
 def percentile(x, q):
     return float(np.percentile(np.asarray(x, float), q)) if len(x) else float("nan")
 
@@ -77,20 +115,32 @@ class Server:
             r.footprint = be.footprint(r)
             if r.footprint > self.budget:
                 raise ValueError(f"request {r.rid} needs {r.footprint} B, more than the budget {self.budget} B")
-        waiting, admitting, active, retiring, done = deque(), [], [], [], []
         self.failed = []
-        used = 0
-
-        def fail(r, exc):
-            nonlocal used
-            r.error = f"{type(exc).__name__}: {exc}"
-            r.t_done = be.now()
-            used -= r.footprint
-            be.discard(getattr(r, "handle", None))
-            r.handle = None
-            self.failed.append(r)
-
+        self._used = 0
+        done = []
         be.start()
+        try:
+            self._loop(be, pending, done)
+        finally:
+            be.finish()          # admission workers joined even when the loop raises
+        self.elapsed = be.now()
+        self.used_at_end = self._used
+        return done
+
+    def _fail(self, r, exc):
+        """Request r fails alone: error recorded, resources and reservation released."""
+        r.error = f"{type(exc).__name__}: {exc}"
+        r.t_done = self.be.now()
+        self._used -= r.footprint
+        try:
+            self.be.discard(getattr(r, "handle", None))
+        except Exception:
+            pass
+        r.handle = None
+        self.failed.append(r)
+
+    def _loop(self, be, pending, done):
+        waiting, admitting, active, retiring = deque(), [], [], []
         while pending or waiting or admitting or active or retiring:
             progressed = False
             now = be.now()
@@ -98,10 +148,10 @@ class Server:
                 waiting.append(pending.popleft())
                 progressed = True
             while (waiting and len(active) + len(admitting) < self.max_active
-                   and used + waiting[0].footprint <= self.budget):
+                   and self._used + waiting[0].footprint <= self.budget):
                 r = waiting.popleft()
-                used += r.footprint
-                self.max_used = max(self.max_used, used)
+                self._used += r.footprint
+                self.max_used = max(self.max_used, self._used)
                 r.t_submit = be.now()
                 r.handle = None
                 r.admit_tok = be.admit_submit(r)
@@ -112,7 +162,7 @@ class Server:
                 try:
                     h = be.admit_poll(r.admit_tok)
                 except Exception as exc:      # this request fails alone
-                    fail(r, exc)
+                    self._fail(r, exc)
                     progressed = True
                     continue
                 if h is None:
@@ -132,17 +182,26 @@ class Server:
                     except Exception as exc:
                         r.inflight = exc
                     progressed = True
+            for h, exc in be.flush():             # batched launches of the steps asked for
+                for q in active:
+                    if q.handle is h:
+                        q.inflight = exc
             still = []
             for r in active:
                 if isinstance(r.inflight, Exception):
-                    fail(r, r.inflight)
+                    self._fail(r, r.inflight)
                     continue
                 if r.inflight is not None and be.is_done(r.inflight):
                     r.step_times.append(be.done_time(r.inflight))
                     r.inflight = None
                     progressed = True
                 if len(r.step_times) == r.nsteps and r.inflight is None:
-                    r.retire_tok = be.retire_submit(r.handle, self.keep_orbitals)
+                    try:
+                        r.retire_tok = be.retire_submit(r.handle, self.keep_orbitals)
+                    except Exception as exc:
+                        self._fail(r, exc)
+                        progressed = True
+                        continue
                     retiring.append(r)
                     progressed = True
                 else:
@@ -150,23 +209,24 @@ class Server:
             active = still
             still = []
             for r in retiring:
-                res = be.retire_poll(r.retire_tok)
+                try:
+                    res = be.retire_poll(r.retire_tok)
+                except Exception as exc:
+                    self._fail(r, exc)
+                    progressed = True
+                    continue
                 if res is None:
                     still.append(r)
                     continue
                 r.result = res
                 r.t_done = be.now()
                 r.handle = None
-                used -= r.footprint
+                self._used -= r.footprint
                 done.append(r)
                 progressed = True
             retiring = still
             if not progressed:
                 be.idle(pending[0].arrival if pending else None)
-        self.elapsed = be.now()
-        self.used_at_end = used
-        be.finish()
-        return done
 
     @staticmethod
     def report(done, elapsed, hpsi_per_step):
@@ -213,9 +273,15 @@ class HipBackend:
         self.torch = torch
         self.ks = ks
         self.precision = ks.KS_MIXED if precision is None else precision
-        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        # non-blocking streams: graphs are captured on them while other
+        # threads make blocking (legacy-stream) host transfers
+        self.streams = [ks.stream_pool(i).torch for i in range(nstreams)]
+        self._next_admit_stream = nstreams + 1
+        self._stream_lock = threading.Lock()
         self.admit_workers = int(admit_workers)
         self._tls = threading.local()     # one admission stream per worker thread
+        self._rw = _RWLock()
+        self._capture_stream = ks.stream_pool(nstreams)
         self.use_graphs = use_graphs
         self.dt = dt
         self._next = 0
@@ -274,9 +340,13 @@ class HipBackend:
     def _admit(self, r, sysm, sel, vals):
         torch, ks = self.torch, self.ks
         if getattr(self._tls, "stream", None) is None:
-            self._tls.stream = torch.cuda.Stream()
+            with self._stream_lock:
+                idx = self._next_admit_stream
+                self._next_admit_stream += 1
+            self._tls.stream = ks.stream_pool(idx).torch
         stream = self._tls.stream
         h = {"stream": self.streams[r.rid % len(self.streams)]}
+        self._rw.acquire_read()
         try:
             with torch.cuda.stream(stream):
                 gs = ks.system_from_synth(sysm, precision=self.precision, pool=self.pool)
@@ -292,8 +362,10 @@ class HipBackend:
                 occ = torch.full((r.spec.norb,), float(r.spec.occ), dtype=torch.float64, device="cuda")
                 h["occ"] = occ
                 h["occ_sum"] = float(r.spec.occ) * r.spec.norb
-                if self.use_graphs:
-                    st.capture(self.dt, stream=stream)
+                # pinned read-back buffers of the retire, allocated here so
+                # that the issue loop allocates no host memory
+                h["pin_norms"] = torch.empty(r.spec.norb, dtype=torch.float64, pin_memory=True)
+                h["pin_energy"] = torch.empty(1, dtype=torch.float64, pin_memory=True)
                 ready = torch.cuda.Event()
                 ready.record(stream)
                 del c
@@ -301,6 +373,8 @@ class HipBackend:
         except Exception:
             self.discard(h)
             raise
+        finally:
+            self._rw.release_read()
         return h
 
     def admit_submit(self, r):
@@ -310,7 +384,20 @@ class HipBackend:
     def admit_poll(self, tok):
         if not tok.done():
             return None
-        return tok.result()                  # raises the admission's error
+        h = tok.result()                     # raises the admission's error
+        if self.use_graphs and "graph" not in h:
+            # one step captured into a graph, here in the issue loop while
+            # no worker makes HIP calls
+            self._rw.acquire_write()
+            try:
+                h["state"].capture(self.dt, stream=self._capture_stream.torch)
+                h["graph"] = True
+            except Exception:
+                self.discard(h)
+                raise
+            finally:
+                self._rw.release_write()
+        return h
 
     def issue_step(self, h):
         with self.torch.cuda.stream(h["stream"]):
@@ -322,8 +409,13 @@ class HipBackend:
             ev.record(h["stream"])
         return [ev, None]
 
+    def flush(self):
+        """Launch what issue_step deferred; returns [(handle, error)] of
+        requests whose launch failed."""
+        return []
+
     def is_done(self, tok):
-        if tok[1] is None and tok[0].query():
+        if tok[1] is None and tok[0] is not None and tok[0].query():
             tok[1] = self.now()
         return tok[1] is not None
 
@@ -334,27 +426,22 @@ class HipBackend:
         torch = self.torch
         with torch.cuda.stream(h["stream"]):
             norms, energy = h["state"].reduce(h["occ"], stream=h["stream"])
-            out = {"norms": torch.empty(norms.shape, dtype=norms.dtype, pin_memory=True),
-                   "energy": torch.empty(1, dtype=torch.float64, pin_memory=True)}
-            out["norms"].copy_(norms, non_blocking=True)
-            out["energy"].copy_(energy, non_blocking=True)
-            if keep_orbitals:
-                psi = h["state"].download(stream=h["stream"])
-                out["orbitals"] = torch.empty(psi.shape, dtype=psi.dtype, pin_memory=True)
-                out["orbitals"].copy_(psi, non_blocking=True)
+            h["pin_norms"].copy_(norms, non_blocking=True)
+            h["pin_energy"].copy_(energy, non_blocking=True)
+            psi = h["state"].download(stream=h["stream"]) if keep_orbitals else None
             ev = torch.cuda.Event()
             ev.record(h["stream"])
-        h["retire"] = (ev, out, (norms, energy))
+        h["retire"] = (ev, psi, (norms, energy))
         return h
 
     def retire_poll(self, h):
-        ev, out, _ = h["retire"]
+        ev, psi, _ = h["retire"]
         if not ev.query():
             return None
-        res = {"norms": out["norms"].numpy().copy(), "energy": float(out["energy"][0]),
+        res = {"norms": h["pin_norms"].numpy().copy(), "energy": float(h["pin_energy"][0]),
                "electrons": float(h["occ_sum"])}
-        if "orbitals" in out:
-            res["orbitals"] = out["orbitals"].numpy().copy()
+        if psi is not None:
+            res["orbitals"] = psi.cpu().numpy()     # complete: its event has passed
         self.discard(h)
         return res
 
@@ -373,12 +460,100 @@ class HipBackend:
         time.sleep(20e-6)
 
 
+class BatchedHipBackend(HipBackend):
+    """HipBackend whose steps are ragged-batched: the resident requests of
+    one grid (one plane-wave sphere) that want a step are stepped together by
+    one launch per kernel (ks_batch), on the grid's stream.  A grid issues its
+    next batched step once the previous one has completed, so requests that
+    became ready meanwhile join it.  Every request's orbitals go through the
+    same arithmetic as alone, so results are bit-identical to HipBackend's."""
+
+    def __init__(self, *args, **kw):
+        kw.setdefault("use_graphs", False)
+        super().__init__(*args, **kw)
+        self._want = {}       # grid -> [(handle, token)]
+        self._inflight = {}   # grid -> event of the grid's step in flight
+        self._batches = {}    # grid -> (composition, ks.Batch)
+        self.batched_steps = 0
+        self.batch_sizes = []
+        self._grid_slot = {}  # grid -> stream index (round-robin on first sight)
+        self._grid_lock = threading.Lock()
+
+    def _grid(self, h):
+        return h["grid"]
+
+    def _grid_stream(self, grid):
+        with self._grid_lock:
+            if grid not in self._grid_slot:
+                self._grid_slot[grid] = len(self._grid_slot) % len(self.streams)
+            return self.streams[self._grid_slot[grid]]
+
+    def _admit(self, r, sysm, sel, vals):
+        h = super()._admit(r, sysm, sel, vals)
+        h["grid"] = tuple(r.spec.n)
+        h["stream"] = self._grid_stream(h["grid"])   # steps and retire on the grid's stream, in order
+        return h
+
+    def issue_step(self, h):
+        tok = [None, None]
+        self._want.setdefault(h["grid"], []).append((h, tok))
+        return tok
+
+    def flush(self):
+        torch, ks = self.torch, self.ks
+        failed = []
+        for gi, (grid, items) in enumerate(sorted(self._want.items())):
+            ev = self._inflight.get(grid)
+            if not items or (ev is not None and not ev.query()):
+                continue
+            hs = [h for h, _ in items]
+            comp = tuple(id(h["state"]) for h in hs)
+            cur = self._batches.get(grid)
+            stream = self._grid_stream(grid)
+            try:
+                if cur is None or cur[0] != comp:
+                    if cur is not None:
+                        cur[1].close()
+                    cur = (comp, ks.Batch([h["state"] for h in hs]))
+                    self._batches[grid] = cur
+                with torch.cuda.stream(stream):
+                    cur[1].propagate(self.dt, 1, stream=stream)
+                    ev = torch.cuda.Event()
+                    ev.record(stream)
+            except Exception as exc:            # the grid's requests fail; others carry on
+                self._batches.pop(grid, None)
+                failed.extend((h, exc) for h in hs)
+                self._want[grid] = []
+                continue
+            self._inflight[grid] = ev
+            for _, tok in items:
+                tok[0] = ev
+            self._want[grid] = []
+            self.batched_steps += 1
+            self.batch_sizes.append(len(hs))
+        return failed
+
+    def discard(self, h):
+        if h and h.get("grid") in self._batches:
+            comp, b = self._batches[h["grid"]]
+            if h.get("state") is not None and id(h["state"]) in comp:
+                b.close()
+                del self._batches[h["grid"]]
+        super().discard(h)
+
+    def finish(self):
+        for _, b in self._batches.values():
+            b.close()
+        self._batches.clear()
+        super().finish()
+
+
 class FakeBackend:
     """Simulated device for testing the scheduler on the CPU: a virtual clock,
     per-request step durations from a cost model, and `lanes` steps that can
     run at once (a step waits for the earliest free lane)."""
 
-    def __init__(self, lanes=4, cost_per_hpsi=1e-6, footprint_fn=None, fail_admit=(), fail_step=()):
+    def __init__(self, lanes=4, cost_per_hpsi=1e-6, footprint_fn=None, fail_admit=(), fail_step=(), fail_retire=()):
         self.lanes = lanes
         self.cost = cost_per_hpsi
         self.footprint_fn = footprint_fn or (lambda r: r.spec.norb * r.spec.npoints * 16)
@@ -390,6 +565,7 @@ class FakeBackend:
         self.discarded = []
         self.fail_admit = set(fail_admit)
         self.fail_step = set(fail_step)
+        self.fail_retire = set(fail_retire)
 
     def footprint(self, r):
         return self.footprint_fn(r)
@@ -433,10 +609,15 @@ class FakeBackend:
     def done_time(self, tok):
         return tok
 
+    def flush(self):
+        return []
+
     def retire_submit(self, h, keep_orbitals):
         return h
 
     def retire_poll(self, h):
+        if h["rid"] in self.fail_retire:
+            raise RuntimeError(f"read-back of request {h['rid']} failed")
         self.retired.append(h["rid"])
         return {"rid": h["rid"]}
 

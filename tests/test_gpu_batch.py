@@ -1,0 +1,147 @@
+"""Batched steps (ks_batch_*): resident states of several systems of one grid
+stepped by one launch per kernel must equal each state stepped alone, bit
+for bit (same arithmetic per orbital), in FP64 and mixed precision; one
+batched state is also checked against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ks_oracle as ko
+from paper_2106_03872_amd import synth
+
+from gpu_common import oracle_ham, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ks():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2106_03872_amd import ks as ksmod
+    return ksmod
+
+
+NO_PROJ = "b3"      # this system's projectors are removed after set-up
+
+
+def _specs(n=32, L=10.56):
+    # same grid and cell, ragged orbital and atom counts (one without projectors)
+    return [synth.cubic_spec(f"b{i}", n, L, norb, nat, 5100 + i)
+            for i, (norb, nat) in enumerate([(7, 3), (16, 1), (3, 5), (11, 1), (24, 2)])]
+
+
+def _states(ks, specs, precision):
+    out = []
+    for sp in specs:
+        sysm = synth.system(sp)
+        gs = ks.system_from_synth(sysm, precision=precision)
+        if sp.name == NO_PROJ:
+            gs.set_projectors(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros((0, 4)))
+        st = ks.State(gs, sp.norb)
+        st.upload(torch.from_numpy(synth.orbitals_box(sp)).cuda())
+        out.append((sysm, gs, st))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_equals_alone(ks, precision):
+    print(f"[case] batch vs alone precision {precision}", file=sys.stderr, flush=True)
+    specs = _specs()
+    alone = _states(ks, specs, precision)
+    batched = _states(ks, specs, precision)
+    for _, _, st in alone:
+        st.propagate(0.05, 3)
+    b = ks.Batch([st for _, _, st in batched])
+    b.propagate(0.05, 3)
+    torch.cuda.synchronize()
+    for (_, _, a), (_, _, c) in zip(alone, batched):
+        assert torch.equal(a.download(), c.download())
+    b.close()
+
+
+def test_batch_graph_and_one_shot(ks):
+    print("[case] batch graph replays", file=sys.stderr, flush=True)
+    specs = _specs(24, 7.92)[:4]
+    ref = _states(ks, specs, 0)
+    cap = _states(ks, specs, 0)
+    one = _states(ks, specs, 0)
+    s = ks.Stream()
+    b = ks.Batch([st for _, _, st in cap])
+    b.capture(0.05, s.torch)
+    for k in range(4):                                # several replays, eager work in between
+        b.replay(s.torch)
+        for _, _, st in ref:
+            st.propagate(0.05, 1)
+        ks.propagate_batch([st for _, _, st in one], 0.05, 1)
+        s.torch.synchronize()
+        torch.cuda.synchronize()
+        for (_, _, a), (_, _, c), (_, _, d) in zip(ref, cap, one):
+            ra = a.download()
+            assert torch.equal(ra, c.download()), k
+            assert torch.equal(ra, d.download()), k
+    b.close()
+    s.close()
+
+
+def test_batched_state_vs_oracle(ks):
+    print("[case] batch vs oracle", file=sys.stderr, flush=True)
+    specs = _specs(40, 13.2)[:3]
+    sts = _states(ks, specs, 0)
+    b = ks.Batch([st for _, _, st in sts])
+    b.propagate(0.05, 2)
+    for sp, (sysm, _, st) in zip(specs, sts):
+        ham = oracle_ham(sysm)
+        ref = ko.taylor4_step(ham, synth.orbitals_box(sp), 0.05, 2)
+        assert rel_err(st.download().cpu().numpy(), ref) < 1e-12
+    b.close()
+
+
+def test_batch_errors(ks):
+    print("[case] batch errors", file=sys.stderr, flush=True)
+    a = _states(ks, _specs(24, 7.92)[:2], 0)
+    c = _states(ks, _specs(32, 10.56)[:1], 0)
+    with pytest.raises(ks.KSError) as e:              # different grids
+        ks.Batch([a[0][2], c[0][2]])
+    assert e.value.status == ks.KS_EINVAL
+    st2 = ks.State(a[0][1], 2)
+    with pytest.raises(ks.KSError) as e:              # two states of one system
+        ks.Batch([a[0][2], st2])
+    assert e.value.status == ks.KS_EINVAL
+    with pytest.raises(ks.KSError) as e:              # mixed precisions
+        m = _states(ks, _specs(24, 7.92)[:1], 1)
+        ks.Batch([a[0][2], m[0][2]])
+    assert e.value.status == ks.KS_EINVAL
+    b = ks.Batch([a[0][2], a[1][2]])
+    b.propagate(0.05, 1)
+    a[1][1].set_tuning(2, 2)                          # a system changed: the batch is stale
+    with pytest.raises(ks.KSError) as e:
+        b.propagate(0.05, 1)
+    assert e.value.status == ks.KS_EINVAL
+    b.close()
+    torch.cuda.synchronize()
+
+
+def test_handles_released_in_any_order(ks):
+    """Destroying a system first releases its states and batches: their
+    handles stay valid, refuse work and can be destroyed afterwards."""
+    print("[case] release order", file=sys.stderr, flush=True)
+    sts = _states(ks, _specs(24, 7.92)[:2], 0)
+    b = ks.Batch([st for _, _, st in sts])
+    b.propagate(0.05, 1)
+    (_, g0, s0), (_, g1, s1) = sts
+    g0.close()                                        # system before its state and the batch
+    with pytest.raises(ks.KSError) as e:
+        s0.propagate(0.05, 1)
+    assert e.value.status == ks.KS_EINVAL
+    with pytest.raises(ks.KSError) as e:
+        b.propagate(0.05, 1)
+    assert e.value.status == ks.KS_EINVAL
+    s1.propagate(0.05, 1)                             # the other system is untouched
+    s1.close()                                        # state before its system
+    g1.close()
+    b.close()
+    s0.close()
+    torch.cuda.synchronize()

@@ -136,13 +136,14 @@ def test_mixed_full_size_120_sampled(ks):
     g64 = ks.system_from_synth(sysm)
     gmx = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
     c = orbitals_device(spec)
-    g64.orthonormalize(c)
+    # H psi on the generator's orbitals (the oracle's input never comes from the library)
     sample = [0, 511, spec.norb - 1]
     hs = gmx.ham_apply(c)[sample].cpu().numpy()
     err = rel_err(hs, ko.ham_apply(ham, c[sample].cpu().numpy()))
     print(f"[mixed] 120^3 H psi rel err {err:.2e}", file=sys.stderr)
     assert err < TOL_H
     del hs
+    g64.orthonormalize(c)      # the start of the 50-step comparison of the two precisions
     occ = torch.full((spec.norb,), 2.0, dtype=torch.float64, device="cuda")
     s64, smx = ks.State(g64, spec.norb), ks.State(gmx, spec.norb)
     s64.upload(c)

@@ -27,14 +27,16 @@ def gpu():
         pytest.skip("no HIP device")
 
 
-def _run(reqs, budget=None, use_graphs=True, pool_bytes=None):
-    be = serve.HipBackend(use_graphs=use_graphs, pool_bytes=pool_bytes)
+def _run(reqs, budget=None, use_graphs=True, pool_bytes=None, batched=False):
+    cls = serve.BatchedHipBackend if batched else serve.HipBackend
+    be = cls(use_graphs=use_graphs, pool_bytes=pool_bytes)
     be.prepare(reqs)
     if budget is None:
         budget = sum(be.footprint(r) for r in reqs) * 2
     srv = serve.Server(be, budget, keep_orbitals=True)
     done = srv.run(reqs)
     assert not srv.failed, [r.error for r in srv.failed]
+    srv.be = be
     return {r.rid: r for r in done}, srv
 
 
@@ -60,6 +62,26 @@ def test_serving_alone_equals_mix(gpu):
         m = mix[r.rid].result["orbitals"]
         assert np.array_equal(a, m), np.abs(a - m).max()
         assert abs(alone[r.rid].result["energy"] - mix[r.rid].result["energy"]) == 0.0
+
+
+def test_serving_batched_equals_alone(gpu):
+    """The same trace with ragged-batched steps (one launch per kernel for
+    the resident requests of a grid): every result bit-identical to the
+    request run alone with its own kernels."""
+    print("[case] serving batched mix", file=sys.stderr, flush=True)
+    reqs = _requests()
+    be = serve.HipBackend()
+    be.prepare(reqs, pretune=False)
+    budget = sum(be.footprint(r) for r in reqs) * 2
+    mix, srv = _run(_requests(), budget, use_graphs=False, pool_bytes=budget + (64 << 20), batched=True)
+    assert len(mix) == len(reqs)
+    assert srv.be.batched_steps < sum(r.nsteps for r in reqs)       # steps were shared
+    assert max(srv.be.batch_sizes) >= 2
+    for r in _requests():
+        print(f"[case] serving batched alone {r.rid}", file=sys.stderr, flush=True)
+        alone, _ = _run([serve.Request(rid=r.rid, arrival=0.0, spec=r.spec, nsteps=r.nsteps)])
+        assert np.array_equal(alone[r.rid].result["orbitals"], mix[r.rid].result["orbitals"])
+        assert alone[r.rid].result["energy"] == mix[r.rid].result["energy"]
 
 
 def test_graph_replay_equals_direct_steps(gpu):

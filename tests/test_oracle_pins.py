@@ -666,3 +666,41 @@ def test_sd_converges_to_the_lowest_dense_eigenvalues():
     assert rn.max() < 1e-4
     ov = np.linalg.svd(c.reshape(4, -1).conj() @ V[:, :4], compute_uv=False)
     assert ov.min() > 1 - 1e-8                               # same occupied subspace
+
+
+# ------------------------------------------- absorption spectrum (Section "Results")
+
+def test_spectrum_damped_sine_closed_form():
+    """x(t) = A sin(w0 t) along the kick: the trapezoid sum is two geometric
+    series, sum_{n<=M} z^n = (1 - z^{M+1}) / (1 - z) with z = e^{(i w - eta
+    +- i w0) dt}, minus half the last term (the first is zero)."""
+    w0, A, dt, M, eta, kk = 0.7, 3e-3, 0.05, 4000, 0.01, 2e-3
+    t = dt * np.arange(M + 1)
+    dip = np.zeros((M + 1, 3))
+    dip[:, 1] = 0.4 + A * np.sin(w0 * t)                 # along y, with an offset d(0)
+    w = np.array([0.1, 0.69, 0.7, 1.3])
+    alpha, S = ko.spectrum(dip, dt, (0.0, -kk, 0.0), w, eta)
+    for i, om in enumerate(w):
+        zp = np.exp((1j * om - eta + 1j * w0) * dt)
+        zm = np.exp((1j * om - eta - 1j * w0) * dt)
+        geo = ((1 - zp ** (M + 1)) / (1 - zp) - (1 - zm ** (M + 1)) / (1 - zm)) / 2j
+        last = np.sin(w0 * M * dt) * np.exp((1j * om - eta) * M * dt)
+        ref = -A * dt * (geo - 0.5 * last) / kk          # kick along -y: the projection flips the sign
+        assert abs(alpha[i] - ref) <= 1e-10 * abs(ref)
+        assert abs(S[i] - 2 * om / math.pi * ref.imag) <= 1e-10 * abs(ref) * om
+
+
+def test_spectrum_sum_rule_peak_and_direction():
+    # f electrons kicked with momentum k oscillate as d(t) - d(0) = k f / w0
+    # sin(w0 t): the strength peaks at w0 and integrates to f; a kick
+    # orthogonal to the motion sees nothing
+    w0, f, kk, dt = 0.6, 0.8, 1e-3, 0.05
+    t = dt * np.arange(8000)
+    dip = np.stack([np.zeros_like(t), np.zeros_like(t), kk * f / w0 * np.sin(w0 * t)], axis=1)
+    w = np.linspace(0.05, 1.5, 2901)
+    _, S = ko.spectrum(dip, dt, (0.0, 0.0, kk), w, 0.01)
+    assert abs(w[np.argmax(S)] - w0) < 0.01
+    integral = np.sum(0.5 * (S[1:] + S[:-1]) * np.diff(w))
+    assert abs(integral - f) < 0.05 * f
+    _, S0 = ko.spectrum(dip, dt, (kk, 0.0, 0.0), w[:10], 0.01)
+    assert np.all(S0 == 0)

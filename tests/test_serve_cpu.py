@@ -63,12 +63,12 @@ def test_more_lanes_finish_sooner():
 
 def test_failing_requests_fail_alone():
     reqs = _trace(24)
-    be = serve.FakeBackend(lanes=3, fail_admit={3, 11}, fail_step={7})
+    be = serve.FakeBackend(lanes=3, fail_admit={3, 11}, fail_step={7}, fail_retire={15})
     budget = 4 * max(be.footprint(r) for r in reqs)
     srv = serve.Server(be, budget)
     done = srv.run(reqs)
     failed = {r.rid for r in srv.failed}
-    assert failed == {3, 7, 11}
+    assert failed == {3, 7, 11, 15}
     assert sorted(r.rid for r in done) == sorted(set(range(24)) - failed)
     assert all(len(r.step_times) == 5 and not r.error for r in done)
     assert all(r.error for r in srv.failed)
