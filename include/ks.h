@@ -199,6 +199,23 @@ ks_status ks_hartree(ks_system* sys, const double* rho, double* v, int add_vloc,
 ks_status ks_dipole(ks_system* sys, const double* rho, double* d, void* stream);
 
 /*
+ * Allocation-free ks_dipole, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops): no ks_system is needed,
+ * and the call makes no hipMalloc/hipFree or other allocating call.  Same
+ * kernels and summation order as ks_dipole, so the results are identical.
+ * n[3], L[3]: host; rho: device float64 [n0][n1][n2]; d: device float64 [3].
+ * The partial sums live in a fixed 6 KiB array in the library's device image,
+ * one per GPU, kept until the process ends; its device address is looked up
+ * on the first call on each device.  Every call on one GPU uses that GPU's
+ * array, so calls that overlap in time on one GPU (different streams or
+ * threads) race: order them.  Errors: KS_EINVAL (null, n_a < 1, L_a <= 0, more
+ * than KS_DIPOLE_NOALLOC_MAX_POINTS grid points), KS_EDEVICE; the message is
+ * ks_last_error(NULL).
+ */
+#define KS_DIPOLE_NOALLOC_MAX_POINTS 2147483647LL
+ks_status ks_dipole_noalloc(const int n[3], const double L[3], const double* rho, double* d, void* stream);
+
+/*
  * Absorption spectrum of a kicked propagation (Section "Results": the
  * spectrum is the Fourier transform of the dipole moments after the kick):
  *   x(t_n) = (d(t_n) - d(0)) . k / |k|,  t_n = n dt,

@@ -10,6 +10,8 @@
 //   z analysis (rows; the real density in), y analysis, x analysis + Poisson
 //   kernel + x synthesis, y synthesis, z synthesis (real part out, plus V_loc
 //   when given).  Nothing is pruned: the density fills the box.
+#include <mutex>
+
 #include "ks_common.hpp"
 
 namespace ks {
@@ -286,12 +288,47 @@ bool launch_kick(const ks_system* s, double2* W, const double k[3], hipStream_t 
   return kick_yz_pass(s, W, -1, st);
 }
 
+void launch_dipole_grid(const int n[3], const double L[3], const double* rho, double* part, double* d,
+                        hipStream_t st) {
+  const double dV = (L[0] * L[1] * L[2]) / ((double)n[0] * n[1] * n[2]);
+  dipole_part_kernel<<<DIP_BLOCKS, NT, 0, st>>>(rho, n[0], n[1], n[2], L[0] / n[0], L[1] / n[1], L[2] / n[2], part);
+  dipole_sum_kernel<<<1, 64, 0, st>>>(part, dV, d);
+}
+
 bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t st) {
   double* part = reinterpret_cast<double*>(s->d_hbox);   // 3 * DIP_BLOCKS doubles of the work box
-  dipole_part_kernel<<<DIP_BLOCKS, NT, 0, st>>>(rho, s->n[0], s->n[1], s->n[2], s->L[0] / s->n[0],
-                                                s->L[1] / s->n[1], s->L[2] / s->n[2], part);
-  dipole_sum_kernel<<<1, 64, 0, st>>>(part, s->dV, d);
+  launch_dipole_grid(s->n, s->L, rho, part, d, st);
   return true;
+}
+
+// Partial sums of the allocation-free dipole (ks_dipole_noalloc): a fixed
+// array in the library's device image, one copy per device, held until the
+// process ends.  Host code never passes the array's name to a kernel: it
+// takes the array's device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[DIPOLE_SCRATCH_DOUBLES];
+static_assert(DIPOLE_SCRATCH_DOUBLES >= 3 * DIP_BLOCKS, "dipole partials exceed the static scratch");
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t dipole_scratch(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace ks

@@ -1164,6 +1164,28 @@ ks_status ks_dipole(ks_system* s, const double* rho, double* d, void* stream) {
   return launch_ok(s, launch_dipole(s, rho, d, (hipStream_t)stream), "dipole");
 }
 
+ks_status ks_dipole_noalloc(const int n[3], const double L[3], const double* rho, double* d, void* stream) {
+  if (!n || !L || !rho || !d) return fail(nullptr, KS_EINVAL, "null argument");
+  long long N = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return fail(nullptr, KS_EINVAL, "grid size must be positive");
+    if (!(L[a] > 0.0) || !std::isfinite(L[a])) return fail(nullptr, KS_EINVAL, "cell lengths must be positive");
+    N *= n[a];
+  }
+  if (N > KS_DIPOLE_NOALLOC_MAX_POINTS)
+    return fail(nullptr, KS_EINVAL,
+                "grid of " + std::to_string(N) + " points exceeds the allocation-free dipole's limit of " +
+                    std::to_string(KS_DIPOLE_NOALLOC_MAX_POINTS));
+  double* part = nullptr;
+  const hipError_t e = dipole_scratch(&part);
+  if (e != hipSuccess) return fail(nullptr, KS_EDEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+  const hipStream_t st = (hipStream_t)stream;
+  launch_dipole_grid(n, L, rho, part, d, st);
+  const hipError_t e2 = hipGetLastError();
+  if (e2 != hipSuccess) return fail(nullptr, KS_EDEVICE, std::string("dipole: ") + hipGetErrorString(e2));
+  return KS_OK;
+}
+
 ks_status ks_spectrum(const double* dipoles, int nt, double dt, const double k[3], const double* omegas, int nw,
                       double damping, double* alpha, double* strength, void* stream) {
   if (!dipoles || !k || (nw > 0 && (!omegas || !alpha || !strength))) return fail(nullptr, KS_EINVAL, "null argument");

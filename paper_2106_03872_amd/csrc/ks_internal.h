@@ -287,6 +287,14 @@ void launch_spectrum(const double* d, int nt, double dt, const double k[3], cons
                      double eta, double2* alpha, double* strength, hipStream_t st);
 // d[0..2] = dV sum_r r rho(r) (device output; uses the work box for partial sums)
 bool launch_dipole(const ks_system* s, const double* rho, double* d, hipStream_t st);
+// the same on grid n, cell L, with the partial sums in part (DIPOLE_SCRATCH_DOUBLES)
+void launch_dipole_grid(const int n[3], const double L[3], const double* rho, double* part, double* d,
+                        hipStream_t st);
+// doubles of the static scratch of the allocation-free dipole
+constexpr int DIPOLE_SCRATCH_DOUBLES = 3 * 256;
+// device address of the static dipole scratch on the current device (looked
+// up once per device)
+hipError_t dipole_scratch(double** out);
 
 // dense complex products for the eigensolver (MFMA FP64):
 // S[i][j] = sum_e conj(A[i][e]) B[j][e]   (norb x norb, rows of length npw)

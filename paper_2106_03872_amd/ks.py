@@ -94,6 +94,7 @@ def _load():
         "ks_hartree": (I, [P, P, P, I, P]),
         "ks_dipole": (I, [P, P, P, P]),
         "ks_spectrum": (I, [P, I, D, ctypes.POINTER(D), P, I, D, P, P, P]),
+        "ks_dipole_noalloc": (I, [ctypes.POINTER(I), ctypes.POINTER(D), P, P, P]),
         "ks_state_kick": (I, [P, ctypes.POINTER(D), P]),
         "ks_state_eigensolve": (I, [P, I, P, P, P]),
         "ks_state_reduce": (I, [P, P, P, P, P]),
@@ -623,6 +624,21 @@ def plan_footprint(n, L, ecut, norb, npoints, nproj=4, precision=KS_FP64, chunk=
 
 
 # module-level entry points with the names of the C ABI
+def dipole_noalloc(n, L, rho, d):
+    """ks_dipole_noalloc: dipole moment of the density rho (float64 box of
+    shape n on the device) into d (float64 tensor of 3 on the device), with no
+    system and no device allocation."""
+    import torch
+    n = tuple(int(x) for x in n)
+    nn = (ctypes.c_int * 3)(*n)
+    LL = (ctypes.c_double * 3)(*[float(x) for x in L])
+    st = _lib.ks_dipole_noalloc(nn, LL, _ptr(rho, torch.float64, n, "rho"), _ptr(d, torch.float64, (3,), "d"),
+                                _stream())
+    if st != KS_OK:
+        raise KSError(st, _lib.ks_last_error(None).decode())
+    return d
+
+
 def ham_apply(system, psi, hpsi=None):
     return system.ham_apply(psi, hpsi)
 
