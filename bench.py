@@ -308,27 +308,35 @@ def run_mixed_large(steps, log):
             "orbital_rel_err_vs_fp64_max": float(d.max().item()), "orbitals_compared": len(sample)}
 
 
-def run_serving(nreq, nsteps, budget_gb, log, batched=True):
+def run_serving(nreq, nsteps, budget_gb, log, batched=True, max_active=256, lockstep=True):
     """The serving trace: Poisson arrivals of small systems, continuous
     batching under an HBM budget.  batched: the resident requests of a grid
     are stepped by shared launches (ks_batch); otherwise each request replays
-    its own captured step.  Systems live in a device pool of the budget's
-    size; launch schedules are tuned per grid bucket before the trace."""
+    its own captured step.  lockstep: global rounds (every resident request
+    advances once per round).  Systems live in a device pool of 1.25 times
+    the budget (fragmentation slack); launch schedules are tuned per grid
+    bucket before the trace."""
     from paper_2106_03872_amd import serve, synth
     trace = synth.serving_trace(nreq, 200.0, 2000)
     reqs = [serve.Request(rid=i, arrival=t, spec=sp, nsteps=nsteps) for i, (t, sp) in enumerate(trace)]
+    import torch
+    torch.cuda.empty_cache()                    # the earlier sections' cached blocks
     budget = int(budget_gb * 2 ** 30)
-    cls = serve.BatchedHipBackend if batched else serve.HipBackend
-    be = cls(pool_bytes=budget + (256 << 20))
+    pool = int(1.25 * budget) + (256 << 20)     # slack for the pool's fragmentation
+    if batched:
+        be = serve.BatchedHipBackend(pool_bytes=pool, lockstep=lockstep)
+    else:
+        be = serve.HipBackend(pool_bytes=pool)
     log(f"[bench] serving ({'batched launches' if batched else 'one graph per request'}): preparing {nreq} requests")
     be.prepare(reqs)
-    srv = serve.Server(be, budget)
+    srv = serve.Server(be, budget, max_active=max_active)
     done = srv.run(reqs)
     rep = serve.Server.report(done, srv.elapsed, serve.hpsi_per_step)
-    rep.update({"mode": "batched launches per grid" if batched else "captured graph per request",
+    rep.update({"mode": ("batched launches per grid" + (", global rounds" if lockstep else "")) if batched
+                else "captured graph per request", "max_active": max_active,
                 "hbm_budget_GiB": budget_gb, "max_reserved_GiB": round(srv.max_used / 2 ** 30, 2),
                 "pool_peak_GiB": round(be.pool.usage()[1] / 2 ** 30, 2) if be.pool is not None else None,
-                "max_resident_requests": srv.max_resident, "failed": len(srv.failed),
+                "max_resident_requests": srv.max_resident, "failed": len(srv.failed), "requeued": srv.requeued,
                 "pretune_s": round(be.tuning_s, 2),
                 "precision": "mixed", "steps_per_request": nsteps, "arrivals": "Poisson, mean 200/s",
                 "drift_max": max(float(abs(r.result["norms"] - 1.0).max()) for r in done)})
@@ -359,6 +367,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=50)
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serving-full-budget-gb", type=float, default=160.0,
+                    help="also run the trace with a budget the whole trace fits in (0: skip)")
     ap.add_argument("--serving-compare", action="store_true",
                     help="also run the trace with one captured graph per request")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -434,8 +444,18 @@ def main():
         log(f"[bench] serving: p50 {serving['step_latency_ms_p50']:.2f} ms, p99 {serving['step_latency_ms_p99']:.2f} ms, "
             f"first step p99 {serving['time_to_first_step_ms_p99']:.0f} ms, "
             f"{serving['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s over {serving['makespan_s']:.1f} s")
+        if args.serving_full_budget_gb > 0:
+            full = run_serving(args.serving_requests, args.serving_steps, args.serving_full_budget_gb, log)
+            log(f"[bench] serving ({args.serving_full_budget_gb:.0f} GiB budget): p50 {full['step_latency_ms_p50']:.2f} ms, "
+                f"p99 {full['step_latency_ms_p99']:.2f} ms, first step p99 {full['time_to_first_step_ms_p99']:.0f} ms, "
+                f"{full['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s")
+            serving["full_budget"] = {k: full[k] for k in (
+                "hbm_budget_GiB", "step_latency_ms_p50", "step_latency_ms_p99", "time_to_first_step_ms_p50",
+                "time_to_first_step_ms_p99", "admission_ms_p99", "orbital_hpsi_per_s", "makespan_s",
+                "max_resident_requests", "max_reserved_GiB", "failed")}
         if args.serving_compare:
-            alt = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log, batched=False)
+            alt = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log, batched=False,
+                              max_active=64, lockstep=False)
             log(f"[bench] serving (graph per request): p50 {alt['step_latency_ms_p50']:.2f} ms, "
                 f"p99 {alt['step_latency_ms_p99']:.2f} ms, {alt['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s")
             serving["graph_per_request"] = {k: alt[k] for k in (

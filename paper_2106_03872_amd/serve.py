@@ -141,13 +141,16 @@ class Server:
 
     def _loop(self, be, pending, done):
         waiting, admitting, active, retiring = deque(), [], [], []
+        self._hold = False         # admissions paused until the next retire (device memory short)
+        self.requeued = 0
         while pending or waiting or admitting or active or retiring:
             progressed = False
             now = be.now()
+            requeue = []
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
                 progressed = True
-            while (waiting and len(active) + len(admitting) < self.max_active
+            while (waiting and not self._hold and len(active) + len(admitting) < self.max_active
                    and self._used + waiting[0].footprint <= self.budget):
                 r = waiting.popleft()
                 self._used += r.footprint
@@ -161,8 +164,15 @@ class Server:
             for r in admitting:
                 try:
                     h = be.admit_poll(r.admit_tok)
-                except Exception as exc:      # this request fails alone
-                    self._fail(r, exc)
+                except Exception as exc:
+                    r.admit_tries = getattr(r, "admit_tries", 0) + 1
+                    others = active or retiring or len(admitting) > 1
+                    if be.retryable(exc) and (others or r.admit_tries < 3):   # memory short: retry later
+                        self._used -= r.footprint
+                        requeue.append(r)
+                        self._hold = True
+                    else:                     # this request fails alone
+                        self._fail(r, exc)
                     progressed = True
                     continue
                 if h is None:
@@ -174,6 +184,11 @@ class Server:
                 active.append(r)
                 progressed = True
             admitting = still
+            for r in reversed(sorted(requeue, key=lambda q: (q.arrival, q.rid))):
+                waiting.appendleft(r)      # back at the head, in arrival order
+                self.requeued += 1
+            if self._hold and not active and not admitting and not retiring:
+                self._hold = False         # nothing left to retire: try again
             self.max_resident = max(self.max_resident, len(active))
             for r in active:
                 if r.inflight is None and len(r.step_times) < r.nsteps:
@@ -222,6 +237,7 @@ class Server:
                 r.t_done = be.now()
                 r.handle = None
                 self._used -= r.footprint
+                self._hold = False
                 done.append(r)
                 progressed = True
             retiring = still
@@ -414,6 +430,11 @@ class HipBackend:
         requests whose launch failed."""
         return []
 
+    def retryable(self, exc):
+        """Admission errors that mean "not now": the device pool (or device)
+        is short of memory, so the request waits for a retire and tries again."""
+        return isinstance(exc, self.ks.KSError) and exc.status == self.ks.KS_ENOMEM
+
     def is_done(self, tok):
         if tok[1] is None and tok[0] is not None and tok[0].query():
             tok[1] = self.now()
@@ -468,9 +489,13 @@ class BatchedHipBackend(HipBackend):
     became ready meanwhile join it.  Every request's orbitals go through the
     same arithmetic as alone, so results are bit-identical to HipBackend's."""
 
-    def __init__(self, *args, **kw):
+    def __init__(self, *args, lockstep=False, **kw):
         kw.setdefault("use_graphs", False)
         super().__init__(*args, **kw)
+        # lockstep: every grid's next batched step waits until the steps of
+        # all grids in flight have completed (global rounds: every resident
+        # request advances once per round, whatever its grid)
+        self.lockstep = lockstep
         self._want = {}       # grid -> [(handle, token)]
         self._inflight = {}   # grid -> event of the grid's step in flight
         self._batches = {}    # grid -> (composition, ks.Batch)
@@ -502,6 +527,10 @@ class BatchedHipBackend(HipBackend):
     def flush(self):
         torch, ks = self.torch, self.ks
         failed = []
+        if self.lockstep:
+            if any(not ev.query() for ev in self._inflight.values()):
+                return failed
+            self._inflight.clear()
         for gi, (grid, items) in enumerate(sorted(self._want.items())):
             ev = self._inflight.get(grid)
             if not items or (ev is not None and not ev.query()):
@@ -553,7 +582,8 @@ class FakeBackend:
     per-request step durations from a cost model, and `lanes` steps that can
     run at once (a step waits for the earliest free lane)."""
 
-    def __init__(self, lanes=4, cost_per_hpsi=1e-6, footprint_fn=None, fail_admit=(), fail_step=(), fail_retire=()):
+    def __init__(self, lanes=4, cost_per_hpsi=1e-6, footprint_fn=None, fail_admit=(), fail_step=(), fail_retire=(),
+                 short_once=()):
         self.lanes = lanes
         self.cost = cost_per_hpsi
         self.footprint_fn = footprint_fn or (lambda r: r.spec.norb * r.spec.npoints * 16)
@@ -566,6 +596,7 @@ class FakeBackend:
         self.fail_admit = set(fail_admit)
         self.fail_step = set(fail_step)
         self.fail_retire = set(fail_retire)
+        self.short_once = set(short_once)       # admission is short of memory the first time
 
     def footprint(self, r):
         return self.footprint_fn(r)
@@ -580,6 +611,9 @@ class FakeBackend:
         self.admitted.append(r.rid)
         if r.rid in self.fail_admit:
             return RuntimeError(f"admission of request {r.rid} failed")
+        if r.rid in self.short_once:
+            self.short_once.discard(r.rid)
+            return MemoryError(f"no device memory for request {r.rid} now")
         return {"rid": r.rid, "cost": self.cost * 4 * r.spec.norb * (r.spec.npoints / 1e5)}
 
     def admit_poll(self, tok):
@@ -611,6 +645,9 @@ class FakeBackend:
 
     def flush(self):
         return []
+
+    def retryable(self, exc):
+        return isinstance(exc, MemoryError)
 
     def retire_submit(self, h, keep_orbitals):
         return h

@@ -74,3 +74,14 @@ def test_failing_requests_fail_alone():
     assert all(r.error for r in srv.failed)
     assert 7 in be.discarded                       # the failed step's request was freed
     assert srv.used_at_end == 0                    # every reservation was released
+
+
+def test_memory_short_admission_is_retried():
+    reqs = _trace(20)
+    be = serve.FakeBackend(lanes=3, short_once={2, 9})
+    srv = serve.Server(be, 6 * max(be.footprint(r) for r in reqs))
+    done = srv.run(reqs)
+    assert not srv.failed and sorted(r.rid for r in done) == list(range(20))
+    assert srv.requeued == 2
+    assert be.admitted.count(2) == 2 and be.admitted.count(9) == 2
+    assert srv.used_at_end == 0
