@@ -165,7 +165,7 @@ def setup_workload(spec, precision, chunk=0):
     state = ks.State(gs, spec.norb)
     state.upload(c)
     del c
-    gs.tuning = gs.autotune(spec.norb)   # launch schedule (orbital-group caps), timed on the device
+    gs.tuning = gs.autotune(spec.norb)   # launch schedule (x-tile shape, orbital-group caps), timed on the device
     torch.cuda.synchronize()
     return sysm, gs, state
 
@@ -296,8 +296,9 @@ def run_mixed_large(steps, log):
         ms, _, phys, _ = run_steps(spec, g, st, steps, 1, timing=False)
         psi[name] = st.download()[sample].clone()
         res[name] = {"ms_per_step": round(ms, 3), "value": round(4 * spec.norb / (ms * 1e-3), 1),
-                     "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"]}
-        log(f"[bench] 120^3 / {spec.norb} orbitals {name}: {ms:.2f} ms/step, {res[name]['value']:.0f} orbital.Hpsi/s")
+                     "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"], "tuning": g.tuning}
+        log(f"[bench] 120^3 / {spec.norb} orbitals {name}: {ms:.2f} ms/step, {res[name]['value']:.0f} orbital.Hpsi/s, "
+            f"tuning {g.tuning}")
         st.close()
         g.close()
     a, b = psi["mixed"], psi["fp64"]
@@ -429,7 +430,8 @@ def main():
                  "speedup_vs_fp64": round(ms_step / ms_m, 3), "orbital_rel_err_vs_fp64_max": float(d.max().item()),
                  "band_energy_per_electron_diff_vs_fp64":
                      abs(phys_m["band_energy_per_electron_end"] - phys["band_energy_per_electron_end"]),
-                 "kernels": kernel_table(gm.info(), spec, kt_m, args.steps, ms_m), "chunk": gm.info()["chunk"]}
+                 "kernels": kernel_table(gm.info(), spec, kt_m, args.steps, ms_m), "chunk": gm.info()["chunk"],
+                 "tuning": gm.tuning}
         log(f"[bench] mixed: {ms_m:.2f} ms/step ({mixed['speedup_vs_fp64']}x), err vs FP64 {mixed['orbital_rel_err_vs_fp64_max']:.2e}")
         sm.close()
         gm.close()
@@ -496,7 +498,7 @@ def main():
                                f"on HBM-resident orbitals",
                    "global_batch": spec.norb, "grid": list(spec.n), "npw": info["npw"],
                    "chunk": info["chunk"], "orbitals_per_pass": per_pass,
-                   "tuning": {"x_group": gs.tuning["x_group"], "plane_group": gs.tuning["plane_group"]},
+                   "tuning": {k: gs.tuning[k] for k in ("x_group", "plane_group", "x_shape")},
                    "hpsi_per_step": hpsi_per_step,
                    "parallelism": "single GPU"},
         "roofline": roof,

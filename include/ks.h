@@ -455,6 +455,8 @@ typedef struct {
                        transforms only the nonzero half of its first-stage inputs */
   int x_group;      /* largest orbital group of an x-pencil block (tuning) */
   int plane_group;  /* largest orbital group of a plane block (tuning) */
+  int x_shape;      /* tile shape of the x-pencil passes (see ks_tuning) */
+  int x_threads;    /* threads per block in the x-pencil passes */
 } ks_info;
 
 /* Fill *info for sys.  KS_EINVAL on null arguments. */
@@ -467,26 +469,39 @@ ks_status ks_system_info(const ks_system* sys, ks_info* info);
  * caps trade the per-block set-up (twiddles, potential, KB tables, column
  * tables, loaded once per block) against the number of blocks that fill the
  * chip.  The results of H psi do not depend on them (every orbital is
- * transformed by the same arithmetic in the same order).
+ * transformed by the same arithmetic in the same order).  The x-tile shape
+ * trades LDS per block against blocks per compute unit; every transform is
+ * computed the same way in either shape, but the projections are summed per
+ * (tile, atom) before they are added across tiles, so results of the two
+ * shapes differ by rounding only.
  */
 typedef struct {
   int x_group;       /* cap on orbitals per x-pencil block, 1..64 */
   int plane_group;   /* cap on orbitals per plane block, 1..64 */
   double ms;         /* measured time of one H psi pass over the tuned orbital count (0 if not measured) */
   int from_cache;    /* 1 if the result came from the process-wide cache */
+  int x_shape;       /* tile shape of the x-pencil passes: 0 = 64 pencils x 256 threads for n0 <= 32,
+                        32 x 256 above; 1 = 16 pencils x 192 threads (n0 = 96 and 120 only; fewer
+                        LDS bytes per block, more blocks resident per compute unit); -1 in
+                        ks_system_set_tuning keeps the current shape */
 } ks_tuning;
 
 /* Time one H psi pass over min(norb, chunk) orbitals (zero coefficients; the
- * kernels' timing does not depend on the values) for each candidate pair of
- * group caps on `stream`, keep the fastest, and return it in *out (nullable).
+ * kernels' timing does not depend on the values) for each candidate of tile
+ * shape and group caps on `stream`, keep the fastest, and return it in *out
+ * (nullable).  A change of tile shape rebuilds the per-tile projector tables
+ * from the inputs of the last ks_system_set_projectors.
  * Results are cached per process by (grid, precision, number of sphere
  * planes, orbitals per pass rounded up to a power of two): a later system of
  * the same shape takes the cached caps without timing.  Synchronises `stream`; overwrites the
  * system's internal workspace.  KS_EINVAL for norb outside [1, max_norb]. */
 ks_status ks_autotune(ks_system* sys, int norb, void* stream, ks_tuning* out);
 
-/* Set the group caps (x_group, plane_group in [1, 64]; ms and from_cache are
- * ignored).  KS_EINVAL otherwise. */
+/* Set the group caps (x_group, plane_group in [1, 64]) and the tile shape
+ * (x_shape: -1 keeps it; a shape the grid lacks is KS_EINVAL); ms and
+ * from_cache are ignored.  A change of shape waits for the system's work and
+ * rebuilds the projector tables (as ks_system_set_projectors does).  KS_EINVAL
+ * otherwise. */
 ks_status ks_system_set_tuning(ks_system* sys, const ks_tuning* t);
 
 /* Kernel classes reported by ks_kernel_time. */

@@ -42,8 +42,8 @@ __device__ __forceinline__ T wave_sum(T x) {
 // BATCH: one launch over several systems of the grid (no density); the
 // block's system (T, partial sums, projector tables, orbital count) comes
 // from jobs[rows[blockIdx.y].x].
-template <int N0, typename R, bool HB, bool DENS, bool BATCH = false>
-__global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ Tin, int nb,
+template <int N0, class SH, typename R, bool HB, bool DENS, bool BATCH = false>
+__global__ __launch_bounds__(SH::XT) void xproj_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    cplx<R>* __restrict__ partial, SphereTab tab, ProjTab pt,
                                                    const cplx<R>* __restrict__ tw0, double scale,
                                                    const double* __restrict__ occ, double* __restrict__ dpart,
@@ -51,9 +51,9 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
                                                    const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
   static_assert(!(BATCH && DENS), "batched launches carry no density");
-  constexpr int NB = xnb<N0>::value;
-  using FR = fft_regs<N0, NB, NT, C, HB>;
-  using LS = last_shape<N0, NB, NT>;
+  constexpr int NB = SH::NB, XT = SH::XT;
+  using FR = fft_regs<N0, NB, XT, C, HB>;
+  using LS = last_shape<N0, NB, XT>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ C tw[N0];
   const int tile = blockIdx.x, tid = threadIdx.x;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   const int p0 = tile * NB;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
   if (!DENS && ns == 0) return;  // no sphere point in this tile (uniform per block)
-  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
+  for (int i = tid; i < N0; i += XT) tw[i] = tw0[i];
   double a[DENS ? LS::items : 1][DENS ? LS::radix : 1];
   if constexpr (DENS) {
 #pragma unroll
@@ -84,9 +84,9 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   // (slot, projector) pair of the tile (in point order); the 2^g lanes of a
   // pair, adjacent and aligned, are then added by a fixed butterfly and the
   // group's first lane writes the pair (work planned per tile on the host).
-  static_assert(NT == KB_ITEM_LANES, "projection items are planned per block lane");
+  // (the host plans XT projection lanes per tile)
   const int np = pt.nproj;
-  const int4 item = pt.item[(long long)tile * NT + tid];
+  const int4 item = pt.item[(long long)tile * XT + tid];
   const int ka = item.x, kb = item.y;
   const int sl = item.z / np, kq = item.z - sl * np;
   const int glanes = 1 << (item.w & 0xff);
@@ -106,15 +106,15 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   C* pout = partial + (long long)(sA + sl) * np + kq;
   const long long pstride = (long long)pt.nslots * np;
   FR pre;
-  if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
+  if (oa < ob) fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
     auto next = [&] {
       if (o + 1 < ob)
-        fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+        fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     };
     if constexpr (DENS) {
       const double f = occ[o] * inv_omega;
-      fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next),
+      fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next),
                                                    [&](int t, int e, C v, int it, int q) {
                                                      X[t * (N0 + 1) + e] = v;
                                                      a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
         continue;
       }
     } else {
-      fft_io<N0, +1, NB, NT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
+      fft_io<N0, +1, NB, XT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
     }
     double sx = 0.0, sy = 0.0;
 #pragma unroll
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(NT) void xproj_kernel(const cplx<R>* __restrict__ T
   }
   if constexpr (DENS) {
     double* pb = dpart + (long long)blockIdx.y * tab.n0 * npl + p0;
-    last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+    last_stage_positions<N0, NB, XT>(NB, [&](int it, int q, int t, int e) {
       if (p0 + t < npl) pb[e * npl + t] = a[it][q];
     });
   }
@@ -184,13 +184,13 @@ __device__ __forceinline__ void kb_extra(const double2* dps, const ProjTab& pt, 
 }
 
 // NP projectors per atom fixed at compile time: two unique points per thread
-// and pass, u and u + NT, with the table loads of both issued before either
+// and pass, u and u + XT, with the table loads of both issued before either
 // is used.
-template <int NP, typename C>
+template <int NP, int XT, typename C>
 __device__ __forceinline__ void kb_scatter_fixed(C* X, const double2* dps, const ProjTab& pt, int uA, int uB) {
   const int tid = threadIdx.x;
-  for (int u = uA + tid; u < uB; u += 2 * NT) {
-    const int ub = u + NT;
+  for (int u = uA + tid; u < uB; u += 2 * XT) {
+    const int ub = u + XT;
     const bool two = ub < uB;
     const int ka = pt.up_key[u];
     const int kb = two ? pt.up_key[ub] : 0;
@@ -221,10 +221,10 @@ __device__ __forceinline__ void kb_scatter_fixed(C* X, const double2* dps, const
 }
 
 // any number of projectors per atom: one point at a time
-template <typename C>
+template <int XT, typename C>
 __device__ __forceinline__ void kb_scatter_any(C* X, const double2* dps, const ProjTab& pt, int uA, int uB) {
   const int np = pt.nproj, tid = threadIdx.x;
-  for (int u = uA + tid; u < uB; u += NT) {
+  for (int u = uA + tid; u < uB; u += XT) {
     const int key = pt.up_key[u];
     const double* b = pt.up_beta + (long long)u * np;
     const double2* dp = dps + ((key >> UP_POS_BITS) & UP_MAX_SLOT) * np;
@@ -240,17 +240,17 @@ __device__ __forceinline__ void kb_scatter_any(C* X, const double2* dps, const P
 
 // BATCH: as xproj_kernel (T, U, V, d P, projector tables and orbital count
 // from the block's job).
-template <int N0, typename R, bool HB, bool BATCH = false>
-__global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ Tin, int nb,
+template <int N0, class SH, typename R, bool HB, bool BATCH = false>
+__global__ __launch_bounds__(SH::XT) void xapply_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                     cplx<R>* __restrict__ Uout, const double* __restrict__ V,
                                                     const double2* __restrict__ DP, SphereTab tab, ProjTab pt,
                                                     const cplx<R>* __restrict__ tw0, double sc_v,
                                                     const BatchJob* __restrict__ jobs = nullptr,
                                                     const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
-  constexpr int NB = xnb<N0>::value;
-  using LS = last_shape<N0, NB, NT>;
-  using FR = fft_regs<N0, NB, NT, C, HB>;
+  constexpr int NB = SH::NB, XT = SH::XT;
+  using LS = last_shape<N0, NB, XT>;
+  using FR = fft_regs<N0, NB, XT, C, HB>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ double2 dps[KB_TILE_DP];
   __shared__ C tw[N0];
@@ -268,21 +268,21 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   } else {
     orbital_range(nb, oa, ob);
   }
-  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
+  for (int i = tid; i < N0; i += XT) tw[i] = tw0[i];
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
   // potential at the outputs of this thread's last synthesis stage, times the
   // synthesis and analysis scales Omega^-1/2 Omega^1/2 / N = 1/N
   double vr[LS::items][LS::radix];
   const double* vbase = V + p0;
-  last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+  last_stage_positions<N0, NB, XT>(NB, [&](int it, int q, int t, int e) {
     vr[it][q] = (p0 + t < npl) ? vbase[e * npl + t] * sc_v : 0.0;
   });
   // KB coefficients d*P of this tile's slots: thread tid < ns*np stages one
   // (slot, projector) value per orbital.
   const int np = pt.nproj;
   const int sA = pt.slot_off[tile], ns = pt.slot_off[tile + 1] - sA;
-  const int ndp = ns * np;   // <= KB_TILE_DP <= NT
+  const int ndp = ns * np;   // <= KB_TILE_DP <= XT
   const long long dp_stride = (long long)pt.natoms * np;
   long long dp_off = 0;
   if (tid < ndp) {
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
   const int nplanes = tab.nplanes, m0lo = tab.m0lo;
   const int tvalid = npl - p0;
   FR pre;
-  if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, nplanes, m0lo, p0));
+  if (oa < ob) fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, nplanes, m0lo, p0));
   double2 dnext = {0.0, 0.0};
   if (tid < ndp && oa < ob) dnext = DP[oa * dp_stride + dp_off];
   for (int o = oa; o < ob; ++o) {
@@ -302,17 +302,17 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
     if (tid < ndp) dps[tid] = dnext;
     auto next = [&] {
       if (o + 1 < ob) {
-        fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, nplanes, m0lo, p0));
+        fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, nplanes, m0lo, p0));
         if (tid < ndp) dnext = DP[(o + 1) * dp_stride + dp_off];
       }
     };
     // synthesis, then psi <- V psi as the outputs are written
-    fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int t, int e, C v, int it, int q) {
+    fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int t, int e, C v, int it, int q) {
       X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
     });
     if (ns > 0) {
-      if (np == 4) kb_scatter_fixed<4>(X, dps, pt, uA, uB);
-      else kb_scatter_any(X, dps, pt, uA, uB);
+      if (np == 4) kb_scatter_fixed<4, XT>(X, dps, pt, uA, uB);
+      else kb_scatter_any<XT>(X, dps, pt, uA, uB);
       __syncthreads();
     }
     C* obase = Uout + (long long)o * nplanes * npl + p0;
@@ -321,8 +321,8 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
       if (pi >= 0 && pi < nplanes && t < tvalid) st_stream(obase + (unsigned)(pi * npl + t), v);
     };
     // only the sphere's planes are stored; with HB they all lie in the band |m0| < n0/4
-    if constexpr (HB) fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, banded(store));
-    else fft_io<N0, -1, NB, NT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, store);
+    if constexpr (HB) fft_io<N0, -1, NB, XT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, banded(store));
+    else fft_io<N0, -1, NB, XT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, store);
     __syncthreads();   // X and dps are rewritten for the next orbital
   }
 }
@@ -331,20 +331,20 @@ __global__ __launch_bounds__(NT) void xapply_kernel(const cplx<R>* __restrict__ 
 // straight from the last synthesis stage over the group's orbitals in order
 // and written to the group's partial density; dens_sum adds the groups in
 // order.
-template <int N0, typename R, bool HB>
-__global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ Tin, int nb,
+template <int N0, class SH, typename R, bool HB>
+__global__ __launch_bounds__(SH::XT) void xdens_kernel(const cplx<R>* __restrict__ Tin, int nb,
                                                    const double* __restrict__ occ, double* __restrict__ part,
                                                    SphereTab tab, const cplx<R>* __restrict__ tw0,
                                                    double inv_omega) {
   using C = cplx<R>;
-  constexpr int NB = xnb<N0>::value;
-  using LS = last_shape<N0, NB, NT>;
+  constexpr int NB = SH::NB, XT = SH::XT;
+  using LS = last_shape<N0, NB, XT>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ C tw[N0];
   const int tile = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
   const int npl = tab.n1 * tab.n2;
   const int p0 = tile * NB;
-  for (int i = tid; i < N0; i += NT) tw[i] = tw0[i];
+  for (int i = tid; i < N0; i += XT) tw[i] = tw0[i];
   double a[LS::items][LS::radix];
 #pragma unroll
   for (int it = 0; it < LS::items; ++it)
@@ -353,22 +353,22 @@ __global__ __launch_bounds__(NT) void xdens_kernel(const cplx<R>* __restrict__ T
   int oa, ob;
   orbital_range(nb, oa, ob);
   // the next orbital's T is loaded once the first stage has consumed the current one
-  using FR = fft_regs<N0, NB, NT, C, HB>;
+  using FR = fft_regs<N0, NB, XT, C, HB>;
   FR pre;
-  if (oa < ob) fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
+  if (oa < ob) fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
     auto next = [&] {
       if (o + 1 < ob)
-        fft_preload<N0, NB, NT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+        fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     };
     const double f = occ[o] * inv_omega;
-    fft_io<N0, +1, NB, NT, SRC_PRE, DST_FN, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int, int, C v, int it, int q) {
+    fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int, int, C v, int it, int q) {
       a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
     });
     __syncthreads();
   }
   double* pb = part + (long long)g * tab.n0 * npl + p0;
-  last_stage_positions<N0, NB, NT>(NB, [&](int it, int q, int t, int e) {
+  last_stage_positions<N0, NB, XT>(NB, [&](int it, int q, int t, int e) {
     if (p0 + t < npl) pb[e * npl + t] = a[it][q];
   });
 }
@@ -395,34 +395,75 @@ static int x_groups(const ks_system* s, int nb) {
   return (int)((nb + g - 1) / g);
 }
 
+// Tile shapes of the x-pencil blocks (pencils NB x threads XT).  Shape 0
+// is xnb<N0> pencils x NT threads; shape 1 is 16 pencils x 192 threads, for
+// the largest grids only (smaller LDS buffers, more blocks resident per CU).
+// The autotuner picks the shape per grid and precision.
+template <int NB_, int XT_>
+struct XShape {
+  static constexpr int NB = NB_, XT = XT_;
+};
+template <int N0> constexpr bool has_shape1 = N0 == 96 || N0 == 120;
+
+template <int N0, class F>
+static void with_shape(const ks_system* s, F&& f) {
+  if constexpr (has_shape1<N0>) {
+    if (s->xshape == 1) {
+      f(XShape<16, 192>{});
+      return;
+    }
+  }
+  f(XShape<xnb<N0>::value, NT>{});
+}
+
+bool x_shape_available(int n0, int shape) {
+  if (shape == 0) return true;
+  if (shape != 1) return false;
+  switch (n0) {
+#define KS_CASE(v) case v: return has_shape1<v>;
+    KS_SIZES(KS_CASE)
+#undef KS_CASE
+    default:
+      return false;
+  }
+}
+
+int x_shape_nb(int n0, int shape) { return shape == 1 ? 16 : x_tile_nb(n0); }
+int x_shape_threads(int shape) { return shape == 1 ? 192 : NT; }
+
 template <int N0, bool HB>
 static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, const double* occ, double* rho,
                     int accumulate, hipStream_t st) {
   const double scale = s->dV / sqrt(s->omega);
   const double inv_omega = 1.0 / s->omega;
-  if (!rho) {
-    const int ng = x_groups(s, nb);
-    if (!mixed(s))
-      xproj_kernel<N0, double, HB, false><<<dim3(s->ntiles, ng), NT, 0, st>>>(
-          (const double2*)T, nb, (double2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0, scale, nullptr, nullptr,
+  const bool dens = rho != nullptr;
+  // with the density: groups of at least DENS_GROUP orbitals, so the partial
+  // densities fit their buffer
+  const int ng = dens ? std::min(x_groups(s, nb), (nb + DENS_GROUP - 1) / DENS_GROUP) : x_groups(s, nb);
+  with_shape<N0>(s, [&](auto sh) {
+    using SH = decltype(sh);
+    const dim3 grid(s->ntiles, ng);
+    if (!dens) {
+      if (!mixed(s))
+        xproj_kernel<N0, SH, double, HB, false><<<grid, SH::XT, 0, st>>>(
+            (const double2*)T, nb, (double2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0, scale, nullptr, nullptr,
+            inv_omega);
+      else
+        xproj_kernel<N0, SH, float, HB, false><<<grid, SH::XT, 0, st>>>(
+            (const float2*)T, nb, (float2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0f, scale, nullptr, nullptr,
+            inv_omega);
+    } else if (!mixed(s)) {
+      xproj_kernel<N0, SH, double, HB, true><<<grid, SH::XT, 0, st>>>(
+          (const double2*)T, nb, (double2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0, scale, occ, s->dens_part,
           inv_omega);
-    else
-      xproj_kernel<N0, float, HB, false><<<dim3(s->ntiles, ng), NT, 0, st>>>(
-          (const float2*)T, nb, (float2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0f, scale, nullptr, nullptr,
+    } else {
+      xproj_kernel<N0, SH, float, HB, true><<<grid, SH::XT, 0, st>>>(
+          (const float2*)T, nb, (float2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0f, scale, occ, s->dens_part,
           inv_omega);
-    return;
-  }
-  // groups of at least DENS_GROUP orbitals, so the partial densities fit their buffer
-  const int ng = std::min(x_groups(s, nb), (nb + DENS_GROUP - 1) / DENS_GROUP);
-  if (!mixed(s))
-    xproj_kernel<N0, double, HB, true><<<dim3(s->ntiles, ng), NT, 0, st>>>(
-        (const double2*)T, nb, (double2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0, scale, occ, s->dens_part,
-        inv_omega);
-  else
-    xproj_kernel<N0, float, HB, true><<<dim3(s->ntiles, ng), NT, 0, st>>>(
-        (const float2*)T, nb, (float2*)partial, sphere_tab(s), proj_tab(s), s->d_tw0f, scale, occ, s->dens_part,
-        inv_omega);
-  dens_sum_kernel<<<(unsigned)((s->N + NT - 1) / NT), NT, 0, st>>>(s->dens_part, ng, s->N, rho, accumulate);
+    }
+  });
+  if (dens)
+    dens_sum_kernel<<<(unsigned)((s->N + NT - 1) / NT), NT, 0, st>>>(s->dens_part, ng, s->N, rho, accumulate);
 }
 
 bool launch_xproj(const ks_system* s, int nb, const void* T, void* partial, const double* occ, double* rho,
@@ -444,12 +485,16 @@ static void xapply_n(const ks_system* s, int nb, const void* T, const double2* D
   // (the KB coefficients carry the analysis scale from proj_reduce)
   const double sc_v = 1.0 / (double)s->N;
   const int ng = x_groups(s, nb);
-  if (!mixed(s))
-    xapply_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, (double2*)U, s->d_v,
-                                                                   DP, sphere_tab(s), proj_tab(s), s->d_tw0, sc_v);
-  else
-    xapply_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, (float2*)U, s->d_v,
-                                                                  DP, sphere_tab(s), proj_tab(s), s->d_tw0f, sc_v);
+  with_shape<N0>(s, [&](auto sh) {
+    using SH = decltype(sh);
+    const dim3 grid(s->ntiles, ng);
+    if (!mixed(s))
+      xapply_kernel<N0, SH, double, HB><<<grid, SH::XT, 0, st>>>((const double2*)T, nb, (double2*)U, s->d_v, DP,
+                                                                sphere_tab(s), proj_tab(s), s->d_tw0, sc_v);
+    else
+      xapply_kernel<N0, SH, float, HB><<<grid, SH::XT, 0, st>>>((const float2*)T, nb, (float2*)U, s->d_v, DP,
+                                                               sphere_tab(s), proj_tab(s), s->d_tw0f, sc_v);
+  });
 }
 
 bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP, void* U, hipStream_t st) {
@@ -463,28 +508,31 @@ bool launch_xapply(const ks_system* s, int nb, const void* T, const double2* DP,
   }
 }
 
-// Batched launches: one x-pass launch over several systems of the grid.
+// Batched launches: one x-pass launch over several systems of the grid (all
+// of one tile shape, that of s).
 template <int N0, bool HB>
 static void x_batch_n(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool apply,
                       hipStream_t st) {
   const dim3 grid(s->ntiles, nrows);
-  if (!apply) {
-    const double scale = s->dV / sqrt(s->omega);
-    if (!mixed(s))
-      xproj_kernel<N0, double, HB, false, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, sphere_tab(s), ProjTab{},
-                                                                   s->d_tw0, scale, nullptr, nullptr, 0.0, jobs, rows);
-    else
-      xproj_kernel<N0, float, HB, false, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, sphere_tab(s), ProjTab{},
-                                                                  s->d_tw0f, scale, nullptr, nullptr, 0.0, jobs, rows);
-    return;
-  }
+  const double scale = s->dV / sqrt(s->omega);
   const double sc_v = 1.0 / (double)s->N;
-  if (!mixed(s))
-    xapply_kernel<N0, double, HB, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, nullptr, nullptr, sphere_tab(s),
-                                                           ProjTab{}, s->d_tw0, sc_v, jobs, rows);
-  else
-    xapply_kernel<N0, float, HB, true><<<grid, NT, 0, st>>>(nullptr, 0, nullptr, nullptr, nullptr, sphere_tab(s),
-                                                          ProjTab{}, s->d_tw0f, sc_v, jobs, rows);
+  with_shape<N0>(s, [&](auto sh) {
+    using SH = decltype(sh);
+    if (!apply) {
+      if (!mixed(s))
+        xproj_kernel<N0, SH, double, HB, false, true><<<grid, SH::XT, 0, st>>>(
+            nullptr, 0, nullptr, sphere_tab(s), ProjTab{}, s->d_tw0, scale, nullptr, nullptr, 0.0, jobs, rows);
+      else
+        xproj_kernel<N0, SH, float, HB, false, true><<<grid, SH::XT, 0, st>>>(
+            nullptr, 0, nullptr, sphere_tab(s), ProjTab{}, s->d_tw0f, scale, nullptr, nullptr, 0.0, jobs, rows);
+    } else if (!mixed(s)) {
+      xapply_kernel<N0, SH, double, HB, true><<<grid, SH::XT, 0, st>>>(
+          nullptr, 0, nullptr, nullptr, nullptr, sphere_tab(s), ProjTab{}, s->d_tw0, sc_v, jobs, rows);
+    } else {
+      xapply_kernel<N0, SH, float, HB, true><<<grid, SH::XT, 0, st>>>(
+          nullptr, 0, nullptr, nullptr, nullptr, sphere_tab(s), ProjTab{}, s->d_tw0f, sc_v, jobs, rows);
+    }
+  });
 }
 
 bool launch_x_batch(const ks_system* s, const BatchJob* jobs, const int4* rows, int nrows, bool apply,
@@ -517,12 +565,16 @@ static int dens_groups(const ks_system* s, int nb) {
 template <int N0, bool HB>
 static void xdens_n(const ks_system* s, int nb, const void* T, const double* occ, double* part, hipStream_t st) {
   const int ng = dens_groups(s, nb);
-  if (!mixed(s))
-    xdens_kernel<N0, double, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const double2*)T, nb, occ, part, sphere_tab(s),
-                                                                  s->d_tw0, 1.0 / s->omega);
-  else
-    xdens_kernel<N0, float, HB><<<dim3(s->ntiles, ng), NT, 0, st>>>((const float2*)T, nb, occ, part, sphere_tab(s),
-                                                                 s->d_tw0f, 1.0 / s->omega);
+  with_shape<N0>(s, [&](auto sh) {
+    using SH = decltype(sh);
+    const dim3 grid(s->ntiles, ng);
+    if (!mixed(s))
+      xdens_kernel<N0, SH, double, HB><<<grid, SH::XT, 0, st>>>((const double2*)T, nb, occ, part, sphere_tab(s),
+                                                               s->d_tw0, 1.0 / s->omega);
+    else
+      xdens_kernel<N0, SH, float, HB><<<grid, SH::XT, 0, st>>>((const float2*)T, nb, occ, part, sphere_tab(s),
+                                                              s->d_tw0f, 1.0 / s->omega);
+  });
 }
 
 bool launch_xdens(const ks_system* s, int nb, const void* T, const double* occ, double* rho, int accumulate,

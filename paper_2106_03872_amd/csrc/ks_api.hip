@@ -273,7 +273,7 @@ ks_status build_sphere(const int n[3], const double L[3], double ecut, SphereHos
 // grid points of each tile with their (slot, beta row) entries ordered by
 // atom.  LDS positions are w*(n0+1) + j0 within the tile's pencil buffer.
 struct ProjHost {
-  int nproj = 1, npoints = 0, nruns = 0, ntiles = 0, xnb = 32;
+  int nproj = 1, npoints = 0, nruns = 0, ntiles = 0, xnb = 32, lanes = 256;
   std::vector<double> brows;
   std::vector<int> brow_input;   // input row of each beta row
   std::vector<int> pt_lds, slot_off, slot_atom, slot_pt, atom_slot_off, atom_slots;
@@ -281,10 +281,11 @@ struct ProjHost {
   std::vector<int4> item;
 };
 
-ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* npts, const int* idx,
+ks_status build_proj(const int n[3], int xnb, int lanes, int natoms, int nproj, const int* npts, const int* idx,
                      const double* beta, ProjHost& h, std::string& err) {
   if (natoms < 0) { err = "natoms < 0"; return KS_EINVAL; }
   if (natoms > 0 && (nproj < 1 || !npts)) { err = "nproj < 1 or npts is null"; return KS_EINVAL; }
+  if (lanes < KB_TILE_DP) { err = "x-block narrower than the staged KB pairs"; return KS_EINVAL; }
   if (nproj > KB_MAX_NPROJ) {
     err = "more than " + std::to_string(KB_MAX_NPROJ) + " projectors per atom";
     return KS_EUNSUPPORTED;
@@ -305,6 +306,7 @@ ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* 
   h.npoints = (int)total;
   h.ntiles = nt;
   h.xnb = xnb;
+  h.lanes = lanes;
   struct Pt { int tile, p, atom, j0, row; };
   std::vector<Pt> pts;
   pts.reserve(total);
@@ -364,7 +366,7 @@ ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* 
   // largest groups are halved (their lanes then loop over extra rows).
   // item = (first row, end row, local slot * nproj + projector, g | 256 for
   // the group's first lane).
-  h.item.assign((size_t)nt * KB_ITEM_LANES, make_int4(0, 0, 0, 0));
+  h.item.assign((size_t)nt * lanes, make_int4(0, 0, 0, 0));
   for (int t = 0; t < nt; ++t) {
     const int s0 = h.slot_off[t], ns = h.slot_off[t + 1] - s0;
     std::vector<int> lg(ns, 0);
@@ -374,9 +376,9 @@ ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* 
       while ((1 << lg[j]) < need && lg[j] < KB_MAX_GROUP_LOG) ++lg[j];
     }
     for (;;) {
-      long long lanes = 0;
-      for (int j = 0; j < ns; ++j) lanes += (long long)np << lg[j];
-      if (lanes <= KB_ITEM_LANES) break;
+      long long used = 0;
+      for (int j = 0; j < ns; ++j) used += (long long)np << lg[j];
+      if (used <= lanes) break;
       int jm = 0;
       for (int j = 1; j < ns; ++j)
         if (lg[j] > lg[jm]) jm = j;
@@ -390,7 +392,7 @@ ks_status build_proj(const int n[3], int xnb, int natoms, int nproj, const int* 
       const int k0 = h.slot_pt[s0 + j], len = h.slot_pt[s0 + j + 1] - k0, g = 1 << lg[j];
       for (int q = 0; q < np; ++q, base += g)
         for (int sg = 0; sg < g; ++sg)
-          h.item[(size_t)t * KB_ITEM_LANES + base + sg] =
+          h.item[(size_t)t * lanes + base + sg] =
               make_int4(k0 + (int)((long long)len * sg / g), k0 + (int)((long long)len * (sg + 1) / g), j * np + q,
                         lg[j] | (sg == 0 ? 256 : 0));
     }
@@ -582,11 +584,13 @@ ks_status taylor_packed(ks_system* s, int nb, double2* state, double dt, int nst
 }
 
 // process-wide autotuning results: (grid, precision, sphere planes, orbitals
-// per pass rounded up to a power of two) -> (x-pass group cap, plane-pass
-// group cap)
+// per pass rounded up to a power of two) -> (group caps, x-tile shape)
 using TuneKey = std::tuple<int, int, int, int, int, int>;
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+struct TuneResult {
+  int xg = 0, pg = 0, shape = 0;   // group caps and x-tile shape (xg == 0: none)
+};
+std::map<TuneKey, TuneResult> g_tune_cache;
 
 // Density of the nb-orbital passes of a resident state (all passes, in
 // order) into rho.
@@ -900,7 +904,9 @@ static ks_status system_create(ks_pool* pool, const int n[3], const double L[3],
   s->ncols = (int)col_m2lo.size();
   s->npw = npw;
   s->npw_stride = (npw + 63) / 64 * 64;
-  s->xnb = x_tile_nb(n[0]);
+  s->xshape = 0;
+  s->xnb = x_shape_nb(n[0], 0);
+  s->xnt = x_shape_threads(0);
   s->ntiles = (s->npl + s->xnb - 1) / s->xnb;
   s->x_half = s->m0lo >= -(n[0] / 4) && s->m0lo + s->nplanes - 1 < n[0] / 4;
   s->yz_half = true;
@@ -1021,20 +1027,10 @@ ks_status ks_system_set_vloc(ks_system* s, const double* v, void* stream) {
   return KS_OK;
 }
 
-ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
-                                   const double* beta, const double* d, void* stream) {
-  if (!s) return fail(nullptr, KS_EINVAL, "null system");
-  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
-  if (natoms > 0 && !d) return fail(s, KS_EINVAL, "d is null");
-  ProjHost ph;
-  {
-    std::string msg;
-    const ks_status r = build_proj(s->n, s->xnb, natoms, nproj, npts, idx, beta, ph, msg);
-    if (r != KS_OK) return fail(s, r, msg);
-  }
-  KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
-  wait_own(s);   // the old tables may still be read by work on another stream
-  ++s->gen;
+// Uploads the per-tile projector tables ph (built for the system's current
+// tile shape) and the KB energies d [natoms][nproj]; the caller has waited
+// for the system's work.
+static ks_status install_proj(ks_system* s, const ProjHost& ph, int natoms, const double* d) {
   const int np = ph.nproj;
   std::vector<double> kb((size_t)natoms * np);
   for (size_t k = 0; k < kb.size(); ++k) kb[k] = d[k];
@@ -1073,6 +1069,55 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
   s->npoints = ph.npoints;
   s->nuniq = (int)ph.up_lds.size();
   return alloc_proj_workspace(s);
+}
+
+ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
+                                   const double* beta, const double* d, void* stream) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
+  if (natoms > 0 && !d) return fail(s, KS_EINVAL, "d is null");
+  ProjHost ph;
+  {
+    std::string msg;
+    const ks_status r = build_proj(s->n, s->xnb, s->xnt, natoms, nproj, npts, idx, beta, ph, msg);
+    if (r != KS_OK) return fail(s, r, msg);
+  }
+  KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
+  wait_own(s);   // the old tables may still be read by work on another stream
+  ++s->gen;
+  // keep the inputs: another tile shape rebuilds the tables from them
+  auto& in = s->proj_in;
+  const int na = std::max(0, natoms), np = ph.nproj;
+  in.natoms = na;
+  in.nproj = nproj;
+  in.npts.assign(npts, npts + na);
+  in.idx.assign(idx, idx + ph.npoints);
+  in.beta.assign(beta, beta + (size_t)ph.npoints * np);
+  in.d.assign(d, d + (size_t)na * np);
+  return install_proj(s, ph, na, in.d.data());
+}
+
+// Switch the x-pencil passes to tile shape `shape`: the per-tile projector
+// tables are rebuilt for the new tiles from the stored inputs.
+static ks_status set_x_shape(ks_system* s, int shape) {
+  if (shape == s->xshape) return KS_OK;
+  if (!x_shape_available(s->n[0], shape)) return fail(s, KS_EINVAL, "x-tile shape not available for this grid");
+  const int nb = x_shape_nb(s->n[0], shape), nt = x_shape_threads(shape);
+  const auto& in = s->proj_in;
+  ProjHost ph;
+  {
+    std::string msg;
+    const ks_status r = build_proj(s->n, nb, nt, in.natoms, in.nproj, in.npts.data(), in.idx.data(),
+                                   in.beta.data(), ph, msg);
+    if (r != KS_OK) return fail(s, r, msg);
+  }
+  wait_own(s);
+  ++s->gen;
+  s->xshape = shape;
+  s->xnb = nb;
+  s->xnt = nt;
+  s->ntiles = (s->npl + nb - 1) / nb;
+  return install_proj(s, ph, in.natoms, in.d.data());
 }
 
 ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void* stream) {
@@ -1296,7 +1341,7 @@ ks_status ks_plan_projectors(const int n[3], int natoms, int nproj, const int* n
   ProjHost h;
   std::string msg;
   const int xnb = x_tile_nb(n[0]);
-  const ks_status r = build_proj(n, xnb, natoms, nproj, npts, idx, beta, h, msg);
+  const ks_status r = build_proj(n, xnb, x_shape_threads(0), natoms, nproj, npts, idx, beta, h, msg);
   if (r != KS_OK) return fail(nullptr, r, msg);
   const int nuniq = (int)h.up_lds.size(), nent = (int)h.ent_slot.size();
   counts[0] = (int)h.slot_atom.size();
@@ -1644,6 +1689,8 @@ ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out) 
     if (!t) return fail(nullptr, KS_EINVAL, "null state");
     if (!same_grid(t->sys, s0))
       return fail(nullptr, KS_EINVAL, "the states' systems differ in grid, cell, cutoff or precision");
+    if (t->sys->xshape != s0->xshape)
+      return fail(nullptr, KS_EINVAL, "the states' systems differ in x-tile shape (tuning)");
     for (int i = 0; i < j; ++i)
       if (states[i]->sys == t->sys) return fail(nullptr, KS_EINVAL, "two states of one system (they share its workspace)");
     if (t->norb > t->sys->cb)
@@ -1895,6 +1942,8 @@ ks_status ks_system_info(const ks_system* s, ks_info* info) {
   info->x_half = s->x_half ? 1 : 0;
   info->x_group = s->xg_max;
   info->plane_group = s->pg_max;
+  info->x_shape = s->xshape;
+  info->x_threads = s->xnt;
   return KS_OK;
 }
 
@@ -1904,6 +1953,11 @@ ks_status ks_system_set_tuning(ks_system* s, const ks_tuning* t) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
   if (!t || t->x_group < 1 || t->x_group > 64 || t->plane_group < 1 || t->plane_group > 64)
     return fail(s, KS_EINVAL, "group caps must lie in [1, 64]");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
+  if (t->x_shape != -1) {
+    const ks_status r = set_x_shape(s, t->x_shape);
+    if (r != KS_OK) return r;
+  }
   s->xg_max = t->x_group;
   s->pg_max = t->plane_group;
   ++s->gen;
@@ -1919,16 +1973,19 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
   int nb2 = 1;
   while (nb2 < nb) nb2 *= 2;
   const TuneKey key{s->n[0], s->n[1], s->n[2], s->prec, s->nplanes, nb2};
+  TuneResult found;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
-      s->xg_max = it->second.first;
-      s->pg_max = it->second.second;
-      ++s->gen;
-      if (out) *out = ks_tuning{s->xg_max, s->pg_max, 0.0, 1};
-      return KS_OK;
-    }
+    if (it != g_tune_cache.end()) found = it->second;
+  }
+  if (found.xg > 0) {
+    if ((r = set_x_shape(s, found.shape)) != KS_OK) return r;
+    s->xg_max = found.xg;
+    s->pg_max = found.pg;
+    ++s->gen;
+    if (out) *out = ks_tuning{s->xg_max, s->pg_max, 0.0, 1, s->xshape};
+    return KS_OK;
   }
   const bool timing = s->timing;
   s->timing = false;   // keep the search out of the kernel-time counters
@@ -1946,36 +2003,41 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
   Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   const int xgs[] = {2, 4, 8, 16, 32, 64};
   const int pgs[] = {1, 2, 4, 8, 16};
-  int best_x = s->xg_max, best_p = s->pg_max;
-  float best = -1.0f;
-  for (int xg : xgs) {
-    for (int pg : pgs) {
-      s->xg_max = xg;
-      s->pg_max = pg;
-      if ((r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return done(r);
-      if (hipEventRecord(e0, st) != hipSuccess) return done(fail(s, KS_EDEVICE, "hipEventRecord failed"));
-      for (int rep = 0; rep < 2; ++rep)
+  TuneResult best{s->xg_max, s->pg_max, s->xshape};
+  float best_ms = -1.0f;
+  for (int shape = 0; shape < 2; ++shape) {
+    if (!x_shape_available(s->n[0], shape)) continue;
+    if ((r = set_x_shape(s, shape)) != KS_OK) return done(r);
+    for (int xg : xgs) {
+      for (int pg : pgs) {
+        s->xg_max = xg;
+        s->pg_max = pg;
         if ((r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return done(r);
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-        return done(fail(s, KS_EDEVICE, "event timing failed"));
-      float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return done(fail(s, KS_EDEVICE, "hipEventElapsedTime failed"));
-      ms *= 0.5f;
-      if (best < 0.0f || ms < best) {
-        best = ms;
-        best_x = xg;
-        best_p = pg;
+        if (hipEventRecord(e0, st) != hipSuccess) return done(fail(s, KS_EDEVICE, "hipEventRecord failed"));
+        for (int rep = 0; rep < 2; ++rep)
+          if ((r = hpsi_packed(s, nb, s->pk[0], true, s->pk[1], nullptr, H_OUT, none, st)) != KS_OK) return done(r);
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+          return done(fail(s, KS_EDEVICE, "event timing failed"));
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          return done(fail(s, KS_EDEVICE, "hipEventElapsedTime failed"));
+        ms *= 0.5f;
+        if (best_ms < 0.0f || ms < best_ms) {
+          best_ms = ms;
+          best = TuneResult{xg, pg, shape};
+        }
       }
     }
   }
-  s->xg_max = best_x;
-  s->pg_max = best_p;
+  if ((r = set_x_shape(s, best.shape)) != KS_OK) return done(r);
+  s->xg_max = best.xg;
+  s->pg_max = best.pg;
   ++s->gen;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = {best_x, best_p};
+    g_tune_cache[key] = best;
   }
-  if (out) *out = ks_tuning{best_x, best_p, (double)best, 0};
+  if (out) *out = ks_tuning{best.xg, best.pg, (double)best_ms, 0, best.shape};
   return done(KS_OK);
 }
 

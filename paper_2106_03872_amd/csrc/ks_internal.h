@@ -49,7 +49,7 @@ struct ProjTab {
   const double* x_beta;      // [nextra][nproj]
   const double* beta;        // [npoints][nproj], rows in slot order
   const double* d;           // [natoms][nproj]
-  const int4* item;          // [ntiles][KB_ITEM_LANES] projection work of each lane (see build_proj)
+  const int4* item;          // [ntiles][threads per x-block] projection work of each lane (see build_proj)
   int natoms, nproj, nslots;
 };
 
@@ -78,7 +78,6 @@ constexpr int UP_MAX_SLOT = (1 << UP_SLOT_BITS) - 1, UP_MAX_EXTRA = 127;
 constexpr int KB_MAX_NPROJ = 8;        // projectors per atom
 constexpr size_t GEMM_PART_MAX = 256ull << 20;    // largest split-K partial buffer of the n x n products
 constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-tile
-constexpr int KB_ITEM_LANES = 256;     // lanes of an x-pencil block (projection work items)
 constexpr int KB_CACHED_POINTS = 16;   // points of an item held in registers across orbitals
 constexpr int KB_MAX_GROUP_LOG = 4;    // at most 16 lanes per (slot, projector) pair
 
@@ -139,7 +138,9 @@ struct ks_system {
 
   // projectors
   int natoms = 0, nproj = 0, nslots = 0, nruns = 0, npoints = 0, nuniq = 0;
-  int xnb = 32, ntiles = 0;
+  // x-tile shape (see x_shape_nb / x_shape_threads): pencils per tile and
+  // threads per block of the x-pencil passes
+  int xshape = 0, xnb = 32, xnt = 256, ntiles = 0;
   bool x_half = false;   // every sphere plane has |m0| < n0/4 (band-limited x-synthesis input)
   bool yz_half = false;  // every sphere point has |m1| < n1/4 and |m2| < n2/4 (band-limited y, z transforms)
   int xg_max = 8, pg_max = 8;   // orbital-group caps of the x-pencil and plane passes (tunable)
@@ -148,6 +149,13 @@ struct ks_system {
       *d_up_x = nullptr, *d_x_slot = nullptr;
   double *d_beta = nullptr, *d_up_beta = nullptr, *d_x_beta = nullptr, *d_kb = nullptr;
   int4* d_item = nullptr;
+  // the projector inputs as last set, kept so the per-tile tables can be
+  // rebuilt for another tile shape
+  struct {
+    int natoms = 0, nproj = 0;
+    std::vector<int> npts, idx;
+    std::vector<double> beta, d;
+  } proj_in;
 
   // workspace (one chunk of cb orbitals)
   int cb = 1;
@@ -326,6 +334,9 @@ void launch_sd_update(int norb, int npw, int stride, double2* C, const double2* 
 
 bool supported_size(int n);
 int x_tile_nb(int n0);
+bool x_shape_available(int n0, int shape);
+int x_shape_nb(int n0, int shape);
+int x_shape_threads(int shape);
 size_t plane_lds_bytes(const ks_system* s);
 
 // kernel-side views of a system's sphere and projector tables

@@ -27,7 +27,7 @@ KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "pla
 class Info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nruns",
                                             "nslots", "npoints", "x_tile", "precision", "x_half", "x_group",
-                                            "plane_group")]
+                                            "plane_group", "x_shape", "x_threads")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -35,7 +35,7 @@ class Info(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("x_group", ctypes.c_int), ("plane_group", ctypes.c_int), ("ms", ctypes.c_double),
-                ("from_cache", ctypes.c_int)]
+                ("from_cache", ctypes.c_int), ("x_shape", ctypes.c_int)]
 
 
 _STATUS = {1: "KS_EINVAL", 2: "KS_ENOMEM", 3: "KS_EDEVICE", 4: "KS_EUNSUPPORTED"}
@@ -394,15 +394,18 @@ class System:
         return inf.as_dict()
 
     def autotune(self, norb):
-        """Time the launch-schedule candidates (orbital-group caps) for H psi
-        over `norb` orbitals and keep the fastest (cached per process by
-        shape).  Returns {x_group, plane_group, ms, from_cache}."""
+        """Time the launch-schedule candidates (x-tile shape and orbital-group
+        caps) for H psi over `norb` orbitals and keep the fastest (cached per
+        process by grid, precision and size).  Returns {x_group, plane_group,
+        ms, from_cache, x_shape}."""
         t = Tuning()
         self._check(_lib.ks_autotune(self._h, int(norb), _stream(), ctypes.byref(t)))
-        return {"x_group": t.x_group, "plane_group": t.plane_group, "ms": t.ms, "from_cache": bool(t.from_cache)}
+        return {"x_group": t.x_group, "plane_group": t.plane_group, "ms": t.ms, "from_cache": bool(t.from_cache),
+                "x_shape": t.x_shape}
 
-    def set_tuning(self, x_group, plane_group):
-        t = Tuning(int(x_group), int(plane_group), 0.0, 0)
+    def set_tuning(self, x_group, plane_group, x_shape=None):
+        """Set the group caps and, unless x_shape is None, the x-tile shape."""
+        t = Tuning(int(x_group), int(plane_group), 0.0, 0, -1 if x_shape is None else int(x_shape))
         self._check(_lib.ks_system_set_tuning(self._h, ctypes.byref(t)))
 
     def hartree(self, rho, add_vloc=False, out=None):
