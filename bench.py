@@ -68,23 +68,13 @@ def alg_bytes(info, spec, kernel, S=16):
     return 0, 0
 
 
-def csrc_fingerprint():
-    """sha256 over the library's kernel and runtime sources (csrc/, sorted)."""
-    import hashlib
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2106_03872_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        h.update(f.encode())
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def measured_traffic(kernel, workload, orbitals_per_pass):
+def measured_traffic(kernel, workload, orbitals_per_pass, info):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by the copy-kernel
-    calibration), or None when the summary is missing or was taken on other
-    sources or another pass size."""
+    calibration; written by `python -m paper_2106_03872_amd.profiling
+    traffic`), or None when the summary is missing, was taken on other
+    sources or another pass size, or on another x-tile shape."""
+    from paper_2106_03872_amd.profiling import csrc_fingerprint
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}_fp64.json")
     if not os.path.exists(path):
         return None
@@ -93,7 +83,11 @@ def measured_traffic(kernel, workload, orbitals_per_pass):
     if rec.get("csrc_sha256") != csrc_fingerprint() or rec.get("orbitals_per_pass") != orbitals_per_pass:
         return None
     k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["bytes_per_launch"]
+    if k is None:
+        return None
+    if kernel.startswith("x") and f"XShape<{info['x_tile']}, {info['x_threads']}>" not in k.get("kernel", ""):
+        return None
+    return k["bytes_per_launch"]
 
 
 def cpu_baseline(spec, sysm, norb_sample=128):
@@ -404,7 +398,7 @@ def main():
     per_pass = orbitals_per_pass(spec, info)    # orbitals per launch
     roof = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(dk["alg_GBs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom, spec.name, per_pass), "avg_launch_us": dk["avg_us"],
+            "traffic": measured_traffic(dom, spec.name, per_pass, gs.info()), "avg_launch_us": dk["avg_us"],
             "alg_bytes_per_orbital": po, "alg_bytes_per_launch_shared": pl,
             "alg_bytes_per_launch": po * per_pass + pl, "orbitals_per_launch": per_pass}
     psi64 = state.download()

@@ -49,113 +49,133 @@ static_assert(BJ_B * BJ_B == BJ_NT, "one thread per 2x2 block of a sub-problem")
 // Hermitian block [[a, b], [conj(b), c]]: with b = |b| e^{i phi}, the phase
 // D = diag(1, e^{-i phi}) makes the block real, and the real symmetric
 // rotation [[cs, sn], [-sn, cs]] with t = tan(theta) the smaller root of
-// t^2 + 2 tau t - 1 = 0, tau = (c - a) / (2|b|), zeroes it; J = D R.
+// t^2 + 2 tau t - 1 = 0, tau = (c - a) / (2|b|), zeroes it; J = D R, i.e.
+//   J = [[cs, sn], [-f, g]],  f = sn e, g = cs e,  e = e^{-i phi}.
+// With h = |tau| + sqrt(1 + tau^2) = 1/|t|: cs = h / sqrt(1 + h^2) and
+// sn = sign(tau) / sqrt(1 + h^2), so the chain has two reciprocal square
+// roots and one square root and no division.  An element so small against
+// the diagonal gap that h^2 would overflow is left alone (the rotation angle
+// would be below 1e-150).
 struct Rot {
   double cs, sn;
-  double2 e;   // e^{-i phi}
+  double2 f, g;
 };
 
 __device__ __forceinline__ Rot make_rot(double a, double c, double2 b) {
-  Rot r{1.0, 0.0, double2{1.0, 0.0}};
-  const double ab = sqrt(b.x * b.x + b.y * b.y);
-  if (ab == 0.0) return r;
-  const double tau = (c - a) / (2.0 * ab);
-  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  r.cs = 1.0 / sqrt(1.0 + t * t);
-  r.sn = t * r.cs;
-  r.e = double2{b.x / ab, -b.y / ab};
+  Rot r{1.0, 0.0, double2{0.0, 0.0}, double2{1.0, 0.0}};
+  const double b2 = b.x * b.x + b.y * b.y;
+  if (b2 == 0.0) return r;
+  const double rb = rsqrt(b2);   // 1 / |b|
+  const double tau = 0.5 * (c - a) * rb;
+  const double at = fabs(tau);
+  if (!(at < 1e150)) return r;
+  const double h = at + sqrt(fma(tau, tau, 1.0));
+  const double rh = rsqrt(fma(h, h, 1.0));
+  r.cs = h * rh;
+  r.sn = tau >= 0.0 ? rh : -rh;
+  const double2 e{b.x * rb, -b.y * rb};
+  r.f = cscale(e, r.sn);
+  r.g = cscale(e, r.cs);
   return r;
 }
 
-// J entries: J00 = cs, J01 = sn, J10 = -sn e, J11 = cs e
-__device__ __forceinline__ double2 jent(const Rot& r, int i, int j) {
-  if (i == 0) return double2{j == 0 ? r.cs : r.sn, 0.0};
-  return cscale(r.e, j == 0 ? -r.sn : r.cs);
+// (x0, x1) J: the row vector (x0, x1) times the rotation
+__device__ __forceinline__ void rot_right(const Rot& r, double2 x0, double2 x1, double2& y0, double2& y1) {
+  const double2 a = cmul(x1, r.f), b = cmul(x1, r.g);
+  y0 = double2{r.cs * x0.x - a.x, r.cs * x0.y - a.y};
+  y1 = double2{r.sn * x0.x + b.x, r.sn * x0.y + b.y};
+}
+
+// J^H (x0, x1)^T: the rotation's adjoint times the column vector (x0, x1)
+__device__ __forceinline__ void rot_left_adj(const Rot& r, double2 x0, double2 x1, double2& y0, double2& y1) {
+  const double2 a = cmul(cconj(r.f), x1), b = cmul(cconj(r.g), x1);
+  y0 = double2{r.cs * x0.x - a.x, r.cs * x0.y - a.y};
+  y1 = double2{r.sn * x0.x + b.x, r.sn * x0.y + b.y};
 }
 
 // global index of local index l of block pair (I, J)
 __device__ __forceinline__ int bj_index(int I, int J, int l) { return l < BJ_B ? I * BJ_B + l : J * BJ_B + (l - BJ_B); }
 
 // Block k of round t: one cyclic sweep on the sub-problem of block pair k;
-// its unitary goes to Ublk[k] (row-major BJ_M x BJ_M).
+// its unitary goes to Ublk[k] (row-major BJ_M x BJ_M).  S and U are kept in
+// two LDS copies: inner round r reads one and writes the other (every entry
+// is rewritten), so a round has two barriers (rotations formed; update
+// done).
 __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restrict__ A, int N2, int t,
                                                          double2* __restrict__ Ublk) {
-  __shared__ double2 S[BJ_M][BJ_M + 1];
-  __shared__ double2 U[BJ_M][BJ_M + 1];
+  __shared__ double2 S[2][BJ_M][BJ_M + 1];
+  __shared__ double2 U[2][BJ_M][BJ_M + 1];
   __shared__ Rot rot[BJ_B];
   const int k = blockIdx.x, tid = threadIdx.x;
   int I, J;
   round_pair(t, k, N2 / BJ_B, I, J);
   for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) {
     const int r = e / BJ_M, c = e % BJ_M;
-    S[r][c] = A[(long long)bj_index(I, J, r) * N2 + bj_index(I, J, c)];
-    U[r][c] = double2{r == c ? 1.0 : 0.0, 0.0};
+    S[0][r][c] = A[(long long)bj_index(I, J, r) * N2 + bj_index(I, J, c)];
+    U[0][r][c] = double2{r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
   const int P2 = tid / BJ_B, Q2 = tid % BJ_B;
+  int cur = 0;
   for (int r = 0; r < BJ_M - 1; ++r) {
+    // 2x2 block (P2, Q2) of S <- J^H S J, and columns pk of rows P2, P2 +
+    // BJ_B of U <- U J (each entry has one owner); the block's entries are
+    // read before the rotations are formed, so their LDS latency overlaps it
+    int pi[2], pk[2];
+    round_pair(r, P2, BJ_M, pi[0], pi[1]);
+    round_pair(r, Q2, BJ_M, pk[0], pk[1]);
+    double2 sv[2][2], uv[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        sv[a][b] = S[cur][pi[a]][pk[b]];
+        uv[a][b] = U[cur][P2 + a * BJ_B][pk[b]];
+      }
     // the round's BJ_B rotations, one per thread of the first wave (forming
     // them in every thread instead costs more than this barrier)
     if (tid < BJ_B) {
       int p, q;
       round_pair(r, tid, BJ_M, p, q);
-      rot[tid] = make_rot(S[p][p].x, S[q][q].x, S[p][q]);
+      rot[tid] = make_rot(S[cur][p][p].x, S[cur][q][q].x, S[cur][p][q]);
     }
     __syncthreads();
-    // 2x2 block (P2, Q2) of S <- J^H S J (each block has one owner)
-    int pi[2], pk[2];
-    round_pair(r, P2, BJ_M, pi[0], pi[1]);
-    round_pair(r, Q2, BJ_M, pk[0], pk[1]);
     const Rot ri = rot[P2], rk = rot[Q2];
-    double2 blk[2][2];
+    double2 tr[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int a = 0; a < 2; ++a) rot_right(rk, sv[a][0], sv[a][1], tr[a][0], tr[a][1]);
+    const int nx = cur ^ 1;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        double2 s{0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const double2 ja = cconj(jent(ri, a, i));
-#pragma unroll
-          for (int b = 0; b < 2; ++b) s = cadd(s, cmul(ja, cmul(S[pi[a]][pk[b]], jent(rk, b, j))));
-        }
-        blk[i][j] = s;
-      }
-    // columns (p, q) of U <- U J: rows P2 and P2 + BJ_B of the pair Q2
-    double2 u[2][2];
+    for (int j = 0; j < 2; ++j) rot_left_adj(ri, tr[0][j], tr[1][j], S[nx][pi[0]][pk[j]], S[nx][pi[1]][pk[j]]);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int row = P2 + h * BJ_B;
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        u[h][j] = cadd(cmul(U[row][pk[0]], jent(rk, 0, j)), cmul(U[row][pk[1]], jent(rk, 1, j)));
+      rot_right(rk, uv[h][0], uv[h][1], U[nx][row][pk[0]], U[nx][row][pk[1]]);
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) S[pi[i]][pk[j]] = blk[i][j];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) U[P2 + h * BJ_B][pk[j]] = u[h][j];
-    __syncthreads();
+    cur = nx;
   }
   double2* out = Ublk + (long long)k * BJ_M * BJ_M;
-  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) out[e] = U[e / BJ_M][e % BJ_M];
+  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) out[e] = U[cur][e / BJ_M][e % BJ_M];
 }
 
 constexpr int BJ_VCOLS = 64;   // columns of V per block of the V update
+constexpr int BJ_LD = BJ_M + 1;
 
 // Round t: blocks [0, P^2) form An[rows of pair a][columns of pair b] =
 // U_a^H A U_b; the remaining blocks form the rows of pair a of Vn = (V U)^T
-// over BJ_VCOLS columns: Vn[g(i)][c] = sum_k U_a[k][i] Vt[g(k)][c].
+// over BJ_VCOLS columns: Vn[g(i)][c] = sum_k U_a[k][i] Vt[g(k)][c] (the
+// BJ_M rows of Vt staged in LDS first).
 __global__ __launch_bounds__(BJ_NT) void bj_apply_kernel(const double2* __restrict__ A, double2* __restrict__ An,
                                                          const double2* __restrict__ Vt, double2* __restrict__ Vn,
                                                          int N2, int t, const double2* __restrict__ Ublk) {
-  __shared__ double2 Ua[BJ_M][BJ_M + 1];
-  __shared__ double2 Ub[BJ_M][BJ_M + 1];
-  __shared__ double2 X[BJ_M][BJ_M + 1];
+  // A blocks: Ua, Ub, X (BJ_M x BJ_LD each); V blocks: Ua, then the staged
+  // rows of Vt (BJ_M x (BJ_VCOLS + 1))
+  __shared__ double2 sm[3 * BJ_M * BJ_LD];
+  static_assert(BJ_M * (BJ_VCOLS + 1) <= 2 * BJ_M * BJ_LD, "staged V rows fit the A-block buffers");
+  double2* Ua = sm;
+  double2* Ub = sm + BJ_M * BJ_LD;
+  double2* X = sm + 2 * BJ_M * BJ_LD;
   const int tid = threadIdx.x, nblk = N2 / BJ_B, P = nblk / 2;
   constexpr int PER = BJ_M * BJ_M / BJ_NT;
   if ((int)blockIdx.x < P * P) {
@@ -167,9 +187,9 @@ __global__ __launch_bounds__(BJ_NT) void bj_apply_kernel(const double2* __restri
     const double2* ub = Ublk + (long long)kb * BJ_M * BJ_M;
     for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) {
       const int r = e / BJ_M, c = e % BJ_M;
-      Ua[r][c] = ua[e];
-      Ub[r][c] = ub[e];
-      X[r][c] = A[(long long)bj_index(Ia, Ja, r) * N2 + bj_index(Ib, Jb, c)];
+      Ua[r * BJ_LD + c] = ua[e];
+      Ub[r * BJ_LD + c] = ub[e];
+      X[r * BJ_LD + c] = A[(long long)bj_index(Ia, Ja, r) * N2 + bj_index(Ib, Jb, c)];
     }
     __syncthreads();
     double2 tmp[PER];
@@ -178,14 +198,14 @@ __global__ __launch_bounds__(BJ_NT) void bj_apply_kernel(const double2* __restri
       const int e = tid + s * BJ_NT, r = e / BJ_M, c = e % BJ_M;
       double2 acc{0.0, 0.0};
       #pragma unroll 4
-      for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(X[r][l], Ub[l][c]));
+      for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(X[r * BJ_LD + l], Ub[l * BJ_LD + c]));
       tmp[s] = acc;
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
       const int e = tid + s * BJ_NT;
-      X[e / BJ_M][e % BJ_M] = tmp[s];
+      X[(e / BJ_M) * BJ_LD + e % BJ_M] = tmp[s];
     }
     __syncthreads();
 #pragma unroll
@@ -193,7 +213,7 @@ __global__ __launch_bounds__(BJ_NT) void bj_apply_kernel(const double2* __restri
       const int e = tid + s * BJ_NT, r = e / BJ_M, c = e % BJ_M;
       double2 acc{0.0, 0.0};
       #pragma unroll 4
-      for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(cconj(Ua[l][r]), X[l][c]));
+      for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(cconj(Ua[l * BJ_LD + r]), X[l * BJ_LD + c]));
       An[(long long)bj_index(Ia, Ja, r) * N2 + bj_index(Ib, Jb, c)] = acc;
     }
     return;
@@ -203,16 +223,21 @@ __global__ __launch_bounds__(BJ_NT) void bj_apply_kernel(const double2* __restri
   if (ka >= P) return;
   int Ia, Ja;
   round_pair(t, ka, nblk, Ia, Ja);
+  constexpr int VLD = BJ_VCOLS + 1;
+  double2* Vs = sm + BJ_M * BJ_LD;
   const double2* ua = Ublk + (long long)ka * BJ_M * BJ_M;
-  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) Ua[e / BJ_M][e % BJ_M] = ua[e];
+  for (int e = tid; e < BJ_M * BJ_M; e += BJ_NT) Ua[(e / BJ_M) * BJ_LD + e % BJ_M] = ua[e];
+  for (int e = tid; e < BJ_M * BJ_VCOLS; e += BJ_NT) {
+    const int l = e / BJ_VCOLS, cc = e % BJ_VCOLS, c = c0 + cc;
+    Vs[l * VLD + cc] = c < N2 ? Vt[(long long)bj_index(Ia, Ja, l) * N2 + c] : double2{0.0, 0.0};
+  }
   __syncthreads();
   for (int e = tid; e < BJ_M * BJ_VCOLS; e += BJ_NT) {
-    const int i = e / BJ_VCOLS, c = c0 + e % BJ_VCOLS;
-    if (c >= N2) continue;
+    const int i = e / BJ_VCOLS, cc = e % BJ_VCOLS, c = c0 + cc;
     double2 acc{0.0, 0.0};
     #pragma unroll 4
-    for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(Ua[l][i], Vt[(long long)bj_index(Ia, Ja, l) * N2 + c]));
-    Vn[(long long)bj_index(Ia, Ja, i) * N2 + c] = acc;
+    for (int l = 0; l < BJ_M; ++l) acc = cadd(acc, cmul(Ua[l * BJ_LD + i], Vs[l * VLD + cc]));
+    if (c < N2) Vn[(long long)bj_index(Ia, Ja, i) * N2 + c] = acc;
   }
 }
 

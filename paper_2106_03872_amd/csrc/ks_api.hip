@@ -702,7 +702,7 @@ ks_status orthonormalize_packed(ks_system* s, int n, double2* C, double2* Y, hip
   KS_HIP(s, hipMemsetAsync(s->ortho_info, 0, sizeof(int), st));
   if ((r = kcall(s, KS_K_GEMM, st, "overlap", [&] { return launch_overlap(n, s->npw, C, ld, s->ortho_S, s->gemm_part, s->gemm_part_bytes, st); })) != KS_OK)
     return r;
-  if ((r = launch_ok(s, launch_cholesky(n, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_cholesky(n, s->ortho_S, s->ortho_W, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(n, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
   if ((r = kcall(s, KS_K_GEMM, st, "apply", [&] { return launch_apply_lower(n, s->npw, s->ortho_W, C, ld, Y, st); })) !=
       KS_OK)
@@ -1297,7 +1297,7 @@ ks_status ks_orthonormalize(ks_system* s, int norb, void* psi, void* stream) {
   if ((r = kcall(s, KS_K_GEMM, st, "overlap",
                  [&] { return launch_overlap(norb, s->npw, P, s->npw_stride, s->ortho_S, s->gemm_part, s->gemm_part_bytes, st); })) != KS_OK)
     return r;
-  if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
+  if ((r = launch_ok(s, launch_cholesky(norb, s->ortho_S, s->ortho_W, s->ortho_diag, s->ortho_info, st), "cholesky")) != KS_OK) return r;
   if ((r = launch_ok(s, launch_trtri(norb, s->ortho_S, s->ortho_W, st), "trtri")) != KS_OK) return r;
   if ((r = kcall(s, KS_K_GEMM, st, "apply",
                  [&] { return launch_apply_lower(norb, s->npw, s->ortho_W, P, s->npw_stride, Y, st); })) != KS_OK)

@@ -281,7 +281,10 @@ bool launch_overlap(int norb, int npw, const double2* P, int ldp, double2* S, do
                     hipStream_t st);
 // bytes of split-K partials the products of up to n orbitals over K use
 size_t gemm_part_bytes(int n, int K);
-bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st);
+// S = L L^H in place (lower); the inverses of L's diagonal blocks go to the
+// same blocks of X
+bool launch_cholesky(int n, double2* S, double2* X, double* diag0, int* info, hipStream_t st);
+// X = L^-1 (lower, upper triangle zero), given the diagonal blocks from launch_cholesky
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st);
 

@@ -155,15 +155,20 @@ constexpr int CB = 32;
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) { return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ double2 zmulc(double2 a, double2 b) { return double2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
 
-// factor the diagonal block at k0 in place (lower), upper part zeroed; a
-// pivot at or below 1e-12 of the original diagonal entry sets *info (the
-// orbitals are numerically linearly dependent)
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int k0, const double* __restrict__ diag0,
-                                                         int* info) {
+constexpr int CH_NT = 256;
+
+// Factor the diagonal block at k0 in place (lower, upper part zeroed) and
+// write the inverse of the factor into the same block of X; a pivot at or
+// below 1e-12 of the original diagonal entry sets *info (the orbitals are
+// numerically linearly dependent).
+__global__ __launch_bounds__(CH_NT) void potrf_diag_kernel(double2* S, double2* X, int n, int k0,
+                                                           const double* __restrict__ diag0, int* info) {
   __shared__ double2 a[CB][CB + 1];
+  __shared__ double2 x[CB][CB + 1];
+  __shared__ double rd[CB];
   const int tid = threadIdx.x;
   const int nb = min(CB, n - k0);
-  for (int i = tid; i < CB * CB; i += 256) {
+  for (int i = tid; i < CB * CB; i += CH_NT) {
     const int r = i / CB, c = i % CB;
     a[r][c] = (r < nb && c < nb && c <= r) ? S[(long long)(k0 + r) * n + k0 + c] : double2{0.0, 0.0};
   }
@@ -175,13 +180,15 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int 
         info[0] = 1;
         d = 1.0;
       }
-      a[j][j] = double2{sqrt(d), 0.0};
+      const double sd = sqrt(d);
+      a[j][j] = double2{sd, 0.0};
+      rd[j] = 1.0 / sd;
     }
     __syncthreads();
-    const double inv = 1.0 / a[j][j].x;
-    for (int i = j + 1 + tid; i < nb; i += 256) a[i][j] = double2{a[i][j].x * inv, a[i][j].y * inv};
+    const double inv = rd[j];
+    for (int i = j + 1 + tid; i < nb; i += CH_NT) a[i][j] = double2{a[i][j].x * inv, a[i][j].y * inv};
     __syncthreads();
-    for (int t = tid; t < CB * CB; t += 256) {
+    for (int t = tid; t < CB * CB; t += CH_NT) {
       const int r = t / CB, c = t % CB;
       if (c > j && r >= c && r < nb) {
         const double2 u = zmulc(a[r][j], a[c][j]);
@@ -190,45 +197,73 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double2* S, int n, int 
     }
     __syncthreads();
   }
-  for (int i = tid; i < nb * nb; i += 256) {
+  for (int i = tid; i < nb * nb; i += CH_NT) {
     const int r = i / nb, c = i % nb;
     S[(long long)(k0 + r) * n + k0 + c] = c <= r ? a[r][c] : double2{0.0, 0.0};
   }
+  // inverse of the factor by forward substitution, column c by the eight
+  // lanes 8c .. 8c+7 of one wave: row r of column c is
+  //   x[r][c] = (delta_rc - sum_{c <= q < r} a[r][q] x[q][c]) / a[r][r],
+  // the sum split over the lanes by q mod 8 and added by a fixed butterfly
+  const int c = tid >> 3, part = tid & 7;
+  for (int r = 0; r < nb; ++r) {
+    double sx = 0.0, sy = 0.0;
+    for (int q = c + part; q < r; q += 8) {
+      const double2 u = zmul(a[r][q], x[q][c]);
+      sx += u.x;
+      sy += u.y;
+    }
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+      sx += __shfl_xor(sx, m, 64);
+      sy += __shfl_xor(sy, m, 64);
+    }
+    if (part == 0 && c < nb)
+      x[r][c] = r < c ? double2{0.0, 0.0} : double2{((r == c ? 1.0 : 0.0) - sx) * rd[r], -sy * rd[r]};
+  }
+  __syncthreads();
+  for (int i = tid; i < nb * nb; i += CH_NT) {
+    const int r = i / nb, cc = i % nb;
+    X[(long long)(k0 + r) * n + k0 + cc] = x[r][cc];
+  }
 }
 
-// rows below the diagonal block: L_rk = A_rk L_kk^-H (one thread per row,
-// rows staged in LDS and solved in place)
-__global__ __launch_bounds__(64) void trsm_panel_kernel(double2* S, int n, int k0) {
-  __shared__ double2 l[CB][CB + 1];
-  __shared__ double2 x[64][CB + 1];
+// Rows below the diagonal block: L_rk = A_rk L_kk^-H, a product with the
+// inverted diagonal block (Xkk = L_kk^-1, lower):
+//   L_rk[r][c] = sum_{q <= c} A_rk[r][q] conj(Xkk[c][q]).
+// Block of 64 rows; thread (column c, rows r0 + 8 s).
+__global__ __launch_bounds__(256) void trsm_panel_kernel(double2* S, const double2* __restrict__ X, int n, int k0) {
+  __shared__ double2 xk[CB][CB + 1];
+  __shared__ double2 ar[64][CB + 1];
   const int nb = min(CB, n - k0);
   const int tid = threadIdx.x;
   const int rb = k0 + nb + blockIdx.x * 64;
-  for (int i = tid; i < CB * CB; i += 64) {
+  for (int i = tid; i < CB * CB; i += 256) {
     const int r = i / CB, c = i % CB;
-    l[r][c] = (r < nb && c < nb) ? S[(long long)(k0 + r) * n + k0 + c] : double2{0.0, 0.0};
+    xk[r][c] = (r < nb && c < nb) ? X[(long long)(k0 + r) * n + k0 + c] : double2{0.0, 0.0};
   }
-  for (int i = tid; i < 64 * CB; i += 64) {
+  for (int i = tid; i < 64 * CB; i += 256) {
     const int r = i / CB, c = i % CB;
-    x[r][c] = (rb + r < n && c < nb) ? S[(long long)(rb + r) * n + k0 + c] : double2{0.0, 0.0};
+    ar[r][c] = (rb + r < n && c < nb) ? S[(long long)(rb + r) * n + k0 + c] : double2{0.0, 0.0};
   }
   __syncthreads();
-  if (rb + tid < n) {
-    for (int j = 0; j < nb; ++j) {
-      double2 v = x[tid][j];
-      for (int m = 0; m < j; ++m) {
-        const double2 u = zmulc(x[tid][m], l[j][m]);
-        v.x -= u.x;
-        v.y -= u.y;
-      }
-      const double inv = 1.0 / l[j][j].x;
-      x[tid][j] = double2{v.x * inv, v.y * inv};
+  const int c = tid % CB, r0 = tid / CB;
+  double2 acc[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) acc[s] = double2{0.0, 0.0};
+  for (int q = 0; q <= c; ++q) {
+    const double2 xv = xk[c][q];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const double2 u = zmulc(ar[r0 + 8 * s][q], xv);
+      acc[s].x += u.x;
+      acc[s].y += u.y;
     }
   }
-  __syncthreads();
-  for (int i = tid; i < 64 * CB; i += 64) {
-    const int r = i / CB, c = i % CB;
-    if (rb + r < n && c < nb) S[(long long)(rb + r) * n + k0 + c] = x[r][c];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int r = r0 + 8 * s;
+    if (rb + r < n && c < nb) S[(long long)(rb + r) * n + k0 + c] = acc[s];
   }
 }
 
@@ -262,59 +297,64 @@ __global__ __launch_bounds__(256) void herk_update_kernel(double2* S, int n, int
 }
 
 // ------------------------------------------------------- blocked lower inverse
-// Block row I of X = L^-1 for all block columns J <= I (one block per J):
-//   X_II = L_II^-1,   X_IJ = -L_II^-1 sum_{K=J}^{I-1} L_IK X_KJ.
-// The right-hand side is accumulated from LDS tiles; then each of 32 threads
-// solves one column by forward substitution with L_II, in place.
-__global__ __launch_bounds__(256) void trtri_row_kernel(const double2* __restrict__ L, double2* __restrict__ X, int n,
-                                                        int I) {
-  __shared__ double2 lii[CB][CB + 1], lik[CB][CB + 1], xkj[CB][CB + 1], t[CB][CB + 1];
-  const int J = blockIdx.x, tid = threadIdx.x;
-  const int r0 = I * CB, c0 = J * CB;
-  const int nr = min(CB, n - r0), ncl = min(CB, n - c0);
-  for (int i = tid; i < CB * CB; i += 256) {
-    const int r = i / CB, c = i % CB;
-    lii[r][c] = (r < nr && c < nr) ? L[(long long)(r0 + r) * n + r0 + c] : double2{0.0, 0.0};
-    t[r][c] = double2{(J == I && r == c) ? 1.0 : 0.0, 0.0};
-  }
-  for (int K = J; K < I; ++K) {
-    const int k0 = K * CB;
+// X = L^-1 from the inverses of L's diagonal blocks (written by the
+// factorisation) by merging groups of w blocks pairwise, w = 1, 2, 4, ...:
+// for the top group t and the bottom group b of a pair,
+//   X_bt = -X_bb L_bt X_tt,
+// in two stages through T = L_bt X_tt, which is kept transposed in the
+// pair's strict upper block of X (cleared at the end).  Block (tile (ti, tj)
+// of the pair's w x w tiles, pair); X_tt and X_bb are read as lower
+// triangular, so the scratch in the upper triangle is never read as X.
+template <int STAGE>
+__global__ __launch_bounds__(256) void trinv_level_kernel(const double2* __restrict__ L, double2* __restrict__ X, int n,
+                                                          int w) {
+  __shared__ double2 ta[CB][CB + 1], tb[CB][CB + 1];
+  const int nbk = (n + CB - 1) / CB;
+  const int top0 = blockIdx.y * 2 * w, bot0 = top0 + w;
+  const int wb = min(w, nbk - bot0);
+  const int ti = blockIdx.x / w, tj = blockIdx.x % w;
+  if (wb <= 0 || ti >= wb) return;
+  const int tid = threadIdx.x, c = tid % CB, r0 = tid / CB;
+  double2 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = double2{0.0, 0.0};
+  const int kbeg = STAGE == 0 ? tj : 0, kend = STAGE == 0 ? w : ti + 1;
+  for (int kk = kbeg; kk < kend; ++kk) {
     __syncthreads();
-    for (int i = tid; i < CB * CB; i += 256) {
-      const int r = i / CB, c = i % CB;
-      lik[r][c] = (r < nr) ? L[(long long)(r0 + r) * n + k0 + c] : double2{0.0, 0.0};
-      xkj[r][c] = (c < ncl) ? X[(long long)(k0 + r) * n + c0 + c] : double2{0.0, 0.0};
+    for (int e = tid; e < CB * CB; e += 256) {
+      const int r = e / CB, q = e % CB;
+      if (STAGE == 0) {
+        // T(ti, tj) = sum_kk L(b_ti, t_kk) X(t_kk, t_tj)
+        const int lr = (bot0 + ti) * CB + r, lc = (top0 + kk) * CB + q;
+        ta[r][q] = (lr < n && lc < n) ? L[(long long)lr * n + lc] : double2{0.0, 0.0};
+        const int xr = (top0 + kk) * CB + r, xc = (top0 + tj) * CB + q;
+        tb[r][q] = (xr < n && xc < n && xc <= xr) ? X[(long long)xr * n + xc] : double2{0.0, 0.0};
+      } else {
+        // X(b_ti, t_tj) = - sum_kk X(b_ti, b_kk) T(kk, tj); T[i][j] sits at X[j][i]
+        const int xr = (bot0 + ti) * CB + r, xc = (bot0 + kk) * CB + q;
+        ta[r][q] = (xr < n && xc < n && xc <= xr) ? X[(long long)xr * n + xc] : double2{0.0, 0.0};
+        const int tr = (bot0 + kk) * CB + q, tc = (top0 + tj) * CB + r;   // tb[q][r] = T[tr][tc]
+        tb[q][r] = (tr < n && tc < n) ? X[(long long)tc * n + tr] : double2{0.0, 0.0};
+      }
     }
     __syncthreads();
-    for (int i = tid; i < CB * CB; i += 256) {
-      const int r = i / CB, c = i % CB;
-      double sx = 0.0, sy = 0.0;
-      for (int m = 0; m < CB; ++m) {
-        const double2 u = zmul(lik[r][m], xkj[m][c]);
-        sx += u.x;
-        sy += u.y;
+    for (int m = 0; m < CB; ++m) {
+      const double2 bv = tb[m][c];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double2 u = zmul(ta[r0 + 8 * s][m], bv);
+        acc[s].x += u.x;
+        acc[s].y += u.y;
       }
-      t[r][c] = double2{t[r][c].x - sx, t[r][c].y - sy};
     }
   }
-  __syncthreads();
-  if (tid < ncl) {
-    const int c = tid;
-    for (int r = 0; r < nr; ++r) {
-      double2 v = t[r][c];
-      for (int m = 0; m < r; ++m) {
-        const double2 u = zmul(lii[r][m], t[m][c]);
-        v.x -= u.x;
-        v.y -= u.y;
-      }
-      const double inv = 1.0 / lii[r][r].x;
-      t[r][c] = double2{v.x * inv, v.y * inv};
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < CB * CB; i += 256) {
-    const int r = i / CB, c = i % CB;
-    if (r < nr && c < ncl) X[(long long)(r0 + r) * n + c0 + c] = t[r][c];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int r = r0 + 8 * s;
+    const int gi = (bot0 + ti) * CB + r, gj = (top0 + tj) * CB + c;
+    if (gi >= n || gj >= n) continue;
+    if (STAGE == 0) X[(long long)gj * n + gi] = acc[s];
+    else X[(long long)gi * n + gj] = double2{-acc[s].x, -acc[s].y};
   }
 }
 
@@ -398,13 +438,13 @@ __global__ void save_diag_kernel(const double2* __restrict__ S, int n, double* _
   if (i < n) d[i] = S[(long long)i * n + i].x;
 }
 
-bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st) {
+bool launch_cholesky(int n, double2* S, double2* X, double* diag0, int* info, hipStream_t st) {
   save_diag_kernel<<<(n + 255) / 256, 256, 0, st>>>(S, n, diag0);
   for (int k0 = 0; k0 < n; k0 += CB) {
-    potrf_diag_kernel<<<1, 256, 0, st>>>(S, n, k0, diag0, info);
+    potrf_diag_kernel<<<1, CH_NT, 0, st>>>(S, X, n, k0, diag0, info);
     const int rest = n - k0 - min(CB, n - k0);
     if (rest > 0) {
-      trsm_panel_kernel<<<(rest + 63) / 64, 64, 0, st>>>(S, n, k0);
+      trsm_panel_kernel<<<(rest + 63) / 64, 256, 0, st>>>(S, X, n, k0);
       const int nt = (rest + CB - 1) / CB;
       herk_update_kernel<<<dim3(nt, nt), 256, 0, st>>>(S, n, k0);
     }
@@ -414,8 +454,12 @@ bool launch_cholesky(int n, double2* S, double* diag0, int* info, hipStream_t st
 
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st) {
   const int nbk = (n + CB - 1) / CB;
+  for (int w = 1; w < nbk; w *= 2) {
+    const dim3 grid(w * w, (nbk + 2 * w - 1) / (2 * w));
+    trinv_level_kernel<0><<<grid, 256, 0, st>>>(L, X, n, w);
+    trinv_level_kernel<1><<<grid, 256, 0, st>>>(L, X, n, w);
+  }
   zero_upper_kernel<<<(unsigned)(((long long)n * n + 255) / 256), 256, 0, st>>>(X, n);
-  for (int I = 0; I < nbk; ++I) trtri_row_kernel<<<I + 1, 256, 0, st>>>(L, X, n, I);
   return true;
 }
 

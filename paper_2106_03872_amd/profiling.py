@@ -1,0 +1,176 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+  python -m paper_2106_03872_amd.profiling stats <kernel_stats.csv> [--top N]
+      markdown table of a --kernel-trace --stats run (per kernel: calls,
+      total and average time, share)
+  python -m paper_2106_03872_amd.profiling traffic <fetch_dir> <write_dir> <out.json> --orbitals N [--workload W]
+      HBM bytes per launch of each pass from a --pmc FETCH_SIZE run and a
+      --pmc WRITE_SIZE run of the benchmark, scaled by what the counters read
+      for the plain device copy the benchmark adds with --copy-calibration
+  python -m paper_2106_03872_amd.profiling counters <dir> [<dir> ...]
+      markdown table of per-dispatch SQ counters (mean over the dispatches of
+      each kernel's most frequent launch shape)
+
+Each pass is keyed by its class (xapply, xproj, ...); the launch counted is
+the (kernel, grid) pair with the most dispatches, which in a benchmark run is
+the tuned schedule of the timed steps (the autotuner times each candidate
+three times, the timed steps run it more often).  The calibration copy is
+the largest device copy of the run (by counter value).
+"""
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CLASSES = ("plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dens_sum", "dots", "unpack",
+           "pack_kernel", "bj_solve", "bj_apply", "zgemm", "potrf", "trsm", "trinv", "herk", "sd_direction", "sd_update")
+COPY_KIB = 1048576.0   # the calibration copy moves 1 GiB each way
+
+
+def csrc_fingerprint():
+    """sha256 over the library's kernel and runtime sources (csrc/, sorted)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2106_03872_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def short_name(name):
+    """Kernel name without namespaces, argument list and vector type noise."""
+    n = re.sub(r"\(.*\)$", "", name)
+    n = n.replace("void ", "").replace("ks::", "").replace("(anonymous namespace)::", "")
+    n = n.replace("HIP_vector_type<double, 2u>", "double2").replace("HIP_vector_type<float, 2u>", "float2")
+    return n
+
+
+def kernel_class(name):
+    for k in CLASSES:
+        if k in name:
+            return k.replace("_kernel", "")
+    if "copyBuffer" in name:
+        return "copy"
+    return None
+
+
+def stats_table(path, top=20):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def _counter_rows(d, counter=None):
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if counter is None or r.get("Counter_Name") == counter:
+                    rows.append(r)
+    return rows
+
+
+def _grid(r):
+    return int(float(r.get("Grid_Size", r.get("grid_size", 0)) or 0))
+
+
+def per_launch(rows):
+    """class -> (kernel name, grid, dispatches, mean counter value) for the
+    (name, grid) pair of the class with the most dispatches."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in rows:
+        k = kernel_class(r["Kernel_Name"])
+        if k is not None:
+            acc[k][(r["Kernel_Name"], _grid(r))].append(float(r["Counter_Value"]))
+    out = {}
+    for k, groups in acc.items():
+        if k == "copy":
+            # the calibration copy: the copy dispatches within a factor two
+            # of the largest count (the small copies of the run share its grid)
+            top = max(max(v) for v in groups.values())
+            (name, grid), v = max(groups.items(), key=lambda kv: max(kv[1]))
+            v = [x for x in v if x >= 0.5 * top]
+        else:
+            (name, grid), v = max(groups.items(), key=lambda kv: (len(kv[1]), kv[0][1]))
+        out[k] = (name, grid, len(v), sum(v) / len(v))
+    return out
+
+
+def traffic_record(fetch_dir, write_dir, orbitals, workload):
+    F = per_launch(_counter_rows(fetch_dir, "FETCH_SIZE"))
+    W = per_launch(_counter_rows(write_dir, "WRITE_SIZE"))
+    fs = COPY_KIB / F["copy"][3] if "copy" in F else None
+    ws = COPY_KIB / W["copy"][3] if "copy" in W else None
+    if fs is None or ws is None:
+        raise SystemExit("the runs hold no calibration copy (run the benchmark with --copy-calibration)")
+    rec = {"workload": workload, "orbitals_per_pass": orbitals, "csrc_sha256": csrc_fingerprint(),
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "kernels": {}}
+    for k in sorted(set(F) & set(W)):
+        if k == "copy":
+            continue
+        name, grid, n, fk = F[k]
+        wk = W[k][3]
+        rec["kernels"][k] = {"kernel": short_name(name), "grid": grid, "dispatches": n, "fetch_kib": round(fk, 1),
+                             "write_kib": round(wk, 1), "bytes_per_launch": int(round((fk * fs + wk * ws) * 1024))}
+    return rec
+
+
+def counters_table(dirs):
+    rows = []
+    for d in dirs:
+        rows += _counter_rows(d)
+    names = sorted({r["Counter_Name"] for r in rows})
+    by = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(list)))
+    for r in rows:
+        k = kernel_class(r["Kernel_Name"])
+        if k is not None and k != "copy":
+            by[k][(r["Kernel_Name"], _grid(r))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = ["| kernel | grid | " + " | ".join(names) + " |", "|---|---:|" + "---:|" * len(names)]
+    for k in sorted(by):
+        (name, grid), cs = max(by[k].items(), key=lambda kv: (max(len(v) for v in kv[1].values()), kv[0][1]))
+        vals = []
+        for c in names:
+            v = cs.get(c)
+            vals.append(f"{sum(v) / len(v):.4g}" if v else "")
+        out.append(f"| `{short_name(name)}` | {grid} | " + " | ".join(vals) + " |")
+    return "\n".join(out)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--top", type=int, default=20)
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("out")
+    b.add_argument("--orbitals", type=int, required=True)
+    b.add_argument("--workload", default="cfg3_96")
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    args = ap.parse_args(argv)
+    if args.cmd == "stats":
+        print(stats_table(args.csv, args.top))
+    elif args.cmd == "traffic":
+        rec = traffic_record(args.fetch_dir, args.write_dir, args.orbitals, args.workload)
+        with open(args.out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec, indent=1))
+    else:
+        print(counters_table(args.dirs))
+
+
+if __name__ == "__main__":
+    main()
