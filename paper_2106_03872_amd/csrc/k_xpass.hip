@@ -23,12 +23,19 @@ struct TLoader {
   }
 };
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
-  return x;
+// x from another lane of the same row of 16 by the DPP permutation CTRL
+// (quad_perm, row_half_mirror, row_mirror: every source lane is in the row)
+template <int CTRL>
+__device__ __forceinline__ double dpp_lane(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
+constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
 
 // Orbital groups: block (tile, y) handles the orbitals [y*nb/ng, (y+1)*nb/ng)
 // of its tile in order (ng = gridDim.y).  The next orbital's T is loaded into
@@ -141,9 +148,32 @@ __global__ __launch_bounds__(SH::XT) void xproj_kernel(const cplx<R>* __restrict
       sx += bv * double(x.x);
       sy += bv * double(x.y);
     }
-    for (int m = 1; m < (1 << KB_MAX_GROUP_LOG); m <<= 1) {
-      const double vx = __shfl_xor(sx, m, 64), vy = __shfl_xor(sy, m, 64);
-      if (m < glanes) {
+    // the group's lanes add their sums by a fixed butterfly (the partners of
+    // stage m: lane pairs of a quad, then quads, then mirrored halves of 8 and
+    // of 16 lanes; after stage m every lane of an aligned 2m-lane block holds
+    // the block's sum, as with lane index xor m)
+    static_assert(KB_MAX_GROUP_LOG == 4, "four butterfly stages");
+    {
+      double vx = dpp_lane<DPP_QUAD_XOR1>(sx), vy = dpp_lane<DPP_QUAD_XOR1>(sy);
+      if (glanes > 1) {
+        sx += vx;
+        sy += vy;
+      }
+      vx = dpp_lane<DPP_QUAD_XOR2>(sx);
+      vy = dpp_lane<DPP_QUAD_XOR2>(sy);
+      if (glanes > 2) {
+        sx += vx;
+        sy += vy;
+      }
+      vx = dpp_lane<DPP_HALF_MIRROR>(sx);
+      vy = dpp_lane<DPP_HALF_MIRROR>(sy);
+      if (glanes > 4) {
+        sx += vx;
+        sy += vy;
+      }
+      vx = dpp_lane<DPP_MIRROR>(sx);
+      vy = dpp_lane<DPP_MIRROR>(sy);
+      if (glanes > 8) {
         sx += vx;
         sy += vy;
       }
