@@ -68,6 +68,26 @@ def alg_bytes(info, spec, kernel, S=16):
     return 0, 0
 
 
+def plain_copy_bandwidth(reps=5):
+    """Read + write GB/s of a plain 1 GiB device copy (torch), timed with
+    events after one untimed copy; its dispatches also calibrate the HBM
+    traffic counters."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2.0 * (1 << 30) / (ms * 1e-3) / 1e9, 1)
+
+
 def measured_traffic(kernel, workload, orbitals_per_pass, info):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (rocprofv3 FETCH_SIZE and WRITE_SIZE runs, scaled by the copy-kernel
@@ -366,8 +386,6 @@ def main():
                     help="also run the trace with a budget the whole trace fits in (0: skip)")
     ap.add_argument("--serving-compare", action="store_true",
                     help="also run the trace with one captured graph per request")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -458,14 +476,9 @@ def main():
                 "step_latency_ms_p50", "step_latency_ms_p99", "time_to_first_step_ms_p50",
                 "time_to_first_step_ms_p99", "orbital_hpsi_per_s", "makespan_s", "max_resident_requests")}
 
-    if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
-        a.fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+    # a plain 1 GiB device copy: the reference kernel of the HBM traffic
+    # counters, and the read + write bandwidth a streaming kernel reaches
+    roof["plain_copy_GBs"] = plain_copy_bandwidth()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -99,13 +99,11 @@ __device__ __forceinline__ int bj_index(int I, int J, int l) { return l < BJ_B ?
 // Block k of round t: one cyclic sweep on the sub-problem of block pair k;
 // its unitary goes to Ublk[k] (row-major BJ_M x BJ_M).  S and U are kept in
 // two LDS copies: inner round r reads one and writes the other (every entry
-// is rewritten), so a round has two barriers (rotations formed; update
-// done).
+// is rewritten), so a round needs one barrier.
 __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restrict__ A, int N2, int t,
                                                          double2* __restrict__ Ublk) {
   __shared__ double2 S[2][BJ_M][BJ_M + 1];
   __shared__ double2 U[2][BJ_M][BJ_M + 1];
-  __shared__ Rot rot[BJ_B];
   const int k = blockIdx.x, tid = threadIdx.x;
   int I, J;
   round_pair(t, k, N2 / BJ_B, I, J);
@@ -132,15 +130,10 @@ __global__ __launch_bounds__(BJ_NT) void bj_solve_kernel(const double2* __restri
         sv[a][b] = S[cur][pi[a]][pk[b]];
         uv[a][b] = U[cur][P2 + a * BJ_B][pk[b]];
       }
-    // the round's BJ_B rotations, one per thread of the first wave (forming
-    // them in every thread instead costs more than this barrier)
-    if (tid < BJ_B) {
-      int p, q;
-      round_pair(r, tid, BJ_M, p, q);
-      rot[tid] = make_rot(S[cur][p][p].x, S[cur][q][q].x, S[cur][p][q]);
-    }
-    __syncthreads();
-    const Rot ri = rot[P2], rk = rot[Q2];
+    // every thread forms the two rotations it applies (of its row pair and
+    // its column pair) from the current copy, so no barrier publishes them
+    const Rot ri = make_rot(S[cur][pi[0]][pi[0]].x, S[cur][pi[1]][pi[1]].x, S[cur][pi[0]][pi[1]]);
+    const Rot rk = make_rot(S[cur][pk[0]][pk[0]].x, S[cur][pk[1]][pk[1]].x, S[cur][pk[0]][pk[1]]);
     double2 tr[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) rot_right(rk, sv[a][0], sv[a][1], tr[a][0], tr[a][1]);

@@ -6,7 +6,7 @@
   python -m paper_2106_03872_amd.profiling traffic <fetch_dir> <write_dir> <out.json> --orbitals N [--workload W]
       HBM bytes per launch of each pass from a --pmc FETCH_SIZE run and a
       --pmc WRITE_SIZE run of the benchmark, scaled by what the counters read
-      for the plain device copy the benchmark adds with --copy-calibration
+      for the plain 1 GiB device copy every benchmark run times
   python -m paper_2106_03872_amd.profiling counters <dir> [<dir> ...]
       markdown table of per-dispatch SQ counters (mean over the dispatches of
       each kernel's most frequent launch shape)
@@ -112,7 +112,7 @@ def traffic_record(fetch_dir, write_dir, orbitals, workload):
     fs = COPY_KIB / F["copy"][3] if "copy" in F else None
     ws = COPY_KIB / W["copy"][3] if "copy" in W else None
     if fs is None or ws is None:
-        raise SystemExit("the runs hold no calibration copy (run the benchmark with --copy-calibration)")
+        raise SystemExit("the runs hold no calibration copy (a 1 GiB device copy)")
     rec = {"workload": workload, "orbitals_per_pass": orbitals, "csrc_sha256": csrc_fingerprint(),
            "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "kernels": {}}
     for k in sorted(set(F) & set(W)):
