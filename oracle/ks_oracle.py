@@ -38,6 +38,10 @@ or reordering:
   preconditioned steepest descent (Teter preconditioner in Fourier space)
   with subspace diagonalisation and Cholesky orthogonalisation, for a static
   Hamiltonian.
+* The exchange-correlation potential ``v_xc[n]`` of Eq. hamiltonian in the
+  local-density approximation (Slater exchange, Perdew-Zunger 1981
+  correlation of the uniform gas), as an option of the density-dependent
+  potential.
 * The ETRS propagator (Eq. etrs, with the predictor of Eq. etrs0) whose two
   exponentials of ``H(t)`` share the powers ``H(t)^k c`` (the shared-lambda
   evaluation of the truncated Taylor series in Section "Real-time
@@ -235,16 +239,80 @@ def hartree(grid, n):
     return scipy.fft.ifftn(vG, norm="forward", workers=WORKERS).real
 
 
-def with_density(ham, n):
-    """The Hamiltonian of ``ham`` with local potential ``V_loc + V_H[n]``."""
-    h = Hamiltonian(ham.grid, ham.vloc + hartree(ham.grid, n))
+# Perdew-Zunger (1981) parametrisation of the correlation energy per
+# electron of the unpolarised uniform electron gas, eps_c(rs):
+#   rs >= 1: gamma / (1 + beta1 sqrt(rs) + beta2 rs)
+#   rs < 1:  A ln rs + B + C rs ln rs + D rs
+PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334
+PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116
+
+
+def _rs(n):
+    """Wigner-Seitz radius ``rs = (3 / (4 pi n))^(1/3)`` (n > 0)."""
+    return np.cbrt(3.0 / (4.0 * np.pi * n))
+
+
+def lda_exchange(n):
+    """Slater exchange of the uniform gas: ``eps_x = -(3/4) (3 n / pi)^(1/3)``
+    per electron and ``v_x = d(n eps_x)/dn = (4/3) eps_x``; zero where
+    ``n <= 0``.  Returns ``(v_x, eps_x)``."""
+    n = np.asarray(n, np.float64)
+    pos = n > 0
+    e = np.zeros_like(n)
+    e[pos] = -0.75 * np.cbrt(3.0 * n[pos] / np.pi)
+    return 4.0 / 3.0 * e, e
+
+
+def lda_correlation(n):
+    """Perdew-Zunger correlation: ``eps_c(rs)`` from the two branches above
+    and ``v_c = d(n eps_c)/dn = eps_c - (rs/3) d eps_c/d rs``, i.e.
+      rs >= 1: eps_c (1 + 7/6 beta1 sqrt(rs) + 4/3 beta2 rs) / (1 + beta1 sqrt(rs) + beta2 rs)
+      rs < 1:  A ln rs + (B - A/3) + 2/3 C rs ln rs + (2 D - C) rs / 3;
+    zero where ``n <= 0``.  Returns ``(v_c, eps_c)``."""
+    n = np.asarray(n, np.float64)
+    v = np.zeros_like(n)
+    e = np.zeros_like(n)
+    pos = n > 0
+    rs = _rs(n[pos])
+    hi = rs >= 1.0
+    ev = np.empty_like(rs)
+    vv = np.empty_like(rs)
+    s = np.sqrt(rs[hi])
+    q = 1.0 + PZ_BETA1 * s + PZ_BETA2 * rs[hi]
+    ev[hi] = PZ_GAMMA / q
+    vv[hi] = ev[hi] * (1.0 + 7.0 / 6.0 * PZ_BETA1 * s + 4.0 / 3.0 * PZ_BETA2 * rs[hi]) / q
+    r = rs[~hi]
+    lr = np.log(r)
+    ev[~hi] = PZ_A * lr + PZ_B + PZ_C * r * lr + PZ_D * r
+    vv[~hi] = PZ_A * lr + (PZ_B - PZ_A / 3.0) + 2.0 / 3.0 * PZ_C * r * lr + (2.0 * PZ_D - PZ_C) * r / 3.0
+    v[pos], e[pos] = vv, ev
+    return v, e
+
+
+def lda_xc(n):
+    """Local-density exchange-correlation potential ``v_xc[n]`` of
+    Eq. hamiltonian (Slater exchange + Perdew-Zunger correlation, spin
+    unpolarised) and the energy per electron; returns ``(v_xc, eps_xc)``."""
+    vx, ex = lda_exchange(n)
+    vc, ec = lda_correlation(n)
+    return vx + vc, ex + ec
+
+
+def with_density(ham, n, xc=False):
+    """The Hamiltonian of ``ham`` with local potential ``V_loc + V_H[n]``
+    (``+ v_xc[n]`` in the local-density form when ``xc``)."""
+    v = ham.vloc + hartree(ham.grid, n)
+    if xc:
+        v = v + lda_xc(n)[0]
+    h = Hamiltonian(ham.grid, v)
     h.atoms, h.d = ham.atoms, ham.d
     return h
 
 
-def etrs_step(ham, c, dt, occ, nsteps=1):
+def etrs_step(ham, c, dt, occ, nsteps=1, xc=False):
     """``nsteps`` ETRS steps (Eq. etrs) of the orbitals ``c`` under
-    ``H[n] = K + V_loc + V_H[n] + V_nl`` (``ham`` holds ``V_loc``).
+    ``H[n] = K + V_loc + V_H[n] + V_nl`` (``+ v_xc[n]`` when ``xc``; ``ham``
+    holds ``V_loc``).
 
     One step from ``c(t)``:
       1. ``H(t) = H[n(c(t))]``;
@@ -259,7 +327,7 @@ def etrs_step(ham, c, dt, occ, nsteps=1):
     cur = np.where(ham.grid.chi, np.asarray(c, np.complex128), 0.0)
     dens = []
     for _ in range(nsteps):
-        h_t = with_density(ham, density(ham, cur, occ))
+        h_t = with_density(ham, density(ham, cur, occ), xc)
         w = cur
         half = cur.copy()
         full = cur.copy()
@@ -267,7 +335,7 @@ def etrs_step(ham, c, dt, occ, nsteps=1):
             w = ham_apply(h_t, w)
             half = half + ah[k] * w
             full = full + af[k] * w
-        h_next = with_density(ham, density(ham, full, occ))
+        h_next = with_density(ham, density(ham, full, occ), xc)
         cur = taylor4_step(h_next, half, 0.5 * dt, 1)
         dens.append(density(ham, cur, occ))
     return cur, dens

@@ -464,6 +464,92 @@ def test_etrs_second_order_with_hartree():
     assert np.linalg.norm(free - outs[1]) > 100 * d1
 
 
+# ------------------------------------------ local-density exchange-correlation
+
+def test_lda_exchange_closed_form():
+    # Slater exchange per electron -0.4581652.../rs with the constant
+    # (3/4)(9/(4 pi^2))^(1/3) (a different route from -(3/4)(3n/pi)^(1/3)),
+    # and v_x / eps_x = 4/3 exactly; nothing where there is no density
+    n = np.array([1e-7, 1e-3, 0.2, 3.0, 40.0])
+    vx, ex = ko.lda_exchange(n)
+    rs = (3.0 / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    coef = 0.75 * (9.0 / (4.0 * np.pi ** 2)) ** (1.0 / 3.0)
+    assert abs(coef - 0.4581652932831429) < 1e-15
+    np.testing.assert_allclose(ex, -coef / rs, rtol=1e-13)
+    np.testing.assert_allclose(vx / ex, 4.0 / 3.0, rtol=1e-15)
+    v, e = ko.lda_xc(np.array([0.0, -1e-3]))
+    assert np.all(v == 0.0) and np.all(e == 0.0)
+
+
+@pytest.mark.parametrize("part", ["exchange", "correlation"])
+def test_lda_potentials_are_energy_derivatives(part):
+    # v = d(n eps)/dn, checked by a fourth-order central difference at
+    # densities on both Perdew-Zunger branches (rs from 0.2 to 20, away from
+    # the branch point rs = 1); catches a wrong factor in either potential
+    f = ko.lda_exchange if part == "exchange" else ko.lda_correlation
+    for rs in (0.2, 0.6, 0.95, 1.05, 2.0, 6.0, 20.0):
+        n0 = 3.0 / (4.0 * np.pi * rs ** 3)
+        h = 1e-3 * n0
+        F = lambda n: n * f(np.array([n]))[1][0]
+        d = (-F(n0 + 2 * h) + 8 * F(n0 + h) - 8 * F(n0 - h) + F(n0 - 2 * h)) / (12 * h)
+        v = f(np.array([n0]))[0][0]
+        assert abs(d - v) < 1e-9 * abs(v), (rs, d, v)
+
+
+def test_pz_correlation_branches_meet_and_high_density_limit():
+    # the two branches of the fit agree at rs = 1 to the precision of its
+    # published coefficients (energy and potential)
+    n1 = 3.0 / (4.0 * np.pi)
+    v_in, e_in = ko.lda_correlation(np.array([n1 * (1 + 1e-9)]))    # rs just below 1
+    v_out, e_out = ko.lda_correlation(np.array([n1 * (1 - 1e-9)]))  # rs just above 1
+    assert abs(e_in[0] - e_out[0]) < 5e-5 and abs(v_in[0] - v_out[0]) < 5e-5
+    assert -0.07 < v_out[0] < e_out[0] < -0.05
+    # high density: eps_c -> A ln rs + B with the Gell-Mann-Brueckner slope
+    # A = (1 - ln 2) / pi^2
+    rs = np.array([1e-6, 1e-5])
+    e = ko.lda_correlation(3.0 / (4.0 * np.pi * rs ** 3))[1]
+    slope = (e[1] - e[0]) / (np.log(rs[1]) - np.log(rs[0]))
+    assert abs(slope - (1.0 - np.log(2.0)) / np.pi ** 2) < 5e-5
+
+
+def test_etrs_free_electron_with_xc_closed_form():
+    # one plane wave: uniform density n, V_H = 0 and v_xc(n) a constant, so
+    # each step is T4(-i (lam + v_xc) dt/2)^2 on the coefficient
+    g = ko.Grid((8, 6, 10), (5.0, 4.0, 6.0), 0.0)
+    ham = ko.Hamiltonian(g, np.zeros(g.n))
+    c = np.zeros((1,) + g.n, complex)
+    c[0, 1, 2, 3] = 0.7 - 0.2j
+    occ = np.array([2.0])
+    nu = 2.0 * abs(c[0, 1, 2, 3]) ** 2 / g.omega
+    vxc = ko.lda_xc(np.array([nu]))[0][0]
+    lam = g.K[1, 2, 3] + vxc
+    dt, ns = 0.3 / abs(lam), 3
+    out, dens = ko.etrs_step(ham, c, dt, occ, nsteps=ns, xc=True)
+    expect = c * _t4(-1j * lam * dt / 2) ** (2 * ns)
+    np.testing.assert_allclose(out, expect, atol=1e-14)
+    # the xc term acts: without it the phase differs
+    plain = ko.etrs_step(ham, c, dt, occ, nsteps=ns)[0]
+    assert np.abs(plain - out).max() > 1e-3
+
+
+def test_etrs_second_order_with_hartree_and_xc():
+    # as with the Hartree term alone: second order in dt at fixed final time
+    n, L = (6, 6, 6), (6.0, 6.0, 6.0)
+    g = ko.Grid(n, L, 2.0)
+    x = np.arange(n[0]) * L[0] / n[0]
+    ham = ko.Hamiltonian(g, 0.2 * np.cos(2 * np.pi * x / L[0])[:, None, None] * np.ones(n))
+    c = np.where(g.chi, _rand_c(_rng(45), (2,) + n), 0)
+    c = c / np.sqrt(np.sum(np.abs(c) ** 2, axis=(1, 2, 3)))[:, None, None, None]
+    occ = np.array([10.0, 10.0])
+    T = 1.0
+    outs = [ko.etrs_step(ham, c, T / k, occ, nsteps=k, xc=True)[0] for k in (4, 8, 16)]
+    d1 = np.linalg.norm(outs[0] - outs[1])
+    d2 = np.linalg.norm(outs[1] - outs[2])
+    assert 3.6 < d1 / d2 < 4.4
+    plain = ko.etrs_step(ham, c, T / 8, occ, nsteps=8)[0]
+    assert np.linalg.norm(plain - outs[1]) > 100 * d1
+
+
 # ------------------------------------------------- kick and dipole (NEXT-3)
 
 def test_kick_commensurate_is_index_shift():
