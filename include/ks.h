@@ -189,6 +189,32 @@ ks_status ks_density(ks_system* sys, int norb, const void* psi, const double* oc
  */
 ks_status ks_hartree(ks_system* sys, const double* rho, double* v, int add_vloc, void* stream);
 
+/* Exchange-correlation functionals of the density-dependent potential. */
+typedef enum { KS_XC_NONE = 0, KS_XC_LDA = 1 } ks_xc;
+
+/*
+ * The exchange-correlation term v_xc[n] of Eq. hamiltonian that
+ * ks_state_propagate_etrs adds to V_loc + V_H[n]: KS_XC_NONE (the default)
+ * or KS_XC_LDA, the local-density form of the unpolarised electron gas
+ * (see ks_lda_xc).  KS_EINVAL for a null system or another value.
+ */
+ks_status ks_system_set_xc(ks_system* sys, int functional);
+
+/*
+ * Local-density exchange-correlation potential of the density rho:
+ * v (+)= v_xc(rho) pointwise (accumulate != 0 adds), with
+ *   v_xc = v_x + v_c,  v_x = -(3 rho / pi)^(1/3) (Slater exchange),
+ *   v_c = eps_c - (rs/3) d eps_c/d rs,  rs = (3 / (4 pi rho))^(1/3),
+ *   eps_c = gamma / (1 + beta1 sqrt(rs) + beta2 rs)   (rs >= 1),
+ *   eps_c = A ln rs + B + C rs ln rs + D rs           (rs < 1),
+ * the Perdew-Zunger (1981) fit of the uniform gas's correlation energy
+ * (gamma = -0.1423, beta1 = 1.0529, beta2 = 0.3334, A = 0.0311, B = -0.048,
+ * C = 0.0020, D = -0.0116, Hartree atomic units); zero where rho <= 0.
+ * rho, v: device float64 [n0][n1][n2] (may be the same array only without
+ * accumulate).  KS_EINVAL on null arguments.
+ */
+ks_status ks_lda_xc(ks_system* sys, const double* rho, double* v, int accumulate, void* stream);
+
 /*
  * Dipole moment, the first moment of the density (Section "Results", the
  * optical response of a kicked molecule): d_a = dV sum_r r_a rho(r) with grid
@@ -279,8 +305,9 @@ ks_status ks_state_propagate(ks_state* state, double dt, int nsteps, const doubl
 /*
  * nsteps steps of the enforced-time-reversal-symmetry propagator (Eq. etrs)
  * under the density-dependent Hamiltonian H[n] = -1/2 lap + V_loc + V_H[n]
- * + V_nl, V_H the periodic Hartree potential (see ks_hartree) and
- * n = sum_i occ_i |psi_i|^2.  One step from psi(t):
+ * (+ v_xc[n] when ks_system_set_xc chose a functional) + V_nl, V_H the
+ * periodic Hartree potential (see ks_hartree) and n = sum_i occ_i |psi_i|^2.
+ * One step from psi(t):
  *   H(t) = H[n(psi(t))];
  *   w_k = H(t)^k psi for k = 1..4, shared by the two exponentials of H(t)
  *   (Section "Real-time propagation"): half = sum_k (-i dt/2)^k/k! w_k and the

@@ -227,6 +227,46 @@ static bool yz_pass(const ks_system* s, const double* rho, double2* W, double* v
   }
 }
 
+// ------------------------------------------ local-density exchange-correlation
+// v_xc[n] of Eq. hamiltonian for the unpolarised gas: Slater exchange
+// eps_x = -(3/4) (3 n / pi)^(1/3), v_x = (4/3) eps_x, and the Perdew-Zunger
+// (1981) correlation fit in rs = (3 / (4 pi n))^(1/3),
+//   rs >= 1: eps_c = gamma / q,  q = 1 + beta1 sqrt(rs) + beta2 rs,
+//            v_c = eps_c (1 + 7/6 beta1 sqrt(rs) + 4/3 beta2 rs) / q
+//   rs < 1:  v_c = A ln rs + (B - A/3) + 2/3 C rs ln rs + (2 D - C) rs / 3
+// (v_c = eps_c - rs/3 d eps_c / d rs); zero where n <= 0.
+__device__ __forceinline__ double lda_vxc(double n) {
+  if (!(n > 0.0)) return 0.0;
+  constexpr double GAMMA = -0.1423, BETA1 = 1.0529, BETA2 = 0.3334;
+  constexpr double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+  const double ex = -0.75 * cbrt(3.0 * n / M_PI);
+  const double vx = 4.0 / 3.0 * ex;
+  const double rs = cbrt(3.0 / (4.0 * M_PI * n));
+  double vc;
+  if (rs >= 1.0) {
+    const double sq = sqrt(rs);
+    const double q = 1.0 + BETA1 * sq + BETA2 * rs;
+    vc = GAMMA / q * (1.0 + 7.0 / 6.0 * BETA1 * sq + 4.0 / 3.0 * BETA2 * rs) / q;
+  } else {
+    const double lr = log(rs);
+    vc = A * lr + (B - A / 3.0) + 2.0 / 3.0 * C * rs * lr + (2.0 * D - C) * rs / 3.0;
+  }
+  return vx + vc;
+}
+
+// v[i] (+)= v_xc(rho[i])
+__global__ __launch_bounds__(NT) void lda_xc_kernel(const double* __restrict__ rho, double* __restrict__ v,
+                                                    long long N, int accumulate) {
+  const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+  if (i >= N) return;
+  const double x = lda_vxc(rho[i]);
+  v[i] = accumulate ? v[i] + x : x;
+}
+
+void launch_lda_xc(const ks_system* s, const double* rho, double* v, int accumulate, hipStream_t st) {
+  lda_xc_kernel<<<(unsigned)((s->N + NT - 1) / NT), NT, 0, st>>>(rho, v, s->N, accumulate);
+}
+
 bool launch_hartree(const ks_system* s, const double* rho, double* v, const double* vloc, hipStream_t st) {
   double2* W = s->d_hbox;
   if (!yz_pass(s, rho, W, nullptr, nullptr, -1, st)) return false;

@@ -605,9 +605,10 @@ ks_status state_density(ks_system* s, ks_state* t, const double2* orbitals, cons
   return KS_OK;
 }
 
-// d_v = V_loc + V_H[d_rho_w]
+// d_v = V_loc + V_H[d_rho_w] (+ v_xc[d_rho_w])
 ks_status update_potential(ks_system* s, hipStream_t st) {
   if (!launch_hartree(s, s->d_rho_w, s->d_v, s->d_vloc, st)) return fail(s, KS_EUNSUPPORTED, "no Hartree kernel");
+  if (s->xc == KS_XC_LDA) launch_lda_xc(s, s->d_rho_w, s->d_v, 1, st);
   return launch_ok(s, true, "hartree");
 }
 
@@ -1188,6 +1189,23 @@ ks_status ks_density(ks_system* s, int norb, const void* psi, const double* occ,
     if ((r = density_packed(s, nb, s->pk[0], occ + o0, rho, o0 > 0, st)) != KS_OK) return r;
   }
   return KS_OK;
+}
+
+ks_status ks_system_set_xc(ks_system* s, int functional) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (functional != KS_XC_NONE && functional != KS_XC_LDA) return fail(s, KS_EINVAL, "unknown exchange-correlation functional");
+  s->xc = functional;
+  return KS_OK;
+}
+
+ks_status ks_lda_xc(ks_system* s, const double* rho, double* v, int accumulate, void* stream) {
+  if (!s) return fail(nullptr, KS_EINVAL, "null system");
+  if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
+  if (!rho || !v) return fail(s, KS_EINVAL, "rho or v is null");
+  hipStream_t st = (hipStream_t)stream;
+  Track tk(s, st);
+  launch_lda_xc(s, rho, v, accumulate, st);
+  return launch_ok(s, true, "lda_xc");
 }
 
 ks_status ks_hartree(ks_system* s, const double* rho, double* v, int add_vloc, void* stream) {

@@ -144,6 +144,7 @@ struct ks_system {
   bool x_half = false;   // every sphere plane has |m0| < n0/4 (band-limited x-synthesis input)
   bool yz_half = false;  // every sphere point has |m1| < n1/4 and |m2| < n2/4 (band-limited y, z transforms)
   int xg_max = 8, pg_max = 8;   // orbital-group caps of the x-pencil and plane passes (tunable)
+  int xc = 0;                   // exchange-correlation term of the density-dependent potential (ks_xc)
   int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
       *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_key = nullptr,
       *d_up_x = nullptr, *d_x_slot = nullptr;
@@ -290,6 +291,8 @@ bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, i
 
 // v = V_H[rho] (+ vloc when not null); uses the system's work box
 bool launch_hartree(const ks_system* s, const double* rho, double* v, const double* vloc, hipStream_t st);
+// v (+)= v_xc[rho] in the local-density form (N points of the system's box)
+void launch_lda_xc(const ks_system* s, const double* rho, double* v, int accumulate, hipStream_t st);
 
 // psi <- chi exp(i k.r) psi for one orbital held on the complex box W (in place)
 bool launch_kick(const ks_system* s, double2* W, const double k[3], hipStream_t st);

@@ -20,6 +20,7 @@ HEADER = os.path.join(HERE, "..", "include", "ks.h")
 
 KS_OK, KS_EINVAL, KS_ENOMEM, KS_EDEVICE, KS_EUNSUPPORTED = range(5)
 KS_FP64, KS_MIXED = 0, 1
+KS_XC_NONE, KS_XC_LDA = 0, 1
 KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dots",
            "gemm", "eig", "sd"]
 
@@ -92,6 +93,8 @@ def _load():
         "ks_state_propagate": (I, [P, D, I, P, P, P, P]),
         "ks_state_propagate_etrs": (I, [P, D, I, P, P, P, P]),
         "ks_hartree": (I, [P, P, P, I, P]),
+        "ks_system_set_xc": (I, [P, I]),
+        "ks_lda_xc": (I, [P, P, P, I, P]),
         "ks_dipole": (I, [P, P, P, P]),
         "ks_spectrum": (I, [P, I, D, ctypes.POINTER(D), P, I, D, P, P, P]),
         "ks_dipole_noalloc": (I, [ctypes.POINTER(I), ctypes.POINTER(D), P, P, P]),
@@ -418,6 +421,21 @@ class System:
                                     _ptr(out, torch.float64, self.n, "out"), int(bool(add_vloc)), _stream()))
         return out
 
+    def set_xc(self, functional):
+        """Exchange-correlation term of the density-dependent potential used by
+        ETRS: KS_XC_NONE or KS_XC_LDA."""
+        self._check(_lib.ks_system_set_xc(self._h, int(functional)))
+
+    def lda_xc(self, rho, out=None, accumulate=False):
+        """Local-density exchange-correlation potential of the density rho
+        (float64 box on the device); added to out when accumulate."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self._check(_lib.ks_lda_xc(self._h, _ptr(rho, torch.float64, self.n, "rho"),
+                                   _ptr(out, torch.float64, self.n, "out"), int(bool(accumulate)), _stream()))
+        return out
+
     def dipole(self, rho):
         """Dipole moment dV sum_r r rho(r) of a density (float64 box on the
         device); returns a float64 tensor of 3 on the device."""
@@ -566,7 +584,8 @@ class State:
 
     def propagate_etrs(self, dt, nsteps, occ, rho=None, norms=None, stream=None):
         """nsteps ETRS steps under the density-dependent Hamiltonian
-        (V_loc + Hartree); rho [nsteps][n0][n1][n2] and norms [nsteps][norb]
+        (V_loc + Hartree, + LDA exchange-correlation after
+        system.set_xc(KS_XC_LDA)); rho [nsteps][n0][n1][n2] and norms [nsteps][norb]
         (float64, optional) receive the density and norms after each step."""
         import torch
         if rho is not None and rho.numel() < int(nsteps) * int(np.prod(self.system.n)):
