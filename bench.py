@@ -327,14 +327,15 @@ def run_mixed_large(steps, log):
             "orbital_rel_err_vs_fp64_max": float(d.max().item()), "orbitals_compared": len(sample)}
 
 
-def run_serving(nreq, nsteps, budget_gb, log, batched=True, max_active=256, lockstep=True):
+def run_serving(nreq, nsteps, budget_gb, log, batched=True, max_active=256, lockstep=True, chunk=None):
     """The serving trace: Poisson arrivals of small systems, continuous
     batching under an HBM budget.  batched: the resident requests of a grid
     are stepped by shared launches (ks_batch); otherwise each request replays
     its own captured step.  lockstep: global rounds (every resident request
     advances once per round).  Systems live in a device pool of 1.25 times
     the budget (fragmentation slack); launch schedules are tuned per grid
-    bucket before the trace."""
+    bucket before the trace.  chunk: orbitals per pass of each request's
+    system (None: one pass)."""
     from paper_2106_03872_amd import serve, synth
     trace = synth.serving_trace(nreq, 200.0, 2000)
     reqs = [serve.Request(rid=i, arrival=t, spec=sp, nsteps=nsteps) for i, (t, sp) in enumerate(trace)]
@@ -343,9 +344,9 @@ def run_serving(nreq, nsteps, budget_gb, log, batched=True, max_active=256, lock
     budget = int(budget_gb * 2 ** 30)
     pool = int(1.25 * budget) + (256 << 20)     # slack for the pool's fragmentation
     if batched:
-        be = serve.BatchedHipBackend(pool_bytes=pool, lockstep=lockstep)
+        be = serve.BatchedHipBackend(pool_bytes=pool, lockstep=lockstep, chunk=chunk)
     else:
-        be = serve.HipBackend(pool_bytes=pool)
+        be = serve.HipBackend(pool_bytes=pool, chunk=chunk)
     log(f"[bench] serving ({'batched launches' if batched else 'one graph per request'}): preparing {nreq} requests")
     be.prepare(reqs)
     srv = serve.Server(be, budget, max_active=max_active)
@@ -356,7 +357,7 @@ def run_serving(nreq, nsteps, budget_gb, log, batched=True, max_active=256, lock
                 "hbm_budget_GiB": budget_gb, "max_reserved_GiB": round(srv.max_used / 2 ** 30, 2),
                 "pool_peak_GiB": round(be.pool.usage()[1] / 2 ** 30, 2) if be.pool is not None else None,
                 "max_resident_requests": srv.max_resident, "failed": len(srv.failed), "requeued": srv.requeued,
-                "pretune_s": round(be.tuning_s, 2),
+                "pretune_s": round(be.tuning_s, 2), "orbitals_per_pass": chunk,
                 "precision": "mixed", "steps_per_request": nsteps, "arrivals": "Poisson, mean 200/s",
                 "drift_max": max(float(abs(r.result["norms"] - 1.0).max()) for r in done)})
     if batched:
@@ -386,6 +387,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=50)
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serving-pass", type=int, default=64,
+                    help="orbitals per pass of each request's system under the capped budget (0: one pass; "
+                         "the one-pass run is then the only capped run)")
     ap.add_argument("--serving-full-budget-gb", type=float, default=160.0,
                     help="also run the trace with a budget the whole trace fits in (0: skip)")
     ap.add_argument("--serving-compare", action="store_true",
@@ -458,10 +462,23 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log)
-        log(f"[bench] serving: p50 {serving['step_latency_ms_p50']:.2f} ms, p99 {serving['step_latency_ms_p99']:.2f} ms, "
-            f"first step p99 {serving['time_to_first_step_ms_p99']:.0f} ms, "
-            f"{serving['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s over {serving['makespan_s']:.1f} s")
+        # under the capped budget every request's system holds one pass of at
+        # most args.serving_pass orbitals, so the whole trace can reside
+        serving = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log,
+                              chunk=args.serving_pass or None)
+        log(f"[bench] serving (passes of {args.serving_pass}): p50 {serving['step_latency_ms_p50']:.2f} ms, "
+            f"p99 {serving['step_latency_ms_p99']:.2f} ms, first step p99 {serving['time_to_first_step_ms_p99']:.0f} ms, "
+            f"{serving['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s over {serving['makespan_s']:.1f} s, "
+            f"{serving['max_resident_requests']} resident at most")
+        if args.serving_pass:
+            one = run_serving(args.serving_requests, args.serving_steps, args.serving_budget_gb, log)
+            log(f"[bench] serving (one pass per request): p50 {one['step_latency_ms_p50']:.2f} ms, "
+                f"p99 {one['step_latency_ms_p99']:.2f} ms, first step p99 {one['time_to_first_step_ms_p99']:.0f} ms, "
+                f"{one['orbital_hpsi_per_s']:.0f} orbital.Hpsi/s, {one['max_resident_requests']} resident at most")
+            serving["one_pass"] = {k: one[k] for k in (
+                "step_latency_ms_p50", "step_latency_ms_p99", "time_to_first_step_ms_p50",
+                "time_to_first_step_ms_p99", "admission_ms_p99", "orbital_hpsi_per_s", "makespan_s",
+                "max_resident_requests", "max_reserved_GiB", "failed")}
         if args.serving_full_budget_gb > 0:
             full = run_serving(args.serving_requests, args.serving_steps, args.serving_full_budget_gb, log)
             log(f"[bench] serving ({args.serving_full_budget_gb:.0f} GiB budget): p50 {full['step_latency_ms_p50']:.2f} ms, "

@@ -122,6 +122,20 @@ ks_status ks_pool_usage(ks_pool* pool, unsigned long long* used, unsigned long l
 ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
                               int max_norb, ks_system** out);
 
+/*
+ * ks_system_create (pool == NULL) or ks_system_create_in with the orbitals
+ * per pass set at creation: chunk > 0 sizes the workspace (plane
+ * intermediates, packed pass buffers, projection partials) for
+ * min(chunk, max_norb) orbitals, chunk == 0 takes the default (as many
+ * orbitals as 4 GiB of plane intermediates hold).  Calls over more orbitals
+ * run in passes, with the same results.  A caller that holds many systems
+ * (serving) trades passes for memory this way without the default
+ * workspace ever being allocated.  KS_EINVAL for chunk < 0, otherwise as
+ * ks_system_create / ks_system_create_in.
+ */
+ks_status ks_system_create_ex(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
+                              int max_norb, int chunk, ks_system** out);
+
 /* Message of the last failing call on sys (or of the last failing create
  * when sys is NULL).  Valid until the next call on sys. */
 const char* ks_last_error(const ks_system* sys);
@@ -385,11 +399,14 @@ ks_status ks_state_replay(ks_state* state, void* stream);
  * orbital goes through the same arithmetic as in its own ks_state_propagate,
  * so the results are bit-identical to stepping each state alone.
  *
- * ks_batch_create: states[nstates] (host array), distinct systems, each
- * state's norb at most its system's chunk.  Allocates a small device table
- * (from the first system's pool when it has one).  KS_EINVAL (null, empty,
- * systems that differ in grid / cell / cutoff / precision, two states of one
- * system), KS_EUNSUPPORTED (a state larger than its system's pass).
+ * ks_batch_create: states[nstates] (host array), distinct systems of one
+ * x-tile shape.  A state with more orbitals than its system's pass (chunk)
+ * is stepped in passes, as alone: pass p steps chunk p (orbitals
+ * [p chunk, (p+1) chunk)) of every state that has one, so a system's
+ * workspace need only hold one chunk.  Allocates a small device table (from
+ * the first system's pool when it has one).  KS_EINVAL (null, empty, systems
+ * that differ in grid / cell / cutoff / precision / x-tile shape, two states
+ * of one system).
  * The batch holds the systems' buffers: after ks_system_set_projectors,
  * set_chunk, set_tuning or autotune on any of them, the batch calls return
  * KS_EINVAL (create it again).  Destroy the batch before its states.

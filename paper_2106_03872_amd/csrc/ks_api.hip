@@ -760,11 +760,20 @@ ks_status subspace_eigh(ks_system* s, int n, const double2* H, double2* work, do
 extern "C" {
 
 static ks_status system_create(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
-                               int max_norb, ks_system** out);
+                               int max_norb, int chunk, ks_system** out);
 
 ks_status ks_system_create(const int n[3], const double L[3], double ecut, int precision, int max_norb,
                            ks_system** out) {
-  return system_create(nullptr, n, L, ecut, precision, max_norb, out);
+  return system_create(nullptr, n, L, ecut, precision, max_norb, 0, out);
+}
+
+static ks_status check_pool(ks_pool* pool, ks_system** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != pool->device) {
+    if (out) *out = nullptr;
+    return fail(nullptr, KS_EINVAL, "the pool belongs to another device");
+  }
+  return KS_OK;
 }
 
 ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
@@ -773,12 +782,21 @@ ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], 
     if (out) *out = nullptr;
     return fail(nullptr, KS_EINVAL, "pool is null");
   }
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev != pool->device) {
+  const ks_status r = check_pool(pool, out);
+  return r != KS_OK ? r : system_create(pool, n, L, ecut, precision, max_norb, 0, out);
+}
+
+ks_status ks_system_create_ex(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
+                              int max_norb, int chunk, ks_system** out) {
+  if (chunk < 0) {
     if (out) *out = nullptr;
-    return fail(nullptr, KS_EINVAL, "the pool belongs to another device");
+    return fail(nullptr, KS_EINVAL, "chunk must be >= 0");
   }
-  return system_create(pool, n, L, ecut, precision, max_norb, out);
+  if (pool) {
+    const ks_status r = check_pool(pool, out);
+    if (r != KS_OK) return r;
+  }
+  return system_create(pool, n, L, ecut, precision, max_norb, chunk, out);
 }
 
 ks_status ks_stream_create(void** out) {
@@ -845,7 +863,7 @@ ks_status ks_pool_usage(ks_pool* p, unsigned long long* used, unsigned long long
 }
 
 static ks_status system_create(ks_pool* pool, const int n[3], const double L[3], double ecut, int precision,
-                               int max_norb, ks_system** out) {
+                               int max_norb, int chunk, ks_system** out) {
   if (!out) return fail(nullptr, KS_EINVAL, "out is null");
   *out = nullptr;
   if (!n || !L) return fail(nullptr, KS_EINVAL, "n or L is null");
@@ -968,7 +986,7 @@ static ks_status system_create(ks_pool* pool, const int n[3], const double L[3],
     ks_system_destroy(s);
     return st;
   }
-  s->cb = default_chunk(s);
+  s->cb = chunk > 0 ? std::min(chunk, max_norb) : default_chunk(s);
   if ((st = alloc_workspace(s)) != KS_OK) {
     g_create_err = s->err;
     ks_system_destroy(s);
@@ -1699,9 +1717,7 @@ ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out) 
   if (!states || nstates < 1) return fail(nullptr, KS_EINVAL, "a batch needs at least one state");
   ks_system* s0 = states[0] ? states[0]->sys : nullptr;
   if (!s0) return fail(nullptr, KS_EINVAL, "null state");
-  std::vector<int4> rx, rp, rr;
-  int max_natoms = 0;
-  long long total = 0;
+  int npass = 0;
   for (int j = 0; j < nstates; ++j) {
     const ks_state* t = states[j];
     if (!t) return fail(nullptr, KS_EINVAL, "null state");
@@ -1711,54 +1727,74 @@ ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out) 
       return fail(nullptr, KS_EINVAL, "the states' systems differ in x-tile shape (tuning)");
     for (int i = 0; i < j; ++i)
       if (states[i]->sys == t->sys) return fail(nullptr, KS_EINVAL, "two states of one system (they share its workspace)");
-    if (t->norb > t->sys->cb)
-      return fail(nullptr, KS_EUNSUPPORTED, "a state holds more orbitals than its system's pass (chunk)");
-    total += t->norb;
-    max_natoms = std::max(max_natoms, t->sys->natoms);
+    const int cl = chunk_len(t->sys, t->norb);
+    npass = std::max(npass, (t->norb + cl - 1) / cl);
   }
-  const int gx = x_group_size(s0, total), gp = plane_group_size(s0, total);
-  for (int j = 0; j < nstates; ++j) {
-    const int nb = states[j]->norb;
-    const int ngx = (nb + gx - 1) / gx, ngp = (nb + gp - 1) / gp;
-    for (int g = 0; g < ngx; ++g) rx.push_back(make_int4(j, g, ngx, 0));
-    for (int g = 0; g < ngp; ++g) rp.push_back(make_int4(j, g, ngp, 0));
-    if (states[j]->sys->natoms > 0)
-      for (int o = 0; o < nb; ++o) rr.push_back(make_int4(j, o, 0, 0));
+  // Pass p holds chunk p of every state with more than p chunks; each pass's
+  // tables: jobs of the 4 Taylor sub-steps, then the x, plane and reduce rows.
+  struct Host {
+    std::vector<BatchJob> jobs;
+    std::vector<int4> rx, rp, rr;
+    int njobs = 0, max_natoms = 0;
+  };
+  std::vector<Host> hp(npass);
+  size_t total_bytes = 0;
+  for (int p = 0; p < npass; ++p) {
+    Host& h = hp[p];
+    std::vector<int> js, nbs, o0s;
+    long long total = 0;
+    for (int j = 0; j < nstates; ++j) {
+      const ks_state* t = states[j];
+      const int cl = chunk_len(t->sys, t->norb), o0 = p * cl;
+      if (o0 >= t->norb) continue;
+      js.push_back(j);
+      o0s.push_back(o0);
+      nbs.push_back(std::min(cl, t->norb - o0));
+      total += nbs.back();
+      h.max_natoms = std::max(h.max_natoms, t->sys->natoms);
+    }
+    h.njobs = (int)js.size();
+    const int gx = x_group_size(s0, total), gp = plane_group_size(s0, total);
+    for (int q = 0; q < h.njobs; ++q) {
+      const int nb = nbs[q];
+      const int ngx = (nb + gx - 1) / gx, ngp = (nb + gp - 1) / gp;
+      for (int g = 0; g < ngx; ++g) h.rx.push_back(make_int4(q, g, ngx, 0));
+      for (int g = 0; g < ngp; ++g) h.rp.push_back(make_int4(q, g, ngp, 0));
+      if (states[js[q]]->sys->natoms > 0)
+        for (int o = 0; o < nb; ++o) h.rr.push_back(make_int4(q, o, 0, 0));
+    }
+    // jobs of the four Taylor sub-steps: w1 = H c -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored
+    h.jobs.resize((size_t)4 * h.njobs);
+    for (int k = 0; k < 4; ++k) {
+      for (int q = 0; q < h.njobs; ++q) {
+        ks_state* t = states[js[q]];
+        ks_system* s = t->sys;
+        double2* c = t->data + (size_t)o0s[q] * s->npw_stride;
+        BatchJob& x = h.jobs[(size_t)k * h.njobs + q];
+        const void* src[4] = {c, s->pk[1], s->pk[2], s->pk[1]};
+        void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
+        x.win = src[k];
+        x.wout = dst[k];
+        x.acc = c;
+        x.T = s->T;
+        x.U = s->U;
+        x.partial = s->partial;
+        x.DP = s->DP;
+        x.V = s->d_v;
+        x.pt = proj_tab(s);
+        x.nb = nbs[q];
+      }
+    }
+    total_bytes += h.jobs.size() * sizeof(BatchJob) +
+                   (h.rx.size() + h.rp.size() + std::max<size_t>(h.rr.size(), 1)) * sizeof(int4);
   }
   ks_batch* b = new ks_batch();
   b->s0 = s0;
-  b->max_natoms = max_natoms;
-  b->nrows_x = (int)rx.size();
-  b->nrows_p = (int)rp.size();
-  b->nrows_r = (int)rr.size();
   for (int j = 0; j < nstates; ++j) {
     b->states.push_back(states[j]);
     b->gens.push_back(states[j]->sys->gen);
   }
-  // jobs of the four Taylor sub-steps: w1 = H c -> pk1, w2 -> pk2, w3 -> pk1, w4 not stored
-  std::vector<BatchJob> jobs((size_t)4 * nstates);
-  for (int k = 0; k < 4; ++k) {
-    for (int j = 0; j < nstates; ++j) {
-      ks_state* t = states[j];
-      ks_system* s = t->sys;
-      BatchJob& q = jobs[(size_t)k * nstates + j];
-      const void* src[4] = {t->data, s->pk[1], s->pk[2], s->pk[1]};
-      void* dst[4] = {s->pk[1], s->pk[2], s->pk[1], nullptr};
-      q.win = src[k];
-      q.wout = dst[k];
-      q.acc = t->data;
-      q.T = s->T;
-      q.U = s->U;
-      q.partial = s->partial;
-      q.DP = s->DP;
-      q.V = s->d_v;
-      q.pt = proj_tab(s);
-      q.nb = t->norb;
-    }
-  }
-  const size_t jb = jobs.size() * sizeof(BatchJob);
-  const size_t rb = (rx.size() + rp.size() + std::max<size_t>(rr.size(), 1)) * sizeof(int4);
-  b->dev_bytes = jb + rb;
+  b->dev_bytes = total_bytes;
   void* dev = nullptr;
   ks_status r = dalloc(s0, &dev, b->dev_bytes);
   if (r != KS_OK) {
@@ -1767,19 +1803,33 @@ ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out) 
   }
   b->dev = (char*)dev;
   std::vector<char> host(b->dev_bytes, 0);
-  memcpy(host.data(), jobs.data(), jb);
-  memcpy(host.data() + jb, rx.data(), rx.size() * sizeof(int4));
-  memcpy(host.data() + jb + rx.size() * sizeof(int4), rp.data(), rp.size() * sizeof(int4));
-  if (!rr.empty()) memcpy(host.data() + jb + (rx.size() + rp.size()) * sizeof(int4), rr.data(), rr.size() * sizeof(int4));
+  size_t off = 0;
+  b->passes.resize(npass);
+  for (int p = 0; p < npass; ++p) {
+    Host& h = hp[p];
+    ks_batch_pass& bp = b->passes[p];
+    const size_t jb = h.jobs.size() * sizeof(BatchJob);
+    memcpy(host.data() + off, h.jobs.data(), jb);
+    for (int k = 0; k < 4; ++k) bp.jobs[k] = reinterpret_cast<BatchJob*>(b->dev + off) + (size_t)k * h.njobs;
+    off += jb;
+    auto put = [&](const std::vector<int4>& v, int4*& dst, size_t n) {
+      if (!v.empty()) memcpy(host.data() + off, v.data(), v.size() * sizeof(int4));
+      dst = reinterpret_cast<int4*>(b->dev + off);
+      off += n * sizeof(int4);
+    };
+    put(h.rx, bp.rows_x, h.rx.size());
+    put(h.rp, bp.rows_p, h.rp.size());
+    put(h.rr, bp.rows_r, std::max<size_t>(h.rr.size(), 1));
+    bp.nrows_x = (int)h.rx.size();
+    bp.nrows_p = (int)h.rp.size();
+    bp.nrows_r = (int)h.rr.size();
+    bp.max_natoms = h.max_natoms;
+  }
   const hipError_t e = hipMemcpy(b->dev, host.data(), b->dev_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     ks_batch_destroy(b);
     return fail(nullptr, KS_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
   }
-  for (int k = 0; k < 4; ++k) b->jobs[k] = reinterpret_cast<BatchJob*>(b->dev) + (size_t)k * nstates;
-  b->rows_x = reinterpret_cast<int4*>(b->dev + jb);
-  b->rows_p = b->rows_x + rx.size();
-  b->rows_r = b->rows_p + rp.size();
   for (ks_state* t : b->states) t->sys->batches.push_back(b);
   *out = b;
   return KS_OK;
@@ -1816,29 +1866,33 @@ static ks_status batch_taylor(ks_batch* b, double dt, int nsteps, hipStream_t st
   double2 coef[5];
   taylor_coefficients(dt, coef);
   ks_status r;
-  for (int step = 0; step < nsteps; ++step) {
-    for (int k = 1; k <= 4; ++k) {
-      const BatchJob* jobs = b->jobs[k - 1];
-      const bool in64 = k == 1 || s0->prec == KS_FP64;
-      const Taylor tay{coef[k], k < 4 ? 1 : 0, {0.0, 0.0}};
-      if ((r = kcall(s0, KS_K_PLANE_INV, st, "plane_inv",
-                     [&] { return launch_plane_inv_batch(s0, jobs, b->rows_p, b->nrows_p, in64, st); })) != KS_OK)
-        return r;
-      if (b->max_natoms > 0) {
-        if ((r = kcall(s0, KS_K_XPROJ, st, "xproj",
-                       [&] { return launch_x_batch(s0, jobs, b->rows_x, b->nrows_x, false, st); })) != KS_OK)
+  // chunk-outer, step-inner, as a state stepped alone
+  for (const ks_batch_pass& bp : b->passes) {
+    for (int step = 0; step < nsteps; ++step) {
+      for (int k = 1; k <= 4; ++k) {
+        const BatchJob* jobs = bp.jobs[k - 1];
+        const bool in64 = k == 1 || s0->prec == KS_FP64;
+        const Taylor tay{coef[k], k < 4 ? 1 : 0, {0.0, 0.0}};
+        if ((r = kcall(s0, KS_K_PLANE_INV, st, "plane_inv",
+                       [&] { return launch_plane_inv_batch(s0, jobs, bp.rows_p, bp.nrows_p, in64, st); })) != KS_OK)
           return r;
-        if ((r = kcall(s0, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] {
-               return launch_proj_reduce_batch(s0, jobs, b->rows_r, b->nrows_r, b->max_natoms, st);
-             })) != KS_OK)
+        if (bp.max_natoms > 0) {
+          if ((r = kcall(s0, KS_K_XPROJ, st, "xproj",
+                         [&] { return launch_x_batch(s0, jobs, bp.rows_x, bp.nrows_x, false, st); })) != KS_OK)
+            return r;
+          if ((r = kcall(s0, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] {
+                 return launch_proj_reduce_batch(s0, jobs, bp.rows_r, bp.nrows_r, bp.max_natoms, st);
+               })) != KS_OK)
+            return r;
+        }
+        if ((r = kcall(s0, KS_K_XAPPLY, st, "xapply",
+                       [&] { return launch_x_batch(s0, jobs, bp.rows_x, bp.nrows_x, true, st); })) != KS_OK)
+          return r;
+        if ((r = kcall(s0, KS_K_PLANE_FWD, st, "plane_fwd",
+                       [&] { return launch_plane_fwd_batch(s0, jobs, bp.rows_p, bp.nrows_p, in64, tay, st); })) !=
+            KS_OK)
           return r;
       }
-      if ((r = kcall(s0, KS_K_XAPPLY, st, "xapply",
-                     [&] { return launch_x_batch(s0, jobs, b->rows_x, b->nrows_x, true, st); })) != KS_OK)
-        return r;
-      if ((r = kcall(s0, KS_K_PLANE_FWD, st, "plane_fwd",
-                     [&] { return launch_plane_fwd_batch(s0, jobs, b->rows_p, b->nrows_p, in64, tay, st); })) != KS_OK)
-        return r;
     }
   }
   return KS_OK;

@@ -223,19 +223,25 @@ struct ks_state {
   unsigned long long graph_gen = 0;   // system generation at capture
 };
 
-// Several resident states of distinct systems of one grid, stepped together
-// by one launch per H psi kernel (ks_batch_create).
-struct ks_batch {
-  std::vector<ks_state*> states;
-  std::vector<unsigned long long> gens;   // each system's generation at creation
-  ks_system* s0 = nullptr;                // the first system: sphere, twiddles, precision, caps
-  char* dev = nullptr;                    // device tables (jobs of the 4 Taylor sub-steps, rows)
-  size_t dev_bytes = 0;
-  ks::BatchJob* jobs[4] = {nullptr, nullptr, nullptr, nullptr};
+// One pass of a batch: the chunk p (orbitals [p cb, (p+1) cb)) of every
+// state that has one, stepped by one launch per kernel.
+struct ks_batch_pass {
+  ks::BatchJob* jobs[4] = {nullptr, nullptr, nullptr, nullptr};   // the 4 Taylor sub-steps
   int4* rows_x = nullptr;                 // x-pass rows (job, group, groups)
   int4* rows_p = nullptr;                 // plane-pass rows
   int4* rows_r = nullptr;                 // projection-reduce rows (job, orbital)
   int nrows_x = 0, nrows_p = 0, nrows_r = 0, max_natoms = 0;
+};
+
+// Several resident states of distinct systems of one grid, stepped together
+// by one launch per H psi kernel and pass (ks_batch_create).
+struct ks_batch {
+  std::vector<ks_state*> states;
+  std::vector<unsigned long long> gens;   // each system's generation at creation
+  ks_system* s0 = nullptr;                // the first system: sphere, twiddles, precision, caps
+  char* dev = nullptr;                    // device tables (jobs and rows of every pass)
+  size_t dev_bytes = 0;
+  std::vector<ks_batch_pass> passes;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

@@ -61,6 +61,7 @@ def _load():
         "ks_system_create": (I, [ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, ctypes.POINTER(P)]),
         "ks_system_destroy": (None, [P]),
         "ks_system_create_in": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, ctypes.POINTER(P)]),
+        "ks_system_create_ex": (I, [P, ctypes.POINTER(I), ctypes.POINTER(D), D, I, I, I, ctypes.POINTER(P)]),
         "ks_pool_create": (I, [ctypes.c_ulonglong, ctypes.POINTER(P)]),
         "ks_stream_create": (I, [ctypes.POINTER(P)]),
         "ks_stream_destroy": (None, [P]),
@@ -346,7 +347,7 @@ class System:
     """One Kohn-Sham system (grid, cell, cutoff, potential, projectors);
     with `pool`, its device memory comes from that Pool."""
 
-    def __init__(self, n, L, ecut, max_norb, precision=KS_FP64, pool=None):
+    def __init__(self, n, L, ecut, max_norb, precision=KS_FP64, pool=None, chunk=0):
         self.n = tuple(int(x) for x in n)
         self.L = tuple(float(x) for x in L)
         self.ecut = float(ecut)
@@ -355,7 +356,10 @@ class System:
         self.pool = pool
         h = ctypes.c_void_p()
         nn, LL = (ctypes.c_int * 3)(*self.n), (ctypes.c_double * 3)(*self.L)
-        if pool is None:
+        if chunk:
+            st = _lib.ks_system_create_ex(None if pool is None else pool._h, nn, LL, self.ecut, int(precision),
+                                          self.max_norb, int(chunk), ctypes.byref(h))
+        elif pool is None:
             st = _lib.ks_system_create(nn, LL, self.ecut, int(precision), self.max_norb, ctypes.byref(h))
         else:
             st = _lib.ks_system_create_in(pool._h, nn, LL, self.ecut, int(precision), self.max_norb, ctypes.byref(h))
@@ -681,11 +685,12 @@ def orthonormalize(system, psi):
     return system.orthonormalize(psi)
 
 
-def system_from_synth(sysm, max_norb=None, ecut=None, precision=KS_FP64, pool=None):
-    """Create a System from a synth.System (potential + projectors uploaded)."""
+def system_from_synth(sysm, max_norb=None, ecut=None, precision=KS_FP64, pool=None, chunk=0):
+    """Create a System from a synth.System (potential + projectors uploaded);
+    chunk > 0 sets the orbitals per pass at creation."""
     import torch
     spec = sysm.spec
-    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb, precision, pool)
+    s = System(spec.n, spec.L, spec.ecut if ecut is None else ecut, max_norb or spec.norb, precision, pool, chunk)
     s.set_vloc(torch.from_numpy(sysm.vloc).to("cuda"))
     p = sysm.proj
     s.set_projectors(p.npts, p.idx, p.beta, p.d)

@@ -282,7 +282,8 @@ class HipBackend:
     resident state per request, steps replayed from a captured graph on a
     stream pool; admissions on worker threads, each with its own stream."""
 
-    def __init__(self, precision=None, nstreams=4, use_graphs=True, dt=0.05, pool_bytes=None, admit_workers=4):
+    def __init__(self, precision=None, nstreams=4, use_graphs=True, dt=0.05, pool_bytes=None, admit_workers=4,
+                 chunk=None):
         import torch
 
         from paper_2106_03872_amd import ks
@@ -306,6 +307,13 @@ class HipBackend:
         self.pool = None
         self.tuning_s = 0.0
         self._exec = None
+        # orbitals per pass of a request's system (None: the library default,
+        # one pass): a smaller pass shrinks each system's workspace, so more
+        # requests fit the budget, at the cost of more passes per step
+        self.chunk = chunk
+
+    def _chunk(self, r):
+        return 0 if self.chunk is None else min(int(self.chunk), r.spec.norb)
 
     def prepare(self, requests, pretune=True):
         """Draw every request's inputs on the host (the request payload) and,
@@ -320,11 +328,11 @@ class HipBackend:
             t0 = time.perf_counter()
             seen = set()
             for r in sorted(requests, key=lambda q: -q.spec.norb):
-                key = (tuple(r.spec.n), 1 << max(0, (r.spec.norb - 1).bit_length()))
+                key = (tuple(r.spec.n), 1 << max(0, (r.spec.norb - 1).bit_length()), self._chunk(r))
                 if key in seen:
                     continue
                 seen.add(key)
-                gs = self.ks.system_from_synth(self.inputs[r.rid][0], precision=self.precision)
+                gs = self.ks.system_from_synth(self.inputs[r.rid][0], precision=self.precision, chunk=self._chunk(r))
                 gs.autotune(r.spec.norb)
                 gs.close()
             self.torch.cuda.synchronize()
@@ -333,7 +341,8 @@ class HipBackend:
     def footprint(self, r):
         sysm = self.inputs[r.rid][0]
         s = r.spec
-        base = self.ks.plan_footprint(s.n, s.L, s.ecut, s.norb, int(sysm.proj.npts.sum()), 4, self.precision)
+        base = self.ks.plan_footprint(s.n, s.L, s.ecut, s.norb, int(sysm.proj.npts.sum()), 4, self.precision,
+                                      self._chunk(r))
         npw_stride = len(self.ks.plan_sphere(s.n, s.L, s.ecut)) + 64
         ortho = 2 * s.norb * npw_stride * 16 + 2 * s.norb * s.norb * 16
         return base + ortho + 64 * 256        # pool alignment of the system's buffers
@@ -365,7 +374,7 @@ class HipBackend:
         self._rw.acquire_read()
         try:
             with torch.cuda.stream(stream):
-                gs = ks.system_from_synth(sysm, precision=self.precision, pool=self.pool)
+                gs = ks.system_from_synth(sysm, precision=self.precision, pool=self.pool, chunk=self._chunk(r))
                 h["system"] = gs
                 gs.autotune(r.spec.norb)     # cached: tuned before the trace
                 c = torch.zeros((r.spec.norb, r.spec.npoints), dtype=torch.complex128, device="cuda")

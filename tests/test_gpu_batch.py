@@ -62,6 +62,51 @@ def test_batch_equals_alone(ks, precision):
     b.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_batch_in_passes_equals_alone(ks, precision):
+    """States larger than their system's pass are stepped in passes (pass p
+    steps chunk p of every state that has one): bit-identical to each state
+    stepped alone, in one pass or in the same passes; graph replays too."""
+    print(f"[case] batch in passes precision {precision}", file=sys.stderr, flush=True)
+    specs = _specs()
+    chunks = [3, 5, 2, 11, 7]          # 3, 4, 2, 1 and 4 passes of the 7, 16, 3, 11, 24 orbitals
+    def states(chunked):
+        out = []
+        for sp, ch in zip(specs, chunks):
+            sysm = synth.system(sp)
+            gs = ks.system_from_synth(sysm, precision=precision, chunk=ch if chunked else 0)
+            if sp.name == NO_PROJ:
+                gs.set_projectors(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((0, 4)), np.zeros((0, 4)))
+            assert gs.info()["chunk"] == (min(ch, sp.norb) if chunked else sp.norb)
+            st = ks.State(gs, sp.norb)
+            st.upload(torch.from_numpy(synth.orbitals_box(sp)).cuda())
+            out.append((gs, st))
+        return out
+    alone, alone_passes, batched, captured = states(False), states(True), states(True), states(True)
+    for _, st in alone + alone_passes:
+        st.propagate(0.05, 3)
+    b = ks.Batch([st for _, st in batched])
+    b.propagate(0.05, 3)
+    s = ks.Stream()
+    g = ks.Batch([st for _, st in captured])
+    g.capture(0.05, s.torch)
+    for _ in range(3):
+        g.replay(s.torch)
+        s.torch.synchronize()
+    torch.cuda.synchronize()
+    for (_, a), (_, p), (_, c), (_, d) in zip(alone, alone_passes, batched, captured):
+        ra = a.download()
+        assert torch.equal(ra, p.download())
+        assert torch.equal(ra, c.download())
+        assert torch.equal(ra, d.download())
+    b.close()
+    g.close()
+    s.close()
+    with pytest.raises(ks.KSError) as e:
+        ks.System((24, 24, 24), (7.92,) * 3, 10.0, 4, chunk=-1)
+    assert e.value.status == ks.KS_EINVAL
+
+
 def test_batch_graph_and_one_shot(ks):
     print("[case] batch graph replays", file=sys.stderr, flush=True)
     specs = _specs(24, 7.92)[:4]

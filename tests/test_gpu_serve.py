@@ -27,9 +27,9 @@ def gpu():
         pytest.skip("no HIP device")
 
 
-def _run(reqs, budget=None, use_graphs=True, pool_bytes=None, batched=False):
+def _run(reqs, budget=None, use_graphs=True, pool_bytes=None, batched=False, chunk=None):
     cls = serve.BatchedHipBackend if batched else serve.HipBackend
-    be = cls(use_graphs=use_graphs, pool_bytes=pool_bytes)
+    be = cls(use_graphs=use_graphs, pool_bytes=pool_bytes, chunk=chunk)
     be.prepare(reqs)
     if budget is None:
         budget = sum(be.footprint(r) for r in reqs) * 2
@@ -79,6 +79,28 @@ def test_serving_batched_equals_alone(gpu):
     assert max(srv.be.batch_sizes) >= 2
     for r in _requests():
         print(f"[case] serving batched alone {r.rid}", file=sys.stderr, flush=True)
+        alone, _ = _run([serve.Request(rid=r.rid, arrival=0.0, spec=r.spec, nsteps=r.nsteps)])
+        assert np.array_equal(alone[r.rid].result["orbitals"], mix[r.rid].result["orbitals"])
+        assert alone[r.rid].result["energy"] == mix[r.rid].result["energy"]
+
+
+def test_serving_batched_passes_equal_alone(gpu):
+    """Requests whose systems hold a pass of at most 16 orbitals (their
+    batched steps run in passes; every system's workspace is a quarter of the
+    default or less): results bit-identical to each request alone with its own
+    default one-pass system, and the footprints smaller."""
+    print("[case] serving batched passes", file=sys.stderr, flush=True)
+    reqs = _requests()[:6]
+    be = serve.BatchedHipBackend(chunk=16)
+    be.prepare(reqs, pretune=False)
+    one = serve.BatchedHipBackend()
+    one.prepare(reqs, pretune=False)
+    assert all(be.footprint(r) < one.footprint(r) for r in reqs)
+    budget = sum(be.footprint(r) for r in reqs) * 2
+    mix, srv = _run(_requests()[:6], budget, use_graphs=False, pool_bytes=budget + (64 << 20), batched=True,
+                    chunk=16)
+    assert max(srv.be.batch_sizes) >= 2
+    for r in _requests()[:6]:
         alone, _ = _run([serve.Request(rid=r.rid, arrival=0.0, spec=r.spec, nsteps=r.nsteps)])
         assert np.array_equal(alone[r.rid].result["orbitals"], mix[r.rid].result["orbitals"])
         assert alone[r.rid].result["energy"] == mix[r.rid].result["energy"]
