@@ -311,10 +311,11 @@ def run_mixed_large(steps, log):
     res, psi = {}, {}
     for name, prec in (("fp64", ks.KS_FP64), ("mixed", ks.KS_MIXED)):
         _, g, st = setup_workload(spec, prec)
-        ms, _, phys, _ = run_steps(spec, g, st, steps, 1, timing=False)
+        ms, kt, phys, _ = run_steps(spec, g, st, steps, 1)
         psi[name] = st.download()[sample].clone()
         res[name] = {"ms_per_step": round(ms, 3), "value": round(4 * spec.norb / (ms * 1e-3), 1),
-                     "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"], "tuning": g.tuning}
+                     "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"], "tuning": g.tuning,
+                     "kernels": kernel_table(g.info(), spec, kt, steps, ms)}
         log(f"[bench] 120^3 / {spec.norb} orbitals {name}: {ms:.2f} ms/step, {res[name]['value']:.0f} orbital.Hpsi/s, "
             f"tuning {g.tuning}")
         st.close()

@@ -156,9 +156,12 @@ ks_status ks_system_set_vloc(ks_system* sys, const double* v, void* stream);
  *                            atoms concatenated (duplicates count twice)
  *   beta [sum npts][nproj]   projector values at those points (row-major)
  *   d    [natoms][nproj]     KB coefficients
- * The library copies and regroups them; it synchronises `stream` (pass the
- * stream later calls use).  natoms = 0 removes the non-local term.
- * Errors: KS_EINVAL on null arrays or an index outside [0, N).
+ * The library copies and regroups them (it keeps the host copies, so that a
+ * change of x-tile shape can regroup them again); it synchronises `stream`
+ * (pass the stream later calls use).  natoms = 0 removes the non-local term.
+ * The new device tables are allocated and filled before the old ones are
+ * freed: on KS_ENOMEM the system keeps its previous tables.
+ * Errors: KS_EINVAL on null arrays or an index outside [0, N); KS_ENOMEM.
  */
 ks_status ks_system_set_projectors(ks_system* sys, int natoms, int nproj, const int* npts,
                                    const int* idx, const double* beta, const double* d, void* stream);

@@ -1070,24 +1070,72 @@ static ks_status install_proj(ks_system* s, const ProjHost& ph, int natoms, cons
       for (int c = 0; c < np; ++c) x_beta.push_back(ph.brows[(size_t)ph.ent_brow[e] * np + c]);
     }
   }
+  // New device copies first; the system's tables are replaced only when
+  // every one of them was allocated and filled, so a failure (KS_ENOMEM)
+  // leaves the old tables, shape and workspace in place.
+  std::vector<void*> fresh;
+  auto put = [&](auto& vec, auto** dst) -> ks_status {
+    using T = typename std::decay_t<decltype(vec)>::value_type;
+    *dst = nullptr;
+    ks_status st = dalloc(s, reinterpret_cast<void**>(dst), vec.size() * sizeof(T));
+    if (st != KS_OK) return st;
+    fresh.push_back(*dst);
+    if (!vec.empty())
+      KS_HIP(s, hipMemcpy(*dst, vec.data(), vec.size() * sizeof(T), hipMemcpyHostToDevice));
+    return KS_OK;
+  };
+  int *pt_lds, *slot_off, *slot_atom, *slot_pt, *atom_slot_off, *atom_slots, *up_off, *up_key2, *up_x2, *x_slot2;
+  double *brows, *up_beta2, *x_beta2, *kb2;
+  int4* item;
+  void* partial = nullptr;
+  double2* DP = nullptr;
+  const int na = (natoms > 0 && ph.npoints > 0) ? natoms : 0;
+  const size_t pbytes = (size_t)s->cb * std::max<size_t>(1, ph.slot_atom.size()) * std::max(1, np) * sizeof(double2);
+  const size_t dbytes = (size_t)s->cb * std::max(1, na) * std::max(1, np) * sizeof(double2);
   ks_status st;
-  if ((st = upload(s, &s->d_pt_lds, ph.pt_lds)) != KS_OK ||
-      (st = upload(s, &s->d_slot_off, ph.slot_off)) != KS_OK || (st = upload(s, &s->d_slot_atom, ph.slot_atom)) != KS_OK ||
-      (st = upload(s, &s->d_slot_pt, ph.slot_pt)) != KS_OK ||
-      (st = upload(s, &s->d_atom_slot_off, ph.atom_slot_off)) != KS_OK ||
-      (st = upload(s, &s->d_atom_slots, ph.atom_slots)) != KS_OK || (st = upload(s, &s->d_up_off, ph.up_off)) != KS_OK ||
-      (st = upload(s, &s->d_up_key, up_key)) != KS_OK || (st = upload(s, &s->d_up_x, up_x)) != KS_OK ||
-      (st = upload(s, &s->d_x_slot, x_slot)) != KS_OK || (st = upload(s, &s->d_beta, ph.brows)) != KS_OK ||
-      (st = upload(s, &s->d_up_beta, up_beta)) != KS_OK || (st = upload(s, &s->d_x_beta, x_beta)) != KS_OK ||
-      (st = upload(s, &s->d_kb, kb)) != KS_OK || (st = upload(s, &s->d_item, ph.item)) != KS_OK)
+  if ((st = put(ph.pt_lds, &pt_lds)) != KS_OK || (st = put(ph.slot_off, &slot_off)) != KS_OK ||
+      (st = put(ph.slot_atom, &slot_atom)) != KS_OK || (st = put(ph.slot_pt, &slot_pt)) != KS_OK ||
+      (st = put(ph.atom_slot_off, &atom_slot_off)) != KS_OK || (st = put(ph.atom_slots, &atom_slots)) != KS_OK ||
+      (st = put(ph.up_off, &up_off)) != KS_OK || (st = put(up_key, &up_key2)) != KS_OK ||
+      (st = put(up_x, &up_x2)) != KS_OK || (st = put(x_slot, &x_slot2)) != KS_OK ||
+      (st = put(ph.brows, &brows)) != KS_OK || (st = put(up_beta, &up_beta2)) != KS_OK ||
+      (st = put(x_beta, &x_beta2)) != KS_OK || (st = put(kb, &kb2)) != KS_OK || (st = put(ph.item, &item)) != KS_OK ||
+      (st = dalloc(s, &partial, pbytes)) != KS_OK ||
+      (fresh.push_back(partial), st = dalloc(s, reinterpret_cast<void**>(&DP), dbytes)) != KS_OK) {
+    for (void*& q : fresh) dfree(s, q);
     return st;
-  s->natoms = (natoms > 0 && ph.npoints > 0) ? natoms : 0;
+  }
+  auto swap_in = [&](auto*& field, auto* v) {
+    void* old = field;
+    dfree(s, old);
+    field = v;
+  };
+  swap_in(s->d_pt_lds, pt_lds);
+  swap_in(s->d_slot_off, slot_off);
+  swap_in(s->d_slot_atom, slot_atom);
+  swap_in(s->d_slot_pt, slot_pt);
+  swap_in(s->d_atom_slot_off, atom_slot_off);
+  swap_in(s->d_atom_slots, atom_slots);
+  swap_in(s->d_up_off, up_off);
+  swap_in(s->d_up_key, up_key2);
+  swap_in(s->d_up_x, up_x2);
+  swap_in(s->d_x_slot, x_slot2);
+  swap_in(s->d_beta, brows);
+  swap_in(s->d_up_beta, up_beta2);
+  swap_in(s->d_x_beta, x_beta2);
+  swap_in(s->d_kb, kb2);
+  swap_in(s->d_item, item);
+  swap_in(s->partial, partial);
+  swap_in(s->DP, DP);
+  s->partial_cap = pbytes;
+  s->dp_cap = dbytes;
+  s->natoms = na;
   s->nproj = np;
   s->nslots = (int)ph.slot_atom.size();
   s->nruns = ph.nruns;
   s->npoints = ph.npoints;
   s->nuniq = (int)ph.up_lds.size();
-  return alloc_proj_workspace(s);
+  return KS_OK;
 }
 
 ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
@@ -1104,16 +1152,19 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
   KS_HIP(s, hipStreamSynchronize((hipStream_t)stream));
   wait_own(s);   // the old tables may still be read by work on another stream
   ++s->gen;
+  const int na = std::max(0, natoms), np = ph.nproj;
+  std::vector<double> dcopy(d, d + (size_t)na * np);
+  const ks_status r = install_proj(s, ph, na, dcopy.data());
+  if (r != KS_OK) return r;   // the previous tables (and inputs) stay
   // keep the inputs: another tile shape rebuilds the tables from them
   auto& in = s->proj_in;
-  const int na = std::max(0, natoms), np = ph.nproj;
   in.natoms = na;
   in.nproj = nproj;
   in.npts.assign(npts, npts + na);
   in.idx.assign(idx, idx + ph.npoints);
   in.beta.assign(beta, beta + (size_t)ph.npoints * np);
-  in.d.assign(d, d + (size_t)na * np);
-  return install_proj(s, ph, na, in.d.data());
+  in.d = std::move(dcopy);
+  return KS_OK;
 }
 
 // Switch the x-pencil passes to tile shape `shape`: the per-tile projector
@@ -1132,11 +1183,13 @@ static ks_status set_x_shape(ks_system* s, int shape) {
   }
   wait_own(s);
   ++s->gen;
+  const ks_status r = install_proj(s, ph, in.natoms, in.d.data());
+  if (r != KS_OK) return r;   // tables, shape and workspace unchanged
   s->xshape = shape;
   s->xnb = nb;
   s->xnt = nt;
   s->ntiles = (s->npl + nb - 1) / nb;
-  return install_proj(s, ph, in.natoms, in.d.data());
+  return KS_OK;
 }
 
 ks_status ks_ham_apply(ks_system* s, int norb, const void* psi, void* hpsi, void* stream) {

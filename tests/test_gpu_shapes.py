@@ -185,3 +185,29 @@ def test_shape_errors_and_batches(ks):
         ks.Batch([st for _, st in batched])
     assert e.value.status == ks.KS_EINVAL
     torch.cuda.synchronize()
+
+
+def test_shape_switch_without_memory_keeps_the_system(ks):
+    """A shape switch builds the new tables before it frees the old ones: in
+    a pool with no room for them it fails with KS_ENOMEM and the system keeps
+    its shape, tables and results."""
+    print("[case] shape switch out of memory", file=sys.stderr, flush=True)
+    n, L, natoms = GRIDS[0]
+    spec = _spec(n, L, natoms)
+    sysm = synth.system(spec)
+    c = orbitals_device(spec)
+    big = ks.Pool(512 << 20)
+    a = ks.system_from_synth(sysm, pool=big)
+    used = big.usage()[0]
+    ref = a.ham_apply(c).clone()
+    a.close()
+    big.close()
+    tight = ks.Pool(used + 4096)
+    b = ks.system_from_synth(sysm, pool=tight)
+    with pytest.raises(ks.KSError) as e:
+        b.set_tuning(8, 4, x_shape=1)
+    assert e.value.status == ks.KS_ENOMEM
+    assert b.info()["x_shape"] == 0
+    assert torch.equal(b.ham_apply(c), ref)
+    b.close()
+    tight.close()
