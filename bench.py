@@ -65,7 +65,39 @@ def alg_bytes(info, spec, kernel, S=16):
         return npw + N * S, 0
     if kernel == "dots":
         return npw, 0
+    if kernel == "gproj":           # packed input, DP out; the split table (hi + lo BF16) once per launch
+        return npw + info["natoms"] * info["nproj"] * 16, gproj_table_bytes(info)
     return 0, 0
+
+
+def gproj_shape(info):
+    """(columns, padded k) of the reciprocal-space projection product."""
+    P = info["natoms"] * info["nproj"]
+    return 2 * (-(-P // 64) * 64), -(-2 * info["npw"] // 32) * 32
+
+
+def gproj_table_bytes(info):
+    ncol, kpad = gproj_shape(info)
+    return ncol * kpad * 4
+
+
+def gproj_summary(info, spec, kt):
+    """The split-BF16 projection product per launch: time, MFMA rate (three
+    BF16 products per real multiply-add) against the 2.5 PFLOP/s dense BF16
+    peak, and algorithmic HBM bytes (input, table, DP) per second."""
+    ms, n = kt.get("gproj", (0.0, 0))
+    if n == 0:
+        return None
+    nb = orbitals_per_pass(spec, info)
+    ncol, kpad = gproj_shape(info)
+    us = 1e3 * ms / n
+    flop = 6.0 * nb * ncol * kpad
+    po, pl = alg_bytes(info, spec, "gproj", S=8)
+    byt = po * nb + pl
+    return {"avg_us": round(us, 2), "launches": n, "orbitals": nb, "columns": ncol, "k": kpad,
+            "mfma_tflops": round(flop / (us * 1e-6) / 1e12, 1), "mfma_peak_tflops": 2500.0,
+            "mfma_frac": round(flop / (us * 1e-6) / 2.5e15, 4), "alg_bytes": int(byt),
+            "alg_GBs": round(byt / (us * 1e-6) / 1e9, 1)}
 
 
 def plain_copy_bandwidth(reps=5):
@@ -311,21 +343,40 @@ def run_mixed_large(steps, log):
     res, psi = {}, {}
     for name, prec in (("fp64", ks.KS_FP64), ("mixed", ks.KS_MIXED)):
         _, g, st = setup_workload(spec, prec)
-        ms, kt, phys, _ = run_steps(spec, g, st, steps, 1)
-        psi[name] = st.download()[sample].clone()
-        res[name] = {"ms_per_step": round(ms, 3), "value": round(4 * spec.norb / (ms * 1e-3), 1),
-                     "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"], "tuning": g.tuning,
-                     "kernels": kernel_table(g.info(), spec, kt, steps, ms)}
-        log(f"[bench] 120^3 / {spec.norb} orbitals {name}: {ms:.2f} ms/step, {res[name]['value']:.0f} orbital.Hpsi/s, "
-            f"tuning {g.tuning}")
+        # mixed: the split-BF16 reciprocal-space projections (1), then the
+        # real-space sums (0) from the same start
+        projs = (1, 0) if prec == ks.KS_MIXED else (0,)
+        start = st.download() if len(projs) > 1 else None
+        for proj in projs:
+            key = name if proj == projs[0] else f"{name}_projection_0"
+            if prec == ks.KS_MIXED:
+                g.set_tuning(g.tuning["x_group"], g.tuning["plane_group"], projection=proj)
+                st.upload(start)
+            ms, kt, phys, _ = run_steps(spec, g, st, steps, 1)
+            psi[key] = st.download()[sample].clone()
+            res[key] = {"ms_per_step": round(ms, 3), "value": round(4 * spec.norb / (ms * 1e-3), 1),
+                        "chunk": g.info()["chunk"], "norm_drift_max": phys["norm_drift_max"], "tuning": g.tuning,
+                        "projection": proj, "kernels": kernel_table(g.info(), spec, kt, steps, ms)}
+            if proj == 1:
+                res[key]["gproj"] = gproj_summary(g.info(), spec, kt)
+            log(f"[bench] 120^3 / {spec.norb} orbitals {key}: {ms:.2f} ms/step, {res[key]['value']:.0f} "
+                f"orbital.Hpsi/s, tuning {g.tuning}")
+        del start
         st.close()
         g.close()
-    a, b = psi["mixed"], psi["fp64"]
-    d = (a - b).reshape(len(sample), -1).norm(dim=1) / b.reshape(len(sample), -1).norm(dim=1)
+    b = psi["fp64"]
+    err = {}
+    for key in ("mixed", "mixed_projection_0"):
+        d = (psi[key] - b).reshape(len(sample), -1).norm(dim=1) / b.reshape(len(sample), -1).norm(dim=1)
+        err[key] = float(d.max().item())
+    res["mixed_projection_0"]["orbital_rel_err_vs_fp64_max"] = err["mixed_projection_0"]
+    res["mixed_projection_0"]["speedup_vs_fp64"] = round(
+        res["fp64"]["ms_per_step"] / res["mixed_projection_0"]["ms_per_step"], 3)
+    res["mixed"]["projection_0"] = res.pop("mixed_projection_0")
     return {"workload": f"{spec.n[0]}^3, {spec.norb} orbitals, {spec.natoms} atoms", "steps": 1 + steps,
             "fp64": res["fp64"], "mixed": res["mixed"],
             "speedup_vs_fp64": round(res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"], 3),
-            "orbital_rel_err_vs_fp64_max": float(d.max().item()), "orbitals_compared": len(sample)}
+            "orbital_rel_err_vs_fp64_max": err["mixed"], "orbitals_compared": len(sample)}
 
 
 def run_serving(nreq, nsteps, budget_gb, log, batched=True, max_active=256, lockstep=True, chunk=None):
@@ -443,20 +494,37 @@ def main():
     mixed = None
     if not args.no_mixed:
         _, gm, sm = setup_workload(spec, ks.KS_MIXED, 0)
-        ms_m, kt_m, phys_m, _ = run_steps(spec, gm, sm, args.steps, args.warmup)
-        psim = sm.download()
-        # compare after the same number of steps from the same orthonormalised start
-        d = (psim - psi64).reshape(spec.norb, -1).norm(dim=1) / psi64.reshape(spec.norb, -1).norm(dim=1)
-        mixed = {"value": round(hpsi_per_step / (ms_m * 1e-3), 1), "ms_per_step": round(ms_m, 3),
-                 "speedup_vs_fp64": round(ms_step / ms_m, 3), "orbital_rel_err_vs_fp64_max": float(d.max().item()),
-                 "band_energy_per_electron_diff_vs_fp64":
-                     abs(phys_m["band_energy_per_electron_end"] - phys["band_energy_per_electron_end"]),
-                 "kernels": kernel_table(gm.info(), spec, kt_m, args.steps, ms_m), "chunk": gm.info()["chunk"],
-                 "tuning": gm.tuning}
-        log(f"[bench] mixed: {ms_m:.2f} ms/step ({mixed['speedup_vs_fp64']}x), err vs FP64 {mixed['orbital_rel_err_vs_fp64_max']:.2e}")
+        start = sm.download()        # the orthonormalised start, again for the second projection mode
+        runs = {}
+        # projection 1: the split-BF16 reciprocal-space product; 0: real-space sums in the x-pass
+        for proj in (1, 0):
+            gm.set_tuning(gm.tuning["x_group"], gm.tuning["plane_group"], projection=proj)
+            sm.upload(start)
+            ms_m, kt_m, phys_m, _ = run_steps(spec, gm, sm, args.steps, args.warmup)
+            psim = sm.download()
+            # compare after the same number of steps from the same orthonormalised start
+            d = (psim - psi64).reshape(spec.norb, -1).norm(dim=1) / psi64.reshape(spec.norb, -1).norm(dim=1)
+            runs[proj] = {"value": round(hpsi_per_step / (ms_m * 1e-3), 1), "ms_per_step": round(ms_m, 3),
+                          "speedup_vs_fp64": round(ms_step / ms_m, 3), "projection": proj,
+                          "orbital_rel_err_vs_fp64_max": float(d.max().item()),
+                          "band_energy_per_electron_diff_vs_fp64":
+                              abs(phys_m["band_energy_per_electron_end"] - phys["band_energy_per_electron_end"]),
+                          "kernels": kernel_table(gm.info(), spec, kt_m, args.steps, ms_m),
+                          "chunk": gm.info()["chunk"], "tuning": gm.tuning}
+            if proj == 1:
+                runs[proj]["gproj"] = gproj_summary(gm.info(), spec, kt_m)
+            log(f"[bench] mixed, projection {proj}: {ms_m:.2f} ms/step ({runs[proj]['speedup_vs_fp64']}x), "
+                f"err vs FP64 {runs[proj]['orbital_rel_err_vs_fp64_max']:.2e}")
+            del psim
+        mixed = runs[1]
+        mixed["projection_0"] = {k: runs[0][k] for k in ("value", "ms_per_step", "speedup_vs_fp64",
+                                                         "orbital_rel_err_vs_fp64_max", "kernels")}
+        if mixed["gproj"]:
+            log(f"[bench] split-BF16 projection product: {mixed['gproj']['avg_us']:.1f} us/launch, "
+                f"{mixed['gproj']['mfma_tflops']} TFLOP/s MFMA ({mixed['gproj']['mfma_frac']:.3f} of BF16 peak)")
         sm.close()
         gm.close()
-        del psim
+        del start
     del psi64
 
     mixed_120 = None if (args.no_mixed or args.no_mixed_120) else run_mixed_large(3, log)

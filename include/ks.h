@@ -504,6 +504,7 @@ typedef struct {
   int plane_group;  /* largest orbital group of a plane block (tuning) */
   int x_shape;      /* tile shape of the x-pencil passes (see ks_tuning) */
   int x_threads;    /* threads per block in the x-pencil passes */
+  int projection;   /* how the KB projections are formed (see ks_tuning) */
 } ks_info;
 
 /* Fill *info for sys.  KS_EINVAL on null arguments. */
@@ -531,6 +532,17 @@ typedef struct {
                         32 x 256 above; 1 = 16 pencils x 192 threads (n0 = 96 and 120 only; fewer
                         LDS bytes per block, more blocks resident per compute unit); -1 in
                         ks_system_set_tuning keeps the current shape */
+  int projection;    /* KB projections P_Ip (Eq. vnl): 0 = sphere sums of the synthesised orbitals in the
+                        x-pass (real space; every precision); 1 = KS_MIXED only: the same sums taken in
+                        reciprocal space, P_Ip = sum_G c_G w_Ip(G) with w_Ip(G) = (Omega^1/2 / N) sum_j
+                        beta_Ip(r_j) e^{iG.r_j} tabulated once per set of projectors (d_Ip folded in),
+                        as a split-BF16 product on the
+                        matrix cores (x = hi + lo, a b = hi hi + hi lo + lo hi, FP32 accumulation; about
+                        1e-7 relative on the projections).  Mode 1 holds the table (4 bytes per plane
+                        wave and projector, and FP32 split-K partials of at most 64 MiB for passes of up to
+                        8192 orbitals and 4096 projectors); the density-fused
+                        first sub-step of a propagation with densities keeps the real-space sums.
+                        ks_autotune does not change it; -1 in ks_system_set_tuning keeps it */
 } ks_tuning;
 
 /* Time one H psi pass over min(norb, chunk) orbitals (zero coefficients; the
@@ -554,7 +566,7 @@ ks_status ks_system_set_tuning(ks_system* sys, const ks_tuning* t);
 /* Kernel classes reported by ks_kernel_time. */
 typedef enum {
   KS_K_PACK = 0, KS_K_UNPACK, KS_K_PLANE_INV, KS_K_XPROJ, KS_K_PROJ_REDUCE, KS_K_XAPPLY,
-  KS_K_PLANE_FWD, KS_K_XDENS, KS_K_DOTS, KS_K_GEMM, KS_K_EIG, KS_K_SD, KS_K_COUNT
+  KS_K_PLANE_FWD, KS_K_XDENS, KS_K_DOTS, KS_K_GEMM, KS_K_EIG, KS_K_SD, KS_K_GPROJ, KS_K_COUNT
 } ks_kernel_id;
 
 /*

@@ -444,9 +444,28 @@ void free_workspace(ks_system* s) {
   s->partial_cap = s->dp_cap = 0;
 }
 
+void free_gtab(ks_system* s, GTab& g) {
+  void* w = g.w;
+  void* part = g.part;
+  dfree(s, w);
+  dfree(s, part);
+  g = GTab{};
+}
+
 ks_status alloc_proj_workspace(ks_system* s) {
   dfree(s, s->partial);
   dfree(s, reinterpret_cast<void*&>(s->DP));
+  if (s->gp.P > 0) {   // the reciprocal-space product's partials follow the pass size
+    void* part = s->gp.part;
+    dfree(s, part);
+    s->gp.part = nullptr;
+    s->gp.part_bytes = 0;
+    const size_t bytes = gproj_part_bytes(s->cb, s->gp.ncol, s->gp.kpad / 32);
+    ks_status st = dalloc(s, &part, bytes);
+    if (st != KS_OK) return st;
+    s->gp.part = static_cast<float*>(part);
+    s->gp.part_bytes = bytes;
+  }
   const size_t pbytes = (size_t)s->cb * std::max(1, s->nslots) * std::max(1, s->nproj) * sizeof(double2);
   const size_t dbytes = (size_t)s->cb * std::max(1, s->natoms) * std::max(1, s->nproj) * sizeof(double2);
   ks_status st = dalloc(s, &s->partial, pbytes);
@@ -515,7 +534,10 @@ ks_status hpsi_packed(ks_system* s, int nb, const void* win, bool win_fp64, void
                       void* acc2 = nullptr) {
   ks_status r = kcall(s, KS_K_PLANE_INV, st, "plane_inv", [&] { return launch_plane_inv(s, nb, win, win_fp64, s->T, st); });
   if (r != KS_OK) return r;
-  if (s->natoms > 0) {
+  if (s->natoms > 0 && s->proj_mode == 1 && !rho) {
+    r = kcall(s, KS_K_GPROJ, st, "gproj", [&] { return launch_gproj(s, nb, win, win_fp64, s->DP, st); });
+    if (r != KS_OK) return r;
+  } else if (s->natoms > 0) {
     r = kcall(s, KS_K_XPROJ, st, "xproj", [&] { return launch_xproj(s, nb, s->T, s->partial, occ, rho, accumulate, st); });
     if (r != KS_OK) return r;
     r = kcall(s, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] { return launch_proj_reduce(s, nb, s->partial, s->DP, st); });
@@ -1011,6 +1033,7 @@ void ks_system_destroy(ks_system* s) {
   }
   timing_free(s);
   free_workspace(s);
+  free_gtab(s, s->gp);
   void* ptrs[] = {s->d_plane_col0, s->d_plane_m1lo, s->d_col_off, s->d_col_m2lo, s->d_tw0, s->d_tw1,
                   s->d_tw0f, s->d_tw1f, s->d_v, s->d_vloc, s->d_kin, s->d_hbox, s->d_rho_w, s->d_pt_lds, s->d_slot_off, s->d_slot_atom, s->d_slot_pt,
                   s->d_atom_slot_off, s->d_atom_slots,
@@ -1138,6 +1161,68 @@ static ks_status install_proj(ks_system* s, const ProjHost& ph, int natoms, cons
   return KS_OK;
 }
 
+// The reciprocal-space projection table of the projector inputs (natoms
+// atoms of np projectors; npts, idx, beta, d as ks_system_set_projectors
+// takes them) in fresh device buffers; the caller swaps them in (or frees
+// them).  Synchronous; the caller has waited for the system's work.
+static ks_status build_gtab(ks_system* s, int natoms, int np, const int* npts, const int* idx, const double* beta,
+                            const double* d, GTab& out) {
+  out = GTab{};
+  const int P = natoms * np;
+  if (P == 0) return KS_OK;   // nothing to project
+  std::vector<int> off((size_t)natoms + 1, 0);
+  for (int I = 0; I < natoms; ++I) off[I + 1] = off[I] + npts[I];
+  const size_t npoints = (size_t)off[natoms];
+  GTab g;
+  g.P = P;
+  g.ncol = 2 * ((P + 63) / 64 * 64);
+  g.kpad = (2 * s->npw + 31) / 32 * 32;
+  g.part_bytes = gproj_part_bytes(s->cb, g.ncol, g.kpad / 32);
+  const size_t wbytes = (size_t)g.ncol * 2 * g.kpad * sizeof(__bf16);
+  void *w = nullptr, *part = nullptr, *t_off = nullptr, *t_idx = nullptr, *t_beta = nullptr, *t_d = nullptr;
+  auto release = [&](bool keep) {
+    dfree(s, t_off);
+    dfree(s, t_idx);
+    dfree(s, t_beta);
+    dfree(s, t_d);
+    if (!keep) {
+      dfree(s, w);
+      dfree(s, part);
+    }
+  };
+  ks_status st;
+  if ((st = dalloc(s, &w, wbytes)) != KS_OK || (st = dalloc(s, &part, g.part_bytes)) != KS_OK ||
+      (st = dalloc(s, &t_off, off.size() * sizeof(int))) != KS_OK ||
+      (st = dalloc(s, &t_idx, npoints * sizeof(int))) != KS_OK ||
+      (st = dalloc(s, &t_beta, npoints * np * sizeof(double))) != KS_OK ||
+      (st = dalloc(s, &t_d, (size_t)P * sizeof(double))) != KS_OK) {
+    release(false);
+    return st;
+  }
+  hipError_t e = hipMemcpy(t_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && npoints) e = hipMemcpy(t_idx, idx, npoints * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && npoints) e = hipMemcpy(t_beta, beta, npoints * np * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(t_d, d, (size_t)P * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemsetAsync(w, 0, wbytes, nullptr);
+  if (e == hipSuccess && !launch_gproj_table(s, static_cast<const int*>(t_off), static_cast<const int*>(t_idx),
+                                             static_cast<const double*>(t_beta), static_cast<const double*>(t_d),
+                                             natoms, np, static_cast<__bf16*>(w), g.kpad, nullptr)) {
+    release(false);
+    return fail(s, KS_EUNSUPPORTED, "no reciprocal-space projection table for this grid or projector count");
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) {
+    release(false);
+    return fail(s, KS_EDEVICE, std::string("projection table: ") + hipGetErrorString(e));
+  }
+  release(true);
+  g.w = static_cast<__bf16*>(w);
+  g.part = static_cast<float*>(part);
+  out = g;
+  return KS_OK;
+}
+
 ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const int* npts, const int* idx,
                                    const double* beta, const double* d, void* stream) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
@@ -1154,8 +1239,18 @@ ks_status ks_system_set_projectors(ks_system* s, int natoms, int nproj, const in
   ++s->gen;
   const int na = std::max(0, natoms), np = ph.nproj;
   std::vector<double> dcopy(d, d + (size_t)na * np);
+  GTab fresh;
+  if (s->proj_mode == 1 && ph.npoints > 0) {
+    const ks_status r = build_gtab(s, na, np, npts, idx, beta, dcopy.data(), fresh);
+    if (r != KS_OK) return r;
+  }
   const ks_status r = install_proj(s, ph, na, dcopy.data());
-  if (r != KS_OK) return r;   // the previous tables (and inputs) stay
+  if (r != KS_OK) {
+    free_gtab(s, fresh);
+    return r;   // the previous tables (and inputs) stay
+  }
+  free_gtab(s, s->gp);
+  s->gp = fresh;
   // keep the inputs: another tile shape rebuilds the tables from them
   auto& in = s->proj_in;
   in.natoms = na;
@@ -1189,6 +1284,29 @@ static ks_status set_x_shape(ks_system* s, int shape) {
   s->xnb = nb;
   s->xnt = nt;
   s->ntiles = (s->npl + nb - 1) / nb;
+  return KS_OK;
+}
+
+// Form the KB projections in real space (mode 0) or as the reciprocal-space
+// split-BF16 product (mode 1, mixed precision; the table is built from the
+// stored projector inputs).  A failure leaves the mode and table as they were.
+static ks_status set_projection(ks_system* s, int mode) {
+  if (mode == s->proj_mode) return KS_OK;
+  if (mode != 0 && mode != 1) return fail(s, KS_EINVAL, "projection must be 0 or 1");
+  if (mode == 1 && s->prec != KS_MIXED)
+    return fail(s, KS_EINVAL, "the split-BF16 projection (1) is for mixed-precision systems only");
+  wait_own(s);
+  ++s->gen;
+  GTab fresh;
+  if (mode == 1 && s->natoms > 0) {
+    const auto& in = s->proj_in;
+    const ks_status r = build_gtab(s, in.natoms, in.nproj, in.npts.data(), in.idx.data(), in.beta.data(),
+                                   in.d.data(), fresh);
+    if (r != KS_OK) return r;
+  }
+  free_gtab(s, s->gp);
+  s->gp = fresh;
+  s->proj_mode = mode;
   return KS_OK;
 }
 
@@ -1778,6 +1896,8 @@ ks_status ks_batch_create(ks_state* const* states, int nstates, ks_batch** out) 
       return fail(nullptr, KS_EINVAL, "the states' systems differ in grid, cell, cutoff or precision");
     if (t->sys->xshape != s0->xshape)
       return fail(nullptr, KS_EINVAL, "the states' systems differ in x-tile shape (tuning)");
+    if (t->sys->proj_mode != 0)
+      return fail(nullptr, KS_EINVAL, "batches form the projections in real space (projection 0)");
     for (int i = 0; i < j; ++i)
       if (states[i]->sys == t->sys) return fail(nullptr, KS_EINVAL, "two states of one system (they share its workspace)");
     const int cl = chunk_len(t->sys, t->norb);
@@ -2069,6 +2189,7 @@ ks_status ks_system_info(const ks_system* s, ks_info* info) {
   info->plane_group = s->pg_max;
   info->x_shape = s->xshape;
   info->x_threads = s->xnt;
+  info->projection = s->proj_mode;
   return KS_OK;
 }
 
@@ -2079,6 +2200,10 @@ ks_status ks_system_set_tuning(ks_system* s, const ks_tuning* t) {
   if (!t || t->x_group < 1 || t->x_group > 64 || t->plane_group < 1 || t->plane_group > 64)
     return fail(s, KS_EINVAL, "group caps must lie in [1, 64]");
   if (s->pool_lost) return fail(s, KS_EINVAL, "the system's pool was destroyed");
+  if (t->projection != -1 && t->projection != 0 && t->projection != 1)
+    return fail(s, KS_EINVAL, "projection must be -1, 0 or 1");
+  if (t->projection == 1 && s->prec != KS_MIXED)
+    return fail(s, KS_EINVAL, "the split-BF16 projection (1) is for mixed-precision systems only");
   if (t->x_shape != -1) {
     const ks_status r = set_x_shape(s, t->x_shape);
     if (r != KS_OK) return r;
@@ -2086,6 +2211,7 @@ ks_status ks_system_set_tuning(ks_system* s, const ks_tuning* t) {
   s->xg_max = t->x_group;
   s->pg_max = t->plane_group;
   ++s->gen;
+  if (t->projection != -1) return set_projection(s, t->projection);
   return KS_OK;
 }
 
@@ -2109,7 +2235,7 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
     s->xg_max = found.xg;
     s->pg_max = found.pg;
     ++s->gen;
-    if (out) *out = ks_tuning{s->xg_max, s->pg_max, 0.0, 1, s->xshape};
+    if (out) *out = ks_tuning{s->xg_max, s->pg_max, 0.0, 1, s->xshape, s->proj_mode};
     return KS_OK;
   }
   const bool timing = s->timing;
@@ -2162,7 +2288,7 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = best;
   }
-  if (out) *out = ks_tuning{best.xg, best.pg, (double)best_ms, 0, best.shape};
+  if (out) *out = ks_tuning{best.xg, best.pg, (double)best_ms, 0, best.shape, s->proj_mode};
   return done(KS_OK);
 }
 

@@ -71,6 +71,18 @@ struct BatchJob {
   int nb;             // orbitals
 };
 
+// Reciprocal-space projection table of the mixed-precision path (k_gproj.hip):
+// W_Ip(G) of the P = natoms * nproj projectors in real form, split into BF16
+// hi and lo parts, [ncol][kpad / 8][16] (per column and group of 8 k: 8 hi,
+// then 8 lo), ncol = 2 * P rounded up to a multiple of 128 columns, kpad =
+// 2 * npw rounded up to a multiple of 32; and the split-K partial products.
+struct GTab {
+  __bf16* w = nullptr;
+  float* part = nullptr;
+  size_t part_bytes = 0;
+  int ncol = 0, kpad = 0, P = 0;
+};
+
 // up_key fields
 constexpr int UP_POS_BITS = 16, UP_SLOT_BITS = 8;
 constexpr int UP_MAX_SLOT = (1 << UP_SLOT_BITS) - 1, UP_MAX_EXTRA = 127;
@@ -145,11 +157,16 @@ struct ks_system {
   bool yz_half = false;  // every sphere point has |m1| < n1/4 and |m2| < n2/4 (band-limited y, z transforms)
   int xg_max = 8, pg_max = 8;   // orbital-group caps of the x-pencil and plane passes (tunable)
   int xc = 0;                   // exchange-correlation term of the density-dependent potential (ks_xc)
+  // projections: 0 = summed in the x-pass from the synthesised orbitals
+  // (real space), 1 = the reciprocal-space split-BF16 product with the table
+  // gp (mixed precision; ks_tuning.projection)
+  int proj_mode = 0;
   int *d_pt_lds = nullptr, *d_slot_off = nullptr, *d_slot_atom = nullptr, *d_slot_pt = nullptr,
       *d_atom_slot_off = nullptr, *d_atom_slots = nullptr, *d_up_off = nullptr, *d_up_key = nullptr,
       *d_up_x = nullptr, *d_x_slot = nullptr;
   double *d_beta = nullptr, *d_up_beta = nullptr, *d_x_beta = nullptr, *d_kb = nullptr;
   int4* d_item = nullptr;
+  ks::GTab gp;
   // the projector inputs as last set, kept so the per-tile tables can be
   // rebuilt for another tile shape
   struct {
@@ -294,6 +311,17 @@ bool launch_cholesky(int n, double2* S, double2* X, double* diag0, int* info, hi
 // X = L^-1 (lower, upper triangle zero), given the diagonal blocks from launch_cholesky
 bool launch_trtri(int n, const double2* L, double2* X, hipStream_t st);
 bool launch_apply_lower(int norb, int npw, const double2* X, const double2* P, int ldp, double2* Y, hipStream_t st);
+
+// reciprocal-space projections (k_gproj.hip): k-chunks of a product over nb
+// orbitals, the partial-product bytes of passes of up to cb orbitals, the
+// table W (zeroed by the caller) from the projector inputs (pt_off
+// [natoms+1] point offsets, idx, beta [points][np], d [natoms][np], all in
+// device memory), and DP [nb][natoms][nproj] from the packed orbitals win
+bool launch_gproj_table(const ks_system* s, const int* pt_off, const int* idx, const double* beta, const double* d,
+                        int natoms, int np, __bf16* W, int kpad, hipStream_t st);
+int gproj_splits(int nb, int ncol, int ksteps);
+size_t gproj_part_bytes(int cb, int ncol, int ksteps);
+bool launch_gproj(const ks_system* s, int nb, const void* win, bool win_fp64, double2* DP, hipStream_t st);
 
 // v = V_H[rho] (+ vloc when not null); uses the system's work box
 bool launch_hartree(const ks_system* s, const double* rho, double* v, const double* vloc, hipStream_t st);

@@ -22,13 +22,13 @@ KS_OK, KS_EINVAL, KS_ENOMEM, KS_EDEVICE, KS_EUNSUPPORTED = range(5)
 KS_FP64, KS_MIXED = 0, 1
 KS_XC_NONE, KS_XC_LDA = 0, 1
 KERNELS = ["pack", "unpack", "plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dots",
-           "gemm", "eig", "sd"]
+           "gemm", "eig", "sd", "gproj"]
 
 
 class Info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int) for f in ("npw", "nplanes", "ncols", "chunk", "natoms", "nproj", "nruns",
                                             "nslots", "npoints", "x_tile", "precision", "x_half", "x_group",
-                                            "plane_group", "x_shape", "x_threads")]
+                                            "plane_group", "x_shape", "x_threads", "projection")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -36,7 +36,7 @@ class Info(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("x_group", ctypes.c_int), ("plane_group", ctypes.c_int), ("ms", ctypes.c_double),
-                ("from_cache", ctypes.c_int), ("x_shape", ctypes.c_int)]
+                ("from_cache", ctypes.c_int), ("x_shape", ctypes.c_int), ("projection", ctypes.c_int)]
 
 
 _STATUS = {1: "KS_EINVAL", 2: "KS_ENOMEM", 3: "KS_EDEVICE", 4: "KS_EUNSUPPORTED"}
@@ -404,15 +404,18 @@ class System:
         """Time the launch-schedule candidates (x-tile shape and orbital-group
         caps) for H psi over `norb` orbitals and keep the fastest (cached per
         process by grid, precision and size).  Returns {x_group, plane_group,
-        ms, from_cache, x_shape}."""
+        ms, from_cache, x_shape, projection}; the projection mode is kept."""
         t = Tuning()
         self._check(_lib.ks_autotune(self._h, int(norb), _stream(), ctypes.byref(t)))
         return {"x_group": t.x_group, "plane_group": t.plane_group, "ms": t.ms, "from_cache": bool(t.from_cache),
-                "x_shape": t.x_shape}
+                "x_shape": t.x_shape, "projection": t.projection}
 
-    def set_tuning(self, x_group, plane_group, x_shape=None):
-        """Set the group caps and, unless x_shape is None, the x-tile shape."""
-        t = Tuning(int(x_group), int(plane_group), 0.0, 0, -1 if x_shape is None else int(x_shape))
+    def set_tuning(self, x_group, plane_group, x_shape=None, projection=None):
+        """Set the group caps and, unless None, the x-tile shape and the
+        projection mode (0: real-space sums; 1: reciprocal-space split-BF16
+        product, mixed precision only)."""
+        t = Tuning(int(x_group), int(plane_group), 0.0, 0, -1 if x_shape is None else int(x_shape),
+                   -1 if projection is None else int(projection))
         self._check(_lib.ks_system_set_tuning(self._h, ctypes.byref(t)))
 
     def hartree(self, rho, add_vloc=False, out=None):

@@ -27,7 +27,7 @@ import os
 import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CLASSES = ("plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dens_sum", "dots", "unpack",
+CLASSES = ("gproj_gemm", "gproj_reduce", "gproj_table", "plane_inv", "xproj", "proj_reduce", "xapply", "plane_fwd", "xdens", "dens_sum", "dots", "unpack",
            "pack_kernel", "bj_solve", "bj_apply", "zgemm", "potrf", "trsm", "trinv", "herk", "sd_direction", "sd_update")
 COPY_KIB = 1048576.0   # the calibration copy moves 1 GiB each way
 
