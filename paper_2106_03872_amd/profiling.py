@@ -45,8 +45,9 @@ def csrc_fingerprint():
 
 def short_name(name):
     """Kernel name without namespaces, argument list and vector type noise."""
-    n = re.sub(r"\(.*\)$", "", name)
-    n = n.replace("void ", "").replace("ks::", "").replace("(anonymous namespace)::", "")
+    n = name.replace("(anonymous namespace)::", "")
+    n = re.sub(r"\(.*\)$", "", n)
+    n = n.replace("void ", "").replace("ks::", "")
     n = n.replace("HIP_vector_type<double, 2u>", "double2").replace("HIP_vector_type<float, 2u>", "float2")
     return n
 
