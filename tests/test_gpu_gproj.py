@@ -7,7 +7,9 @@ H psi against the FP64 oracle at the mixed-precision target (1e-5) on small
 systems that leave ragged orbital, column and k tails, with 1, 3, 4 and 8
 projectors per atom, over several passes, at the 96^3 / 512-orbital /
 128-atom and 120^3 / 1024-orbital / 256-atom sizes on sampled orbitals;
-propagation (with and without the per-step densities) against the oracle;
+propagation (with and without the per-step densities, resident over several
+passes) and ETRS with the Hartree and local-density xc potentials against the
+oracle;
 the band energy after 50 steps against the FP64 path; mode switches, graph
 replays, refused cases and a table that does not fit.
 """
@@ -127,6 +129,57 @@ def test_gproj_propagation_vs_oracle(ks):
     b = c.clone()
     gs.propagate_step(b, spec.dt, spec.nsteps)
     assert rel_err(b.cpu().numpy(), ref) < TOL_H
+    gs.close()
+
+
+def test_gproj_resident_passes_and_etrs_vs_oracle(ks):
+    """Resident states in mode 1: Taylor-4 steps with per-step densities over
+    passes of 4 orbitals (10 orbitals: passes of 4, 3, 3), and ETRS under the
+    density-dependent Hamiltonian with the local-density xc term, both
+    against the oracle."""
+    print("[case] gproj resident passes and ETRS", file=sys.stderr, flush=True)
+    spec = synth.CONFIGS["t24"]
+    sysm = synth.system(spec)
+    ham = oracle_ham(sysm)
+    c = orbitals_device(spec)
+    c0 = c.cpu().numpy()
+    occ_np = synth.occupations(spec)
+    occ = torch.from_numpy(occ_np).cuda()
+    gs = _mode1(ks, sysm, chunk=4)
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    K = 3
+    rho = torch.empty((K,) + spec.n, dtype=torch.float64, device="cuda")
+    st.propagate(spec.dt, K, occ, rho)
+    ref = c0
+    for k in range(K):
+        ref = ko.taylor4_step(ham, ref, spec.dt, 1)
+        rr = ko.density(ham, ref, occ_np)
+        assert np.linalg.norm(rho[k].cpu().numpy() - rr) / np.linalg.norm(rr) < TOL_H, k
+    assert rel_err(st.download().cpu().numpy(), ref) < TOL_H
+    st.close()
+    gs.close()
+    # ETRS with V_H and v_xc (t48: 33 orbitals, 6 atoms), orthonormalised start
+    spec = synth.CONFIGS["t48"]
+    sysm = synth.system(spec)
+    ham = oracle_ham(sysm)
+    gs = _mode1(ks, sysm)
+    gs.set_xc(ks.KS_XC_LDA)
+    c = orbitals_device(spec)
+    gs.orthonormalize(c)
+    c0 = c.cpu().numpy()
+    occ_np = np.full(spec.norb, 2.0)
+    occ = torch.from_numpy(occ_np).cuda()
+    st = ks.State(gs, spec.norb)
+    st.upload(c)
+    rho = torch.empty((K,) + spec.n, dtype=torch.float64, device="cuda")
+    st.propagate_etrs(spec.dt, K, occ, rho)
+    ref, dens = ko.etrs_step(ham, c0, spec.dt, occ_np, nsteps=K, xc=True)
+    err = rel_err(st.download().cpu().numpy(), ref)
+    print(f"[gproj] ETRS with xc, 3 steps: orbitals {err:.2e}", file=sys.stderr)
+    assert err < TOL_H
+    assert np.linalg.norm(rho[-1].cpu().numpy() - dens[-1]) / np.linalg.norm(dens[-1]) < TOL_H
+    st.close()
     gs.close()
 
 
