@@ -127,7 +127,7 @@ ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], 
  * per pass set at creation: chunk > 0 sizes the workspace (plane
  * intermediates, packed pass buffers, projection partials) for
  * min(chunk, max_norb) orbitals, chunk == 0 takes the default (as many
- * orbitals as 4 GiB of plane intermediates hold).  Calls over more orbitals
+ * orbitals as 16 GiB of plane intermediates hold).  Calls over more orbitals
  * run in passes, with the same results.  A caller that holds many systems
  * (serving) trades passes for memory this way without the default
  * workspace ever being allocated.  KS_EINVAL for chunk < 0, otherwise as
@@ -446,7 +446,7 @@ int ks_system_npw(const ks_system* sys);
 
 /* Largest number of orbitals processed per pass (chunk size of the internal
  * pipeline).  The default is min(max_norb, the count whose plane intermediate
- * takes 4 GiB).  A call over norb orbitals runs ceil(norb / chunk) passes of
+ * takes 16 GiB).  A call over norb orbitals runs ceil(norb / chunk) passes of
  * equal size (up to one orbital). */
 int ks_system_chunk(const ks_system* sys);
 

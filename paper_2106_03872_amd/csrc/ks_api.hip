@@ -499,8 +499,9 @@ ks_status alloc_workspace(ks_system* s) {
 }
 
 // Default orbitals per pass: as many as give KS_CHUNK_BYTES of plane
-// intermediate T (larger passes mean fewer, fuller launches).
-constexpr double KS_CHUNK_BYTES = 4.0 * 1024 * 1024 * 1024;
+// intermediate T (larger passes mean fewer, fuller launches; 1024 orbitals
+// of a 120^3 grid in one pass: 12.5 GB each for T and U in FP64).
+constexpr double KS_CHUNK_BYTES = 16.0 * 1024 * 1024 * 1024;
 
 int default_chunk(const ks_system* s) {
   const double per = (double)s->nplanes * s->npl * (s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2));

@@ -128,13 +128,14 @@ def test_mixed_etrs_vs_oracle(ks):
 
 
 def test_mixed_full_size_120_sampled(ks):
-    """120^3 grid, 1024 orbitals, 256 atoms (several passes per call): mixed
+    """120^3 grid, 1024 orbitals, 256 atoms (several passes per call: 3 in
+    FP64, 2 in mixed precision; the default is one pass): mixed
     H psi on sampled orbitals against the oracle, and the band energy after 50
     Taylor-4 steps against the FP64 path on the same orthonormalised start."""
     spec, sysm = _case("cfg4_120")
     ham = oracle_ham(sysm)
-    g64 = ks.system_from_synth(sysm)
-    gmx = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
+    g64 = ks.system_from_synth(sysm, chunk=400)
+    gmx = ks.system_from_synth(sysm, precision=ks.KS_MIXED, chunk=512)
     c = orbitals_device(spec)
     # H psi on the generator's orbitals (the oracle's input never comes from the library)
     sample = [0, 511, spec.norb - 1]
