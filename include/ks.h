@@ -436,7 +436,9 @@ ks_status ks_propagate_batch(ks_state* const* states, int nstates, double dt, in
 /*
  * Device bytes a system of this shape plus a resident state of norb orbitals
  * will hold (host-only estimate for admission control; npoints = projector
- * points, chunk = 0 for the default chunk).
+ * points, chunk = 0 for the default chunk).  Counts the real-space
+ * projections (ks_tuning.projection = 0); projection 1 adds its table and
+ * partials (see ks_tuning).
  */
 ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int precision, int norb, int npoints,
                             int nproj, int chunk, unsigned long long* bytes);
