@@ -10,6 +10,22 @@
   python -m paper_2106_03872_amd.profiling counters <dir> [<dir> ...]
       markdown table of per-dispatch SQ counters (mean over the dispatches of
       each kernel's most frequent launch shape)
+  python -m paper_2106_03872_amd.profiling waves <dir> [<dir> ...]
+      the same runs as fractions of SQ_WAVE_CYCLES (issuing, waiting on
+      counters or barriers, waiting on dependencies, VALU and LDS active) and
+      LDS bank-conflict cycles per LDS instruction, per pass
+  python -m paper_2106_03872_amd.profiling mfma <dir> [--match S] [--model-flops F]
+      matrix-core use per dispatch of the kernels that issue MFMAs: BF16
+      flops counted (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512), busy fraction
+      SQ_VALU_MFMA_BUSY_CYCLES / (SIMDs x GRBM_GUI_ACTIVE / XCDs), LDS
+      bank-conflict cycles per LDS instruction
+  python -m paper_2106_03872_amd.profiling durations <kernel_trace.csv> --match S [--split-at M]
+      launch durations of the kernels whose names contain S, grouped by name
+      and by whether the dispatch comes before the first kernel whose name
+      contains M
+  python -m paper_2106_03872_amd.profiling kerneltraffic <fetch_dir> <write_dir> --match S --scale-from <record.json>
+      FETCH_SIZE / WRITE_SIZE per dispatch of the kernels whose names contain
+      S, scaled by the calibration factors of a traffic record
 
 Each pass is keyed by its class (xapply, xproj, ...); the launch counted is
 the (kernel, grid) pair with the most dispatches, which in a benchmark run is
@@ -147,6 +163,89 @@ def counters_table(dirs):
     return "\n".join(out)
 
 
+SIMDS, XCDS = 1024, 8   # MI355X: 256 compute units of 4 SIMDs in 8 XCDs
+
+
+def _by_kernel(dirs, match=None):
+    """short kernel name -> counter -> values, over the counter runs in dirs."""
+    out = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for r in _counter_rows(d):
+            if match is None or match in r["Kernel_Name"]:
+                out[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def waves_table(dirs, classes=("plane_inv", "xproj", "xapply", "plane_fwd", "xdens")):
+    rows = []
+    for d in dirs:
+        rows += _counter_rows(d)
+    by = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(list)))
+    for r in rows:
+        k = kernel_class(r["Kernel_Name"])
+        if k is not None and k != "copy":
+            by[k][(r["Kernel_Name"], _grid(r))][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = ["| kernel | issuing (`ACTIVE_INST_ANY`) | waiting on counters or barriers (`WAIT_ANY`) | "
+           "waiting on dependencies (`WAIT_INST_ANY`) | VALU active | LDS active | "
+           "LDS bank-conflict cycles per LDS instruction |", "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in classes:
+        if k not in by:
+            continue
+        (name, grid), cs = max(by[k].items(), key=lambda kv: (max(len(v) for v in kv[1].values()), kv[0][1]))
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        wc = m["SQ_WAVE_CYCLES"]
+        out.append(f"| `{short_name(name)}` | {m['SQ_ACTIVE_INST_ANY'] / wc:.3f} | {m['SQ_WAIT_ANY'] / wc:.3f} | "
+                   f"{m['SQ_WAIT_INST_ANY'] / wc:.3f} | {m['SQ_ACTIVE_INST_VALU'] / wc:.3f} | "
+                   f"{m['SQ_ACTIVE_INST_LDS'] / wc:.3f} | "
+                   f"{m['SQ_LDS_BANK_CONFLICT'] / max(1.0, m['SQ_INSTS_LDS']):.3f} |")
+    return "\n".join(out)
+
+
+def mfma_table(d, match=None, model_flops=None):
+    by = _by_kernel([d], match)
+    out = ["| kernel | dispatches | BF16 MFMA flops (`MOPS_BF16` x 512) | model flops | MFMA busy "
+           "(`SQ_VALU_MFMA_BUSY_CYCLES` / (1024 SIMDs x `GRBM_GUI_ACTIVE` / 8 XCDs)) | "
+           "LDS bank-conflict cycles per LDS instruction |", "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(by):
+        m = {c: sum(v) / len(v) for c, v in by[k].items()}
+        if m.get("SQ_INSTS_MFMA", 0.0) == 0.0:
+            continue
+        fl = m.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512
+        busy = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * m["GRBM_GUI_ACTIVE"] / XCDS)
+        mf = f"{model_flops:.4g}" if model_flops else ""
+        out.append(f"| `{k}` | {len(by[k]['SQ_INSTS_MFMA'])} | {fl:.4g} | {mf} | {busy:.3f} | "
+                   f"{m['SQ_LDS_BANK_CONFLICT'] / max(1.0, m['SQ_INSTS_LDS']):.2f} |")
+    return "\n".join(out)
+
+
+def durations_table(trace, match, split_at=None, labels=("before", "after")):
+    rows = sorted(csv.DictReader(open(trace)), key=lambda r: int(r["Dispatch_Id"]))
+    cut = None
+    if split_at:
+        cut = next((int(r["Dispatch_Id"]) for r in rows if split_at in r["Kernel_Name"]), None)
+    dur = collections.defaultdict(list)
+    for r in rows:
+        if match in r["Kernel_Name"]:
+            ph = labels[0] if cut is None or int(r["Dispatch_Id"]) < cut else labels[1]
+            dur[(ph, short_name(r["Kernel_Name"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["| part of the run | kernel | launches | mean us | min us | max us |", "|---|---|---:|---:|---:|---:|"]
+    for (ph, k), v in sorted(dur.items()):
+        out.append(f"| {ph} | `{k}` | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+    return "\n".join(out)
+
+
+def kernel_traffic_table(fetch_dir, write_dir, match, record):
+    rec = json.load(open(record))
+    fs, ws = rec["fetch_scale"], rec["write_scale"]
+    F, W = _by_kernel([fetch_dir], match), _by_kernel([write_dir], match)
+    out = ["| kernel | dispatches | FETCH KiB | WRITE KiB | counted MB per launch |", "|---|---:|---:|---:|---:|"]
+    for k in sorted(set(F) & set(W)):
+        f = sum(F[k]["FETCH_SIZE"]) / len(F[k]["FETCH_SIZE"])
+        w = sum(W[k]["WRITE_SIZE"]) / len(W[k]["WRITE_SIZE"])
+        out.append(f"| `{k}` | {len(F[k]['FETCH_SIZE'])} | {f:.0f} | {w:.0f} | {(f * fs + w * ws) * 1024 / 1e6:.1f} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -161,6 +260,22 @@ def main(argv=None):
     b.add_argument("--workload", default="cfg3_96")
     c = sub.add_parser("counters")
     c.add_argument("dirs", nargs="+")
+    w = sub.add_parser("waves")
+    w.add_argument("dirs", nargs="+")
+    m = sub.add_parser("mfma")
+    m.add_argument("dir")
+    m.add_argument("--match", default=None)
+    m.add_argument("--model-flops", type=float, default=None)
+    u = sub.add_parser("durations")
+    u.add_argument("trace")
+    u.add_argument("--match", required=True)
+    u.add_argument("--split-at", default=None)
+    u.add_argument("--labels", nargs=2, default=("before", "after"))
+    t = sub.add_parser("kerneltraffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--match", required=True)
+    t.add_argument("--scale-from", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats_table(args.csv, args.top))
@@ -169,8 +284,16 @@ def main(argv=None):
         with open(args.out, "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec, indent=1))
-    else:
+    elif args.cmd == "counters":
         print(counters_table(args.dirs))
+    elif args.cmd == "waves":
+        print(waves_table(args.dirs))
+    elif args.cmd == "mfma":
+        print(mfma_table(args.dir, args.match, args.model_flops))
+    elif args.cmd == "durations":
+        print(durations_table(args.trace, args.match, args.split_at, tuple(args.labels)))
+    else:
+        print(kernel_traffic_table(args.fetch_dir, args.write_dir, args.match, args.scale_from))
 
 
 if __name__ == "__main__":

@@ -53,3 +53,57 @@ def test_stats_table(tmp_path):
     t = profiling.stats_table(str(p)).splitlines()
     assert t[2].startswith("| `xapply_kernel<96, XShape<32, 256>, double, true, false>` | 4 | 6.000 | 1500.00")
     assert "dots_kernel" in t[3]
+
+
+def _write_counters(d, rows):
+    """rows: (kernel, grid, counter, value) -> run_counter_collection.csv in d."""
+    d.mkdir(parents=True)
+    with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (name, grid, counter, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+GP = "void ks::(anonymous namespace)::gproj_gemm_kernel<float>(float const*, long long, int)"
+
+
+def test_mfma_table_busy_fraction_and_flops(tmp_path):
+    c = {"SQ_INSTS_MFMA": 100.0, "SQ_INSTS_VALU_MFMA_MOPS_BF16": 1000.0, "SQ_VALU_MFMA_BUSY_CYCLES": 1024 * 50.0,
+         "GRBM_GUI_ACTIVE": 8 * 200.0, "SQ_LDS_BANK_CONFLICT": 30.0, "SQ_INSTS_LDS": 10.0}
+    rows = [(GP, 4096, k, v) for k, v in c.items()] * 2
+    rows += [(XA, 100, "SQ_INSTS_MFMA", 0.0)]                     # no matrix work: left out
+    _write_counters(tmp_path / "m", rows)
+    t = profiling.mfma_table(str(tmp_path / "m"), model_flops=512000.0).splitlines()
+    assert len(t) == 3
+    assert t[2] == "| `gproj_gemm_kernel<float>` | 2 | 5.12e+05 | 5.12e+05 | 0.250 | 3.00 |"
+
+
+def test_waves_table_fractions(tmp_path):
+    c = {"SQ_WAVE_CYCLES": 1000.0, "SQ_ACTIVE_INST_ANY": 300.0, "SQ_WAIT_ANY": 500.0, "SQ_WAIT_INST_ANY": 200.0,
+         "SQ_ACTIVE_INST_VALU": 150.0, "SQ_ACTIVE_INST_LDS": 80.0, "SQ_LDS_BANK_CONFLICT": 50.0, "SQ_INSTS_LDS": 100.0}
+    _write_counters(tmp_path / "s", [(XA, 200, k, v) for k, v in c.items()])
+    t = profiling.waves_table([str(tmp_path / "s")]).splitlines()
+    assert t[2] == "| `xapply_kernel<96, XShape<32, 256>, double, true, false>` | 0.300 | 0.500 | 0.200 | 0.150 | 0.080 | 0.500 |"
+
+
+def test_durations_split_and_kernel_traffic(tmp_path):
+    p = tmp_path / "trace.csv"
+    with open(p, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        w.writerow({"Dispatch_Id": 1, "Kernel_Name": GP, "Start_Timestamp": 0, "End_Timestamp": 2000})
+        w.writerow({"Dispatch_Id": 2, "Kernel_Name": GP, "Start_Timestamp": 0, "End_Timestamp": 4000})
+        w.writerow({"Dispatch_Id": 3, "Kernel_Name": "void ks::xapply_kernel<120, x>(int)", "Start_Timestamp": 0,
+                    "End_Timestamp": 1})
+        w.writerow({"Dispatch_Id": 4, "Kernel_Name": GP, "Start_Timestamp": 0, "End_Timestamp": 9000})
+    t = profiling.durations_table(str(p), "gproj", "<120", ("small", "large")).splitlines()
+    assert t[2] == "| large | `gproj_gemm_kernel<float>` | 1 | 9.0 | 9.0 | 9.0 |"
+    assert t[3] == "| small | `gproj_gemm_kernel<float>` | 2 | 3.0 | 2.0 | 4.0 |"
+    _write_counters(tmp_path / "f", [(GP, 4096, "FETCH_SIZE", 100.0)])
+    _write_counters(tmp_path / "w", [(GP, 4096, "WRITE_SIZE", 50.0)])
+    rec = tmp_path / "rec.json"
+    rec.write_text(json.dumps({"fetch_scale": 2.0, "write_scale": 1.0}))
+    t = profiling.kernel_traffic_table(str(tmp_path / "f"), str(tmp_path / "w"), "gproj", str(rec)).splitlines()
+    assert t[2] == f"| `gproj_gemm_kernel<float>` | 1 | 100 | 50 | {(100 * 2 + 50) * 1024 / 1e6:.1f} |"
