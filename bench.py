@@ -137,7 +137,8 @@ def measured_traffic(kernel, workload, orbitals_per_pass, info):
     k = rec.get("kernels", {}).get(kernel)
     if k is None:
         return None
-    if kernel.startswith("x") and f"XShape<{info['x_tile']}, {info['x_threads']}>" not in k.get("kernel", ""):
+    shape = "XShapeAlt" if info.get("x_shape", 0) >= 2 else "XShape"   # shapes 2, 3: second radix plan
+    if kernel.startswith("x") and f"{shape}<{info['x_tile']}, {info['x_threads']}>" not in k.get("kernel", ""):
         return None
     return k["bytes_per_launch"]
 

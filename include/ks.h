@@ -530,9 +530,11 @@ typedef struct {
   int plane_group;   /* cap on orbitals per plane block, 1..64 */
   double ms;         /* measured time of one H psi pass over the tuned orbital count (0 if not measured) */
   int from_cache;    /* 1 if the result came from the process-wide cache */
-  int x_shape;       /* tile shape of the x-pencil passes: 0 = 64 pencils x 256 threads for n0 <= 32,
-                        32 x 256 above; 1 = 16 pencils x 192 threads (n0 = 96 and 120 only; fewer
-                        LDS bytes per block, more blocks resident per compute unit); -1 in
+  int x_shape;       /* launch shape of the x-pencil passes (tile and x-transform factorisation):
+                        0 = 64 pencils x 256 threads for n0 <= 32, 32 x 256 above; 1 = 16 pencils x
+                        192 threads (n0 = 96 and 120 only; fewer LDS bytes per block, more blocks
+                        resident per compute unit); 2 and 3 = the tiles of 0 and 1 with the second
+                        radix plan of the x-transform (n0 = 96 only: 8 x 12 instead of 12 x 8); -1 in
                         ks_system_set_tuning keeps the current shape */
   int projection;    /* KB projections P_Ip (Eq. vnl): 0 = sphere sums of the synthesised orbitals in the
                         x-pass (real space; every precision); 1 = KS_MIXED only: the same sums taken in
@@ -548,8 +550,11 @@ typedef struct {
 } ks_tuning;
 
 /* Time one H psi pass over min(norb, chunk) orbitals (zero coefficients; the
- * kernels' timing does not depend on the values) for each candidate of tile
- * shape and group caps on `stream`, keep the fastest, and return it in *out
+ * kernels' timing does not depend on the values) for each candidate of
+ * x-pass shape (tile and radix plan) and group caps on `stream`, keep the
+ * fastest (a shape later in the order 0..3 only when it is at least 1 % faster
+ * than the best earlier one, so that near-ties do not flip between runs), and
+ * return it in *out
  * (nullable).  A change of tile shape rebuilds the per-tile projector tables
  * from the inputs of the last ks_system_set_projectors.
  * Results are cached per process by (grid, precision, number of sphere

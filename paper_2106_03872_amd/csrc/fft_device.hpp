@@ -212,6 +212,14 @@ template <> struct plan<100> { using list = radix_list<10, 10>; };
 template <> struct plan<120> { using list = radix_list<12, 10>; };
 template <> struct plan<128> { using list = radix_list<8, 4, 4>; };
 
+// A second factorisation for the x-pencil transforms of some lengths (the
+// launch-schedule autotuner times both): variant 0 is plan<N>, variant 1
+// alt_plan<N>.  A band-limited first stage needs a first radix divisible by 4.
+template <int N> struct alt_plan;
+template <> struct alt_plan<96> { using list = radix_list<8, 12>; };
+template <int N, int V> struct plan_v { using list = typename plan<N>::list; };
+template <int N> struct plan_v<N, 1> { using list = typename alt_plan<N>::list; };
+
 // Where a stage reads from / writes to.  LDS stages work in place on the
 // batch buffer; the first stage may instead pull its inputs from a loader
 // functor and the last stage may push its outputs to a store functor.
@@ -364,9 +372,9 @@ __device__ __forceinline__ void fft_io_impl(radix_list<Rs...>, T* buf, int ts, i
 // (DST_LDS) or store (DST_FN, DST_FN_LDS).  The caller must synchronise the
 // block before a SRC_FN call whose first stage overwrites buf, and after a
 // DST_FN call before buf is overwritten.
-template <int N, int SIGN, int NB, int NT, int SRC, int DST, typename T, class Load, class Store>
+template <int N, int SIGN, int NB, int NT, int SRC, int DST, typename T, int V = 0, class Load, class Store>
 __device__ __forceinline__ void fft_io(T* buf, int ts, int ntrans, const T* tw, Load&& load, Store&& store) {
-  fft_io_impl<N, SIGN, NB, NT, SRC, DST, T>(typename plan<N>::list{}, buf, ts, ntrans, tw, load, store);
+  fft_io_impl<N, SIGN, NB, NT, SRC, DST, T>(typename plan_v<N, V>::list{}, buf, ts, ntrans, tw, load, store);
 }
 
 // First-stage inputs of one batch held in registers, so that the loads of the
@@ -379,6 +387,7 @@ template <int N, int NB, int NT, typename T, int R, int... Rest, bool HALF>
 struct first_stage_regs<N, NB, NT, T, radix_list<R, Rest...>, HALF> {
   static_assert(!HALF || R % 4 == 0, "band-limited input needs a first radix divisible by 4");
   static constexpr int radix = R;
+  static constexpr int nb = NB, nt = NT;
   static constexpr int NBF = N / R;
   static constexpr int TOT = NB * NBF;
   static constexpr int items = (TOT + NT - 1) / NT;
@@ -388,8 +397,8 @@ struct first_stage_regs<N, NB, NT, T, radix_list<R, Rest...>, HALF> {
   T v[items][nq];
   __device__ __forceinline__ T get(int it, int q) const { return held(q) ? v[it][slot(q)] : T{0, 0}; }
 };
-template <int N, int NB, int NT, typename T, bool HALF = false>
-using fft_regs = first_stage_regs<N, NB, NT, T, typename plan<N>::list, HALF>;
+template <int N, int NB, int NT, typename T, bool HALF = false, int V = 0>
+using fft_regs = first_stage_regs<N, NB, NT, T, typename plan_v<N, V>::list, HALF>;
 
 // SRC_PRE source: r holds the first-stage inputs; refill() is called once the
 // first stage has consumed them and written its outputs, so that the loads it
@@ -404,10 +413,11 @@ __device__ __forceinline__ pre_src<FR, F> preloaded(FR& r, F refill) {
   return pre_src<FR, F>{r, refill};
 }
 
-// Load the first-stage inputs of transforms t < ntrans: load(t, e) as in fft_io.
-template <int N, int NB, int NT, typename T, bool HALF, class Load>
-__device__ __forceinline__ void fft_preload(fft_regs<N, NB, NT, T, HALF>& r, int ntrans, Load&& load) {
-  using FR = fft_regs<N, NB, NT, T, HALF>;
+// Load the first-stage inputs of transforms t < ntrans into the register
+// set r (an fft_regs): load(t, e) as in fft_io.
+template <class FR, class Load>
+__device__ __forceinline__ void fft_preload_regs(FR& r, int ntrans, Load&& load) {
+  constexpr int NB = FR::nb, NT = FR::nt;
   const int tid = fresh_tid<NT>();
 #pragma unroll
   for (int it = 0; it < FR::items; ++it) {
@@ -419,6 +429,10 @@ __device__ __forceinline__ void fft_preload(fft_regs<N, NB, NT, T, HALF>& r, int
         if (FR::held(q)) r.v[it][FR::slot(q)] = load(t, b + q * FR::NBF);
     }
   }
+}
+template <int N, int NB, int NT, typename T, bool HALF, class Load>
+__device__ __forceinline__ void fft_preload(fft_regs<N, NB, NT, T, HALF>& r, int ntrans, Load&& load) {
+  fft_preload_regs(r, ntrans, load);
 }
 
 // In-place DFT of transforms in buf (natural order in and out).
@@ -453,9 +467,9 @@ __device__ __forceinline__ void last_positions_run(radix_list<R, Rest...>, int n
   else last_positions_run<N, NB, NT, NSacc * R>(radix_list<Rest...>{}, ntrans, f);
 }
 
-template <int N, int NB, int NT, class F>
+template <int N, int NB, int NT, int V = 0, class F>
 __device__ __forceinline__ void last_stage_positions(int ntrans, F&& f) {
-  last_positions_run<N, NB, NT, 1>(typename plan<N>::list{}, ntrans, f);
+  last_positions_run<N, NB, NT, 1>(typename plan_v<N, V>::list{}, ntrans, f);
 }
 
 // number of (item, q) slots per thread in the last stage
@@ -466,7 +480,8 @@ template <int N, int NB, int NT, int R> struct last_stage_shape<N, NB, NT, radix
 };
 template <int N, int NB, int NT, int R, int R2, int... Rest>
 struct last_stage_shape<N, NB, NT, radix_list<R, R2, Rest...>> : last_stage_shape<N, NB, NT, radix_list<R2, Rest...>> {};
-template <int N, int NB, int NT> using last_shape = last_stage_shape<N, NB, NT, typename plan<N>::list>;
+template <int N, int NB, int NT, int V = 0>
+using last_shape = last_stage_shape<N, NB, NT, typename plan_v<N, V>::list>;
 
 __device__ __forceinline__ int fold(int j, int n) { return 2 * j < n ? j : j - n; }
 __device__ __forceinline__ int wrap(int m, int n) { return m < 0 ? m + n : m; }

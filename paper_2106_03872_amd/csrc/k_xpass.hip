@@ -59,8 +59,8 @@ __global__ __launch_bounds__(SH::XT) void xproj_kernel(const cplx<R>* __restrict
   using C = cplx<R>;
   static_assert(!(BATCH && DENS), "batched launches carry no density");
   constexpr int NB = SH::NB, XT = SH::XT;
-  using FR = fft_regs<N0, NB, XT, C, HB>;
-  using LS = last_shape<N0, NB, XT>;
+  using FR = fft_regs<N0, NB, XT, C, HB, SH::V>;
+  using LS = last_shape<N0, NB, XT, SH::V>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ C tw[N0];
   const int tile = blockIdx.x, tid = threadIdx.x;
@@ -113,15 +113,15 @@ __global__ __launch_bounds__(SH::XT) void xproj_kernel(const cplx<R>* __restrict
   C* pout = partial + (long long)(sA + sl) * np + kq;
   const long long pstride = (long long)pt.nslots * np;
   FR pre;
-  if (oa < ob) fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
+  if (oa < ob) fft_preload_regs(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
     auto next = [&] {
       if (o + 1 < ob)
-        fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+        fft_preload_regs(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     };
     if constexpr (DENS) {
       const double f = occ[o] * inv_omega;
-      fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next),
+      fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN_LDS, C, SH::V>(X, N0 + 1, NB, tw, preloaded(pre, next),
                                                    [&](int t, int e, C v, int it, int q) {
                                                      X[t * (N0 + 1) + e] = v;
                                                      a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(SH::XT) void xproj_kernel(const cplx<R>* __restrict
         continue;
       }
     } else {
-      fft_io<N0, +1, NB, XT, SRC_PRE, DST_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
+      fft_io<N0, +1, NB, XT, SRC_PRE, DST_LDS, C, SH::V>(X, N0 + 1, NB, tw, preloaded(pre, next), no_store{});
     }
     double sx = 0.0, sy = 0.0;
 #pragma unroll
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(SH::XT) void xproj_kernel(const cplx<R>* __restrict
   }
   if constexpr (DENS) {
     double* pb = dpart + (long long)blockIdx.y * tab.n0 * npl + p0;
-    last_stage_positions<N0, NB, XT>(NB, [&](int it, int q, int t, int e) {
+    last_stage_positions<N0, NB, XT, SH::V>(NB, [&](int it, int q, int t, int e) {
       if (p0 + t < npl) pb[e * npl + t] = a[it][q];
     });
   }
@@ -279,8 +279,8 @@ __global__ __launch_bounds__(SH::XT) void xapply_kernel(const cplx<R>* __restric
                                                     const int4* __restrict__ rows = nullptr) {
   using C = cplx<R>;
   constexpr int NB = SH::NB, XT = SH::XT;
-  using LS = last_shape<N0, NB, XT>;
-  using FR = fft_regs<N0, NB, XT, C, HB>;
+  using LS = last_shape<N0, NB, XT, SH::V>;
+  using FR = fft_regs<N0, NB, XT, C, HB, SH::V>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ double2 dps[KB_TILE_DP];
   __shared__ C tw[N0];
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(SH::XT) void xapply_kernel(const cplx<R>* __restric
   // synthesis and analysis scales Omega^-1/2 Omega^1/2 / N = 1/N
   double vr[LS::items][LS::radix];
   const double* vbase = V + p0;
-  last_stage_positions<N0, NB, XT>(NB, [&](int it, int q, int t, int e) {
+  last_stage_positions<N0, NB, XT, SH::V>(NB, [&](int it, int q, int t, int e) {
     vr[it][q] = (p0 + t < npl) ? vbase[e * npl + t] * sc_v : 0.0;
   });
   // KB coefficients d*P of this tile's slots: thread tid < ns*np stages one
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(SH::XT) void xapply_kernel(const cplx<R>* __restric
   const int nplanes = tab.nplanes, m0lo = tab.m0lo;
   const int tvalid = npl - p0;
   FR pre;
-  if (oa < ob) fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, nplanes, m0lo, p0));
+  if (oa < ob) fft_preload_regs(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, nplanes, m0lo, p0));
   double2 dnext = {0.0, 0.0};
   if (tid < ndp && oa < ob) dnext = DP[oa * dp_stride + dp_off];
   for (int o = oa; o < ob; ++o) {
@@ -332,12 +332,12 @@ __global__ __launch_bounds__(SH::XT) void xapply_kernel(const cplx<R>* __restric
     if (tid < ndp) dps[tid] = dnext;
     auto next = [&] {
       if (o + 1 < ob) {
-        fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, nplanes, m0lo, p0));
+        fft_preload_regs(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, nplanes, m0lo, p0));
         if (tid < ndp) dnext = DP[(o + 1) * dp_stride + dp_off];
       }
     };
     // synthesis, then psi <- V psi as the outputs are written
-    fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN_LDS, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int t, int e, C v, int it, int q) {
+    fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN_LDS, C, SH::V>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int t, int e, C v, int it, int q) {
       X[t * (N0 + 1) + e] = C{R(vr[it][q] * double(v.x)), R(vr[it][q] * double(v.y))};
     });
     if (ns > 0) {
@@ -351,8 +351,8 @@ __global__ __launch_bounds__(SH::XT) void xapply_kernel(const cplx<R>* __restric
       if (pi >= 0 && pi < nplanes && t < tvalid) st_stream(obase + (unsigned)(pi * npl + t), v);
     };
     // only the sphere's planes are stored; with HB they all lie in the band |m0| < n0/4
-    if constexpr (HB) fft_io<N0, -1, NB, XT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, banded(store));
-    else fft_io<N0, -1, NB, XT, SRC_LDS, DST_FN, C>(X, N0 + 1, NB, tw, no_load{}, store);
+    if constexpr (HB) fft_io<N0, -1, NB, XT, SRC_LDS, DST_FN, C, SH::V>(X, N0 + 1, NB, tw, no_load{}, banded(store));
+    else fft_io<N0, -1, NB, XT, SRC_LDS, DST_FN, C, SH::V>(X, N0 + 1, NB, tw, no_load{}, store);
     __syncthreads();   // X and dps are rewritten for the next orbital
   }
 }
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(SH::XT) void xdens_kernel(const cplx<R>* __restrict
                                                    double inv_omega) {
   using C = cplx<R>;
   constexpr int NB = SH::NB, XT = SH::XT;
-  using LS = last_shape<N0, NB, XT>;
+  using LS = last_shape<N0, NB, XT, SH::V>;
   __shared__ C X[NB * (N0 + 1)];
   __shared__ C tw[N0];
   const int tile = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
@@ -383,22 +383,22 @@ __global__ __launch_bounds__(SH::XT) void xdens_kernel(const cplx<R>* __restrict
   int oa, ob;
   orbital_range(nb, oa, ob);
   // the next orbital's T is loaded once the first stage has consumed the current one
-  using FR = fft_regs<N0, NB, XT, C, HB>;
+  using FR = fft_regs<N0, NB, XT, C, HB, SH::V>;
   FR pre;
-  if (oa < ob) fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
+  if (oa < ob) fft_preload_regs(pre, NB, TLoader<N0, NB, C>(Tin, oa, npl, tab.nplanes, tab.m0lo, p0));
   for (int o = oa; o < ob; ++o) {
     auto next = [&] {
       if (o + 1 < ob)
-        fft_preload<N0, NB, XT, C>(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
+        fft_preload_regs(pre, NB, TLoader<N0, NB, C>(Tin, o + 1, npl, tab.nplanes, tab.m0lo, p0));
     };
     const double f = occ[o] * inv_omega;
-    fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN, C>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int, int, C v, int it, int q) {
+    fft_io<N0, +1, NB, XT, SRC_PRE, DST_FN, C, SH::V>(X, N0 + 1, NB, tw, preloaded(pre, next), [&](int, int, C v, int it, int q) {
       a[it][q] += f * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
     });
     __syncthreads();
   }
   double* pb = part + (long long)g * tab.n0 * npl + p0;
-  last_stage_positions<N0, NB, XT>(NB, [&](int it, int q, int t, int e) {
+  last_stage_positions<N0, NB, XT, SH::V>(NB, [&](int it, int q, int t, int e) {
     if (p0 + t < npl) pb[e * npl + t] = a[it][q];
   });
 }
@@ -425,18 +425,36 @@ static int x_groups(const ks_system* s, int nb) {
   return (int)((nb + g - 1) / g);
 }
 
-// Tile shapes of the x-pencil blocks (pencils NB x threads XT).  Shape 0
-// is xnb<N0> pencils x NT threads; shape 1 is 16 pencils x 192 threads, for
-// the largest grids only (smaller LDS buffers, more blocks resident per CU).
-// The autotuner picks the shape per grid and precision.
+// Launch shapes of the x-pencil blocks: a tile (pencils NB x threads XT)
+// and the factorisation of the x-transform (plan variant V, fft_device.hpp).
+// Shape 0 is xnb<N0> pencils x NT threads; shape 1 is 16 pencils x 192
+// threads, for the largest grids only (smaller LDS buffers, more blocks
+// resident per CU); shapes 2 and 3 are shapes 0 and 1 with the second
+// factorisation of n0 (n0 = 96: 8 x 12 instead of 12 x 8).  The autotuner
+// picks the shape per grid and precision.
 template <int NB_, int XT_>
 struct XShape {
-  static constexpr int NB = NB_, XT = XT_;
+  static constexpr int NB = NB_, XT = XT_, V = 0;
+};
+template <int NB_, int XT_>
+struct XShapeAlt {
+  static constexpr int NB = NB_, XT = XT_, V = 1;
 };
 template <int N0> constexpr bool has_shape1 = N0 == 96 || N0 == 120;
+template <int N0> constexpr bool has_alt_plan = N0 == 96;
 
 template <int N0, class F>
 static void with_shape(const ks_system* s, F&& f) {
+  if constexpr (has_alt_plan<N0>) {
+    if (s->xshape == 2) {
+      f(XShapeAlt<xnb<N0>::value, NT>{});
+      return;
+    }
+    if (s->xshape == 3) {
+      f(XShapeAlt<16, 192>{});
+      return;
+    }
+  }
   if constexpr (has_shape1<N0>) {
     if (s->xshape == 1) {
       f(XShape<16, 192>{});
@@ -448,9 +466,9 @@ static void with_shape(const ks_system* s, F&& f) {
 
 bool x_shape_available(int n0, int shape) {
   if (shape == 0) return true;
-  if (shape != 1) return false;
+  if (shape < 1 || shape > 3) return false;
   switch (n0) {
-#define KS_CASE(v) case v: return has_shape1<v>;
+#define KS_CASE(v) case v: return (shape == 1 || shape == 3 ? has_shape1<v> : true) && (shape < 2 || has_alt_plan<v>);
     KS_SIZES(KS_CASE)
 #undef KS_CASE
     default:
@@ -458,8 +476,8 @@ bool x_shape_available(int n0, int shape) {
   }
 }
 
-int x_shape_nb(int n0, int shape) { return shape == 1 ? 16 : x_tile_nb(n0); }
-int x_shape_threads(int shape) { return shape == 1 ? 192 : NT; }
+int x_shape_nb(int n0, int shape) { return shape == 1 || shape == 3 ? 16 : x_tile_nb(n0); }
+int x_shape_threads(int shape) { return shape == 1 || shape == 3 ? 192 : NT; }
 
 template <int N0, bool HB>
 static void xproj_n(const ks_system* s, int nb, const void* T, void* partial, const double* occ, double* rho,

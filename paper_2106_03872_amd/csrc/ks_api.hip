@@ -2255,11 +2255,17 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
   Taylor none{{0.0, 0.0}, 0, {0.0, 0.0}};
   const int xgs[] = {2, 4, 8, 16, 32, 64};
   const int pgs[] = {1, 2, 4, 8, 16};
+  // Within a shape the fastest caps win; a later shape (in the order 0..3)
+  // replaces an earlier one only when it is at least SHAPE_MARGIN faster, so
+  // shapes that time within noise of each other do not flip between runs.
+  constexpr float SHAPE_MARGIN = 0.01f;
   TuneResult best{s->xg_max, s->pg_max, s->xshape};
   float best_ms = -1.0f;
-  for (int shape = 0; shape < 2; ++shape) {
+  for (int shape = 0; shape < 4; ++shape) {
     if (!x_shape_available(s->n[0], shape)) continue;
     if ((r = set_x_shape(s, shape)) != KS_OK) return done(r);
+    TuneResult sbest{s->xg_max, s->pg_max, shape};
+    float sbest_ms = -1.0f;
     for (int xg : xgs) {
       for (int pg : pgs) {
         s->xg_max = xg;
@@ -2274,11 +2280,15 @@ ks_status ks_autotune(ks_system* s, int norb, void* stream, ks_tuning* out) {
         if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
           return done(fail(s, KS_EDEVICE, "hipEventElapsedTime failed"));
         ms *= 0.5f;
-        if (best_ms < 0.0f || ms < best_ms) {
-          best_ms = ms;
-          best = TuneResult{xg, pg, shape};
+        if (sbest_ms < 0.0f || ms < sbest_ms) {
+          sbest_ms = ms;
+          sbest = TuneResult{xg, pg, shape};
         }
       }
+    }
+    if (best_ms < 0.0f || sbest_ms < (1.0f - SHAPE_MARGIN) * best_ms) {
+      best_ms = sbest_ms;
+      best = sbest;
     }
   }
   if ((r = set_x_shape(s, best.shape)) != KS_OK) return done(r);

@@ -1,9 +1,10 @@
-"""x-tile shapes of the 96- and 120-point x-pencil passes (16 pencils x 192
-threads next to the default 32 x 256): H psi in both shapes against the FP64
-oracle at 1e-12 (1e-5 mixed), a resident propagation with the fused density
-at 1e-12, switching shapes back and forth (the per-tile projector tables are
-rebuilt from the stored inputs), the autotuner's choice, batches, and the
-errors.  The grids cover the band-limited (HB) and full x-synthesis inputs.
+"""x-pass launch shapes of the 96- and 120-point x-pencil passes (16 pencils
+x 192 threads next to the default 32 x 256; at 96 both tiles also with the
+x-transform factorised 8 x 12 instead of 12 x 8): H psi in every shape
+against the FP64 oracle at 1e-12 (1e-5 mixed), a resident propagation with
+the fused density at 1e-12, switching shapes back and forth (the per-tile
+projector tables are rebuilt from the stored inputs), the autotuner's choice,
+batches, and the errors.  The grids cover the band-limited (HB) and full x-synthesis inputs.
 With n1 = n2 every accepted plane holds a multiple of 16 pencils, so the
 16-pencil tiles are never ragged.
 """
@@ -59,10 +60,12 @@ def test_shapes_vs_oracle(ks, n, L, natoms):
     gs = ks.system_from_synth(sysm)
     assert gs.info()["x_half"] == int(L[0] * np.sqrt(20.0) / (2 * np.pi) < n[0] / 4 - 1)
     out = {}
-    for shape in (0, 1, 0, 1):                       # tables rebuilt on every switch
+    shapes = (0, 1, 2, 3, 0, 2, 1, 3) if n[0] == 96 else (0, 1, 0, 1)   # tables rebuilt on every switch
+    for shape in shapes:
         gs.set_tuning(8, 4, x_shape=shape)
         info = gs.info()
-        assert (info["x_shape"], info["x_tile"], info["x_threads"]) == ((0, 32, 256), (1, 16, 192))[shape]
+        assert (info["x_shape"], info["x_tile"], info["x_threads"]) == \
+            ((0, 32, 256), (1, 16, 192), (2, 32, 256), (3, 16, 192))[shape]
         got = gs.ham_apply(c).clone()
         assert rel_err(got.cpu().numpy(), ref) < TOL, shape
         assert np.all(got.cpu().numpy()[:, ~ham.grid.chi] == 0)
@@ -70,23 +73,26 @@ def test_shapes_vs_oracle(ks, n, L, natoms):
             assert torch.equal(out[shape], got)      # same shape, same tables: bit-identical
         out[shape] = got
     gm = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
-    for shape in (0, 1):
+    for shape in shapes[:len(set(shapes))]:
         gm.set_tuning(8, 4, x_shape=shape)
         assert rel_err(gm.ham_apply(c).cpu().numpy(), ref) < TOL_MIXED, shape
     gm.close()
     gs.close()
 
 
+@pytest.mark.parametrize("shape", [1, 2])
 @pytest.mark.parametrize("n,L,natoms", GRIDS[::3], ids=IDS[::3])
-def test_shape1_propagation_with_fused_density(ks, n, L, natoms):
-    print(f"[case] shape-1 propagation {n} L {L}", file=sys.stderr, flush=True)
+def test_shape1_propagation_with_fused_density(ks, n, L, natoms, shape):
+    if shape == 2 and n[0] != 96:
+        pytest.skip("the second radix plan is built for n0 = 96 only")
+    print(f"[case] shape-{shape} propagation {n} L {L}", file=sys.stderr, flush=True)
     spec = _spec(n, L, natoms, norb=3)
     sysm = synth.system(spec)
     ham = oracle_ham(sysm)
     c = orbitals_device(spec)
     c0 = c.cpu().numpy()
     gs = ks.system_from_synth(sysm)
-    gs.set_tuning(8, 4, x_shape=1)
+    gs.set_tuning(8, 4, x_shape=shape)
     occ_np = np.array([2.0, 1.0, 0.5])
     occ = torch.from_numpy(occ_np).cuda()
     st = ks.State(gs, spec.norb)
@@ -156,6 +162,12 @@ def test_shape_errors_and_batches(ks):
     assert e.value.status == ks.KS_EINVAL
     assert g48.info()["x_shape"] == 0
     g48.close()
+    g120 = ks.system_from_synth(synth.system(_spec(*GRIDS[2])))      # no second radix plan at 120
+    for shape in (2, 3):
+        with pytest.raises(ks.KSError) as e:
+            g120.set_tuning(8, 4, x_shape=shape)
+        assert e.value.status == ks.KS_EINVAL
+    g120.close()
     # batches: one launch per kernel needs one shape; results equal the states stepped alone
     n, L, _ = GRIDS[0]
     specs = [_spec(n, L, na, norb=nb) for na, nb in ((3, 5), (5, 2), (1, 7))]
