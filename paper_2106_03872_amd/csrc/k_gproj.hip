@@ -17,8 +17,9 @@
 // so DP = A B with A[o][k] the interleaved coefficients as stored.
 //
 // Split-BF16: x = hi(x) + lo(x) + O(2^-18 |x|) with hi = bf16(x) and
-// lo = bf16(x - hi); a b is taken as hi hi + hi lo + lo hi (the lo lo term
-// is O(2^-16) of the product and dropped), each on v_mfma_f32_16x16x32_bf16.
+// lo = bf16(x - hi) (|lo| <= 2^-9 |x|); a b is taken as hi hi + hi lo + lo hi
+// (the dropped lo lo term is at most 2^-18 |a b|), each on
+// v_mfma_f32_16x16x32_bf16.
 // B is stored split; A is split as it is staged.
 #include "ks_common.hpp"
 
