@@ -100,12 +100,16 @@ def test_cfg2_taylor_step_density_and_resident_state(ks, cfg2):
     gs.close()
 
 
-def test_cfg2_mixed_precision(ks, cfg2):
+@pytest.mark.parametrize("projection", [0, 1])
+def test_cfg2_mixed_precision(ks, cfg2, projection):
+    """Mixed precision with the real-space projections (0) and with the
+    split-BF16 reciprocal-space product (1)."""
     spec, sysm, ham, c0 = cfg2
     gm = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
+    gm.set_tuning(gm.info()["x_group"], gm.info()["plane_group"], projection=projection)
     c = torch.from_numpy(c0).cuda()
     err = rel_err(gm.ham_apply(c).cpu().numpy(), ko.ham_apply(ham, c0))
-    print(f"[cfg2] mixed H psi rel err {err:.2e}", file=sys.stderr, flush=True)
+    print(f"[cfg2] mixed (projection {projection}) H psi rel err {err:.2e}", file=sys.stderr, flush=True)
     assert err < TOL_MIXED
     occ_np = np.full(spec.norb, 2.0)
     rho = torch.empty((1,) + spec.n, dtype=torch.float64, device="cuda")
