@@ -1,6 +1,6 @@
 """Every grid size the library accepts, as the x-pencil length n0 and as the
 plane size n1 = n2, against the FP64 oracle (H psi at 1e-12 in FP64 and 1e-5
-in mixed precision; a two-step resident propagation with its densities at
+in mixed precision, with either projection mode; a two-step resident propagation with its densities at
 1e-12).  The 16, 24, 32, 40, 48, 60, 64, 96 and 120-point kernels are covered
 by the other parity tests; these anisotropic grids cover the rest with a
 grid spacing of 0.33-0.6 bohr, so the E_cut = 10 Ha sphere stays inside the
@@ -56,6 +56,8 @@ def test_grid_size_parity(ks, n, L, natoms):
     assert rel_err(got, ref) < TOL
     assert np.all(got[:, ~ham.grid.chi] == 0)
     gm = ks.system_from_synth(sysm, precision=ks.KS_MIXED)
+    assert rel_err(gm.ham_apply(c).cpu().numpy(), ref) < TOL_MIXED
+    gm.set_tuning(gm.info()["x_group"], gm.info()["plane_group"], projection=1)   # split-BF16 projections
     assert rel_err(gm.ham_apply(c).cpu().numpy(), ref) < TOL_MIXED
     gm.close()
     occ_np = np.array([2.0, 1.0, 0.5])
