@@ -201,11 +201,39 @@ def waves_table(dirs, classes=("plane_inv", "xproj", "xapply", "plane_fwd", "xde
     return "\n".join(out)
 
 
+def _clock_ghz(d, match=None):
+    """short kernel name -> mean clock over its dispatches in GHz: the GPU's
+    active cycles per XCD (`GRBM_GUI_ACTIVE` / 8) over the dispatch's own
+    duration, where the counter rows carry the dispatch's timestamps."""
+    out = collections.defaultdict(list)
+    for r in _counter_rows(d, "GRBM_GUI_ACTIVE"):
+        if match is not None and match not in r["Kernel_Name"]:
+            continue
+        try:
+            ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        except (KeyError, TypeError, ValueError):
+            continue
+        if ns > 0:
+            out[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]) / XCDS / ns)
+    return {k: sum(v) / len(v) for k, v in out.items()}
+
+
+def clock_table(d, matches):
+    """The clock each matching kernel ran at (`_clock_ghz`), one row per name."""
+    out = ["| kernel | clock GHz (`GRBM_GUI_ACTIVE` / 8 / dispatch time) |", "|---|---:|"]
+    for m in matches:
+        for k, v in sorted(_clock_ghz(d, m).items()):
+            out.append(f"| `{k}` | {v:.2f} |")
+    return "\n".join(out)
+
+
 def mfma_table(d, match=None, model_flops=None):
     by = _by_kernel([d], match)
+    clk = _clock_ghz(d, match)
     out = ["| kernel | dispatches | BF16 MFMA flops (`MOPS_BF16` x 512) | model flops | MFMA busy "
            "(`SQ_VALU_MFMA_BUSY_CYCLES` / (1024 SIMDs x `GRBM_GUI_ACTIVE` / 8 XCDs)) | "
-           "LDS bank-conflict cycles per LDS instruction |", "|---|---:|---:|---:|---:|---:|"]
+           "LDS bank-conflict cycles per LDS instruction | clock GHz (`GRBM_GUI_ACTIVE` / 8 / dispatch time) |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
     for k in sorted(by):
         m = {c: sum(v) / len(v) for c, v in by[k].items()}
         if m.get("SQ_INSTS_MFMA", 0.0) == 0.0:
@@ -213,8 +241,9 @@ def mfma_table(d, match=None, model_flops=None):
         fl = m.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) * 512
         busy = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * m["GRBM_GUI_ACTIVE"] / XCDS)
         mf = f"{model_flops:.4g}" if model_flops else ""
+        ck = f"{clk[k]:.2f}" if k in clk else ""
         out.append(f"| `{k}` | {len(by[k]['SQ_INSTS_MFMA'])} | {fl:.4g} | {mf} | {busy:.3f} | "
-                   f"{m['SQ_LDS_BANK_CONFLICT'] / max(1.0, m['SQ_INSTS_LDS']):.2f} |")
+                   f"{m['SQ_LDS_BANK_CONFLICT'] / max(1.0, m['SQ_INSTS_LDS']):.2f} | {ck} |")
     return "\n".join(out)
 
 
@@ -271,6 +300,9 @@ def main(argv=None):
     u.add_argument("--match", required=True)
     u.add_argument("--split-at", default=None)
     u.add_argument("--labels", nargs=2, default=("before", "after"))
+    k = sub.add_parser("clock")
+    k.add_argument("dir")
+    k.add_argument("--match", nargs="+", required=True)
     t = sub.add_parser("kerneltraffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -290,6 +322,8 @@ def main(argv=None):
         print(waves_table(args.dirs))
     elif args.cmd == "mfma":
         print(mfma_table(args.dir, args.match, args.model_flops))
+    elif args.cmd == "clock":
+        print(clock_table(args.dir, args.match))
     elif args.cmd == "durations":
         print(durations_table(args.trace, args.match, args.split_at, tuple(args.labels)))
     else:

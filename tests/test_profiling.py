@@ -77,7 +77,26 @@ def test_mfma_table_busy_fraction_and_flops(tmp_path):
     _write_counters(tmp_path / "m", rows)
     t = profiling.mfma_table(str(tmp_path / "m"), model_flops=512000.0).splitlines()
     assert len(t) == 3
-    assert t[2] == "| `gproj_gemm_kernel<float>` | 2 | 5.12e+05 | 5.12e+05 | 0.250 | 3.00 |"
+    assert t[2] == "| `gproj_gemm_kernel<float>` | 2 | 5.12e+05 | 5.12e+05 | 0.250 | 3.00 |  |"
+
+
+def test_mfma_table_clock_from_dispatch_time(tmp_path):
+    """The clock column: GRBM_GUI_ACTIVE per XCD over the dispatch's duration
+    (1600 active cycles summed over 8 XCDs in 100 ns: 2 GHz)."""
+    d = tmp_path / "c"
+    d.mkdir()
+    names = FIELDS + ["Start_Timestamp", "End_Timestamp"]
+    c = {"SQ_INSTS_MFMA": 1.0, "SQ_VALU_MFMA_BUSY_CYCLES": 1024.0, "GRBM_GUI_ACTIVE": 1600.0,
+         "SQ_LDS_BANK_CONFLICT": 0.0, "SQ_INSTS_LDS": 1.0}
+    with open(d / "run_counter_collection.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=names)
+        w.writeheader()
+        for disp, (t0, t1) in enumerate(((1000, 1100), (5000, 5080))):
+            for k, v in c.items():
+                w.writerow({"Dispatch_Id": disp, "Kernel_Name": GP, "Grid_Size": 4096, "Counter_Name": k,
+                            "Counter_Value": v, "Start_Timestamp": t0, "End_Timestamp": t1})
+    t = profiling.mfma_table(str(d)).splitlines()
+    assert t[2].endswith("| 2.25 |")                        # mean of 2.0 and 2.5 GHz
 
 
 def test_waves_table_fractions(tmp_path):
