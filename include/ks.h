@@ -126,9 +126,10 @@ ks_status ks_system_create_in(ks_pool* pool, const int n[3], const double L[3], 
  * ks_system_create (pool == NULL) or ks_system_create_in with the orbitals
  * per pass set at creation: chunk > 0 sizes the workspace (plane
  * intermediates, packed pass buffers, projection partials) for
- * min(chunk, max_norb) orbitals, chunk == 0 takes the default (as many
- * orbitals as 16 GiB of plane intermediates hold).  Calls over more orbitals
- * run in passes, with the same results.  A caller that holds many systems
+ * min(chunk, max_norb, 65535) orbitals, chunk == 0 takes the default (as
+ * many orbitals as 16 GiB of plane intermediates hold, at most 65535: the
+ * pass kernels put a pass's orbitals on the y extent of their launch grid).
+ * Calls over more orbitals run in passes, with the same results.  A caller that holds many systems
  * (serving) trades passes for memory this way without the default
  * workspace ever being allocated.  KS_EINVAL for chunk < 0, otherwise as
  * ks_system_create / ks_system_create_in.
@@ -406,7 +407,9 @@ ks_status ks_state_replay(ks_state* state, void* stream);
  * x-tile shape.  A state with more orbitals than its system's pass (chunk)
  * is stepped in passes, as alone: pass p steps chunk p (orbitals
  * [p chunk, (p+1) chunk)) of every state that has one, so a system's
- * workspace need only hold one chunk.  Allocates a small device table (from
+ * workspace need only hold one chunk.  A pass whose launch rows (orbital
+ * groups, or orbitals for the projection sums) exceed a grid's y extent of
+ * 65535 is launched in slices of rows.  Allocates a small device table (from
  * the first system's pool when it has one).  KS_EINVAL (null, empty, systems
  * that differ in grid / cell / cutoff / precision / x-tile shape, two states
  * of one system).
@@ -436,7 +439,8 @@ ks_status ks_propagate_batch(ks_state* const* states, int nstates, double dt, in
 /*
  * Device bytes a system of this shape plus a resident state of norb orbitals
  * will hold (host-only estimate for admission control; npoints = projector
- * points, chunk = 0 for the default chunk).  Counts the real-space
+ * points, chunk = 0 for the default chunk; a chunk is capped at 65535 as
+ * ks_system_create_ex caps it).  Counts the real-space
  * projections (ks_tuning.projection = 0); projection 1 adds its table and
  * partials (see ks_tuning).
  */
@@ -447,13 +451,13 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
 int ks_system_npw(const ks_system* sys);
 
 /* Largest number of orbitals processed per pass (chunk size of the internal
- * pipeline).  The default is min(max_norb, the count whose plane intermediate
- * takes 16 GiB).  A call over norb orbitals runs ceil(norb / chunk) passes of
- * equal size (up to one orbital). */
+ * pipeline).  The default is min(max_norb, 65535, the count whose plane
+ * intermediate takes 16 GiB).  A call over norb orbitals runs
+ * ceil(norb / chunk) passes of equal size (up to one orbital). */
 int ks_system_chunk(const ks_system* sys);
 
-/* Set the chunk size (1 <= chunk <= max_norb); reallocates the workspace, so
- * call it at set-up time only.  KS_EINVAL when out of range. */
+/* Set the chunk size (1 <= chunk <= min(max_norb, 65535)); reallocates the
+ * workspace, so call it at set-up time only.  KS_EINVAL when out of range. */
 ks_status ks_system_set_chunk(ks_system* sys, int chunk);
 
 /* ------------------------------------------------------------------------

@@ -52,10 +52,11 @@ __device__ __forceinline__ void split_store(__bf16* W, long long at, double x0, 
   W[at + 9] = l1;
 }
 
-// One thread per packed plane wave g, one block row per atom I: the sum over
-// the atom's sphere points of beta_Ip(r_j) e^{iG.r_j} in FP64, the phase
-// taken from per-axis tables of unit roots (exact integer residues).
-__global__ __launch_bounds__(256) void gproj_table_kernel(SphereTab sp, int ncols, int npw, int kpad,
+// One thread per packed plane wave g, block row y for the atoms I = y, y +
+// gridDim.y, ...: the sum over the atom's sphere points of
+// beta_Ip(r_j) e^{iG.r_j} in FP64, the phase taken from per-axis tables of
+// unit roots (exact integer residues).
+__global__ __launch_bounds__(256) void gproj_table_kernel(SphereTab sp, int ncols, int npw, int kpad, int natoms,
                                                           const int* __restrict__ pt_off, const int* __restrict__ idx,
                                                           const double* __restrict__ beta,
                                                           const double* __restrict__ d, int np, double scale,
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void gproj_table_kernel(SphereTab sp, int ncol
   __shared__ double2 u[3][GP_MAXN];
   __shared__ int sj[256][3];
   __shared__ double sb[256 * KB_MAX_NPROJ];
-  const int I = blockIdx.y, t = threadIdx.x;
+  const int t = threadIdx.x;
   const int g = blockIdx.x * 256 + t;
   const int n[3] = {sp.n0, sp.n1, sp.n2};
   for (int a = 0; a < 3; ++a)
@@ -81,46 +82,49 @@ __global__ __launch_bounds__(256) void gproj_table_kernel(SphereTab sp, int ncol
     m[2] = sp.col_m2lo[cc] + (g - sp.col_off[cc]);
   }
   for (int a = 0; a < 3; ++a) m[a] = ((m[a] % n[a]) + n[a]) % n[a];
-  double2 acc[KB_MAX_NPROJ];
+  for (int I = blockIdx.y; I < natoms; I += gridDim.y) {   // uniform per block
+    double2 acc[KB_MAX_NPROJ];
 #pragma unroll
-  for (int p = 0; p < KB_MAX_NPROJ; ++p) acc[p] = double2{0.0, 0.0};
-  const int j1 = pt_off[I + 1];
-  for (int j0 = pt_off[I]; j0 < j1; j0 += 256) {
-    const int nj = min(256, j1 - j0);
-    __syncthreads();
-    if (t < nj) {
-      const int f = idx[j0 + t];
-      sj[t][0] = f / (sp.n1 * sp.n2);
-      sj[t][1] = (f / sp.n2) % sp.n1;
-      sj[t][2] = f % sp.n2;
-      for (int p = 0; p < np; ++p) sb[t * KB_MAX_NPROJ + p] = beta[(long long)(j0 + t) * np + p];
+    for (int p = 0; p < KB_MAX_NPROJ; ++p) acc[p] = double2{0.0, 0.0};
+    const int j1 = pt_off[I + 1];
+    for (int j0 = pt_off[I]; j0 < j1; j0 += 256) {
+      const int nj = min(256, j1 - j0);
+      __syncthreads();
+      if (t < nj) {
+        const int f = idx[j0 + t];
+        sj[t][0] = f / (sp.n1 * sp.n2);
+        sj[t][1] = (f / sp.n2) % sp.n1;
+        sj[t][2] = f % sp.n2;
+        for (int p = 0; p < np; ++p) sb[t * KB_MAX_NPROJ + p] = beta[(long long)(j0 + t) * np + p];
+      }
+      __syncthreads();
+      for (int j = 0; j < nj; ++j) {
+        const double2 a0 = u[0][(m[0] * sj[j][0]) % sp.n0];
+        const double2 a1 = u[1][(m[1] * sj[j][1]) % sp.n1];
+        const double2 a2 = u[2][(m[2] * sj[j][2]) % sp.n2];
+        const double2 b01{a0.x * a1.x - a0.y * a1.y, a0.x * a1.y + a0.y * a1.x};
+        const double2 ph{b01.x * a2.x - b01.y * a2.y, b01.x * a2.y + b01.y * a2.x};
+#pragma unroll
+        for (int p = 0; p < KB_MAX_NPROJ; ++p)
+          if (p < np) {
+            const double bv = sb[j * KB_MAX_NPROJ + p];
+            acc[p].x += bv * ph.x;
+            acc[p].y += bv * ph.y;
+          }
+      }
     }
-    __syncthreads();
-    for (int j = 0; j < nj; ++j) {
-      const double2 a0 = u[0][(m[0] * sj[j][0]) % sp.n0];
-      const double2 a1 = u[1][(m[1] * sj[j][1]) % sp.n1];
-      const double2 a2 = u[2][(m[2] * sj[j][2]) % sp.n2];
-      const double2 b01{a0.x * a1.x - a0.y * a1.y, a0.x * a1.y + a0.y * a1.x};
-      const double2 ph{b01.x * a2.x - b01.y * a2.y, b01.x * a2.y + b01.y * a2.x};
+    if (g < npw) {
 #pragma unroll
       for (int p = 0; p < KB_MAX_NPROJ; ++p)
         if (p < np) {
-          const double bv = sb[j * KB_MAX_NPROJ + p];
-          acc[p].x += bv * ph.x;
-          acc[p].y += bv * ph.y;
+          const int q = I * np + p;
+          const double f = d[q] * scale;
+          const double wr = f * acc[p].x, wi = f * acc[p].y;
+          split_store(W, w_at(2 * q, 2 * g, kpad), wr, -wi);
+          split_store(W, w_at(2 * q + 1, 2 * g, kpad), wi, wr);
         }
     }
   }
-  if (g >= npw) return;
-#pragma unroll
-  for (int p = 0; p < KB_MAX_NPROJ; ++p)
-    if (p < np) {
-      const int q = I * np + p;
-      const double f = d[q] * scale;
-      const double wr = f * acc[p].x, wi = f * acc[p].y;
-      split_store(W, w_at(2 * q, 2 * g, kpad), wr, -wi);
-      split_store(W, w_at(2 * q + 1, 2 * g, kpad), wi, wr);
-    }
 }
 
 __device__ __forceinline__ void ld4(const float* p, float v[4]) {
@@ -299,9 +303,9 @@ bool launch_gproj_table(const ks_system* s, const int* pt_off, const int* idx, c
   if (natoms == 0) return true;
   if (np > KB_MAX_NPROJ || s->n[0] > GP_MAXN || s->n[1] > GP_MAXN || s->n[2] > GP_MAXN) return false;
   const double scale = s->omega / ((double)s->N * (double)s->N);
-  const dim3 grid((s->npw + 255) / 256, natoms);
-  gproj_table_kernel<<<grid, 256, 0, st>>>(sphere_tab(s), s->ncols, s->npw, kpad, pt_off, idx, beta, d, np, scale,
-                                           W);
+  const dim3 grid((s->npw + 255) / 256, std::min(natoms, KS_MAX_GRID_Y));
+  gproj_table_kernel<<<grid, 256, 0, st>>>(sphere_tab(s), s->ncols, s->npw, kpad, natoms, pt_off, idx, beta, d, np,
+                                           scale, W);
   return true;
 }
 

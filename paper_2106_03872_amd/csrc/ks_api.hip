@@ -506,7 +506,7 @@ constexpr double KS_CHUNK_BYTES = 16.0 * 1024 * 1024 * 1024;
 int default_chunk(const ks_system* s) {
   const double per = (double)s->nplanes * s->npl * (s->prec == KS_FP64 ? sizeof(double2) : sizeof(float2));
   int cb = (int)std::max(1.0, std::floor(KS_CHUNK_BYTES / per));
-  return std::max(1, std::min(cb, s->max_norb));
+  return std::max(1, std::min({cb, s->max_norb, KS_MAX_GRID_Y}));
 }
 
 // Orbitals per pass for a call over norb orbitals: the passes are balanced
@@ -1009,7 +1009,7 @@ static ks_status system_create(ks_pool* pool, const int n[3], const double L[3],
     ks_system_destroy(s);
     return st;
   }
-  s->cb = chunk > 0 ? std::min(chunk, max_norb) : default_chunk(s);
+  s->cb = chunk > 0 ? std::min({chunk, max_norb, KS_MAX_GRID_Y}) : default_chunk(s);
   if ((st = alloc_workspace(s)) != KS_OK) {
     g_create_err = s->err;
     ks_system_destroy(s);
@@ -1052,7 +1052,8 @@ int ks_system_chunk(const ks_system* s) { return s ? s->cb : 0; }
 
 ks_status ks_system_set_chunk(ks_system* s, int chunk) {
   if (!s) return fail(nullptr, KS_EINVAL, "null system");
-  if (chunk < 1 || chunk > s->max_norb) return fail(s, KS_EINVAL, "chunk outside [1, max_norb]");
+  if (chunk < 1 || chunk > s->max_norb || chunk > KS_MAX_GRID_Y)
+    return fail(s, KS_EINVAL, "chunk outside [1, min(max_norb, " + std::to_string(KS_MAX_GRID_Y) + ")]");
   wait_own(s);
   s->cb = chunk;
   ++s->gen;
@@ -2033,8 +2034,19 @@ void ks_batch_destroy(ks_batch* b) {
   delete b;
 }
 
+// f(rows + r0, n) over consecutive slices of at most KS_MAX_GRID_Y rows (each
+// batched kernel reads its row as rows[blockIdx.y]).
+extern "C++" {
+template <class F>
+static bool row_slices(const int4* rows, int nrows, F&& f) {
+  for (int r0 = 0; r0 < nrows; r0 += KS_MAX_GRID_Y)
+    if (!f(rows + r0, std::min(KS_MAX_GRID_Y, nrows - r0))) return false;
+  return true;
+}
+}
+
 // nsteps Taylor-4 steps of every state of the batch, one launch per kernel
-// and H psi for all of them.
+// (per slice of rows) and H psi for all of them.
 static ks_status batch_taylor(ks_batch* b, double dt, int nsteps, hipStream_t st) {
   ks_system* s0 = b->s0;
   double2 coef[5];
@@ -2048,22 +2060,40 @@ static ks_status batch_taylor(ks_batch* b, double dt, int nsteps, hipStream_t st
         const bool in64 = k == 1 || s0->prec == KS_FP64;
         const Taylor tay{coef[k], k < 4 ? 1 : 0, {0.0, 0.0}};
         if ((r = kcall(s0, KS_K_PLANE_INV, st, "plane_inv",
-                       [&] { return launch_plane_inv_batch(s0, jobs, bp.rows_p, bp.nrows_p, in64, st); })) != KS_OK)
+                       [&] {
+                         return row_slices(bp.rows_p, bp.nrows_p, [&](const int4* rs, int n) {
+                           return launch_plane_inv_batch(s0, jobs, rs, n, in64, st);
+                         });
+                       })) != KS_OK)
           return r;
         if (bp.max_natoms > 0) {
           if ((r = kcall(s0, KS_K_XPROJ, st, "xproj",
-                         [&] { return launch_x_batch(s0, jobs, bp.rows_x, bp.nrows_x, false, st); })) != KS_OK)
+                         [&] {
+                           return row_slices(bp.rows_x, bp.nrows_x, [&](const int4* rs, int n) {
+                             return launch_x_batch(s0, jobs, rs, n, false, st);
+                           });
+                         })) != KS_OK)
             return r;
           if ((r = kcall(s0, KS_K_PROJ_REDUCE, st, "proj_reduce", [&] {
-                 return launch_proj_reduce_batch(s0, jobs, bp.rows_r, bp.nrows_r, bp.max_natoms, st);
+                 return row_slices(bp.rows_r, bp.nrows_r, [&](const int4* rs, int n) {
+                   return launch_proj_reduce_batch(s0, jobs, rs, n, bp.max_natoms, st);
+                 });
                })) != KS_OK)
             return r;
         }
         if ((r = kcall(s0, KS_K_XAPPLY, st, "xapply",
-                       [&] { return launch_x_batch(s0, jobs, bp.rows_x, bp.nrows_x, true, st); })) != KS_OK)
+                       [&] {
+                         return row_slices(bp.rows_x, bp.nrows_x, [&](const int4* rs, int n) {
+                           return launch_x_batch(s0, jobs, rs, n, true, st);
+                         });
+                       })) != KS_OK)
           return r;
         if ((r = kcall(s0, KS_K_PLANE_FWD, st, "plane_fwd",
-                       [&] { return launch_plane_fwd_batch(s0, jobs, bp.rows_p, bp.nrows_p, in64, tay, st); })) !=
+                       [&] {
+                         return row_slices(bp.rows_p, bp.nrows_p, [&](const int4* rs, int n) {
+                           return launch_plane_fwd_batch(s0, jobs, rs, n, in64, tay, st);
+                         });
+                       })) !=
             KS_OK)
           return r;
       }
@@ -2157,6 +2187,7 @@ ks_status ks_plan_footprint(const int n[3], const double L[3], double ecut, int 
   const double stride = (double)((h.npw + 63) / 64 * 64);
   int cb = chunk;
   if (cb <= 0) cb = std::max(1, std::min(norb, (int)std::floor(KS_CHUNK_BYTES / (nplanes * npl * es))));
+  cb = std::min(cb, KS_MAX_GRID_Y);
   const double np = std::max(1, nproj);
   double b = 0.0;
   b += (double)cb * stride * (16.0 + 2.0 * es);         // packed chunk buffers

@@ -92,6 +92,10 @@ constexpr size_t GEMM_PART_MAX = 256ull << 20;    // largest split-K partial buf
 constexpr int KB_TILE_DP = 128;        // (slot, projector) pairs staged per x-tile
 constexpr int KB_CACHED_POINTS = 16;   // points of an item held in registers across orbitals
 constexpr int KB_MAX_GROUP_LOG = 4;    // at most 16 lanes per (slot, projector) pair
+// Largest y extent of a launch grid.  The pass kernels put the orbitals of a
+// pass (or their groups, or the rows of a batch) on it, so a pass holds at
+// most this many orbitals and batched launches are issued in slices of rows.
+constexpr int KS_MAX_GRID_Y = 65535;
 
 enum HMode { H_OUT = 0, H_TAYLOR = 1 };
 

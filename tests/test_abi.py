@@ -72,3 +72,12 @@ def test_build_entry_points_exist():
     ge = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(ge)
     assert callable(ge.build) and callable(ge.smoke)
+
+
+def test_footprint_caps_the_pass_at_the_grid_limit():
+    """A pass holds at most 65535 orbitals (the y extent of a launch grid):
+    the planner counts the default chunk and any larger chunk as 65535."""
+    n, L = (8, 12, 12), (4.8, 7.2, 7.2)
+    fp = lambda chunk: ks.plan_footprint(n, L, 10.0, 100000, 100, chunk=chunk)
+    assert fp(0) == fp(65535) == fp(200000)
+    assert fp(65534) < fp(65535)
