@@ -176,12 +176,17 @@ def _by_kernel(dirs, match=None):
     return out
 
 
-def waves_table(dirs, classes=("plane_inv", "xproj", "xapply", "plane_fwd", "xdens")):
+def waves_table(dirs, classes=("plane_inv", "xproj", "xapply", "plane_fwd", "xdens"), match=None):
+    """Per pass class, the most frequent (kernel, grid) of the counter runs in
+    dirs (only kernels whose short name, template arguments included,
+    contains `match`, when given)."""
     rows = []
     for d in dirs:
         rows += _counter_rows(d)
     by = collections.defaultdict(lambda: collections.defaultdict(lambda: collections.defaultdict(list)))
     for r in rows:
+        if match is not None and match not in short_name(r["Kernel_Name"]):
+            continue
         k = kernel_class(r["Kernel_Name"])
         if k is not None and k != "copy":
             by[k][(r["Kernel_Name"], _grid(r))][r["Counter_Name"]].append(float(r["Counter_Value"]))
@@ -291,6 +296,7 @@ def main(argv=None):
     c.add_argument("dirs", nargs="+")
     w = sub.add_parser("waves")
     w.add_argument("dirs", nargs="+")
+    w.add_argument("--match", default=None)
     m = sub.add_parser("mfma")
     m.add_argument("dir")
     m.add_argument("--match", default=None)
@@ -319,7 +325,7 @@ def main(argv=None):
     elif args.cmd == "counters":
         print(counters_table(args.dirs))
     elif args.cmd == "waves":
-        print(waves_table(args.dirs))
+        print(waves_table(args.dirs, match=args.match))
     elif args.cmd == "mfma":
         print(mfma_table(args.dir, args.match, args.model_flops))
     elif args.cmd == "clock":

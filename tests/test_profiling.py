@@ -105,6 +105,17 @@ def test_waves_table_fractions(tmp_path):
     _write_counters(tmp_path / "s", [(XA, 200, k, v) for k, v in c.items()])
     t = profiling.waves_table([str(tmp_path / "s")]).splitlines()
     assert t[2] == "| `xapply_kernel<96, XShape<32, 256>, double, true, false>` | 0.300 | 0.500 | 0.200 | 0.150 | 0.080 | 0.500 |"
+    # a name filter picks the complex64 instantiation of a mixed run, even
+    # where the FP64 one has more dispatches
+    xf = XA.replace("double", "float")
+    rows = [(XA, 200, k, v) for k, v in c.items()] * 3 + [(xf, 200, k, v / 2 if k == "SQ_WAIT_ANY" else v)
+                                                           for k, v in c.items()]
+    rows = [(n.replace("(int)", "(int, double, float)"), g, k, v) for n, g, k, v in rows]   # parameters do not match
+    _write_counters(tmp_path / "m", rows)
+    t = profiling.waves_table([str(tmp_path / "m")], match=", float,").splitlines()
+    assert len(t) == 3 and t[2].startswith("| `xapply_kernel<96, XShape<32, 256>, float, true, false>` | 0.300 | 0.250 |")
+    t = profiling.waves_table([str(tmp_path / "m")], match=", double,").splitlines()
+    assert len(t) == 3 and t[2].startswith("| `xapply_kernel<96, XShape<32, 256>, double, true, false>` | 0.300 | 0.500 |")
 
 
 def test_durations_split_and_kernel_traffic(tmp_path):
